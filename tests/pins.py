@@ -1,0 +1,193 @@
+"""Independent references that pin the oracle (pure numpy, FP64).
+
+None of these shares code with ``oracle/``; each follows from the geometry of
+the problem of Sec. III-B rather than from the oracle's Newton iteration:
+
+* :func:`image_method` - reflection-only chains, the exact method the paper
+  compares against (Sec. I, Sec. IV-A).
+* :func:`edge_closed_form` - one diffraction edge: unfolding the two segments
+  about the edge line turns the problem into a straight line in a plane.
+* :func:`brute_force` - coarse-to-fine grid search of L(T) on tiny inputs.
+* :func:`path_length`, :func:`segment_dirs` - plain evaluation of Eq. 5.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def path_geometry(b, i):
+    """(TX, RX, [(b_j, a1_j, a2_j)]) of path i of a Batch, in float64."""
+    tx = b.pts[:, b.src[i]].astype(np.float64)
+    rx = b.pts[:, b.dst[i]].astype(np.float64)
+    objs = []
+    for j in range(int(b.order[i])):
+        k = b.ids[j, i]
+        objs.append((b.obj[0:3, k].astype(np.float64),
+                     b.obj[3:6, k].astype(np.float64),
+                     b.obj[6:9, k].astype(np.float64)))
+    return tx, rx, objs
+
+
+def path_points(tx, rx, objs, t):
+    """[x_0, x_1..x_n, x_{n+1}] for t = [(t0, t1)] per object."""
+    xs = [tx]
+    for (bb, a1, a2), (t0, t1) in zip(objs, t):
+        xs.append(bb + t0 * a1 + t1 * a2)
+    xs.append(rx)
+    return np.array(xs)
+
+
+def path_length(xs):
+    return float(np.sum(np.linalg.norm(np.diff(xs, axis=0), axis=1)))
+
+
+def segment_dirs(xs):
+    r = np.diff(xs, axis=0)
+    ell = np.linalg.norm(r, axis=1)
+    return r / ell[:, None], ell
+
+
+def _normal(a1, a2):
+    nv = np.cross(a1, a2)
+    return nv / np.linalg.norm(nv)
+
+
+def _reflect(p, bb, nv):
+    return p - 2.0 * np.dot(p - bb, nv) * nv
+
+
+def image_method(tx, rx, planes):
+    """Image method for a chain of planar reflections.
+
+    Images p_k = mirror of p_{k-1} in plane k (p_0 = TX). Tracing back from
+    RX, x_n is where the segment p_n -> RX meets plane n, x_{n-1} where
+    p_{n-1} -> x_n meets plane n-1, and so on. Returns (points [n][3], L,
+    valid); valid is True when every intersection falls strictly inside its
+    segment, i.e. the unfolded path is a straight line that crosses the
+    mirrors in order, so the points form a specular path and (the problem
+    being convex) the minimiser.
+    """
+    ims = [tx]
+    nvs = []
+    for (bb, a1, a2) in planes:
+        nv = _normal(a1, a2)
+        nvs.append(nv)
+        ims.append(_reflect(ims[-1], bb, nv))
+    n = len(planes)
+    pts = [None] * n
+    target = rx
+    valid = True
+    for k in range(n - 1, -1, -1):
+        p = ims[k + 1]
+        bb = planes[k][0]
+        nv = nvs[k]
+        den = np.dot(target - p, nv)
+        if den == 0.0:
+            return None, None, False
+        s = np.dot(bb - p, nv) / den
+        if not (0.0 < s < 1.0):
+            valid = False
+        pts[k] = p + s * (target - p)
+        target = pts[k]
+    L = float(np.linalg.norm(rx - ims[-1]))
+    return np.array(pts), L, valid
+
+
+def edge_closed_form(tx, rx, bb, a1):
+    """Shortest path TX -> line(b + t a1) -> RX.
+
+    With e = a1/|a1|, s_p = (p-b).e and rho_p = |p - b - s_p e| (likewise for
+    q): rotating q about the line into the half-plane opposite p turns the
+    path into a straight segment of length sqrt((s_q-s_p)^2 + (rho_p+rho_q)^2),
+    crossing the line at s = s_p + (s_q-s_p) rho_p / (rho_p + rho_q).
+    Returns (t in units of a1, point, L)."""
+    na = np.linalg.norm(a1)
+    e = a1 / na
+    sp = np.dot(tx - bb, e)
+    sq = np.dot(rx - bb, e)
+    rp = np.linalg.norm(tx - bb - sp * e)
+    rq = np.linalg.norm(rx - bb - sq * e)
+    s = sp + (sq - sp) * rp / (rp + rq)
+    L = float(np.hypot(sq - sp, rp + rq))
+    return s / na, bb + s * e, L
+
+
+def brute_force(tx, rx, objs, levels=70, pts_per_dim=None, shrink=0.75):
+    """Coarse-to-fine grid search of L over the active parameters.
+
+    The start box is centred on the parameters of the foot of TX on each
+    object, with a half-width (in parameter units) covering every point within
+    L(0) of TX, which contains every point of the minimiser (L* <= L(0)).
+    Each level keeps the best grid point and shrinks the box around it; L is
+    convex, so the minimum is not lost while the grid spacing stays below the
+    new half-width. Returns (t [(t0, t1)], L)."""
+    dims = []  # (object, basis) of each active parameter
+    for j, (bb, a1, a2) in enumerate(objs):
+        dims.append((j, 0))
+        if np.any(a2 != 0):
+            dims.append((j, 1))
+    D = len(dims)
+    if pts_per_dim is None:
+        pts_per_dim = {1: 41, 2: 31, 3: 15, 4: 11}[D]
+    zero_t = [(0.0, 0.0)] * len(objs)
+    L0 = path_length(path_points(tx, rx, objs, zero_t))
+    center = np.zeros(D)
+    half = np.zeros(D)
+    for c, (j, k) in enumerate(dims):
+        bb, a1, a2 = objs[j]
+        A = np.stack([a1, a2], 1)[:, :1 if not np.any(a2 != 0) else 2]
+        # least-squares parameters of the projection of TX on the object
+        tt, *_ = np.linalg.lstsq(A, tx - bb, rcond=None)
+        center[c] = tt[k]
+        smin = np.linalg.svd(A, compute_uv=False).min()
+        half[c] = (L0 + 1.0) / smin * 1.5
+    best_L = np.inf
+    for _ in range(levels):
+        axes = [np.linspace(center[c] - half[c], center[c] + half[c],
+                            pts_per_dim) for c in range(D)]
+        grid = np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, D)
+        xs = [np.broadcast_to(tx, (grid.shape[0], 3))]
+        for j, (bb, a1, a2) in enumerate(objs):
+            x = np.broadcast_to(bb, (grid.shape[0], 3)).copy()
+            for c, (jj, k) in enumerate(dims):
+                if jj == j:
+                    x = x + grid[:, c:c + 1] * (a1 if k == 0 else a2)
+            xs.append(x)
+        xs.append(np.broadcast_to(rx, (grid.shape[0], 3)))
+        L = sum(np.linalg.norm(xs[i + 1] - xs[i], axis=1)
+                for i in range(len(xs) - 1))
+        k = int(np.argmin(L))
+        if L[k] <= best_L:
+            best_L = float(L[k])
+            center = grid[k].copy()
+        half = half * shrink
+    t = [[0.0, 0.0] for _ in objs]
+    for c, (j, k) in enumerate(dims):
+        t[j][k] = center[c]
+    return [tuple(v) for v in t], best_L
+
+
+def batch_from_paths(paths, S):
+    """Batch of explicit paths [(tx, rx, [(b, a1, a2), ...]), ...] (mixed
+    orders allowed): each object gets its own column, each endpoint its own
+    point."""
+    from paper_2510_16172_amd.scenes import Batch
+    N = len(paths)
+    n_max = max(len(p[2]) for p in paths)
+    cols, P = [], []
+    ids = np.full((n_max, N), -1, np.int32)
+    order = np.zeros(N, np.uint8)
+    src = np.zeros(N, np.int32)
+    dst = np.zeros(N, np.int32)
+    for i, (tx, rx, objs) in enumerate(paths):
+        src[i] = len(P)
+        P.append(np.asarray(tx, np.float64))
+        dst[i] = len(P)
+        P.append(np.asarray(rx, np.float64))
+        order[i] = len(objs)
+        for j, (bb, a1, a2) in enumerate(objs):
+            ids[j, i] = len(cols)
+            cols.append(np.concatenate([bb, a1, a2]).astype(np.float64))
+    obj = np.array(cols, np.float32).T.copy()
+    pts = np.array(P, np.float32).T.copy()
+    return Batch(obj, pts, src, dst, order, ids, float(S))

@@ -1,0 +1,342 @@
+"""Pins of the FP64 oracle against what the geometry fixes (CPU only).
+
+Each test compares the oracle with something other than itself: hand-worked
+minimisers (tests/golden), the image method, the single-edge closed form,
+brute-force grid search, optimality conditions and symmetries of the problem
+of Sec. III-B, and central finite differences for the gradient of Sec. III-D.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import pins
+from paper_2510_16172_amd import scenes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_worked.json")
+
+
+def _solve(oracle_mod, b):
+    r = oracle_mod.solve(b, threads=4)
+    assert np.all(r["flags"] & (oracle_mod.INVALID | oracle_mod.NOCONV) == 0)
+    return r
+
+
+def test_golden_hand_worked(oracle_mod):
+    cases = json.load(open(GOLDEN))["cases"]
+    paths = [(np.array(c["tx"], float), np.array(c["rx"], float),
+              [tuple(np.array(v, float) for v in o) for o in c["objects"]])
+             for c in cases]
+    b = pins.batch_from_paths(paths, S=10.0)
+    r = _solve(oracle_mod, b)
+    for i, c in enumerate(cases):
+        n = len(c["objects"])
+        np.testing.assert_allclose(r["x"][i, :n], np.array(c["x"]), atol=1e-9,
+                                   err_msg=c["name"])
+        assert abs(r["len"][i] - c["L"]) < 1e-12, c["name"]
+    names = [c["name"] for c in cases]
+    collapsed = r["flags"] & oracle_mod.COLLAPSED != 0
+    assert collapsed[names.index("collapsed pass-through at a corner line")]
+    assert collapsed.sum() == 1
+
+
+def test_single_reflection_image_method(oracle_mod):
+    N = 400
+    b = scenes.random_paths(N, 1, seed=11, kinds=np.ones((1, N), bool))
+    r = _solve(oracle_mod, b)
+    n_same = 0
+    for i in range(N):
+        tx, rx, objs = pins.path_geometry(b, i)
+        bb, a1, a2 = objs[0]
+        nv = np.cross(a1, a2)
+        same_side = np.dot(tx - bb, nv) * np.dot(rx - bb, nv) > 0
+        if same_side:
+            n_same += 1
+            x, L, valid = pins.image_method(tx, rx, objs)
+            assert valid
+            np.testing.assert_allclose(r["x"][i, 0], x[0], atol=1e-9 * b.S)
+            assert abs(r["len"][i] - L) < 1e-12 * b.S
+        else:
+            # pass-through: the straight segment crosses the plane
+            L = np.linalg.norm(rx - tx)
+            assert abs(r["len"][i] - L) < 1e-12 * b.S
+            s = np.dot(bb - tx, nv) / np.dot(rx - tx, nv)
+            np.testing.assert_allclose(r["x"][i, 0], tx + s * (rx - tx),
+                                       atol=1e-9 * b.S)
+    assert 100 < n_same < 300
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_reflection_chains_image_method(oracle_mod, n):
+    N = 3000
+    b = scenes.random_paths(N, n, seed=20 + n, kinds=np.ones((n, N), bool))
+    r = _solve(oracle_mod, b)
+    n_valid = 0
+    for i in range(N):
+        tx, rx, objs = pins.path_geometry(b, i)
+        x, L, valid = pins.image_method(tx, rx, objs)
+        if not valid:
+            continue
+        n_valid += 1
+        assert abs(r["len"][i] - L) < 1e-11 * b.S
+        np.testing.assert_allclose(r["x"][i, :n], x, atol=1e-8 * b.S)
+    assert n_valid >= 30
+
+
+def test_single_edge_closed_form(oracle_mod):
+    N = 500
+    b = scenes.random_paths(N, 1, seed=31, kinds=np.zeros((1, N), bool))
+    r = _solve(oracle_mod, b)
+    for i in range(N):
+        tx, rx, objs = pins.path_geometry(b, i)
+        bb, a1, _ = objs[0]
+        t, x, L = pins.edge_closed_form(tx, rx, bb, a1)
+        assert abs(r["len"][i] - L) < 1e-12 * b.S
+        np.testing.assert_allclose(r["x"][i, 0], x, atol=1e-9 * b.S)
+        assert abs(r["t"][i, 0, 0] - t) < 1e-9 * b.S
+        assert r["t"][i, 0, 1] == 0.0
+
+
+def test_brute_force_tiny(oracle_mod):
+    b1 = scenes.random_paths(8, 1, seed=41)
+    b2 = scenes.random_paths(10, 2, seed=42)
+    for b in (b1, b2):
+        r = _solve(oracle_mod, b)
+        for i in range(b.N):
+            tx, rx, objs = pins.path_geometry(b, i)
+            t, L = pins.brute_force(tx, rx, objs)
+            # the oracle is at least as short, and not measurably shorter
+            assert r["len"][i] <= L + 1e-12 * b.S
+            assert L - r["len"][i] < 1e-9 * b.S
+            xb = pins.path_points(tx, rx, objs, t)[1:-1]
+            np.testing.assert_allclose(r["x"][i, :len(objs)], xb,
+                                       atol=1e-4 * b.S)
+
+
+def _check_optimality(oracle_mod, b, r, rng):
+    """Stationarity, reflection / Keller-cone laws, bounds."""
+    probes = 0
+    for i in range(b.N):
+        tx, rx, objs = pins.path_geometry(b, i)
+        n = len(objs)
+        xs = np.vstack([tx, r["x"][i, :n], rx])
+        u, ell = pins.segment_dirs(xs)
+        assert r["len"][i] >= np.linalg.norm(rx - tx) - 1e-12 * b.S
+        assert abs(r["len"][i] - ell.sum()) < 1e-12 * b.S
+        for j, (bb, a1, a2) in enumerate(objs):
+            x = r["x"][i, j]
+            tt = r["t"][i, j]
+            np.testing.assert_allclose(bb + tt[0] * a1 + tt[1] * a2, x,
+                                       atol=1e-12 * b.S)
+        if r["flags"][i] & oracle_mod.COLLAPSED:
+            continue
+        for j, (bb, a1, a2) in enumerate(objs):
+            du = u[j] - u[j + 1]
+            assert abs(np.dot(a1, du)) < 1e-9 * np.linalg.norm(a1)
+            if np.any(a2 != 0):
+                # law of reflection: equal tangential parts, and the normal
+                # parts are equal (pass-through) or opposite (specular)
+                assert abs(np.dot(a2, du)) < 1e-9 * np.linalg.norm(a2)
+                nv = np.cross(a1, a2)
+                nv /= np.linalg.norm(nv)
+                assert abs(abs(np.dot(u[j], nv)) - abs(np.dot(u[j + 1], nv))) < 1e-9
+            else:
+                # Keller cone: equal angles with the edge direction
+                e = a1 / np.linalg.norm(a1)
+                assert abs(np.dot(u[j], e) - np.dot(u[j + 1], e)) < 1e-9
+    # L* <= L(T) for random T near and far from T*
+    for scale in (1e-3, 1e-1, 3.0):
+        t = r["t"] + scale * rng.standard_normal(r["t"].shape)
+        for j in range(b.n_max):
+            edge = np.all(b.obj[6:9, np.maximum(b.ids[j], 0)] == 0, axis=0)
+            t[edge, j, 1] = 0.0
+        L = oracle_mod.length(b, np.nan_to_num(t))
+        ok = b.order > 0
+        assert np.all(r["len"][ok] <= L[ok] + 1e-12 * b.S)
+        probes += ok.sum()
+    return probes
+
+
+def test_optimality_random(oracle_mod):
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 3, 5):
+        b = scenes.random_paths(300, n, seed=50 + n)
+        r = _solve(oracle_mod, b)
+        _check_optimality(oracle_mod, b, r, rng)
+
+
+def test_optimality_canyon(oracle_mod):
+    rng = np.random.default_rng(6)
+    sc = scenes.canyon_scene()
+    for n in (1, 2, 3, 6):
+        b = scenes.canyon_sample_paths(sc, 400, seed=60 + n, n=n)
+        r = _solve(oracle_mod, b)
+        _check_optimality(oracle_mod, b, r, rng)
+
+
+def test_reversal_symmetry(oracle_mod):
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 500, seed=71, n=3)
+    rev = scenes.Batch(b.obj, b.pts, b.dst.copy(), b.src.copy(), b.order,
+                       np.ascontiguousarray(b.ids[::-1]), b.S)
+    r = _solve(oracle_mod, b)
+    q = _solve(oracle_mod, rev)
+    np.testing.assert_allclose(q["len"], r["len"], rtol=0, atol=1e-11 * b.S)
+    # points are unique unless the Hessian is singular (ILL: e.g. a face
+    # between two of its own edges, where the middle point can slide)
+    unique = ((r["flags"] | q["flags"]) & oracle_mod.ILL) == 0
+    assert unique.sum() > 0.95 * b.N
+    np.testing.assert_allclose(q["x"][unique, ::-1], r["x"][unique],
+                               atol=1e-7 * b.S)
+
+
+def test_rigid_motion_and_reparametrisation(oracle_mod):
+    rng = np.random.default_rng(7)
+    b = scenes.random_paths(300, 3, seed=72)
+    r = _solve(oracle_mod, b)
+    # rigid motion x -> R x + c applied to every point and basis vector
+    Rm, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    c = rng.uniform(-3, 3, 3)
+    obj = b.obj.astype(np.float64)
+    pts = b.pts.astype(np.float64)
+    obj2 = np.vstack([Rm @ obj[0:3] + c[:, None], Rm @ obj[3:6], Rm @ obj[6:9]])
+    edge = np.all(obj[6:9] == 0, axis=0)
+    obj2[6:9, edge] = 0.0
+    pts2 = Rm @ pts + c[:, None]
+    b2 = scenes.Batch(obj2.astype(np.float32), pts2.astype(np.float32),
+                      b.src, b.dst, b.order, b.ids, b.S)
+    r2 = _solve(oracle_mod, b2)
+    # inputs were rounded to FP32 after the motion: compare loosely
+    x_mapped = np.einsum("ab,njb->nja", Rm, r["x"]) + c
+    np.testing.assert_allclose(r2["x"], x_mapped, atol=1e-4 * b.S)
+    np.testing.assert_allclose(r2["len"], r["len"], atol=1e-5 * b.S)
+    # reparametrisation: basis a -> a M (M invertible, exact powers of two
+    # so that FP32 keeps it exact) and origin b -> b + a1 (t shifts by -1)
+    obj3 = obj.copy()
+    a1 = obj[3:6].copy()
+    a2 = obj[6:9].copy()
+    obj3[0:3] = obj[0:3] + a1
+    obj3[3:6] = 2.0 * a1
+    obj3[6:9] = np.where(edge, 0.0, a2 * 0.5 + a1)
+    b3 = scenes.Batch(obj3.astype(np.float32), b.pts, b.src, b.dst, b.order,
+                      b.ids, b.S)
+    r3 = _solve(oracle_mod, b3)
+    np.testing.assert_allclose(r3["x"], r["x"], atol=1e-5 * b.S)
+    np.testing.assert_allclose(r3["len"], r["len"], atol=1e-6 * b.S)
+
+
+def test_edge_scaling_same_point(oracle_mod):
+    """An edge is one parameter whatever the length of its direction (the
+    padded second parameter stays 0); scaling the direction by 4 divides t
+    by 4 and leaves the point unchanged."""
+    N = 200
+    b = scenes.random_paths(N, 2, seed=73, kinds=np.zeros((2, N), bool))
+    r = _solve(oracle_mod, b)
+    obj = b.obj.copy()
+    obj[3:6] *= 4.0
+    r2 = _solve(oracle_mod, scenes.Batch(obj, b.pts, b.src, b.dst, b.order,
+                                         b.ids, b.S))
+    np.testing.assert_allclose(r2["x"], r["x"], atol=1e-9 * b.S)
+    np.testing.assert_allclose(r2["t"] * 4.0, r["t"], atol=1e-9 * b.S)
+    assert np.all(r["t"][..., 1] == 0.0)
+
+
+# ------------------------------------------------------------------ gradient
+
+
+def _fd_grad(oracle_mod, b, gl, gx, h):
+    """Central differences of f = sum_i gl_i L*_i + gx_i . x*_i through the
+    oracle solve, one input coordinate at a time for every path at once
+    (each path owns its objects and points). The inputs are FP32, so the
+    difference quotient divides by the step FP32 actually took."""
+    N, n = b.N, b.n_max
+
+    def f(obj, pts):
+        r = oracle_mod.solve(scenes.Batch(obj, pts, b.src, b.dst, b.order,
+                                          b.ids, b.S), threads=4)
+        return gl * r["len"] + np.einsum("njc,njc->n", gx, r["x"])
+
+    g_tx = np.zeros((N, 3))
+    g_rx = np.zeros((N, 3))
+    g_obj = np.zeros((N, n, 9))
+    for which, col, out in (("src", b.src, g_tx), ("dst", b.dst, g_rx)):
+        for c in range(3):
+            p1, p2 = b.pts.copy(), b.pts.copy()
+            p1[c, col] += h
+            p2[c, col] -= h
+            step = p1[c, col].astype(np.float64) - p2[c, col]
+            out[:, c] = (f(b.obj, p1) - f(b.obj, p2)) / step
+    for j in range(n):
+        for rr in range(9):
+            o1, o2 = b.obj.copy(), b.obj.copy()
+            o1[rr, b.ids[j]] += h
+            o2[rr, b.ids[j]] -= h
+            step = o1[rr, b.ids[j]].astype(np.float64) - o2[rr, b.ids[j]]
+            g_obj[:, j, rr] = (f(o1, b.pts) - f(o2, b.pts)) / step
+    return g_tx, g_rx, g_obj
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_gradient_vs_finite_differences(oracle_mod, n):
+    N = 64
+    b = scenes.random_paths(N, n, seed=80 + n)
+    r = _solve(oracle_mod, b)
+    rng = np.random.default_rng(81)
+    gl = rng.standard_normal(N)
+    gx = rng.standard_normal((N, n, 3))
+    g = oracle_mod.grad(b, r["t"], gl, gx, threads=4)
+    # Richardson extrapolation of central differences at h and h/2: O(h^4)
+    h = 2.0 ** -10
+    d1 = _fd_grad(oracle_mod, b, gl, gx, h)
+    d2 = _fd_grad(oracle_mod, b, gl, gx, h / 2)
+    fd_tx, fd_rx, fd_obj = [(4.0 * b2 - b1) / 3.0 for b1, b2 in zip(d1, d2)]
+    # only well-separated smooth minimisers (FD across a kink is meaningless)
+    seg_min = np.full(N, np.inf)
+    for i in range(N):
+        tx, rx, objs = pins.path_geometry(b, i)
+        xs = np.vstack([tx, r["x"][i, :n], rx])
+        seg_min[i] = pins.segment_dirs(xs)[1].min()
+    ok = (g["status"] == 0) & (seg_min > 0.05 * b.S) & (r["flags"] == 0)
+    assert ok.sum() >= N // 2
+    edge = np.stack([np.all(b.obj[6:9, b.ids[j]] == 0, axis=0)
+                     for j in range(n)], 1)
+    ga = g["g_a"].reshape(N, n, 6)
+    for i in np.nonzero(ok)[0]:
+        scale = 1.0 + np.abs(fd_obj[i]).max()
+        np.testing.assert_allclose(g["g_tx"][i], fd_tx[i], atol=2e-5 * scale)
+        np.testing.assert_allclose(g["g_rx"][i], fd_rx[i], atol=2e-5 * scale)
+        np.testing.assert_allclose(g["g_b"][i], fd_obj[i, :, 0:3],
+                                   atol=2e-5 * scale)
+        for j in range(n):
+            want = fd_obj[i, j, 3:9].copy()
+            if edge[i, j]:
+                want[3:] = 0.0  # padded parameter: no gradient
+            np.testing.assert_allclose(ga[i, j], want, atol=2e-5 * scale)
+
+
+def test_gradient_structure(oracle_mod):
+    """A_j^T g_b_j = 0: moving an object within its own span leaves the
+    solution unchanged; with g_x = 0 the gradient is the envelope term."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 600, seed=90, n=3)
+    r = _solve(oracle_mod, b)
+    rng = np.random.default_rng(91)
+    gl = rng.standard_normal(b.N)
+    gx = rng.standard_normal((b.N, 3, 3))
+    g = oracle_mod.grad(b, r["t"], gl, gx, threads=4)
+    ok = g["status"] == 0
+    assert ok.sum() > b.N // 2
+    for i in np.nonzero(ok)[0]:
+        tx, rx, objs = pins.path_geometry(b, i)
+        for j, (bb, a1, a2) in enumerate(objs):
+            scale = 1.0 + np.abs(g["g_b"][i, j]).max()
+            assert abs(np.dot(a1, g["g_b"][i, j])) < 1e-7 * scale * np.linalg.norm(a1)
+            assert abs(np.dot(a2, g["g_b"][i, j])) < 1e-7 * scale * (1 + np.linalg.norm(a2))
+    g0 = oracle_mod.grad(b, r["t"], gl, np.zeros_like(gx), threads=4)
+    for i in np.nonzero(ok)[0][:100]:
+        tx, rx, objs = pins.path_geometry(b, i)
+        xs = np.vstack([tx, r["x"][i, :3], rx])
+        u, _ = pins.segment_dirs(xs)
+        np.testing.assert_allclose(g0["g_tx"][i], -gl[i] * u[0], atol=1e-9)
+        np.testing.assert_allclose(g0["g_rx"][i], gl[i] * u[-1], atol=1e-9)
