@@ -1,0 +1,162 @@
+/*
+ * fpt.h - C ABI of the MI355X (gfx950) Fermat path solver.
+ *
+ * The library minimises the total length of many independent candidate ray
+ * paths (Sec. III-B, Eqs. 1-5):
+ *     x_0 = TX,  x_j = A_j t_j + b_j  (j = 1..n),  x_{n+1} = RX,
+ *     L(T) = sum_{i=0}^{n} || x_{i+1} - x_i ||,   T* = arg min_T L(T).
+ * A_j holds the two basis vectors of object j: a plane (reflection, d = 2),
+ * or an edge (diffraction, d = 1) padded to d = 2 with a zero second vector,
+ * so that every path of order n has one fixed layout (Sec. III-B).
+ * The solve is the paper's BFGS with the fixed-point step-size iteration of
+ * Eq. 6 (Sec. III-C) in FP32, followed by FP64 Newton refinement steps on the
+ * block-tridiagonal Hessian. The gradient is the implicit-differentiation
+ * vector-Jacobian product of Sec. III-D (Eqs. 8-13).
+ *
+ * Memory: every pointer passed to fpt_solve / fpt_grad is a DEVICE pointer
+ * owned by the caller; the library never frees it. All arrays are
+ * structure-of-arrays with the path index fastest (coalesced):
+ *   obj   float [9][K]      rows b(3), a1(3), a2(3); a2 == 0 (all three
+ *                           components exactly 0) marks an edge
+ *   pts   float [3][Q]      endpoint table
+ *   src, dst int32 [N]      x_0 = pts[:, src[i]], x_{n+1} = pts[:, dst[i]]
+ *   order uint8 [N]         interactions of path i, 1..n_max; NULL means
+ *                           every path has order n_max
+ *   ids   int32 [n_max][N]  object of interaction j of path i (entries
+ *                           beyond the path's order are ignored)
+ *   t_init float [n_max][2][N] or NULL (start at T = 0, i.e. x_j = b_j)
+ * Outputs (written for every path):
+ *   x      float  [n_max][3][N]   interaction points X*
+ *   len    float  [N]             L(T*)
+ *   t      float  [n_max][2][N]   T* in the caller's parametrisation (the
+ *                                 padded parameter of an edge is 0)
+ *   status uint8  [N]             FPT_ST_* bits
+ *   iters  uint16 [N]             BFGS iterations run
+ * Entries beyond a path's order are written as NaN (x, t).
+ *
+ * Errors: a whole-call error (null or misaligned pointer, n_max outside
+ * 1..FPT_NMAX, N < 0, K/Q out of range, bad options) returns a negative
+ * fpt_status and launches nothing; fpt_last_error() describes it. A problem
+ * of a single path (order outside 1..n_max, an id or point index out of
+ * range, non-finite input) is not a call error: that path gets
+ * FPT_ST_INVALID and NaN outputs.
+ *
+ * Execution: asynchronous on the caller's HIP stream (hipStream_t passed as
+ * void*; NULL = the legacy default stream). Input buffers must stay valid
+ * until the stream has passed the call. The handle owns a device workspace
+ * that grows on demand (hipMalloc) and is freed by fpt_destroy; calls that
+ * share a handle must be ordered on one stream.
+ */
+#ifndef FPT_H
+#define FPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { FPT_NMAX = 6, FPT_MAX_LEVELS = 8 };
+
+typedef enum {
+  FPT_OK = 0,
+  FPT_EINVAL = -1,      /* bad argument; nothing launched */
+  FPT_EUNSUPPORTED = -2,/* no gfx950 device, or feature not built */
+  FPT_EHIP = -3,        /* a HIP runtime call failed */
+  FPT_ENOMEM = -4       /* workspace allocation failed */
+} fpt_status;
+
+/* per-path status bits */
+enum {
+  FPT_ST_CONVERGED = 1, /* FP64 Newton certificate: the last full Newton step
+                           moved no point by more than cert_rtol * scale */
+  FPT_ST_REFINED = 2,   /* at least one FP64 refinement step was accepted */
+  FPT_ST_COLLAPSED = 4, /* two consecutive points closer than 1e-6 * scale */
+  FPT_ST_NONFINITE = 8, /* the solve produced a non-finite value */
+  FPT_ST_INVALID = 16   /* bad order / id / point index, or non-finite input */
+};
+
+typedef struct fpt_handle fpt_handle;
+
+typedef struct {
+  int32_t K;          /* objects */
+  const float* obj;   /* [9][K] device */
+  int32_t Q;          /* points */
+  const float* pts;   /* [3][Q] device */
+} fpt_scene;
+
+typedef struct {
+  int64_t N;              /* paths (0 is allowed: nothing is launched) */
+  int32_t n_max;          /* 1..FPT_NMAX */
+  const int32_t* src;     /* [N] */
+  const int32_t* dst;     /* [N] */
+  const uint8_t* order;   /* [N] or NULL */
+  const int32_t* ids;     /* [n_max][N] */
+  const float* t_init;    /* [n_max][2][N] or NULL */
+} fpt_paths;
+
+typedef struct {
+  int32_t iters;        /* BFGS iterations (Sec. III-C runs a fixed count) */
+  int32_t fp_iters;     /* fixed-point iterations of Eq. 6 per BFGS step */
+  int32_t early_exit;   /* 1: a wavefront stops once every lane's last step
+                           moved each point by < exit_rtol * scale */
+  float exit_rtol;
+  float scale;          /* scene size S (> 0): unit of every tolerance */
+  int32_t n_levels;     /* FP64 refinement levels, 0..FPT_MAX_LEVELS */
+  float level_eps[FPT_MAX_LEVELS];  /* smoothing eps / scale of each level
+                                       (0 = exact length) */
+  int32_t level_steps[FPT_MAX_LEVELS]; /* Newton steps at each level */
+  float cert_rtol;      /* certificate threshold / scale */
+} fpt_opts;
+
+/* Defaults: 64 iterations, 1 fixed-point iteration, no early exit, refinement
+ * levels eps/S = 1e-3, 1e-5, 1e-7 (2 steps each) and 1e-9 (3 steps),
+ * cert_rtol = 1e-5, scale = 1. */
+void fpt_default_opts(fpt_opts* opts);
+
+typedef struct {
+  float* x;         /* [n_max][3][N] */
+  float* len;       /* [N] */
+  float* t;         /* [n_max][2][N] */
+  uint8_t* status;  /* [N] */
+  uint16_t* iters;  /* [N] */
+} fpt_out;
+
+/* Creates a handle bound to HIP device `device` (must be gfx950).
+ * *h receives the handle, or NULL on error. */
+fpt_status fpt_create(int device, fpt_handle** h);
+
+/* Frees the handle and its workspace (synchronises the device first). */
+fpt_status fpt_destroy(fpt_handle* h);
+
+/* Solves every path (Sec. III-B Eq. 4 by the BFGS / fixed-point method of
+ * Sec. III-C, then FP64 refinement). See the layout notes above. */
+fpt_status fpt_solve(fpt_handle* h, const fpt_scene* scene,
+                     const fpt_paths* paths, const fpt_opts* opts,
+                     const fpt_out* out, void* hip_stream);
+
+/* Implicit-differentiation backward pass (Sec. III-D, Eqs. 8-13) at the
+ * solution `fwd` of fpt_solve, for the loss
+ *     sum_i g_len[i] * len[i] + sum_{i,j} g_x[j][:][i] . x[j][:][i].
+ * g_len [N] and g_x [n_max][3][N] may each be NULL (= zero).
+ * Accumulates (+=, caller zeroes) d loss / d pts into g_pts [3][Q] and
+ * d loss / d obj into g_obj [9][K] (rows b, a1, a2; the padded a2 of an
+ * edge receives nothing). g_slot [n_max][9][N] (optional, may be NULL)
+ * receives the unreduced per-path, per-interaction object gradient; g_end
+ * [6][N] (optional) the per-path TX and RX gradients. Paths whose status
+ * has FPT_ST_COLLAPSED, FPT_ST_INVALID or FPT_ST_NONFINITE contribute zero
+ * (the Hessian of Eq. 12 is singular or undefined there). */
+fpt_status fpt_grad(fpt_handle* h, const fpt_scene* scene,
+                    const fpt_paths* paths, const fpt_out* fwd,
+                    const float* g_len, const float* g_x, float* g_pts,
+                    float* g_obj, float* g_slot, float* g_end,
+                    void* hip_stream);
+
+/* Thread-local description of the last non-OK status of this thread. */
+const char* fpt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPT_H */

@@ -1,0 +1,75 @@
+// Device-side helpers shared by the solver and the backward kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fpt.h"
+
+namespace fpt {
+
+constexpr int kBlock = 256;  // threads per workgroup: four wave64s
+
+// Hardware reciprocal square root (v_rsq_f32), about 1 ulp.
+__device__ __forceinline__ float rsq32(float x) {
+  return __builtin_amdgcn_rsqf(x);
+}
+// Hardware reciprocal (v_rcp_f32), about 1 ulp.
+__device__ __forceinline__ float rcp32(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+
+// FP64 reciprocal square root: the hardware estimate (v_rsq_f64) refined by
+// two Newton-Raphson steps y <- y (3 - x y^2) / 2, each of which doubles the
+// number of correct bits.
+__device__ __forceinline__ double rsq64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// FP64 reciprocal: hardware estimate refined by two Newton-Raphson steps
+// y <- y (2 - x y).
+__device__ __forceinline__ double rcp64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+
+__device__ __forceinline__ float dot3(const float* a, const float* b) {
+  return fmaf(a[2], b[2], fmaf(a[1], b[1], a[0] * b[0]));
+}
+__device__ __forceinline__ double dot3d(const double* a, const double* b) {
+  return fma(a[2], b[2], fma(a[1], b[1], a[0] * b[0]));
+}
+
+// Arguments shared by every launch of one fpt_solve call.
+struct SolveArgs {
+  const float* obj;
+  const float* pts;
+  const int32_t* src;
+  const int32_t* dst;
+  const uint8_t* order;
+  const int32_t* ids;
+  const float* t_init;
+  float* x;
+  float* len;
+  float* t;
+  uint8_t* status;
+  uint16_t* iters;
+  int64_t N;
+  int32_t K, Q, n_max;
+  // options
+  int32_t n_iter, fp_iters, early_exit;
+  float exit_d2;  // (exit_rtol * scale)^2
+  float scale;
+  int32_t n_levels;
+  float level_eps[FPT_MAX_LEVELS];
+  int32_t level_steps[FPT_MAX_LEVELS];
+  float cert_abs;  // cert_rtol * scale
+};
+
+}  // namespace fpt

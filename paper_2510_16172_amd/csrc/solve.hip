@@ -1,0 +1,769 @@
+// Batched Fermat path solver for gfx950: one path per lane, the whole state
+// of a path in VGPRs.
+//
+// Phase 1 (FP32): BFGS on L(T) (Sec. III-C) with the fixed-point step-size
+// iteration of Eq. 6. The iteration is started at the unit step, and a
+// step that does not shorten the path falls back to the first fixed-point
+// iterate started at 0 (that one minimises a quadratic majorant of L along
+// the direction, so it always shortens the path).
+// Phase 2 (FP64): damped Newton steps on the length with every segment
+// smoothed to sqrt(|r|^2 + eps^2), eps decreasing level by level, using the
+// block-tridiagonal Hessian (2x2 blocks, Sec. III-D notes it is the Hessian
+// of a convex function). The last full Newton step gives a certificate.
+//
+// Parametrisation (Sec. III-B, Eq. 3): x_j = b_j + t_j0 a1_j + t_j1 a2_j;
+// an edge has a2 = 0 (padding). Slot j = 0..n-1 is interaction j+1;
+// segment i = 0..n runs from point i-1 to point i (point -1 = TX,
+// point n = RX), so slot j touches segments j (incoming) and j+1.
+#include "common.h"
+
+namespace fpt {
+
+template <int NO>
+struct Geo32 {
+  float tx[3], rx[3];
+  float b[NO][3];
+  float a[NO][2][3];  // basis vectors scaled to unit length (0 for padding)
+};
+
+// 1/|a| as the FP32 phase uses it (0 for the padding of an edge)
+__device__ __forceinline__ void basis_inv32(const float* a1, const float* a2,
+                                            bool edge, float& i1, float& i2) {
+  float n1 = dot3(a1, a1), n2 = dot3(a2, a2);
+  i1 = rsq32(n1 > 0.f ? n1 : 1.f);
+  i2 = edge ? 0.f : rsq32(n2 > 0.f ? n2 : 1.f);
+}
+
+// Reads path p's geometry in FP64 (exact widening of the FP32 tables) and
+// the FP32 1/|a| factors that map the FP32 phase's unit-vector parameters
+// back to the caller's parametrisation.
+template <int NO>
+struct Geo64;
+template <int NO>
+__device__ __forceinline__ void load_geo64(const SolveArgs& A, int64_t p,
+                                           Geo64<NO>& D, float (*inv)[2]);
+
+// Gradient of L at T (Sec. III-B Eq. 5): g_j = A_j^T (u_j - u_{j+1}).
+template <int NO>
+__device__ __forceinline__ void grad32(const Geo32<NO>& G, const float* T,
+                                       float* g, float (*r)[3], float* l2,
+                                       float* il) {
+  float x[NO][3];
+#pragma unroll
+  for (int j = 0; j < NO; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      x[j][c] = fmaf(T[2 * j + 1], G.a[j][1][c],
+                     fmaf(T[2 * j], G.a[j][0][c], G.b[j][c]));
+  float u[NO + 1][3];
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float nx = (i == NO) ? G.rx[c] : x[i][c];
+      float px = (i == 0) ? G.tx[c] : x[i - 1][c];
+      r[i][c] = nx - px;
+    }
+    l2[i] = fmaxf(dot3(r[i], r[i]), 1e-30f);
+    il[i] = rsq32(l2[i]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[i][c] = r[i][c] * il[i];
+  }
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    float du[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) du[c] = u[j][c] - u[j + 1][c];
+    g[2 * j] = dot3(G.a[j][0], du);
+    g[2 * j + 1] = dot3(G.a[j][1], du);
+  }
+}
+
+// packed upper-triangular index of (a, b), a <= b, of an m x m matrix
+__host__ __device__ constexpr int pk(int m, int a, int b) {
+  return a * m - a * (a - 1) / 2 + (b - a);
+}
+
+// y = H x for symmetric packed H
+template <int M>
+__device__ __forceinline__ void symv(const float* H, const float* x,
+                                     float* y) {
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    float s = 0.f;
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+      int ia = a < b ? a : b, ib = a < b ? b : a;
+      s = fmaf(H[pk(M, ia, ib)], x[b], s);
+    }
+    y[a] = s;
+  }
+}
+
+struct RefineOut {
+  bool certified, refined, finite;
+};
+
+// ---------------------------------------------------------------- FP64 ----
+
+template <int NO>
+struct Geo64 {
+  double tx[3], rx[3];
+  double b[NO][3];
+  double a[NO][2][3];  // caller's basis vectors (a[j][1] = 0 for an edge)
+  bool edge[NO];
+};
+
+template <int NO>
+__device__ __forceinline__ void load_geo64(const SolveArgs& A, int64_t p,
+                                           Geo64<NO>& D, float (*inv)[2]) {
+  int32_t s = A.src[p], e = A.dst[p];
+  s = (s >= 0 && s < A.Q) ? s : 0;
+  e = (e >= 0 && e < A.Q) ? e : 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    D.tx[c] = A.pts[(int64_t)c * A.Q + s];
+    D.rx[c] = A.pts[(int64_t)c * A.Q + e];
+  }
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    int32_t k = A.ids[(int64_t)j * A.N + p];
+    k = (k >= 0 && k < A.K) ? k : 0;
+    float a1[3], a2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      D.b[j][c] = A.obj[(int64_t)c * A.K + k];
+      a1[c] = A.obj[(int64_t)(3 + c) * A.K + k];
+      a2[c] = A.obj[(int64_t)(6 + c) * A.K + k];
+    }
+    bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
+    D.edge[j] = edge;
+    basis_inv32(a1, a2, edge, inv[j][0], inv[j][1]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      D.a[j][0][c] = a1[c];
+      D.a[j][1][c] = edge ? 0.0 : (double)a2[c];
+    }
+  }
+}
+
+template <int NO>
+__device__ __forceinline__ void points64(const Geo64<NO>& G, const double* t,
+                                         double (*x)[3]) {
+#pragma unroll
+  for (int j = 0; j < NO; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      x[j][c] = fma(t[2 * j + 1], G.a[j][1][c],
+                    fma(t[2 * j], G.a[j][0][c], G.b[j][c]));
+}
+
+template <int NO>
+__device__ __forceinline__ double length64(const Geo64<NO>& G,
+                                           const double* t, double eps2) {
+  double x[NO][3];
+  points64<NO>(G, t, x);
+  double L = 0.0;
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
+    double q = fmax(dot3d(r, r) + eps2, 1e-300);
+    L += q * rsq64(q);
+  }
+  return L;
+}
+
+// One Newton direction d = -H^{-1} g of the eps-smoothed length at t.
+// H is block tridiagonal with 2x2 blocks
+//   D_j = A_j^T (M_j + M_{j+1}) A_j,  E_j = -A_j^T M_{j+1} A_{j+1},
+//   M_i = (I - v_i v_i^T) / l_i,  v_i = r_i / l_i,  l_i = sqrt(|r_i|^2+eps^2),
+// solved by block-Thomas elimination. The padded parameter of an edge has
+// a zero row and column; its diagonal is set to 1, so its step is 0.
+// Returns false if a pivot block is singular or non-finite.
+template <int NO>
+__device__ __forceinline__ bool newton_dir64(const Geo64<NO>& G,
+                                             const double* t, double eps2,
+                                             double* d) {
+  double x[NO][3];
+  points64<NO>(G, t, x);
+  double v[NO + 1][3], il[NO + 1];
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
+    double q = fmax(dot3d(r, r) + eps2, 1e-300);
+    il[i] = rsq64(q);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[i][c] = r[c] * il[i];
+  }
+  // per slot: projections of v on the basis, gradient, blocks
+  double Sinv[NO][3], E[NO][4], z[NO][2];
+  double pSinv[3] = {0, 0, 0}, pE[4] = {0, 0, 0, 0}, pz[2] = {0, 0};
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    const double* a0 = G.a[j][0];
+    const double* a1 = G.a[j][1];
+    double pin0 = dot3d(a0, v[j]), pin1 = dot3d(a1, v[j]);
+    double pout0 = dot3d(a0, v[j + 1]), pout1 = dot3d(a1, v[j + 1]);
+    double g0 = pin0 - pout0, g1 = pin1 - pout1;
+    double G00 = dot3d(a0, a0), G01 = dot3d(a0, a1), G11 = dot3d(a1, a1);
+    // D_j (symmetric: 00, 01, 11)
+    double D00 = (G00 - pin0 * pin0) * il[j] + (G00 - pout0 * pout0) * il[j + 1];
+    double D01 = (G01 - pin0 * pin1) * il[j] + (G01 - pout0 * pout1) * il[j + 1];
+    double D11 = (G11 - pin1 * pin1) * il[j] + (G11 - pout1 * pout1) * il[j + 1];
+    if (G.edge[j]) {
+      D01 = 0.0;
+      D11 = 1.0;
+      g1 = 0.0;
+    }
+    double rhs0 = -g0, rhs1 = -g1;
+    if (j > 0) {
+      // S_j = D_j - E_{j-1}^T S_{j-1}^{-1} E_{j-1}; z_j = rhs - E^T S^-1 z
+      // W = S^{-1} E (2x2), E = [[e00 e01][e10 e11]] rows: prev slot params
+      double W00 = pSinv[0] * pE[0] + pSinv[1] * pE[2];
+      double W01 = pSinv[0] * pE[1] + pSinv[1] * pE[3];
+      double W10 = pSinv[1] * pE[0] + pSinv[2] * pE[2];
+      double W11 = pSinv[1] * pE[1] + pSinv[2] * pE[3];
+      D00 -= pE[0] * W00 + pE[2] * W10;
+      D01 -= pE[0] * W01 + pE[2] * W11;
+      D11 -= pE[1] * W01 + pE[3] * W11;
+      double w0 = pSinv[0] * pz[0] + pSinv[1] * pz[1];
+      double w1 = pSinv[1] * pz[0] + pSinv[2] * pz[1];
+      rhs0 -= pE[0] * w0 + pE[2] * w1;
+      rhs1 -= pE[1] * w0 + pE[3] * w1;
+    }
+    double det = D00 * D11 - D01 * D01;
+    ok = ok && (det > 0.0) && (D00 > 0.0) && isfinite(det);
+    double idet = rcp64(det);
+    Sinv[j][0] = D11 * idet;
+    Sinv[j][1] = -D01 * idet;
+    Sinv[j][2] = D00 * idet;
+    z[j][0] = rhs0;
+    z[j][1] = rhs1;
+    if (j + 1 < NO) {
+      // E_j = -A_j^T M_{j+1} A_{j+1}
+      const double* b0 = G.a[j + 1][0];
+      const double* b1 = G.a[j + 1][1];
+      double qn0 = dot3d(b0, v[j + 1]), qn1 = dot3d(b1, v[j + 1]);
+      double il1 = il[j + 1];
+      E[j][0] = -(dot3d(a0, b0) - pout0 * qn0) * il1;
+      E[j][1] = -(dot3d(a0, b1) - pout0 * qn1) * il1;
+      E[j][2] = -(dot3d(a1, b0) - pout1 * qn0) * il1;
+      E[j][3] = -(dot3d(a1, b1) - pout1 * qn1) * il1;
+      if (G.edge[j]) E[j][2] = E[j][3] = 0.0;
+      if (G.edge[j + 1]) E[j][1] = E[j][3] = 0.0;
+    } else {
+      E[j][0] = E[j][1] = E[j][2] = E[j][3] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pSinv[k] = Sinv[j][k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pE[k] = E[j][k];
+    pz[0] = z[j][0];
+    pz[1] = z[j][1];
+  }
+  // back substitution: d_j = S_j^{-1} (z_j - E_j d_{j+1})
+  double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+  for (int j = NO - 1; j >= 0; --j) {
+    double c0 = z[j][0] - (E[j][0] * n0 + E[j][1] * n1);
+    double c1 = z[j][1] - (E[j][2] * n0 + E[j][3] * n1);
+    double d0 = Sinv[j][0] * c0 + Sinv[j][1] * c1;
+    double d1 = Sinv[j][1] * c0 + Sinv[j][2] * c1;
+    if (G.edge[j]) d1 = 0.0;
+    d[2 * j] = d0;
+    d[2 * j + 1] = d1;
+    n0 = d0;
+    n1 = d1;
+    ok = ok && isfinite(d0) && isfinite(d1);
+  }
+  return ok;
+}
+
+template <int NO>
+__device__ __forceinline__ double max_disp64(const Geo64<NO>& G,
+                                             const double* d) {
+  double m = 0.0;
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    double w[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      w[c] = d[2 * j] * G.a[j][0][c] + d[2 * j + 1] * G.a[j][1][c];
+    m = fmax(m, dot3d(w, w));
+  }
+  return m;  // squared
+}
+
+// Damped Newton refinement, level by level. t is in the caller's
+// parametrisation. A trial step s*d (s = 1, 1/4, 1/16, ...) is taken if it
+// does not lengthen the smoothed path beyond the rounding of L itself.
+template <int NO>
+__device__ __forceinline__ RefineOut refine64(const Geo64<NO>& G, double* t,
+                                              const SolveArgs& A) {
+  RefineOut o{false, false, true};
+  bool last_full = false;
+  double last_d2 = INFINITY;
+  for (int lv = 0; lv < A.n_levels; ++lv) {
+    double eps = (double)A.level_eps[lv] * (double)A.scale;
+    double eps2 = eps * eps;
+    for (int st = 0; st < A.level_steps[lv]; ++st) {
+      double d[2 * NO];
+      bool ok = newton_dir64<NO>(G, t, eps2, d);
+      if (!ok) {
+        last_full = false;
+        last_d2 = INFINITY;
+        continue;
+      }
+      last_d2 = max_disp64<NO>(G, d);
+      double L0 = length64<NO>(G, t, eps2);
+      double slack = 1e-15 * fabs(L0);
+      double s = 1.0;
+      bool acc = false;
+      for (int h = 0; h < 7; ++h) {
+        double tn[2 * NO];
+#pragma unroll
+        for (int k = 0; k < 2 * NO; ++k) tn[k] = fma(s, d[k], t[k]);
+        double L1 = length64<NO>(G, tn, eps2);
+        if (L1 <= L0 + slack) {
+#pragma unroll
+          for (int k = 0; k < 2 * NO; ++k) t[k] = tn[k];
+          acc = true;
+          break;
+        }
+        s *= 0.25;
+      }
+      last_full = acc && (s == 1.0);
+      o.refined = o.refined || acc;
+    }
+  }
+  double cert = (double)A.cert_abs;
+  o.certified = A.n_levels > 0 && last_full && (last_d2 <= cert * cert);
+  return o;
+}
+
+// ------------------------------------------------------------- kernel -----
+
+template <int NO>
+__global__ __launch_bounds__(kBlock) void solve_kernel(
+    SolveArgs A, const int32_t* __restrict__ perm,
+    const int64_t* __restrict__ bucket) {
+  constexpr int M = 2 * NO;
+  constexpr int HP = M * (M + 1) / 2;
+  int64_t begin = 0, count = A.N;
+  if (bucket) {
+    begin = bucket[NO - 1];
+    count = bucket[NO] - begin;
+  }
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
+       idx += stride) {
+    const int64_t p = perm ? (int64_t)perm[begin + idx] : idx;
+    // ---------------------------------------------------------- gather
+    bool valid = true;
+    Geo32<NO> G;
+    {
+      int32_t s = A.src[p], e = A.dst[p];
+      valid = valid && s >= 0 && s < A.Q && e >= 0 && e < A.Q;
+      s = valid ? s : 0;
+      e = valid ? e : 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        G.tx[c] = A.pts[(int64_t)c * A.Q + s];
+        G.rx[c] = A.pts[(int64_t)c * A.Q + e];
+        valid = valid && isfinite(G.tx[c]) && isfinite(G.rx[c]);
+      }
+    }
+    float tinit[NO][2];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      int32_t k = A.ids[(int64_t)j * A.N + p];
+      bool kok = k >= 0 && k < A.K;
+      valid = valid && kok;
+      k = kok ? k : 0;
+      float bb[3], a1[3], a2[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        bb[c] = A.obj[(int64_t)c * A.K + k];
+        a1[c] = A.obj[(int64_t)(3 + c) * A.K + k];
+        a2[c] = A.obj[(int64_t)(6 + c) * A.K + k];
+        valid = valid && isfinite(bb[c]) && isfinite(a1[c]) && isfinite(a2[c]);
+      }
+      bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
+      valid = valid && dot3(a1, a1) > 0.f && (edge || dot3(a2, a2) > 0.f);
+      float i1, i2;
+      basis_inv32(a1, a2, edge, i1, i2);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        G.b[j][c] = bb[c];
+        G.a[j][0][c] = a1[c] * i1;
+        G.a[j][1][c] = a2[c] * i2;
+      }
+      float t0 = 0.f, t1 = 0.f;
+      if (A.t_init) {
+        // to unit-vector coordinates: that = t * |a|
+        t0 = A.t_init[(int64_t)(2 * j) * A.N + p] * rcp32(i1);
+        t1 = edge ? 0.f : A.t_init[(int64_t)(2 * j + 1) * A.N + p] * rcp32(i2);
+        if (!isfinite(t0)) t0 = 0.f;
+        if (!isfinite(t1)) t1 = 0.f;
+      }
+      tinit[j][0] = t0;
+      tinit[j][1] = t1;
+    }
+    if (A.order) valid = valid && (int)A.order[p] == NO;
+    // ---------------------------------------------------- FP32 BFGS phase
+    float T[M], g[M], P[M], H[HP];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      T[2 * j] = tinit[j][0];
+      T[2 * j + 1] = tinit[j][1];
+    }
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+      for (int b = a; b < M; ++b) H[pk(M, a, b)] = (a == b) ? 1.f : 0.f;
+    float r[NO + 1][3], l2[NO + 1], il[NO + 1];
+    grad32<NO>(G, T, g, r, l2, il);
+#pragma unroll
+    for (int k = 0; k < M; ++k) P[k] = -g[k];
+    int it = 0;
+    for (; it < A.n_iter; ++it) {
+      // direction in point space: q_j = A_j p_j; segment change D_i
+      float q[NO][3];
+#pragma unroll
+      for (int j = 0; j < NO; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          q[j][c] = fmaf(P[2 * j + 1], G.a[j][1][c], P[2 * j] * G.a[j][0][c]);
+      float dr[NO + 1], dd[NO + 1];
+      float num0 = 0.f, den0 = 0.f, phi0 = 0.f;
+#pragma unroll
+      for (int i = 0; i <= NO; ++i) {
+        float Dv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          Dv[c] = ((i == NO) ? 0.f : q[i][c]) - ((i == 0) ? 0.f : q[i - 1][c]);
+        dr[i] = dot3(Dv, r[i]);
+        dd[i] = dot3(Dv, Dv);
+        num0 = fmaf(dr[i], il[i], num0);
+        den0 = fmaf(dd[i], il[i], den0);
+        phi0 = fmaf(l2[i], il[i], phi0);
+      }
+      // Eq. 6 started at alpha = 0: one step is the majorant minimiser
+      float a_mm = (den0 > 1e-30f) ? -num0 * rcp32(den0) : 0.f;
+      if (!isfinite(a_mm)) a_mm = 0.f;
+      // Eq. 6 iterated from the unit step
+      float alpha = 1.f;
+      for (int f = 0; f < A.fp_iters; ++f) {
+        float num = 0.f, den = 0.f;
+#pragma unroll
+        for (int i = 0; i <= NO; ++i) {
+          float rho2 = fmaxf(fmaf(alpha, fmaf(alpha, dd[i], 2.f * dr[i]), l2[i]), 1e-30f);
+          float ir = rsq32(rho2);
+          num = fmaf(dr[i], ir, num);
+          den = fmaf(dd[i], ir, den);
+        }
+        alpha = (den > 1e-30f) ? -num * rcp32(den) : 0.f;
+      }
+      // keep it only if it shortens the path
+      float phi = 0.f;
+#pragma unroll
+      for (int i = 0; i <= NO; ++i) {
+        float rho2 = fmaxf(fmaf(alpha, fmaf(alpha, dd[i], 2.f * dr[i]), l2[i]), 1e-30f);
+        phi = fmaf(rho2, rsq32(rho2), phi);
+      }
+      if (!(phi < phi0) || !(alpha > 0.f) || !isfinite(alpha)) alpha = a_mm;
+      // step, new gradient
+      float s[M], gn[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        s[k] = alpha * P[k];
+        T[k] += s[k];
+      }
+      grad32<NO>(G, T, gn, r, l2, il);
+      // BFGS inverse update (Nocedal & Wright eq. 6.17), with
+      // H y = H g' - H g = H g' + P
+      float Hg[M], Hy[M], y[M];
+      symv<M>(H, gn, Hg);
+      float sy = 0.f, yHy = 0.f, ss = 0.f, yy = 0.f;
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        y[k] = gn[k] - g[k];
+        Hy[k] = Hg[k] + P[k];
+        sy = fmaf(s[k], y[k], sy);
+        yHy = fmaf(y[k], Hy[k], yHy);
+        ss = fmaf(s[k], s[k], ss);
+        yy = fmaf(y[k], y[k], yy);
+      }
+      bool upd = (sy > 1e-30f) && (sy * sy > 1e-12f * ss * yy) &&
+                 isfinite(yHy);
+      float rho = upd ? rcp32(sy) : 0.f;
+      float c1 = rho * fmaf(rho, yHy, 1.f);
+      float w[M], v[M];
+      float wg = 0.f, sg = 0.f;
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        v[k] = -rho * Hy[k];
+        w[k] = fmaf(c1, s[k], v[k]);
+        wg = fmaf(w[k], gn[k], wg);
+        sg = fmaf(s[k], gn[k], sg);
+      }
+#pragma unroll
+      for (int a = 0; a < M; ++a)
+#pragma unroll
+        for (int b = a; b < M; ++b)
+          H[pk(M, a, b)] = fmaf(v[a], s[b], fmaf(s[a], w[b], H[pk(M, a, b)]));
+      float pp = 0.f;
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        P[k] = -fmaf(v[k], sg, fmaf(s[k], wg, Hg[k]));
+        g[k] = gn[k];
+        pp = fmaf(P[k], P[k], pp);
+      }
+      if (!(pp < 1e30f)) {
+        // overflow or NaN in the update: restart from the identity
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+          for (int b = a; b < M; ++b) H[pk(M, a, b)] = (a == b) ? 1.f : 0.f;
+#pragma unroll
+        for (int k = 0; k < M; ++k) P[k] = -g[k];
+      }
+      if (A.early_exit) {
+        float m2 = 0.f;
+#pragma unroll
+        for (int j = 0; j < NO; ++j) m2 = fmaxf(m2, dot3(q[j], q[j]));
+        bool done = !(alpha * alpha * m2 > A.exit_d2);
+        if (__all(done || !valid)) {
+          ++it;
+          break;
+        }
+      }
+    }
+    // --------------------------------------------------- FP64 refinement
+    Geo64<NO> D;
+    float inv[NO][2];
+    load_geo64<NO>(A, p, D, inv);
+    double td[2 * NO];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      td[2 * j] = (double)T[2 * j] * (double)inv[j][0];
+      td[2 * j + 1] = D.edge[j] ? 0.0 : (double)T[2 * j + 1] * (double)inv[j][1];
+    }
+    RefineOut ro = refine64<NO>(D, td, A);
+    // ---------------------------------------------------------- store
+    double xs[NO][3];
+    points64<NO>(D, td, xs);
+    double Lx = 0.0, minl2 = INFINITY;
+#pragma unroll
+    for (int i = 0; i <= NO; ++i) {
+      double rr[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        rr[c] = ((i == NO) ? D.rx[c] : xs[i][c]) - ((i == 0) ? D.tx[c] : xs[i - 1][c]);
+      double q2 = dot3d(rr, rr);
+      minl2 = fmin(minl2, q2);
+      Lx += (q2 > 0.0) ? q2 * rsq64(q2) : 0.0;
+    }
+    bool finite = isfinite(Lx);
+#pragma unroll
+    for (int k = 0; k < 2 * NO; ++k) finite = finite && isfinite(td[k]);
+    uint8_t st = 0;
+    if (!valid) {
+      st = FPT_ST_INVALID;
+    } else {
+      double cs = 1e-6 * (double)A.scale;
+      if (ro.certified && finite) st |= FPT_ST_CONVERGED;
+      if (ro.refined) st |= FPT_ST_REFINED;
+      if (minl2 < cs * cs) st |= FPT_ST_COLLAPSED;
+      if (!finite) st |= FPT_ST_NONFINITE;
+    }
+    const float qnan = __builtin_nanf("");
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        A.x[(int64_t)(3 * j + c) * A.N + p] = valid ? (float)xs[j][c] : qnan;
+      A.t[(int64_t)(2 * j) * A.N + p] = valid ? (float)td[2 * j] : qnan;
+      A.t[(int64_t)(2 * j + 1) * A.N + p] = valid ? (float)td[2 * j + 1] : qnan;
+    }
+    for (int j = NO; j < A.n_max; ++j) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) A.x[(int64_t)(3 * j + c) * A.N + p] = qnan;
+      A.t[(int64_t)(2 * j) * A.N + p] = qnan;
+      A.t[(int64_t)(2 * j + 1) * A.N + p] = qnan;
+    }
+    A.len[p] = valid ? (float)Lx : qnan;
+    A.status[p] = st;
+    A.iters[p] = (uint16_t)(it > 65535 ? 65535 : it);
+  }
+}
+
+// ------------------------------------------------------ order bucketing ---
+// counts[0] collects paths whose order is outside 1..n_max, counts[n] those
+// of order n. bucket offsets: bucket[n-1] .. bucket[n] is the range of order
+// n in perm; bucket[n_max] .. bucket[n_max+1] holds the invalid ones.
+
+__global__ __launch_bounds__(kBlock) void bucket_count_kernel(
+    const uint8_t* __restrict__ order, int64_t N, int n_max,
+    unsigned long long* __restrict__ counts) {
+  __shared__ unsigned int loc[FPT_NMAX + 1];
+  if (threadIdx.x <= FPT_NMAX) loc[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += stride) {
+    int o = order[i];
+    int b = (o >= 1 && o <= n_max) ? o : 0;
+    atomicAdd(&loc[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x <= FPT_NMAX && loc[threadIdx.x])
+    atomicAdd(&counts[threadIdx.x], (unsigned long long)loc[threadIdx.x]);
+}
+
+// bucket[0..n_max+1] from counts; cursor[] = running insert positions
+__global__ void bucket_scan_kernel(const unsigned long long* __restrict__ counts,
+                                   int n_max, int64_t* __restrict__ bucket,
+                                   unsigned long long* __restrict__ cursor) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int64_t acc = 0;
+    bucket[0] = 0;
+    for (int n = 1; n <= n_max; ++n) {
+      cursor[n] = (unsigned long long)acc;
+      acc += (int64_t)counts[n];
+      bucket[n] = acc;
+    }
+    cursor[0] = (unsigned long long)acc;
+    acc += (int64_t)counts[0];
+    bucket[n_max + 1] = acc;
+  }
+}
+
+// Scatter path indices into their order bucket. Each workgroup reserves one
+// contiguous range per order, so paths keep their relative order inside a
+// workgroup's chunk.
+__global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
+    const uint8_t* __restrict__ order, int64_t N, int n_max,
+    unsigned long long* __restrict__ cursor, int32_t* __restrict__ perm) {
+  __shared__ unsigned int loc[FPT_NMAX + 1];
+  __shared__ unsigned long long base[FPT_NMAX + 1];
+  const int64_t chunk = (int64_t)kBlock;
+  for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < N; c0 += (int64_t)gridDim.x * chunk) {
+    if (threadIdx.x <= FPT_NMAX) loc[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t i = c0 + threadIdx.x;
+    int b = -1;
+    unsigned int rank = 0;
+    if (i < N) {
+      int o = order[i];
+      b = (o >= 1 && o <= n_max) ? o : 0;
+      rank = atomicAdd(&loc[b], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x <= FPT_NMAX)
+      base[threadIdx.x] = loc[threadIdx.x]
+                              ? atomicAdd(&cursor[threadIdx.x], (unsigned long long)loc[threadIdx.x])
+                              : 0ull;
+    __syncthreads();
+    if (b >= 0) perm[base[b] + rank] = (int32_t)i;
+    __syncthreads();
+  }
+}
+
+// Paths with an order outside 1..n_max: NaN outputs, INVALID status.
+__global__ __launch_bounds__(kBlock) void invalid_kernel(
+    SolveArgs A, const int32_t* __restrict__ perm, const int64_t* __restrict__ bucket) {
+  int64_t begin = bucket[A.n_max], count = bucket[A.n_max + 1] - begin;
+  const float qnan = __builtin_nanf("");
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count; idx += stride) {
+    int64_t p = perm[begin + idx];
+    for (int j = 0; j < A.n_max; ++j) {
+      for (int c = 0; c < 3; ++c) A.x[(int64_t)(3 * j + c) * A.N + p] = qnan;
+      A.t[(int64_t)(2 * j) * A.N + p] = qnan;
+      A.t[(int64_t)(2 * j + 1) * A.N + p] = qnan;
+    }
+    A.len[p] = qnan;
+    A.status[p] = FPT_ST_INVALID;
+    A.iters[p] = 0;
+  }
+}
+
+// ------------------------------------------------------------- launch -----
+
+template <int NO>
+static hipError_t launch_solve_order(const SolveArgs& A, const int32_t* perm,
+                                     const int64_t* bucket, int grid,
+                                     hipStream_t st) {
+  hipLaunchKernelGGL(solve_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
+                     perm, bucket);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve(int order, const SolveArgs& A, const int32_t* perm,
+                        const int64_t* bucket, int grid, hipStream_t st) {
+  switch (order) {
+    case 1: return launch_solve_order<1>(A, perm, bucket, grid, st);
+    case 2: return launch_solve_order<2>(A, perm, bucket, grid, st);
+    case 3: return launch_solve_order<3>(A, perm, bucket, grid, st);
+    case 4: return launch_solve_order<4>(A, perm, bucket, grid, st);
+    case 5: return launch_solve_order<5>(A, perm, bucket, grid, st);
+    case 6: return launch_solve_order<6>(A, perm, bucket, grid, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+const void* solve_kernel_ptr(int order) {
+  switch (order) {
+    case 1: return (const void*)solve_kernel<1>;
+    case 2: return (const void*)solve_kernel<2>;
+    case 3: return (const void*)solve_kernel<3>;
+    case 4: return (const void*)solve_kernel<4>;
+    case 5: return (const void*)solve_kernel<5>;
+    case 6: return (const void*)solve_kernel<6>;
+  }
+  return nullptr;
+}
+
+hipError_t launch_bucketing(const uint8_t* order, int64_t N, int n_max,
+                            unsigned long long* counts, unsigned long long* cursor,
+                            int64_t* bucket, int32_t* perm, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(bucket_count_kernel, dim3(grid), dim3(kBlock), 0, st,
+                     order, N, n_max, counts);
+  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(64), 0, st, counts,
+                     n_max, bucket, cursor);
+  hipLaunchKernelGGL(bucket_scatter_kernel, dim3(grid), dim3(kBlock), 0, st,
+                     order, N, n_max, cursor, perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_invalid(const SolveArgs& A, const int32_t* perm,
+                          const int64_t* bucket, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(invalid_kernel, dim3(grid), dim3(kBlock), 0, st, A, perm,
+                     bucket);
+  return hipGetLastError();
+}
+
+}  // namespace fpt
+
+namespace fpt {
+
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+  int i = threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// clears small counters with a kernel rather than a memset node, so that the
+// sequence can be captured into a HIP graph
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace fpt

@@ -1,0 +1,233 @@
+"""ctypes binding of libfpt.so (the C ABI in include/fpt.h).
+
+Argument marshalling only: every step of the solve and of the gradient runs
+in the HIP kernels of the library. PyTorch provides device memory and the
+stream (``torch.cuda.current_stream()``). There is no CPU fallback: if the
+library is missing or no gfx950 device is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfpt.so")
+
+FPT_NMAX = 6
+FPT_MAX_LEVELS = 8
+
+ST_CONVERGED, ST_REFINED, ST_COLLAPSED, ST_NONFINITE, ST_INVALID = 1, 2, 4, 8, 16
+
+_P = ctypes.c_void_p
+
+
+class _Scene(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("obj", _P), ("Q", ctypes.c_int32),
+                ("pts", _P)]
+
+
+class _Paths(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("n_max", ctypes.c_int32),
+                ("src", _P), ("dst", _P), ("order", _P), ("ids", _P),
+                ("t_init", _P)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("fp_iters", ctypes.c_int32),
+                ("early_exit", ctypes.c_int32), ("exit_rtol", ctypes.c_float),
+                ("scale", ctypes.c_float), ("n_levels", ctypes.c_int32),
+                ("level_eps", ctypes.c_float * FPT_MAX_LEVELS),
+                ("level_steps", ctypes.c_int32 * FPT_MAX_LEVELS),
+                ("cert_rtol", ctypes.c_float)]
+
+
+class _Out(ctypes.Structure):
+    _fields_ = [("x", _P), ("len", _P), ("t", _P), ("status", _P),
+                ("iters", _P)]
+
+
+EXPORTED = ["fpt_default_opts", "fpt_create", "fpt_destroy", "fpt_solve",
+            "fpt_grad", "fpt_last_error"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libfpt.so and declares the signatures. Raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with `python -m "
+            "paper_2510_16172_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    lib.fpt_default_opts.argtypes = [ctypes.POINTER(_Opts)]
+    lib.fpt_default_opts.restype = None
+    lib.fpt_create.argtypes = [ctypes.c_int, ctypes.POINTER(_P)]
+    lib.fpt_create.restype = ctypes.c_int
+    lib.fpt_destroy.argtypes = [_P]
+    lib.fpt_destroy.restype = ctypes.c_int
+    lib.fpt_solve.argtypes = [_P, ctypes.POINTER(_Scene),
+                              ctypes.POINTER(_Paths), ctypes.POINTER(_Opts),
+                              ctypes.POINTER(_Out), _P]
+    lib.fpt_solve.restype = ctypes.c_int
+    lib.fpt_grad.argtypes = [_P, ctypes.POINTER(_Scene),
+                             ctypes.POINTER(_Paths), ctypes.POINTER(_Out),
+                             _P, _P, _P, _P, _P, _P, _P]
+    lib.fpt_grad.restype = ctypes.c_int
+    lib.fpt_last_error.argtypes = []
+    lib.fpt_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class FptError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = load_library().fpt_last_error().decode()
+        raise FptError(f"{what} failed ({rc}): {msg}")
+
+
+@dataclass
+class Opts:
+    """Mirror of fpt_opts (defaults of fpt_default_opts)."""
+    iters: int = 64
+    fp_iters: int = 1
+    early_exit: bool = False
+    exit_rtol: float = 1e-6
+    scale: float = 1.0
+    level_eps: list = field(default_factory=lambda: [1e-3, 1e-5, 1e-7, 1e-9])
+    level_steps: list = field(default_factory=lambda: [2, 2, 2, 3])
+    cert_rtol: float = 1e-5
+
+    def to_c(self) -> _Opts:
+        o = _Opts()
+        load_library().fpt_default_opts(ctypes.byref(o))
+        o.iters = int(self.iters)
+        o.fp_iters = int(self.fp_iters)
+        o.early_exit = 1 if self.early_exit else 0
+        o.exit_rtol = float(self.exit_rtol)
+        o.scale = float(self.scale)
+        if len(self.level_eps) != len(self.level_steps):
+            raise ValueError("level_eps and level_steps differ in length")
+        if len(self.level_eps) > FPT_MAX_LEVELS:
+            raise ValueError("at most 8 refinement levels")
+        o.n_levels = len(self.level_eps)
+        for i in range(FPT_MAX_LEVELS):
+            o.level_eps[i] = float(self.level_eps[i]) if i < o.n_levels else 0.0
+            o.level_steps[i] = int(self.level_steps[i]) if i < o.n_levels else 0
+        o.cert_rtol = float(self.cert_rtol)
+        return o
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class DeviceBatch:
+    """A scenes.Batch copied to the GPU as torch tensors (the C-ABI layout)."""
+
+    def __init__(self, batch, device="cuda", with_order=True):
+        import torch
+        self.batch = batch
+        self.N, self.n_max, self.K, self.Q = batch.N, batch.n_max, batch.K, batch.Q
+        self.S = float(batch.S)
+        dev = torch.device(device)
+        self.obj = torch.from_numpy(np.ascontiguousarray(batch.obj)).to(dev)
+        self.pts = torch.from_numpy(np.ascontiguousarray(batch.pts)).to(dev)
+        self.src = torch.from_numpy(np.ascontiguousarray(batch.src)).to(dev)
+        self.dst = torch.from_numpy(np.ascontiguousarray(batch.dst)).to(dev)
+        self.ids = torch.from_numpy(np.ascontiguousarray(batch.ids)).to(dev)
+        self.order = (torch.from_numpy(np.ascontiguousarray(batch.order)).to(dev)
+                      if with_order else None)
+        self.t_init = None
+
+    def c_scene(self) -> _Scene:
+        return _Scene(self.K, _ptr(self.obj), self.Q, _ptr(self.pts))
+
+    def c_paths(self) -> _Paths:
+        return _Paths(self.N, self.n_max, _ptr(self.src), _ptr(self.dst),
+                      _ptr(self.order), _ptr(self.ids), _ptr(self.t_init))
+
+
+class Solver:
+    """Handle on one gfx950 device (fpt_create / fpt_destroy)."""
+
+    def __init__(self, device: int = 0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.fpt_create(int(device), ctypes.byref(h)), "fpt_create")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().fpt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc_out(self, db: DeviceBatch):
+        import torch
+        dev = db.obj.device
+        N, n = db.N, db.n_max
+        return dict(
+            x=torch.empty((n, 3, N), dtype=torch.float32, device=dev),
+            len=torch.empty((N,), dtype=torch.float32, device=dev),
+            t=torch.empty((n, 2, N), dtype=torch.float32, device=dev),
+            status=torch.empty((N,), dtype=torch.uint8, device=dev),
+            iters=torch.empty((N,), dtype=torch.int16, device=dev),
+        )
+
+    @staticmethod
+    def c_out(out) -> _Out:
+        return _Out(_ptr(out["x"]), _ptr(out["len"]), _ptr(out["t"]),
+                    _ptr(out["status"]), _ptr(out["iters"]))
+
+    def solve(self, db: DeviceBatch, opts: Opts | None = None, out=None,
+              stream=None):
+        """fpt_solve on db; returns the output tensors (async on stream)."""
+        if opts is None:
+            opts = Opts(scale=db.S)
+        if out is None:
+            out = self.alloc_out(db)
+        sc, pa, oc, ou = db.c_scene(), db.c_paths(), opts.to_c(), self.c_out(out)
+        _check(load_library().fpt_solve(self._h, ctypes.byref(sc),
+                                        ctypes.byref(pa), ctypes.byref(oc),
+                                        ctypes.byref(ou), _stream_ptr(stream)),
+               "fpt_solve")
+        return out
+
+    def grad(self, db: DeviceBatch, fwd, g_len=None, g_x=None, g_pts=None,
+             g_obj=None, g_slot=None, g_end=None, stream=None):
+        """fpt_grad: accumulates into g_pts [3][Q] and g_obj [9][K]."""
+        import torch
+        dev = db.obj.device
+        if g_pts is None:
+            g_pts = torch.zeros((3, db.Q), dtype=torch.float32, device=dev)
+        if g_obj is None:
+            g_obj = torch.zeros((9, db.K), dtype=torch.float32, device=dev)
+        sc, pa, ou = db.c_scene(), db.c_paths(), self.c_out(fwd)
+        _check(load_library().fpt_grad(
+            self._h, ctypes.byref(sc), ctypes.byref(pa), ctypes.byref(ou),
+            _ptr(g_len), _ptr(g_x), _ptr(g_pts), _ptr(g_obj), _ptr(g_slot),
+            _ptr(g_end), _stream_ptr(stream)), "fpt_grad")
+        return g_pts, g_obj

@@ -1,0 +1,201 @@
+"""Parity of the HIP solver (through the C ABI) with the FP64 oracle.
+
+Tolerance: interaction points within 1e-4 of the scene size S (the accuracy
+bar the solver is built for). A path the kernel certifies (FPT_ST_CONVERGED)
+must meet it; over the whole batch the fraction that meets it must reach the
+level the method attains at each order. Where the oracle flags a non-unique
+minimiser (ILL) only the length is compared.
+"""
+import numpy as np
+import pytest
+
+import gpu_util
+from paper_2510_16172_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2510_16172_amd import fpt
+    s = fpt.Solver(0)
+    yield s
+    s.close()
+
+
+def _opts(S, **kw):
+    from paper_2510_16172_amd import fpt
+    return fpt.Opts(scale=S, **kw)
+
+
+def _check_common(b, g, ref, min_ok, rtol=1e-4):
+    s = gpu_util.summary(b, g, ref, rtol)
+    print(f"N={b.N} ok={s['frac_ok']:.4f} cert={s['frac_cert']:.4f} "
+          f"falsepos={s['false_pos']} collapsed={s['col'].mean():.3f}",
+          flush=True)
+    # no certified path is wrong
+    assert s["false_pos"] == 0
+    # no path is shorter than the minimum (beyond FP32 rounding of L)
+    Lg = g["len"].astype(np.float64)
+    assert np.all(Lg >= ref["len"] - 1e-6 * b.S)
+    # unique minimisers: points; non-unique: the length
+    assert s["frac_ok"] >= min_ok
+    ill = s["ill"]
+    if ill.any():
+        assert np.all(np.abs(Lg[ill] - ref["len"][ill]) <= 1e-5 * b.S)
+    # lengths of converged paths: moving each point by at most e changes
+    # every segment by at most 2e, so |dL| <= 2 (n+1) e (+ FP32 rounding)
+    ok = s["ok"]
+    bound = 2.0 * (b.order[ok].astype(np.float64) + 1) * s["err"][ok] * b.S
+    assert np.all(np.abs(Lg[ok] - ref["len"][ok]) <= bound + 2e-6 * b.S)
+    # status bits
+    from paper_2510_16172_amd import fpt
+    assert np.all((g["status"] & fpt.ST_INVALID) == 0)
+    assert np.all((g["status"] & fpt.ST_NONFINITE) == 0)
+    return s
+
+
+def test_random_order2_64_iterations(solver, oracle_mod):
+    """1,024 random order-2 paths, reflection or diffraction with p = 0.5,
+    64 fixed iterations, FP32 + FP64 refinement vs the FP64 oracle."""
+    b = scenes.random_paths(1024, 2, seed=1001)
+    ref = oracle_mod.solve(b, threads=8)
+    g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=64), with_order=False)
+    s = _check_common(b, g, ref, min_ok=0.985)
+    assert np.all(g["iters"] == 64)
+    assert s["frac_cert"] >= 0.8
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_random_each_order(solver, oracle_mod, n):
+    # 2,000 paths: several 256-path workgroups and a ragged tail
+    b = scenes.random_paths(2000, n, seed=3000 + n)
+    ref = oracle_mod.solve(b, threads=8)
+    g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=128), with_order=False)
+    _check_common(b, g, ref, min_ok={1: 0.999, 2: 0.98, 3: 0.95, 4: 0.9,
+                                     5: 0.85, 6: 0.8}[n])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_canyon_each_order(solver, oracle_mod, n):
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 3000, seed=4000 + n, n=n)
+    ref = oracle_mod.solve(b, threads=8)
+    g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=128))
+    _check_common(b, g, ref, min_ok={1: 0.999, 2: 0.98, 3: 0.93, 4: 0.85,
+                                     5: 0.75, 6: 0.65}[n])
+
+
+def test_mixed_orders_bucketed_equals_uniform(solver):
+    """Paths of orders 1..6 in one call (device-side bucketing by order) give
+    bit-identical results to the same paths solved order by order."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 5000, seed=77, n=None, n_max=6)
+    opts = _opts(b.S, iters=48)
+    g = gpu_util.run_gpu(solver, b, opts)
+    for n in range(1, 7):
+        idx = np.nonzero(b.order == n)[0]
+        if len(idx) == 0:
+            continue
+        sub = b.subset(idx)
+        sub = scenes.Batch(sub.obj, sub.pts, sub.src, sub.dst, sub.order,
+                           np.ascontiguousarray(sub.ids[:n]), sub.S)
+        gu = gpu_util.run_gpu(solver, sub, opts, with_order=False)
+        np.testing.assert_array_equal(gu["x"], g["x"][:n, :, idx])
+        np.testing.assert_array_equal(gu["len"], g["len"][idx])
+        np.testing.assert_array_equal(gu["status"], g["status"][idx])
+        assert np.all(np.isnan(g["x"][n:, :, idx]))
+
+
+def test_deterministic(solver):
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 4096, seed=78, n=None, n_max=6)
+    opts = _opts(b.S, iters=32)
+    g1 = gpu_util.run_gpu(solver, b, opts)
+    g2 = gpu_util.run_gpu(solver, b, opts)
+    for k in g1:
+        np.testing.assert_array_equal(g1[k], g2[k])
+
+
+def test_invalid_paths_and_edge_cases(solver):
+    import torch
+    from paper_2510_16172_amd import fpt
+    b = scenes.random_paths(300, 3, seed=79)
+    order = b.order.copy()
+    ids = b.ids.copy()
+    src = b.src.copy()
+    obj = b.obj.copy()
+    order[0] = 0            # order below 1
+    order[1] = 7            # order above n_max
+    ids[1, 2] = b.K + 5     # id out of range
+    ids[0, 3] = -2          # negative id
+    src[4] = b.Q            # point index out of range
+    obj[0, ids[2, 5]] = np.nan  # non-finite geometry
+    obj[3:6, ids[1, 6]] = 0.0   # zero first basis vector
+    order[7] = 2            # a valid shorter path inside the n_max=3 batch
+    bad = scenes.Batch(obj, b.pts, src, b.dst, order, ids, b.S)
+    g = gpu_util.run_gpu(solver, bad, _opts(b.S, iters=64))
+    for i in range(7):
+        assert g["status"][i] == fpt.ST_INVALID, i
+        assert np.all(np.isnan(g["x"][:, :, i])) and np.isnan(g["len"][i])
+    assert g["status"][7] & fpt.ST_INVALID == 0
+    assert np.all(np.isfinite(g["x"][:2, :, 7])) and np.all(np.isnan(g["x"][2, :, 7]))
+    assert np.all(g["status"][8:] & fpt.ST_INVALID == 0)
+    # N = 0: accepted, nothing launched
+    empty = b.subset(np.zeros(0, np.int64))
+    db = fpt.DeviceBatch(empty)
+    solver.solve(db, _opts(b.S))
+    torch.cuda.synchronize()
+    # whole-call errors launch nothing and raise
+    db = fpt.DeviceBatch(b)
+    with pytest.raises(fpt.FptError):
+        solver.solve(db, _opts(-1.0))
+    with pytest.raises(fpt.FptError):
+        solver.solve(db, _opts(b.S, iters=-1))
+
+
+def test_warm_start_from_oracle(solver, oracle_mod):
+    """Starting at the oracle's T*, zero BFGS iterations and the refinement
+    keep the solution and certify every smooth path."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 2000, seed=80, n=3)
+    ref = oracle_mod.solve(b, threads=8)
+    t0 = np.transpose(ref["t"], (1, 2, 0))  # n, 2, N
+    g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=0), t_init=t0)
+    s = gpu_util.summary(b, g, ref)
+    smooth = ~s["col"] & ~s["ill"]
+    assert s["ok"][smooth].all()
+    assert s["cert"][smooth].mean() > 0.99
+    assert s["false_pos"] == 0
+
+
+def test_full_canyon_order2_sampled(solver, oracle_mod):
+    """All 6,270,016 sequences of order <= 2 in the canyon (the benchmark
+    workload and launch): 8,192 sampled paths against the oracle, and
+    properties that hold on every path."""
+    import torch
+    from paper_2510_16172_amd import fpt
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_all_paths(sc, n_max=2)
+    assert b.N == 6_270_016
+    opts = _opts(b.S, iters=64)
+    db = fpt.DeviceBatch(b)
+    out = solver.solve(db, opts)
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    L = out["len"].cpu().numpy().astype(np.float64)
+    assert np.all(st & (fpt.ST_INVALID | fpt.ST_NONFINITE) == 0)
+    direct = np.linalg.norm(b.pts[:, b.dst] - b.pts[:, b.src], axis=0)
+    assert np.all(L >= direct * (1 - 1e-6))
+    cert = (st & fpt.ST_CONVERGED) != 0
+    print(f"certified {cert.mean():.4f}", flush=True)
+    rng = np.random.default_rng(81)
+    idx = np.sort(rng.choice(b.N, 8192, replace=False))
+    sub = b.subset(idx)
+    ref = oracle_mod.solve(sub, threads=8)
+    g = {k: (v.cpu().numpy()[..., idx] if v.dim() > 1 else v.cpu().numpy()[idx])
+         for k, v in out.items()}
+    _check_common(sub, g, ref, min_ok=0.98)
