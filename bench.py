@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Throughput of the Fermat path solver on one MI355X.
+
+Workload: the street canyon (24 boxes, 121 faces + 192 edges, 64 TX/RX
+pairs), every interaction sequence of order 1 and 2 with no immediate repeat:
+6,270,016 paths, solved in FP32 (BFGS with the fixed-point step of Eq. 6)
+plus FP64 refinement. One step = one fpt_solve over all paths, inputs
+resident in HBM. Metric: converged paths per second, where converged means
+certified by the kernel's FP64 Newton check (a path within 1e-4 S of the
+true minimiser in every sampled comparison with the oracle).
+
+Prints ONE JSON line (see the keys at the end of main()).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12      # published FP32 vector peak (counts packed FP32)
+PEAK_FP32_UNPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop x 2.4 GHz
+PEAK_HBM = 8.0e12
+
+
+def bfgs_flops_per_iter(n: int, fp_iters: int, early_exit: bool) -> int:
+    """FP32 flops of one iteration of bfgs_kernel<n> (FMA = 2, every other
+    arithmetic op and each rsq / rcp = 1; comparisons and selects = 0).
+    Counted term by term from the kernel with m = 2n parameters (the padded
+    layout) and s = n + 1 segments:
+      direction in point space q_j      9n      segment changes D_i  3(n-1)
+      dr_i, dd_i                       10s      num0, den0, phi0      6s
+      majorant step                     2       fixed-point iteration f(10s+2)
+      descent check phi(alpha)          8s      step s, T += s        2m
+      new gradient                25n + 12s      H g'                 2m^2 - m
+      y, Hy, s.y, y.Hy, s.s, y.y      10m      curvature test, rho, c1  7
+      v, w, w.g', s.g'                 7m      packed update H      2m(m+1)
+      new direction, |P|^2             6m
+    = 16 n^2 + 125 n + 42 + f (10 n + 12)   (+ 5n + 3 with early exit)."""
+    f = int(fp_iters)
+    v = 16 * n * n + 125 * n + 42 + f * (10 * n + 12)
+    if early_exit:
+        v += 5 * n + 3
+    return v
+
+
+def bfgs_init_flops(n: int) -> int:
+    """Initial gradient (25n + 12(n+1)) and basis normalisation (18n)."""
+    return 25 * n + 12 * (n + 1) + 18 * n
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("solve.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2510_16172_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if there is none for the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}__{workload}.counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_digest") != source_digest():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(batch, out_np, seconds: float, threads: int, seed: int = 7):
+    """The FP64 oracle timed on host cores on a seeded random sample of the
+    workload (chunks of 2^14 paths until `seconds` have elapsed), and the GPU
+    result checked against it on that sample."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(batch.N)
+    chunk = 1 << 14
+    done, t_used, n_ok, n_fp, n_cert = 0, 0.0, 0, 0, 0
+    while t_used < seconds and done < batch.N:
+        idx = np.sort(perm[done:done + chunk])
+        sub = batch.subset(idx)
+        t0 = time.perf_counter()
+        ref = oracle.solve(sub, threads=threads)
+        t_used += time.perf_counter() - t0
+        done += len(idx)
+        x = np.transpose(out_np["x"][:, :, idx], (2, 0, 1)).astype(np.float64)
+        d = np.linalg.norm(x - ref["x"], axis=-1)
+        j = np.arange(sub.n_max)[None, :]
+        d = np.where(j < sub.order[:, None].astype(np.int64), d, 0.0)
+        err = np.where(np.isfinite(d), d, np.inf).max(axis=1) / sub.S
+        ok = err <= 1e-4
+        cert = (out_np["status"][idx] & 1) != 0
+        ill = (ref["flags"] & 2) != 0
+        n_ok += int(ok.sum())
+        n_cert += int(cert.sum())
+        n_fp += int((cert & ~ok & ~ill).sum())
+    return {"value": done / t_used, "unit": "paths/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{done} seeded random paths of the workload "
+                      f"({t_used:.1f} s on {threads} threads)",
+            "gpu_within_1e-4_on_sample": n_ok / done,
+            "gpu_certified_on_sample": n_cert / done,
+            "gpu_certified_but_wrong_on_sample": n_fp}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--iters", type=int, default=64)
+    ap.add_argument("--fp-iters", type=int, default=1)
+    ap.add_argument("--early-exit", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain device copy of known size (for "
+                         "calibrating the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is "
+              "not supported (paths are independent: the design for several "
+              "GPUs shards the path list, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_16172_amd import fpt, scenes
+
+    scene = scenes.canyon_scene()
+    batch = scenes.canyon_all_paths(scene, n_max=2)
+    N = batch.N
+    solver = fpt.Solver(0)
+    db = fpt.DeviceBatch(batch, device="cuda:0")
+    opts = fpt.Opts(scale=batch.S, iters=args.iters, fp_iters=args.fp_iters,
+                    early_exit=args.early_exit)
+    out = solver.alloc_out(db)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calib:
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")  # 256 MiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copy calibration: {a.numel() * 4} bytes read and written per copy",
+              file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        solver.solve(db, opts, out=out, stream=stream)
+    torch.cuda.synchronize()
+    solver.set_timing(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(args.steps):
+        solver.solve(db, opts, out=out, stream=stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = t0.elapsed_time(t1) / args.steps
+    kt = solver.kernel_times()
+    solver.set_timing(False)
+
+    out_np = {k: v.cpu().numpy() for k, v in out.items()}
+    st = out_np["status"]
+    certified = int(((st & fpt.ST_CONVERGED) != 0).sum())
+    value = certified / (ms_step / 1e3)
+
+    # roofline of the dominant kernel: bfgs_kernel<2> over the order-2 bucket
+    o2 = batch.order == 2
+    it2 = out_np["iters"][o2].astype(np.int64)
+    fl = (int(it2.sum()) * bfgs_flops_per_iter(2, args.fp_iters, args.early_exit)
+          + int(o2.sum()) * bfgs_init_flops(2))
+    t_bfgs2 = kt[fpt.T_BFGS + 1] * 1e-3
+    achieved = fl / t_bfgs2
+    workload = "canyon_order2_all"
+    traffic = read_traffic("bfgs_kernel_2", workload)
+    kernels_ms = {
+        "bucketing": kt[fpt.T_BUCKET],
+        "bfgs_order1": kt[fpt.T_BFGS + 0], "bfgs_order2": kt[fpt.T_BFGS + 1],
+        "refine_order1": kt[fpt.T_REFINE + 0],
+        "refine_order2": kt[fpt.T_REFINE + 1],
+    }
+    res = {
+        "metric": "converged paths/s (fwd) at <=1e-4 rel error",
+        "value": value,
+        "unit": "paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "street canyon: all 6,270,016 interaction sequences "
+                        "of order <= 2 (313 objects, 64 TX/RX pairs)",
+            "paths": N, "iters": args.iters, "fp_iters": args.fp_iters,
+            "early_exit": bool(args.early_exit),
+            "refine_levels": list(zip(opts.level_eps, opts.level_steps)),
+        },
+        "certified_fraction": certified / N,
+        "paths_per_s_all": N / (ms_step / 1e3),
+        "kernel_ms": kernels_ms,
+        "roofline": {
+            "kernel": "bfgs_kernel<2>",
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP32 / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32,
+            "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED,
+            "flops_per_launch": fl,
+            "traffic": traffic,
+        },
+    }
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+        res["cpu_baseline"] = cpu_baseline(batch, out_np, args.cpu_seconds, threads)
+    print(json.dumps(res), flush=True)
+    solver.close()
+
+
+if __name__ == "__main__":
+    main()

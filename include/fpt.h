@@ -98,8 +98,10 @@ typedef struct {
 typedef struct {
   int32_t iters;        /* BFGS iterations (Sec. III-C runs a fixed count) */
   int32_t fp_iters;     /* fixed-point iterations of Eq. 6 per BFGS step */
-  int32_t early_exit;   /* 1: a wavefront stops once every lane's last step
-                           moved each point by < exit_rtol * scale */
+  int32_t early_exit;   /* 0: every path runs exactly `iters` iterations.
+                           1: a path stops after two consecutive steps that
+                           move no point by more than exit_rtol * scale (or
+                           after `iters`), and its lane takes the next path */
   float exit_rtol;
   float scale;          /* scene size S (> 0): unit of every tolerance */
   int32_t n_levels;     /* FP64 refinement levels, 0..FPT_MAX_LEVELS */
@@ -107,10 +109,14 @@ typedef struct {
                                        (0 = exact length) */
   int32_t level_steps[FPT_MAX_LEVELS]; /* Newton steps at each level */
   float cert_rtol;      /* certificate threshold / scale */
+  int32_t refill_min;   /* early exit: refill once this many lanes of a
+                           wavefront are idle (1..64) ... */
+  int32_t refill_every; /* ... or this many iterations have passed (>= 1) */
 } fpt_opts;
 
-/* Defaults: 64 iterations, 1 fixed-point iteration, no early exit, refinement
- * levels eps/S = 1e-3, 1e-5, 1e-7 (2 steps each) and 1e-9 (3 steps),
+/* Defaults: 64 iterations, 1 fixed-point iteration, no early exit
+ * (exit_rtol = 1e-6, refill_min = 8, refill_every = 4), refinement levels
+ * eps/S = 1e-3, 1e-5, 1e-7 (2 steps each) and 1e-9 (3 steps),
  * cert_rtol = 1e-5, scale = 1. */
 void fpt_default_opts(fpt_opts* opts);
 
@@ -151,6 +157,30 @@ fpt_status fpt_grad(fpt_handle* h, const fpt_scene* scene,
                     const float* g_len, const float* g_x, float* g_pts,
                     float* g_obj, float* g_slot, float* g_end,
                     void* hip_stream);
+
+/* Optional per-kernel timing. While enabled, every kernel (group) that
+ * fpt_solve and fpt_grad launch is bracketed by a pair of HIP events recorded
+ * on the caller's stream, into a ring of 32 event pairs per slot (no host
+ * synchronisation is added). fpt_kernel_times waits for the recorded events
+ * and writes, per timer slot, the mean duration in milliseconds over the
+ * launches recorded since the previous read (at most the last 32), or -1 if
+ * there were none, to ms[FPT_TIMERS]; it then clears the counts. Slots:
+ *   FPT_T_BUCKET           order bucketing (count, scan, scatter)
+ *   FPT_T_BFGS + n - 1     FP32 BFGS kernel of order n (n = 1..6)
+ *   FPT_T_REFINE + n - 1   FP64 refinement kernel of order n
+ *   FPT_T_GRAD             implicit-differentiation kernel
+ *   FPT_T_REDUCE           per-object gradient reduction
+ * Enabling allocates the events (returns FPT_EHIP if that fails). */
+enum {
+  FPT_T_BUCKET = 0,
+  FPT_T_BFGS = 1,
+  FPT_T_REFINE = 7,
+  FPT_T_GRAD = 13,
+  FPT_T_REDUCE = 14,
+  FPT_TIMERS = 16
+};
+fpt_status fpt_set_timing(fpt_handle* h, int enable);
+fpt_status fpt_kernel_times(fpt_handle* h, float* ms);
 
 /* Thread-local description of the last non-OK status of this thread. */
 const char* fpt_last_error(void);

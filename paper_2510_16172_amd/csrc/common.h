@@ -64,12 +64,34 @@ struct SolveArgs {
   int32_t K, Q, n_max;
   // options
   int32_t n_iter, fp_iters, early_exit;
+  int32_t refill_min, refill_every;  // early-exit refill policy
   float exit_d2;  // (exit_rtol * scale)^2
   float scale;
   int32_t n_levels;
   float level_eps[FPT_MAX_LEVELS];
   int32_t level_steps[FPT_MAX_LEVELS];
   float cert_abs;  // cert_rtol * scale
+};
+
+// Arguments of one fpt_grad call.
+struct GradArgs {
+  const float* obj;
+  const float* pts;
+  const int32_t* src;
+  const int32_t* dst;
+  const uint8_t* order;
+  const int32_t* ids;
+  const float* t;         // forward T* [n_max][2][N] (caller's parametrisation)
+  const uint8_t* status;  // forward status [N]
+  const float* g_len;     // [N] or null
+  const float* g_x;       // [n_max][3][N] or null
+  float* g_pts;           // [3][Q] +=
+  float* g_obj;           // [9][K] +=
+  float* g_slot;          // [n_max][9][N] or null
+  float* g_end;           // [6][N] or null
+  int64_t N;
+  int32_t K, Q, n_max;
+  int32_t lds;            // accumulate per workgroup in LDS first
 };
 
 }  // namespace fpt

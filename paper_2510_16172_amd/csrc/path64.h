@@ -1,0 +1,215 @@
+// FP64 algebra of one path (device side), shared by the refinement of the
+// solver and by the implicit-differentiation backward pass.
+//
+// Parametrisation (Sec. III-B, Eq. 3): x_j = b_j + t_j0 a1_j + t_j1 a2_j,
+// with a2 = 0 for an edge (padding). Slot j = 0..n-1 is interaction j+1;
+// segment i = 0..n runs from point i-1 to point i (point -1 = TX, point n =
+// RX): slot j touches segment j (incoming) and segment j+1 (outgoing).
+#pragma once
+
+#include "common.h"
+
+namespace fpt {
+
+template <int NO>
+struct Geo64 {
+  double tx[3], rx[3];
+  double b[NO][3];
+  double a[NO][2][3];  // caller's basis vectors (a[j][1] = 0 for an edge)
+  bool edge[NO];
+};
+
+// Geometry of path p in FP64 (exact widening of the FP32 tables). Indices out
+// of range are clamped to 0 (the caller has flagged such a path invalid).
+template <int NO>
+__device__ __forceinline__ void load_geo64(const float* __restrict__ obj,
+                                           const float* __restrict__ pts,
+                                           const int32_t* __restrict__ ids,
+                                           int32_t s, int32_t e, int32_t K,
+                                           int32_t Q, int64_t N, int64_t p,
+                                           Geo64<NO>& D) {
+  s = (s >= 0 && s < Q) ? s : 0;
+  e = (e >= 0 && e < Q) ? e : 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    D.tx[c] = pts[(int64_t)c * Q + s];
+    D.rx[c] = pts[(int64_t)c * Q + e];
+  }
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    int32_t k = ids[(int64_t)j * N + p];
+    k = (k >= 0 && k < K) ? k : 0;
+    float a2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      D.b[j][c] = obj[(int64_t)c * K + k];
+      D.a[j][0][c] = obj[(int64_t)(3 + c) * K + k];
+      a2[c] = obj[(int64_t)(6 + c) * K + k];
+    }
+    bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
+    D.edge[j] = edge;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) D.a[j][1][c] = edge ? 0.0 : (double)a2[c];
+  }
+}
+
+template <int NO>
+__device__ __forceinline__ void points64(const Geo64<NO>& G, const double* t,
+                                         double (*x)[3]) {
+#pragma unroll
+  for (int j = 0; j < NO; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      x[j][c] = fma(t[2 * j + 1], G.a[j][1][c],
+                    fma(t[2 * j], G.a[j][0][c], G.b[j][c]));
+}
+
+// Segments at t: v_i = r_i / l_i and il_i = 1 / l_i with
+// l_i = sqrt(|r_i|^2 + eps^2) (eps = 0: the exact length of Eq. 5).
+template <int NO>
+__device__ __forceinline__ void segments64(const Geo64<NO>& G,
+                                           const double* t, double eps2,
+                                           double (*v)[3], double* il) {
+  double x[NO][3];
+  points64<NO>(G, t, x);
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
+    double q = fmax(dot3d(r, r) + eps2, 1e-300);
+    il[i] = rsq64(q);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[i][c] = r[c] * il[i];
+  }
+}
+
+template <int NO>
+__device__ __forceinline__ double length64(const Geo64<NO>& G,
+                                           const double* t, double eps2) {
+  double x[NO][3];
+  points64<NO>(G, t, x);
+  double L = 0.0;
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
+    double q = fmax(dot3d(r, r) + eps2, 1e-300);
+    L += q * rsq64(q);
+  }
+  return L;
+}
+
+// Gradient of the (smoothed) length: g_j = A_j^T (v_j - v_{j+1}); the padded
+// parameter of an edge gets 0.
+template <int NO>
+__device__ __forceinline__ void gradient64(const Geo64<NO>& G,
+                                           const double (*v)[3], double* g) {
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    double du[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) du[c] = v[j][c] - v[j + 1][c];
+    g[2 * j] = dot3d(G.a[j][0], du);
+    g[2 * j + 1] = G.edge[j] ? 0.0 : dot3d(G.a[j][1], du);
+  }
+}
+
+// Solves H d = rhs for the Hessian of the (smoothed) length, given the
+// segments (v, il) at the current point. H is block tridiagonal with 2x2
+// blocks (slot j couples only to j-1 and j+1):
+//   D_j = A_j^T (M_j + M_{j+1}) A_j,  E_j = H_{j,j+1} = -A_j^T M_{j+1} A_{j+1},
+//   M_i = (I - v_i v_i^T) / l_i  (the Hessian of l_i in r_i),
+// and is solved by block-Thomas elimination (forward Schur complements
+// S_j = D_j - E_{j-1}^T S_{j-1}^{-1} E_{j-1}, then back substitution).
+// The padded parameter of an edge has a zero row and column in H; its
+// diagonal is set to 1 and its right-hand side to 0, so its d is 0.
+// Returns false if a pivot block is not positive definite or d is not finite.
+template <int NO>
+__device__ __forceinline__ bool hess_solve64(const Geo64<NO>& G,
+                                             const double (*v)[3],
+                                             const double* il,
+                                             const double* rhs, double* d) {
+  double Sinv[NO][3], E[NO][4], z[NO][2];
+  double pSinv[3] = {0, 0, 0}, pE[4] = {0, 0, 0, 0}, pz[2] = {0, 0};
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    const double* a0 = G.a[j][0];
+    const double* a1 = G.a[j][1];
+    double pin0 = dot3d(a0, v[j]), pin1 = dot3d(a1, v[j]);
+    double pout0 = dot3d(a0, v[j + 1]), pout1 = dot3d(a1, v[j + 1]);
+    double G00 = dot3d(a0, a0), G01 = dot3d(a0, a1), G11 = dot3d(a1, a1);
+    double D00 = (G00 - pin0 * pin0) * il[j] + (G00 - pout0 * pout0) * il[j + 1];
+    double D01 = (G01 - pin0 * pin1) * il[j] + (G01 - pout0 * pout1) * il[j + 1];
+    double D11 = (G11 - pin1 * pin1) * il[j] + (G11 - pout1 * pout1) * il[j + 1];
+    double rhs0 = rhs[2 * j], rhs1 = rhs[2 * j + 1];
+    if (G.edge[j]) {
+      D01 = 0.0;
+      D11 = 1.0;
+      rhs1 = 0.0;
+    }
+    if (j > 0) {
+      // W = S_{j-1}^{-1} E_{j-1}; E rows: parameters of slot j-1
+      double W00 = pSinv[0] * pE[0] + pSinv[1] * pE[2];
+      double W01 = pSinv[0] * pE[1] + pSinv[1] * pE[3];
+      double W10 = pSinv[1] * pE[0] + pSinv[2] * pE[2];
+      double W11 = pSinv[1] * pE[1] + pSinv[2] * pE[3];
+      D00 -= pE[0] * W00 + pE[2] * W10;
+      D01 -= pE[0] * W01 + pE[2] * W11;
+      D11 -= pE[1] * W01 + pE[3] * W11;
+      double w0 = pSinv[0] * pz[0] + pSinv[1] * pz[1];
+      double w1 = pSinv[1] * pz[0] + pSinv[2] * pz[1];
+      rhs0 -= pE[0] * w0 + pE[2] * w1;
+      rhs1 -= pE[1] * w0 + pE[3] * w1;
+    }
+    double det = D00 * D11 - D01 * D01;
+    ok = ok && (det > 0.0) && (D00 > 0.0) && isfinite(det);
+    double idet = rcp64(det);
+    Sinv[j][0] = D11 * idet;
+    Sinv[j][1] = -D01 * idet;
+    Sinv[j][2] = D00 * idet;
+    z[j][0] = rhs0;
+    z[j][1] = rhs1;
+    if (j + 1 < NO) {
+      const double* b0 = G.a[j + 1][0];
+      const double* b1 = G.a[j + 1][1];
+      double qn0 = dot3d(b0, v[j + 1]), qn1 = dot3d(b1, v[j + 1]);
+      double il1 = il[j + 1];
+      E[j][0] = -(dot3d(a0, b0) - pout0 * qn0) * il1;
+      E[j][1] = -(dot3d(a0, b1) - pout0 * qn1) * il1;
+      E[j][2] = -(dot3d(a1, b0) - pout1 * qn0) * il1;
+      E[j][3] = -(dot3d(a1, b1) - pout1 * qn1) * il1;
+      if (G.edge[j]) E[j][2] = E[j][3] = 0.0;
+      if (G.edge[j + 1]) E[j][1] = E[j][3] = 0.0;
+    } else {
+      E[j][0] = E[j][1] = E[j][2] = E[j][3] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pSinv[k] = Sinv[j][k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pE[k] = E[j][k];
+    pz[0] = z[j][0];
+    pz[1] = z[j][1];
+  }
+  double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+  for (int j = NO - 1; j >= 0; --j) {
+    double c0 = z[j][0] - (E[j][0] * n0 + E[j][1] * n1);
+    double c1 = z[j][1] - (E[j][2] * n0 + E[j][3] * n1);
+    double d0 = Sinv[j][0] * c0 + Sinv[j][1] * c1;
+    double d1 = Sinv[j][1] * c0 + Sinv[j][2] * c1;
+    if (G.edge[j]) d1 = 0.0;
+    d[2 * j] = d0;
+    d[2 * j + 1] = d1;
+    n0 = d0;
+    n1 = d1;
+    ok = ok && isfinite(d0) && isfinite(d1);
+  }
+  return ok;
+}
+
+}  // namespace fpt

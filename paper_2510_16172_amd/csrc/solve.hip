@@ -16,6 +16,7 @@
 // segment i = 0..n runs from point i-1 to point i (point -1 = TX,
 // point n = RX), so slot j touches segments j (incoming) and j+1.
 #include "common.h"
+#include "path64.h"
 
 namespace fpt {
 
@@ -33,15 +34,6 @@ __device__ __forceinline__ void basis_inv32(const float* a1, const float* a2,
   i1 = rsq32(n1 > 0.f ? n1 : 1.f);
   i2 = edge ? 0.f : rsq32(n2 > 0.f ? n2 : 1.f);
 }
-
-// Reads path p's geometry in FP64 (exact widening of the FP32 tables) and
-// the FP32 1/|a| factors that map the FP32 phase's unit-vector parameters
-// back to the caller's parametrisation.
-template <int NO>
-struct Geo64;
-template <int NO>
-__device__ __forceinline__ void load_geo64(const SolveArgs& A, int64_t p,
-                                           Geo64<NO>& D, float (*inv)[2]);
 
 // Gradient of L at T (Sec. III-B Eq. 5): g_j = A_j^T (u_j - u_{j+1}).
 template <int NO>
@@ -106,184 +98,35 @@ struct RefineOut {
 
 // ---------------------------------------------------------------- FP64 ----
 
-template <int NO>
-struct Geo64 {
-  double tx[3], rx[3];
-  double b[NO][3];
-  double a[NO][2][3];  // caller's basis vectors (a[j][1] = 0 for an edge)
-  bool edge[NO];
-};
-
+// Reads path p's geometry in FP64 and the FP32 1/|a| factors that map the
+// FP32 phase's unit-vector parameters back to the caller's parametrisation.
 template <int NO>
 __device__ __forceinline__ void load_geo64(const SolveArgs& A, int64_t p,
                                            Geo64<NO>& D, float (*inv)[2]) {
-  int32_t s = A.src[p], e = A.dst[p];
-  s = (s >= 0 && s < A.Q) ? s : 0;
-  e = (e >= 0 && e < A.Q) ? e : 0;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    D.tx[c] = A.pts[(int64_t)c * A.Q + s];
-    D.rx[c] = A.pts[(int64_t)c * A.Q + e];
-  }
+  load_geo64<NO>(A.obj, A.pts, A.ids, A.src[p], A.dst[p], A.K, A.Q, A.N, p, D);
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
-    int32_t k = A.ids[(int64_t)j * A.N + p];
-    k = (k >= 0 && k < A.K) ? k : 0;
     float a1[3], a2[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      D.b[j][c] = A.obj[(int64_t)c * A.K + k];
-      a1[c] = A.obj[(int64_t)(3 + c) * A.K + k];
-      a2[c] = A.obj[(int64_t)(6 + c) * A.K + k];
+      a1[c] = (float)D.a[j][0][c];
+      a2[c] = (float)D.a[j][1][c];
     }
-    bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
-    D.edge[j] = edge;
-    basis_inv32(a1, a2, edge, inv[j][0], inv[j][1]);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      D.a[j][0][c] = a1[c];
-      D.a[j][1][c] = edge ? 0.0 : (double)a2[c];
-    }
+    basis_inv32(a1, a2, D.edge[j], inv[j][0], inv[j][1]);
   }
 }
 
-template <int NO>
-__device__ __forceinline__ void points64(const Geo64<NO>& G, const double* t,
-                                         double (*x)[3]) {
-#pragma unroll
-  for (int j = 0; j < NO; ++j)
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      x[j][c] = fma(t[2 * j + 1], G.a[j][1][c],
-                    fma(t[2 * j], G.a[j][0][c], G.b[j][c]));
-}
-
-template <int NO>
-__device__ __forceinline__ double length64(const Geo64<NO>& G,
-                                           const double* t, double eps2) {
-  double x[NO][3];
-  points64<NO>(G, t, x);
-  double L = 0.0;
-#pragma unroll
-  for (int i = 0; i <= NO; ++i) {
-    double r[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
-    double q = fmax(dot3d(r, r) + eps2, 1e-300);
-    L += q * rsq64(q);
-  }
-  return L;
-}
-
-// One Newton direction d = -H^{-1} g of the eps-smoothed length at t.
-// H is block tridiagonal with 2x2 blocks
-//   D_j = A_j^T (M_j + M_{j+1}) A_j,  E_j = -A_j^T M_{j+1} A_{j+1},
-//   M_i = (I - v_i v_i^T) / l_i,  v_i = r_i / l_i,  l_i = sqrt(|r_i|^2+eps^2),
-// solved by block-Thomas elimination. The padded parameter of an edge has
-// a zero row and column; its diagonal is set to 1, so its step is 0.
-// Returns false if a pivot block is singular or non-finite.
+// Newton direction d = -H^{-1} g of the eps-smoothed length at t.
 template <int NO>
 __device__ __forceinline__ bool newton_dir64(const Geo64<NO>& G,
                                              const double* t, double eps2,
                                              double* d) {
-  double x[NO][3];
-  points64<NO>(G, t, x);
-  double v[NO + 1][3], il[NO + 1];
+  double v[NO + 1][3], il[NO + 1], g[2 * NO];
+  segments64<NO>(G, t, eps2, v, il);
+  gradient64<NO>(G, v, g);
 #pragma unroll
-  for (int i = 0; i <= NO; ++i) {
-    double r[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
-    double q = fmax(dot3d(r, r) + eps2, 1e-300);
-    il[i] = rsq64(q);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) v[i][c] = r[c] * il[i];
-  }
-  // per slot: projections of v on the basis, gradient, blocks
-  double Sinv[NO][3], E[NO][4], z[NO][2];
-  double pSinv[3] = {0, 0, 0}, pE[4] = {0, 0, 0, 0}, pz[2] = {0, 0};
-  bool ok = true;
-#pragma unroll
-  for (int j = 0; j < NO; ++j) {
-    const double* a0 = G.a[j][0];
-    const double* a1 = G.a[j][1];
-    double pin0 = dot3d(a0, v[j]), pin1 = dot3d(a1, v[j]);
-    double pout0 = dot3d(a0, v[j + 1]), pout1 = dot3d(a1, v[j + 1]);
-    double g0 = pin0 - pout0, g1 = pin1 - pout1;
-    double G00 = dot3d(a0, a0), G01 = dot3d(a0, a1), G11 = dot3d(a1, a1);
-    // D_j (symmetric: 00, 01, 11)
-    double D00 = (G00 - pin0 * pin0) * il[j] + (G00 - pout0 * pout0) * il[j + 1];
-    double D01 = (G01 - pin0 * pin1) * il[j] + (G01 - pout0 * pout1) * il[j + 1];
-    double D11 = (G11 - pin1 * pin1) * il[j] + (G11 - pout1 * pout1) * il[j + 1];
-    if (G.edge[j]) {
-      D01 = 0.0;
-      D11 = 1.0;
-      g1 = 0.0;
-    }
-    double rhs0 = -g0, rhs1 = -g1;
-    if (j > 0) {
-      // S_j = D_j - E_{j-1}^T S_{j-1}^{-1} E_{j-1}; z_j = rhs - E^T S^-1 z
-      // W = S^{-1} E (2x2), E = [[e00 e01][e10 e11]] rows: prev slot params
-      double W00 = pSinv[0] * pE[0] + pSinv[1] * pE[2];
-      double W01 = pSinv[0] * pE[1] + pSinv[1] * pE[3];
-      double W10 = pSinv[1] * pE[0] + pSinv[2] * pE[2];
-      double W11 = pSinv[1] * pE[1] + pSinv[2] * pE[3];
-      D00 -= pE[0] * W00 + pE[2] * W10;
-      D01 -= pE[0] * W01 + pE[2] * W11;
-      D11 -= pE[1] * W01 + pE[3] * W11;
-      double w0 = pSinv[0] * pz[0] + pSinv[1] * pz[1];
-      double w1 = pSinv[1] * pz[0] + pSinv[2] * pz[1];
-      rhs0 -= pE[0] * w0 + pE[2] * w1;
-      rhs1 -= pE[1] * w0 + pE[3] * w1;
-    }
-    double det = D00 * D11 - D01 * D01;
-    ok = ok && (det > 0.0) && (D00 > 0.0) && isfinite(det);
-    double idet = rcp64(det);
-    Sinv[j][0] = D11 * idet;
-    Sinv[j][1] = -D01 * idet;
-    Sinv[j][2] = D00 * idet;
-    z[j][0] = rhs0;
-    z[j][1] = rhs1;
-    if (j + 1 < NO) {
-      // E_j = -A_j^T M_{j+1} A_{j+1}
-      const double* b0 = G.a[j + 1][0];
-      const double* b1 = G.a[j + 1][1];
-      double qn0 = dot3d(b0, v[j + 1]), qn1 = dot3d(b1, v[j + 1]);
-      double il1 = il[j + 1];
-      E[j][0] = -(dot3d(a0, b0) - pout0 * qn0) * il1;
-      E[j][1] = -(dot3d(a0, b1) - pout0 * qn1) * il1;
-      E[j][2] = -(dot3d(a1, b0) - pout1 * qn0) * il1;
-      E[j][3] = -(dot3d(a1, b1) - pout1 * qn1) * il1;
-      if (G.edge[j]) E[j][2] = E[j][3] = 0.0;
-      if (G.edge[j + 1]) E[j][1] = E[j][3] = 0.0;
-    } else {
-      E[j][0] = E[j][1] = E[j][2] = E[j][3] = 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) pSinv[k] = Sinv[j][k];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) pE[k] = E[j][k];
-    pz[0] = z[j][0];
-    pz[1] = z[j][1];
-  }
-  // back substitution: d_j = S_j^{-1} (z_j - E_j d_{j+1})
-  double n0 = 0.0, n1 = 0.0;
-#pragma unroll
-  for (int j = NO - 1; j >= 0; --j) {
-    double c0 = z[j][0] - (E[j][0] * n0 + E[j][1] * n1);
-    double c1 = z[j][1] - (E[j][2] * n0 + E[j][3] * n1);
-    double d0 = Sinv[j][0] * c0 + Sinv[j][1] * c1;
-    double d1 = Sinv[j][1] * c0 + Sinv[j][2] * c1;
-    if (G.edge[j]) d1 = 0.0;
-    d[2 * j] = d0;
-    d[2 * j + 1] = d1;
-    n0 = d0;
-    n1 = d1;
-    ok = ok && isfinite(d0) && isfinite(d1);
-  }
-  return ok;
+  for (int k = 0; k < 2 * NO; ++k) g[k] = -g[k];
+  return hess_solve64<NO>(G, v, il, g, d);
 }
 
 template <int NO>
@@ -350,12 +193,225 @@ __device__ __forceinline__ RefineOut refine64(const Geo64<NO>& G, double* t,
 
 // ------------------------------------------------------------- kernel -----
 
+// Per-lane FP32 state of the BFGS iteration.
 template <int NO>
-__global__ __launch_bounds__(kBlock) void solve_kernel(
+struct State32 {
+  static constexpr int M = 2 * NO;
+  static constexpr int HP = M * (M + 1) / 2;
+  float T[M], g[M], P[M], H[HP];    // parameters, gradient, direction, H
+  float r[NO + 1][3], l2[NO + 1], il[NO + 1];  // segments at T
+};
+
+// Gathers path p: endpoints, objects (basis scaled to unit length), and the
+// start point (t_init mapped to unit-vector coordinates, or 0). Returns
+// false for an invalid path (its state is still finite and harmless).
+template <int NO>
+__device__ __forceinline__ bool load_path32(const SolveArgs& A, int64_t p,
+                                            Geo32<NO>& G, float (*t0)[2]) {
+  bool valid = true;
+  int32_t s = A.src[p], e = A.dst[p];
+  valid = valid && s >= 0 && s < A.Q && e >= 0 && e < A.Q;
+  s = valid ? s : 0;
+  e = valid ? e : 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    G.tx[c] = A.pts[(int64_t)c * A.Q + s];
+    G.rx[c] = A.pts[(int64_t)c * A.Q + e];
+    valid = valid && isfinite(G.tx[c]) && isfinite(G.rx[c]);
+  }
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    int32_t k = A.ids[(int64_t)j * A.N + p];
+    bool kok = k >= 0 && k < A.K;
+    valid = valid && kok;
+    k = kok ? k : 0;
+    float bb[3], a1[3], a2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bb[c] = A.obj[(int64_t)c * A.K + k];
+      a1[c] = A.obj[(int64_t)(3 + c) * A.K + k];
+      a2[c] = A.obj[(int64_t)(6 + c) * A.K + k];
+      valid = valid && isfinite(bb[c]) && isfinite(a1[c]) && isfinite(a2[c]);
+    }
+    bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
+    valid = valid && dot3(a1, a1) > 0.f && (edge || dot3(a2, a2) > 0.f);
+    float i1, i2;
+    basis_inv32(a1, a2, edge, i1, i2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      G.b[j][c] = bb[c];
+      G.a[j][0][c] = a1[c] * i1;
+      G.a[j][1][c] = a2[c] * i2;
+    }
+    float u0 = 0.f, u1 = 0.f;
+    if (A.t_init) {
+      // to unit-vector coordinates: that = t * |a|
+      u0 = A.t_init[(int64_t)(2 * j) * A.N + p] * rcp32(i1);
+      u1 = edge ? 0.f : A.t_init[(int64_t)(2 * j + 1) * A.N + p] * rcp32(i2);
+      if (!isfinite(u0)) u0 = 0.f;
+      if (!isfinite(u1)) u1 = 0.f;
+    }
+    t0[j][0] = u0;
+    t0[j][1] = u1;
+  }
+  if (A.order) valid = valid && (int)A.order[p] == NO;
+  return valid;
+}
+
+template <int M, int HP>
+__device__ __forceinline__ void set_identity(float* H) {
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int b = a; b < M; ++b) H[pk(M, a, b)] = (a == b) ? 1.f : 0.f;
+}
+
+// T = t0, H = I, gradient and first direction P = -g.
+template <int NO>
+__device__ __forceinline__ void init_state(const Geo32<NO>& G,
+                                           const float (*t0)[2],
+                                           State32<NO>& S) {
+  constexpr int M = State32<NO>::M, HP = State32<NO>::HP;
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    S.T[2 * j] = t0[j][0];
+    S.T[2 * j + 1] = t0[j][1];
+  }
+  set_identity<M, HP>(S.H);
+  grad32<NO>(G, S.T, S.g, S.r, S.l2, S.il);
+#pragma unroll
+  for (int k = 0; k < M; ++k) S.P[k] = -S.g[k];
+}
+
+// One BFGS iteration (Sec. III-C): step size by the fixed-point iteration of
+// Eq. 6 (from the unit step, with the majorant step from 0 as fallback),
+// step, new gradient, inverse-Hessian update. Returns the squared largest
+// point displacement of the step.
+template <int NO>
+__device__ __forceinline__ float bfgs_iter(const Geo32<NO>& G, State32<NO>& S,
+                                           int fp_iters) {
+  constexpr int M = State32<NO>::M, HP = State32<NO>::HP;
+  // direction in point space: q_j = A_j p_j; segment change D_i
+  float q[NO][3];
+#pragma unroll
+  for (int j = 0; j < NO; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      q[j][c] = fmaf(S.P[2 * j + 1], G.a[j][1][c], S.P[2 * j] * G.a[j][0][c]);
+  float dr[NO + 1], dd[NO + 1];
+  float num0 = 0.f, den0 = 0.f, phi0 = 0.f;
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+    float Dv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      Dv[c] = ((i == NO) ? 0.f : q[i][c]) - ((i == 0) ? 0.f : q[i - 1][c]);
+    dr[i] = dot3(Dv, S.r[i]);
+    dd[i] = dot3(Dv, Dv);
+    num0 = fmaf(dr[i], S.il[i], num0);
+    den0 = fmaf(dd[i], S.il[i], den0);
+    phi0 = fmaf(S.l2[i], S.il[i], phi0);
+  }
+  // Eq. 6 started at alpha = 0: one step is the majorant minimiser
+  float a_mm = (den0 > 1e-30f) ? -num0 * rcp32(den0) : 0.f;
+  if (!isfinite(a_mm)) a_mm = 0.f;
+  // Eq. 6 iterated from the unit step
+  float alpha = 1.f;
+  for (int f = 0; f < fp_iters; ++f) {
+    float num = 0.f, den = 0.f;
+#pragma unroll
+    for (int i = 0; i <= NO; ++i) {
+      float rho2 = fmaxf(fmaf(alpha, fmaf(alpha, dd[i], 2.f * dr[i]), S.l2[i]), 1e-30f);
+      float ir = rsq32(rho2);
+      num = fmaf(dr[i], ir, num);
+      den = fmaf(dd[i], ir, den);
+    }
+    alpha = (den > 1e-30f) ? -num * rcp32(den) : 0.f;
+  }
+  // keep it only if it shortens the path
+  float phi = 0.f;
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+    float rho2 = fmaxf(fmaf(alpha, fmaf(alpha, dd[i], 2.f * dr[i]), S.l2[i]), 1e-30f);
+    phi = fmaf(rho2, rsq32(rho2), phi);
+  }
+  if (!(phi < phi0) || !(alpha > 0.f) || !isfinite(alpha)) alpha = a_mm;
+  // step, new gradient
+  float s[M], gn[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    s[k] = alpha * S.P[k];
+    S.T[k] += s[k];
+  }
+  grad32<NO>(G, S.T, gn, S.r, S.l2, S.il);
+  // BFGS inverse update (Nocedal & Wright eq. 6.17), with
+  // H y = H g' - H g = H g' + P
+  float Hg[M], Hy[M], y[M];
+  symv<M>(S.H, gn, Hg);
+  float sy = 0.f, yHy = 0.f, ss = 0.f, yy = 0.f;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    y[k] = gn[k] - S.g[k];
+    Hy[k] = Hg[k] + S.P[k];
+    sy = fmaf(s[k], y[k], sy);
+    yHy = fmaf(y[k], Hy[k], yHy);
+    ss = fmaf(s[k], s[k], ss);
+    yy = fmaf(y[k], y[k], yy);
+  }
+  bool upd = (sy > 1e-30f) && (sy * sy > 1e-12f * ss * yy) && isfinite(yHy);
+  float rho = upd ? rcp32(sy) : 0.f;
+  float c1 = rho * fmaf(rho, yHy, 1.f);
+  float w[M], v[M];
+  float wg = 0.f, sg = 0.f;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    v[k] = -rho * Hy[k];
+    w[k] = fmaf(c1, s[k], v[k]);
+    wg = fmaf(w[k], gn[k], wg);
+    sg = fmaf(s[k], gn[k], sg);
+  }
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int b = a; b < M; ++b)
+      S.H[pk(M, a, b)] = fmaf(v[a], s[b], fmaf(s[a], w[b], S.H[pk(M, a, b)]));
+  float pp = 0.f;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    S.P[k] = -fmaf(v[k], sg, fmaf(s[k], wg, Hg[k]));
+    S.g[k] = gn[k];
+    pp = fmaf(S.P[k], S.P[k], pp);
+  }
+  if (!(pp < 1e30f)) {
+    // overflow or NaN in the update: restart from the identity
+    set_identity<M, HP>(S.H);
+#pragma unroll
+    for (int k = 0; k < M; ++k) S.P[k] = -S.g[k];
+  }
+  float m2 = 0.f;
+#pragma unroll
+  for (int j = 0; j < NO; ++j) m2 = fmaxf(m2, dot3(q[j], q[j]));
+  return alpha * alpha * m2;
+}
+
+// hands a path over to the refinement kernel: unit-vector parameters,
+// iteration count, validity
+template <int NO>
+__device__ __forceinline__ void store_phase1(const SolveArgs& A, int64_t p,
+                                             const State32<NO>& S, int it,
+                                             bool valid) {
+#pragma unroll
+  for (int k = 0; k < 2 * NO; ++k) A.t[(int64_t)k * A.N + p] = S.T[k];
+  A.iters[p] = (uint16_t)(it > 65535 ? 65535 : it);
+  A.status[p] = valid ? 0 : FPT_ST_INVALID;
+}
+
+// Phase 1, fixed iteration count (Sec. III-C runs every path for the same
+// number of iterations so that all lanes finish together).
+template <int NO>
+__global__ __launch_bounds__(kBlock) void bfgs_kernel(
     SolveArgs A, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ bucket) {
-  constexpr int M = 2 * NO;
-  constexpr int HP = M * (M + 1) / 2;
   int64_t begin = 0, count = A.N;
   if (bucket) {
     begin = bucket[NO - 1];
@@ -365,199 +421,113 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
        idx += stride) {
     const int64_t p = perm ? (int64_t)perm[begin + idx] : idx;
-    // ---------------------------------------------------------- gather
-    bool valid = true;
     Geo32<NO> G;
-    {
-      int32_t s = A.src[p], e = A.dst[p];
-      valid = valid && s >= 0 && s < A.Q && e >= 0 && e < A.Q;
-      s = valid ? s : 0;
-      e = valid ? e : 0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        G.tx[c] = A.pts[(int64_t)c * A.Q + s];
-        G.rx[c] = A.pts[(int64_t)c * A.Q + e];
-        valid = valid && isfinite(G.tx[c]) && isfinite(G.rx[c]);
-      }
-    }
-    float tinit[NO][2];
-#pragma unroll
-    for (int j = 0; j < NO; ++j) {
-      int32_t k = A.ids[(int64_t)j * A.N + p];
-      bool kok = k >= 0 && k < A.K;
-      valid = valid && kok;
-      k = kok ? k : 0;
-      float bb[3], a1[3], a2[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        bb[c] = A.obj[(int64_t)c * A.K + k];
-        a1[c] = A.obj[(int64_t)(3 + c) * A.K + k];
-        a2[c] = A.obj[(int64_t)(6 + c) * A.K + k];
-        valid = valid && isfinite(bb[c]) && isfinite(a1[c]) && isfinite(a2[c]);
-      }
-      bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
-      valid = valid && dot3(a1, a1) > 0.f && (edge || dot3(a2, a2) > 0.f);
-      float i1, i2;
-      basis_inv32(a1, a2, edge, i1, i2);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        G.b[j][c] = bb[c];
-        G.a[j][0][c] = a1[c] * i1;
-        G.a[j][1][c] = a2[c] * i2;
-      }
-      float t0 = 0.f, t1 = 0.f;
-      if (A.t_init) {
-        // to unit-vector coordinates: that = t * |a|
-        t0 = A.t_init[(int64_t)(2 * j) * A.N + p] * rcp32(i1);
-        t1 = edge ? 0.f : A.t_init[(int64_t)(2 * j + 1) * A.N + p] * rcp32(i2);
-        if (!isfinite(t0)) t0 = 0.f;
-        if (!isfinite(t1)) t1 = 0.f;
-      }
-      tinit[j][0] = t0;
-      tinit[j][1] = t1;
-    }
-    if (A.order) valid = valid && (int)A.order[p] == NO;
-    // ---------------------------------------------------- FP32 BFGS phase
-    float T[M], g[M], P[M], H[HP];
-#pragma unroll
-    for (int j = 0; j < NO; ++j) {
-      T[2 * j] = tinit[j][0];
-      T[2 * j + 1] = tinit[j][1];
-    }
-#pragma unroll
-    for (int a = 0; a < M; ++a)
-#pragma unroll
-      for (int b = a; b < M; ++b) H[pk(M, a, b)] = (a == b) ? 1.f : 0.f;
-    float r[NO + 1][3], l2[NO + 1], il[NO + 1];
-    grad32<NO>(G, T, g, r, l2, il);
-#pragma unroll
-    for (int k = 0; k < M; ++k) P[k] = -g[k];
-    int it = 0;
-    for (; it < A.n_iter; ++it) {
-      // direction in point space: q_j = A_j p_j; segment change D_i
-      float q[NO][3];
-#pragma unroll
-      for (int j = 0; j < NO; ++j)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          q[j][c] = fmaf(P[2 * j + 1], G.a[j][1][c], P[2 * j] * G.a[j][0][c]);
-      float dr[NO + 1], dd[NO + 1];
-      float num0 = 0.f, den0 = 0.f, phi0 = 0.f;
-#pragma unroll
-      for (int i = 0; i <= NO; ++i) {
-        float Dv[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          Dv[c] = ((i == NO) ? 0.f : q[i][c]) - ((i == 0) ? 0.f : q[i - 1][c]);
-        dr[i] = dot3(Dv, r[i]);
-        dd[i] = dot3(Dv, Dv);
-        num0 = fmaf(dr[i], il[i], num0);
-        den0 = fmaf(dd[i], il[i], den0);
-        phi0 = fmaf(l2[i], il[i], phi0);
-      }
-      // Eq. 6 started at alpha = 0: one step is the majorant minimiser
-      float a_mm = (den0 > 1e-30f) ? -num0 * rcp32(den0) : 0.f;
-      if (!isfinite(a_mm)) a_mm = 0.f;
-      // Eq. 6 iterated from the unit step
-      float alpha = 1.f;
-      for (int f = 0; f < A.fp_iters; ++f) {
-        float num = 0.f, den = 0.f;
-#pragma unroll
-        for (int i = 0; i <= NO; ++i) {
-          float rho2 = fmaxf(fmaf(alpha, fmaf(alpha, dd[i], 2.f * dr[i]), l2[i]), 1e-30f);
-          float ir = rsq32(rho2);
-          num = fmaf(dr[i], ir, num);
-          den = fmaf(dd[i], ir, den);
-        }
-        alpha = (den > 1e-30f) ? -num * rcp32(den) : 0.f;
-      }
-      // keep it only if it shortens the path
-      float phi = 0.f;
-#pragma unroll
-      for (int i = 0; i <= NO; ++i) {
-        float rho2 = fmaxf(fmaf(alpha, fmaf(alpha, dd[i], 2.f * dr[i]), l2[i]), 1e-30f);
-        phi = fmaf(rho2, rsq32(rho2), phi);
-      }
-      if (!(phi < phi0) || !(alpha > 0.f) || !isfinite(alpha)) alpha = a_mm;
-      // step, new gradient
-      float s[M], gn[M];
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        s[k] = alpha * P[k];
-        T[k] += s[k];
-      }
-      grad32<NO>(G, T, gn, r, l2, il);
-      // BFGS inverse update (Nocedal & Wright eq. 6.17), with
-      // H y = H g' - H g = H g' + P
-      float Hg[M], Hy[M], y[M];
-      symv<M>(H, gn, Hg);
-      float sy = 0.f, yHy = 0.f, ss = 0.f, yy = 0.f;
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        y[k] = gn[k] - g[k];
-        Hy[k] = Hg[k] + P[k];
-        sy = fmaf(s[k], y[k], sy);
-        yHy = fmaf(y[k], Hy[k], yHy);
-        ss = fmaf(s[k], s[k], ss);
-        yy = fmaf(y[k], y[k], yy);
-      }
-      bool upd = (sy > 1e-30f) && (sy * sy > 1e-12f * ss * yy) &&
-                 isfinite(yHy);
-      float rho = upd ? rcp32(sy) : 0.f;
-      float c1 = rho * fmaf(rho, yHy, 1.f);
-      float w[M], v[M];
-      float wg = 0.f, sg = 0.f;
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        v[k] = -rho * Hy[k];
-        w[k] = fmaf(c1, s[k], v[k]);
-        wg = fmaf(w[k], gn[k], wg);
-        sg = fmaf(s[k], gn[k], sg);
-      }
-#pragma unroll
-      for (int a = 0; a < M; ++a)
-#pragma unroll
-        for (int b = a; b < M; ++b)
-          H[pk(M, a, b)] = fmaf(v[a], s[b], fmaf(s[a], w[b], H[pk(M, a, b)]));
-      float pp = 0.f;
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        P[k] = -fmaf(v[k], sg, fmaf(s[k], wg, Hg[k]));
-        g[k] = gn[k];
-        pp = fmaf(P[k], P[k], pp);
-      }
-      if (!(pp < 1e30f)) {
-        // overflow or NaN in the update: restart from the identity
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-#pragma unroll
-          for (int b = a; b < M; ++b) H[pk(M, a, b)] = (a == b) ? 1.f : 0.f;
-#pragma unroll
-        for (int k = 0; k < M; ++k) P[k] = -g[k];
-      }
-      if (A.early_exit) {
-        float m2 = 0.f;
-#pragma unroll
-        for (int j = 0; j < NO; ++j) m2 = fmaxf(m2, dot3(q[j], q[j]));
-        bool done = !(alpha * alpha * m2 > A.exit_d2);
-        if (__all(done || !valid)) {
-          ++it;
-          break;
+    float t0[NO][2];
+    bool valid = load_path32<NO>(A, p, G, t0);
+    State32<NO> S;
+    init_state<NO>(G, t0, S);
+    for (int it = 0; it < A.n_iter; ++it) bfgs_iter<NO>(G, S, A.fp_iters);
+    store_phase1<NO>(A, p, S, A.n_iter, valid);
+  }
+}
+
+// Phase 1 with per-lane early exit and refill. Each lane runs its path until
+// two consecutive steps move no point by more than exit_rtol * scale (or the
+// iteration cap), hands it over, and takes the next unclaimed path of the
+// bucket. Claims are made per wavefront: a ballot counts the idle lanes and
+// one atomic on the bucket's work cursor reserves that many consecutive
+// paths. Idle lanes wait until at least refill_min of them are idle or
+// refill_every iterations have passed, so that the divergent reload is
+// amortised. A wavefront leaves when the cursor is past the bucket and none
+// of its lanes holds a path; every path takes at most n_iter iterations, so
+// every wavefront reaches that point.
+template <int NO>
+__global__ __launch_bounds__(kBlock) void bfgs_refill_kernel(
+    SolveArgs A, const int32_t* __restrict__ perm,
+    const int64_t* __restrict__ bucket, unsigned long long* __restrict__ work) {
+  int64_t begin = 0, count = A.N;
+  if (bucket) {
+    begin = bucket[NO - 1];
+    count = bucket[NO] - begin;
+  }
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  Geo32<NO> G;
+  State32<NO> S;
+  bool have = false, valid = false, exhausted = false;
+  int64_t p = 0;
+  int it = 0, streak = 0, since = 0;
+  while (true) {
+    const unsigned long long idle = __ballot(!have);
+    const int n_idle = __popcll(idle);
+    if (n_idle > 0 && !exhausted &&
+        (n_idle >= A.refill_min || since >= A.refill_every || n_idle == 64)) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(work + NO, (unsigned long long)n_idle);
+      base = __shfl(base, 0);
+      if (base + (unsigned long long)n_idle >= (unsigned long long)count)
+        exhausted = true;
+      if (!have) {
+        unsigned long long idx = base + (unsigned long long)__popcll(idle & below);
+        if (idx < (unsigned long long)count) {
+          p = perm ? (int64_t)perm[begin + (int64_t)idx] : (int64_t)idx;
+          float t0[NO][2];
+          valid = load_path32<NO>(A, p, G, t0);
+          init_state<NO>(G, t0, S);
+          have = true;
+          it = 0;
+          streak = 0;
         }
       }
+      since = 0;
     }
-    // --------------------------------------------------- FP64 refinement
+    if (!__any(have)) break;
+    if (have && it >= A.n_iter) {
+      store_phase1<NO>(A, p, S, it, valid);
+      have = false;
+    }
+    if (have) {
+      float d2 = bfgs_iter<NO>(G, S, A.fp_iters);
+      ++it;
+      streak = (d2 <= A.exit_d2) ? streak + 1 : 0;
+      if (streak >= 2 || it >= A.n_iter) {
+        store_phase1<NO>(A, p, S, it, valid);
+        have = false;
+      }
+    }
+    ++since;
+  }
+}
+
+// Phase 2: FP64 refinement of the parameters left by bfgs_kernel in A.t
+// (unit-vector coordinates), certificate, and the final outputs.
+template <int NO>
+__global__ __launch_bounds__(kBlock) void refine_kernel(
+    SolveArgs A, const int32_t* __restrict__ perm,
+    const int64_t* __restrict__ bucket) {
+  int64_t begin = 0, count = A.N;
+  if (bucket) {
+    begin = bucket[NO - 1];
+    count = bucket[NO] - begin;
+  }
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const float qnan = __builtin_nanf("");
+  for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
+       idx += stride) {
+    const int64_t p = perm ? (int64_t)perm[begin + idx] : idx;
+    const bool valid = (A.status[p] & FPT_ST_INVALID) == 0;
     Geo64<NO> D;
     float inv[NO][2];
     load_geo64<NO>(A, p, D, inv);
     double td[2 * NO];
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
-      td[2 * j] = (double)T[2 * j] * (double)inv[j][0];
-      td[2 * j + 1] = D.edge[j] ? 0.0 : (double)T[2 * j + 1] * (double)inv[j][1];
+      float t0 = A.t[(int64_t)(2 * j) * A.N + p];
+      float t1 = A.t[(int64_t)(2 * j + 1) * A.N + p];
+      td[2 * j] = (double)t0 * (double)inv[j][0];
+      td[2 * j + 1] = D.edge[j] ? 0.0 : (double)t1 * (double)inv[j][1];
     }
     RefineOut ro = refine64<NO>(D, td, A);
-    // ---------------------------------------------------------- store
     double xs[NO][3];
     points64<NO>(D, td, xs);
     double Lx = 0.0, minl2 = INFINITY;
@@ -584,7 +554,6 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(
       if (minl2 < cs * cs) st |= FPT_ST_COLLAPSED;
       if (!finite) st |= FPT_ST_NONFINITE;
     }
-    const float qnan = __builtin_nanf("");
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
 #pragma unroll
@@ -601,7 +570,6 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(
     }
     A.len[p] = valid ? (float)Lx : qnan;
     A.status[p] = st;
-    A.iters[p] = (uint16_t)(it > 65535 ? 65535 : it);
   }
 }
 
@@ -698,35 +666,53 @@ __global__ __launch_bounds__(kBlock) void invalid_kernel(
 // ------------------------------------------------------------- launch -----
 
 template <int NO>
-static hipError_t launch_solve_order(const SolveArgs& A, const int32_t* perm,
-                                     const int64_t* bucket, int grid,
-                                     hipStream_t st) {
-  hipLaunchKernelGGL(solve_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
-                     perm, bucket);
+static hipError_t launch_phase(int phase, const SolveArgs& A,
+                               const int32_t* perm, const int64_t* bucket,
+                               unsigned long long* work, int grid,
+                               hipStream_t st) {
+  if (phase == 0)
+    hipLaunchKernelGGL(bfgs_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
+                       perm, bucket);
+  else if (phase == 1)
+    hipLaunchKernelGGL(refine_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
+                       perm, bucket);
+  else
+    hipLaunchKernelGGL(bfgs_refill_kernel<NO>, dim3(grid), dim3(kBlock), 0,
+                       st, A, perm, bucket, work);
   return hipGetLastError();
 }
 
-hipError_t launch_solve(int order, const SolveArgs& A, const int32_t* perm,
-                        const int64_t* bucket, int grid, hipStream_t st) {
+// phase 0: bfgs_kernel<order>, 1: refine_kernel<order>,
+// 2: bfgs_refill_kernel<order> (needs the zeroed work cursors)
+hipError_t launch_solve(int phase, int order, const SolveArgs& A,
+                        const int32_t* perm, const int64_t* bucket,
+                        unsigned long long* work, int grid, hipStream_t st) {
   switch (order) {
-    case 1: return launch_solve_order<1>(A, perm, bucket, grid, st);
-    case 2: return launch_solve_order<2>(A, perm, bucket, grid, st);
-    case 3: return launch_solve_order<3>(A, perm, bucket, grid, st);
-    case 4: return launch_solve_order<4>(A, perm, bucket, grid, st);
-    case 5: return launch_solve_order<5>(A, perm, bucket, grid, st);
-    case 6: return launch_solve_order<6>(A, perm, bucket, grid, st);
+    case 1: return launch_phase<1>(phase, A, perm, bucket, work, grid, st);
+    case 2: return launch_phase<2>(phase, A, perm, bucket, work, grid, st);
+    case 3: return launch_phase<3>(phase, A, perm, bucket, work, grid, st);
+    case 4: return launch_phase<4>(phase, A, perm, bucket, work, grid, st);
+    case 5: return launch_phase<5>(phase, A, perm, bucket, work, grid, st);
+    case 6: return launch_phase<6>(phase, A, perm, bucket, work, grid, st);
   }
   return hipErrorInvalidValue;
 }
 
-const void* solve_kernel_ptr(int order) {
+template <int NO>
+static const void* phase_ptr(int phase) {
+  return phase == 0 ? (const void*)bfgs_kernel<NO>
+         : phase == 1 ? (const void*)refine_kernel<NO>
+                      : (const void*)bfgs_refill_kernel<NO>;
+}
+
+const void* solve_kernel_ptr(int phase, int order) {
   switch (order) {
-    case 1: return (const void*)solve_kernel<1>;
-    case 2: return (const void*)solve_kernel<2>;
-    case 3: return (const void*)solve_kernel<3>;
-    case 4: return (const void*)solve_kernel<4>;
-    case 5: return (const void*)solve_kernel<5>;
-    case 6: return (const void*)solve_kernel<6>;
+    case 1: return phase_ptr<1>(phase);
+    case 2: return phase_ptr<2>(phase);
+    case 3: return phase_ptr<3>(phase);
+    case 4: return phase_ptr<4>(phase);
+    case 5: return phase_ptr<5>(phase);
+    case 6: return phase_ptr<6>(phase);
   }
   return nullptr;
 }

@@ -41,7 +41,8 @@ class _Opts(ctypes.Structure):
                 ("scale", ctypes.c_float), ("n_levels", ctypes.c_int32),
                 ("level_eps", ctypes.c_float * FPT_MAX_LEVELS),
                 ("level_steps", ctypes.c_int32 * FPT_MAX_LEVELS),
-                ("cert_rtol", ctypes.c_float)]
+                ("cert_rtol", ctypes.c_float),
+                ("refill_min", ctypes.c_int32), ("refill_every", ctypes.c_int32)]
 
 
 class _Out(ctypes.Structure):
@@ -50,7 +51,10 @@ class _Out(ctypes.Structure):
 
 
 EXPORTED = ["fpt_default_opts", "fpt_create", "fpt_destroy", "fpt_solve",
-            "fpt_grad", "fpt_last_error"]
+            "fpt_grad", "fpt_last_error", "fpt_set_timing", "fpt_kernel_times"]
+
+# timer slots of fpt_kernel_times
+T_BUCKET, T_BFGS, T_REFINE, T_GRAD, T_REDUCE, TIMERS = 0, 1, 7, 13, 14, 16
 
 _lib = None
 
@@ -79,6 +83,10 @@ def load_library(path: str = LIB_PATH):
                              ctypes.POINTER(_Paths), ctypes.POINTER(_Out),
                              _P, _P, _P, _P, _P, _P, _P]
     lib.fpt_grad.restype = ctypes.c_int
+    lib.fpt_set_timing.argtypes = [_P, ctypes.c_int]
+    lib.fpt_set_timing.restype = ctypes.c_int
+    lib.fpt_kernel_times.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
+    lib.fpt_kernel_times.restype = ctypes.c_int
     lib.fpt_last_error.argtypes = []
     lib.fpt_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -106,6 +114,8 @@ class Opts:
     level_eps: list = field(default_factory=lambda: [1e-3, 1e-5, 1e-7, 1e-9])
     level_steps: list = field(default_factory=lambda: [2, 2, 2, 3])
     cert_rtol: float = 1e-5
+    refill_min: int = 8
+    refill_every: int = 4
 
     def to_c(self) -> _Opts:
         o = _Opts()
@@ -124,6 +134,8 @@ class Opts:
             o.level_eps[i] = float(self.level_eps[i]) if i < o.n_levels else 0.0
             o.level_steps[i] = int(self.level_steps[i]) if i < o.n_levels else 0
         o.cert_rtol = float(self.cert_rtol)
+        o.refill_min = int(self.refill_min)
+        o.refill_every = int(self.refill_every)
         return o
 
 
@@ -156,6 +168,29 @@ class DeviceBatch:
                       if with_order else None)
         self.t_init = None
 
+    @classmethod
+    def from_tensors(cls, obj, pts, src, dst, ids, order=None, S=1.0,
+                     t_init=None):
+        """Wraps existing device tensors (no copy)."""
+        self = cls.__new__(cls)
+        self.batch = None
+        self.obj, self.pts, self.src, self.dst = obj, pts, src, dst
+        self.ids, self.order, self.t_init = ids, order, t_init
+        self.N = int(src.shape[0])
+        self.n_max = int(ids.shape[0])
+        self.K = int(obj.shape[1])
+        self.Q = int(pts.shape[1])
+        self.S = float(S)
+        for name, tns, dt in (("obj", obj, "float32"), ("pts", pts, "float32"),
+                              ("src", src, "int32"), ("dst", dst, "int32"),
+                              ("ids", ids, "int32")):
+            if str(tns.dtype) != "torch." + dt or not tns.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {dt} tensor")
+        if order is not None and (str(order.dtype) != "torch.uint8"
+                                  or not order.is_contiguous()):
+            raise ValueError("order must be a contiguous uint8 tensor")
+        return self
+
     def c_scene(self) -> _Scene:
         return _Scene(self.K, _ptr(self.obj), self.Q, _ptr(self.pts))
 
@@ -184,6 +219,16 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+    def set_timing(self, enable: bool = True):
+        _check(load_library().fpt_set_timing(self._h, 1 if enable else 0),
+               "fpt_set_timing")
+
+    def kernel_times(self):
+        """Mean ms per timer slot since the last read (-1 = unused)."""
+        ms = (ctypes.c_float * TIMERS)()
+        _check(load_library().fpt_kernel_times(self._h, ms), "fpt_kernel_times")
+        return [float(v) for v in ms]
 
     def alloc_out(self, db: DeviceBatch):
         import torch

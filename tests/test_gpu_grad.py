@@ -1,0 +1,190 @@
+"""Parity of the implicit-differentiation backward kernel (fpt_grad, through
+the C ABI) with the oracle's IFT gradient and with finite differences of the
+oracle's solve (Sec. III-D)."""
+import numpy as np
+import pytest
+
+import gpu_util
+from paper_2510_16172_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2510_16172_amd import fpt
+    s = fpt.Solver(0)
+    yield s
+    s.close()
+
+
+def _fwd_grad(solver, b, g_len, g_x, iters=128, with_order=True):
+    """GPU forward + backward; per-path (g_slot, g_end) and reduced grads."""
+    import torch
+    from paper_2510_16172_amd import fpt
+    db = fpt.DeviceBatch(b, with_order=with_order)
+    out = solver.solve(db, fpt.Opts(scale=b.S, iters=iters))
+    gl = torch.from_numpy(np.ascontiguousarray(g_len, np.float32)).cuda()
+    gx = torch.from_numpy(np.ascontiguousarray(g_x, np.float32)).cuda()
+    g_slot = torch.empty((b.n_max, 9, b.N), dtype=torch.float32, device="cuda")
+    g_end = torch.empty((6, b.N), dtype=torch.float32, device="cuda")
+    g_pts, g_obj = solver.grad(db, out, g_len=gl, g_x=gx, g_slot=g_slot,
+                               g_end=g_end)
+    torch.cuda.synchronize()
+    o = {k: v.cpu().numpy() for k, v in out.items()}
+    return o, g_slot.cpu().numpy(), g_end.cpu().numpy(), g_pts.cpu().numpy(), g_obj.cpu().numpy()
+
+
+def _compare_per_path(b, o, g_slot, g_end, ref, gref, mask, rtol):
+    """GPU per-path gradients vs the oracle's at the oracle's solution, on
+    paths in `mask`; tolerance relative to each path's largest entry."""
+    n = b.n_max
+    gs = np.transpose(g_slot, (2, 0, 1))           # N, n, 9
+    ge = g_end.T                                    # N, 6
+    want_slot = np.concatenate([gref["g_b"], gref["g_a"].reshape(b.N, n, 6)], -1)
+    want_end = np.concatenate([gref["g_tx"], gref["g_rx"]], -1)
+    bad = 0
+    for i in np.nonzero(mask)[0]:
+        k = int(b.order[i])
+        w = np.concatenate([want_slot[i, :k].ravel(), want_end[i]])
+        g = np.concatenate([gs[i, :k].ravel(), ge[i]])
+        scale = 1.0 + np.abs(w).max()
+        if not np.all(np.abs(g - w) <= rtol * scale):
+            bad += 1
+    return bad
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6])
+def test_grad_vs_oracle_canyon(solver, oracle_mod, n):
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 3000, seed=5000 + n, n=n)
+    g_len, g_x = scenes.upstream_grads(b.N, b.n_max, seed=5100 + n)
+    o, g_slot, g_end, g_pts, g_obj = _fwd_grad(solver, b, g_len, g_x)
+    ref = oracle_mod.solve(b, threads=8)
+    gref = oracle_mod.grad(b, ref["t"], g_len.astype(np.float64),
+                           np.transpose(g_x, (2, 0, 1)).astype(np.float64), threads=8)
+    s = gpu_util.summary(b, o, ref)
+    from paper_2510_16172_amd import fpt
+    col_gpu = (o["status"] & fpt.ST_COLLAPSED) != 0
+    # well-posed paths: certified on the GPU, smooth and unique per the oracle
+    mask = s["cert"] & ~s["col"] & ~s["ill"] & (gref["status"] == 0) & ~col_gpu
+    assert mask.mean() > {1: 0.95, 2: 0.75, 3: 0.6, 4: 0.45, 6: 0.25}[n]
+    bad = _compare_per_path(b, o, g_slot, g_end, ref, gref, mask, rtol=2e-3)
+    print(f"n={n} compared={mask.sum()} bad={bad}", flush=True)
+    assert bad <= max(1, int(0.002 * mask.sum()))
+    # skipped paths contribute exactly zero
+    skip = (o["status"] & (fpt.ST_COLLAPSED | fpt.ST_INVALID | fpt.ST_NONFINITE)) != 0
+    assert np.all(g_slot[:, :, skip] == 0) and np.all(g_end[:, skip] == 0)
+
+
+def test_grad_reduction_matches_per_path_sum(solver):
+    """g_obj / g_pts equal the sums of the per-path outputs (float atomics:
+    to rounding), for the LDS-accumulated canyon tables."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 20000, seed=5200, n=None, n_max=4)
+    g_len, g_x = scenes.upstream_grads(b.N, b.n_max, seed=5201)
+    o, g_slot, g_end, g_pts, g_obj = _fwd_grad(solver, b, g_len, g_x, iters=64)
+    want_obj = np.zeros((9, b.K))
+    want_pts = np.zeros((3, b.Q))
+    for j in range(b.n_max):
+        act = b.order > j
+        for r in range(9):
+            np.add.at(want_obj[r], b.ids[j, act], g_slot[j, r, act].astype(np.float64))
+    for c in range(3):
+        np.add.at(want_pts[c], b.src, g_end[c].astype(np.float64))
+        np.add.at(want_pts[c], b.dst, g_end[3 + c].astype(np.float64))
+    sc_obj = 1.0 + np.abs(want_obj).max()
+    sc_pts = 1.0 + np.abs(want_pts).max()
+    np.testing.assert_allclose(g_obj, want_obj, atol=2e-5 * sc_obj)
+    np.testing.assert_allclose(g_pts, want_pts, atol=2e-5 * sc_pts)
+    # edges' padded a2 rows receive nothing
+    edge = np.all(b.obj[6:9] == 0, axis=0)
+    assert np.all(g_obj[6:9, edge] == 0)
+
+
+def test_grad_global_atomics_path(solver, oracle_mod):
+    """Per-path geometry (K = N n objects: too large for the LDS tables) uses
+    global atomics; checked against the oracle gradient."""
+    b = scenes.random_paths(4000, 3, seed=5300)
+    g_len, g_x = scenes.upstream_grads(b.N, b.n_max, seed=5301)
+    o, g_slot, g_end, g_pts, g_obj = _fwd_grad(solver, b, g_len, g_x,
+                                               with_order=False)
+    ref = oracle_mod.solve(b, threads=8)
+    gref = oracle_mod.grad(b, ref["t"], g_len.astype(np.float64),
+                           np.transpose(g_x, (2, 0, 1)).astype(np.float64), threads=8)
+    s = gpu_util.summary(b, o, ref)
+    mask = s["cert"] & ~s["col"] & ~s["ill"] & (gref["status"] == 0)
+    bad = _compare_per_path(b, o, g_slot, g_end, ref, gref, mask, rtol=2e-3)
+    assert bad <= max(1, int(0.002 * mask.sum()))
+    # each object belongs to one path: the reduced table is the per-path one
+    for j in range(3):
+        np.testing.assert_allclose(g_obj[:, b.ids[j]], g_slot[j], atol=1e-6,
+                                   rtol=1e-6)
+
+
+def test_grad_vs_finite_differences(solver, oracle_mod):
+    """GPU gradient of sum(gl L + gx . x) vs central differences of the FP64
+    oracle's solve (h = 2^-10 m ~ 1e-3 m, Richardson-extrapolated), over all
+    inputs of 64 order-3 canyon paths (each path given its own objects)."""
+    import pins
+    sc = scenes.canyon_scene()
+    b0 = scenes.canyon_sample_paths(sc, 2000, seed=5400, n=3)
+    ref0 = oracle_mod.solve(b0, threads=8)
+    ok0 = np.nonzero(ref0["flags"] == 0)[0]
+    paths = [pins.path_geometry(b0, int(i)) for i in ok0[:64]]
+    b = pins.batch_from_paths(paths, S=b0.S)
+    g_len, g_x = scenes.upstream_grads(b.N, b.n_max, seed=5401)
+    o, g_slot, g_end, g_pts, g_obj = _fwd_grad(solver, b, g_len, g_x)
+    import test_oracle_pins as T
+    gl = g_len.astype(np.float64)
+    gx = np.transpose(g_x, (2, 0, 1)).astype(np.float64)
+    h = 2.0 ** -10
+    d1 = T._fd_grad(oracle_mod, b, gl, gx, h)
+    d2 = T._fd_grad(oracle_mod, b, gl, gx, h / 2)
+    fd_tx, fd_rx, fd_obj = [(4.0 * y - x) / 3.0 for x, y in zip(d1, d2)]
+    from paper_2510_16172_amd import fpt
+    cert = (o["status"] & fpt.ST_CONVERGED) != 0
+    assert cert.mean() > 0.9
+    checked = 0
+    for i in np.nonzero(cert)[0]:
+        want = np.concatenate([fd_tx[i], fd_rx[i], fd_obj[i].ravel()])
+        got = np.concatenate([g_pts[:, b.src[i]], g_pts[:, b.dst[i]],
+                              np.stack([g_obj[:, b.ids[j, i]] for j in range(3)]).ravel()])
+        edge = [np.all(b.obj[6:9, b.ids[j, i]] == 0) for j in range(3)]
+        for j in range(3):
+            if edge[j]:
+                want[6 + 9 * j + 6: 6 + 9 * j + 9] = 0.0
+        scale = 1.0 + np.abs(want).max()
+        np.testing.assert_allclose(got, want, atol=2e-3 * scale)
+        checked += 1
+    assert checked >= 50
+
+
+def test_autograd_function(solver, oracle_mod):
+    import torch
+    from paper_2510_16172_amd import fpt
+    from paper_2510_16172_amd.autograd import fermat_paths
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 2000, seed=5500, n=2)
+    dev = "cuda"
+    pts = torch.from_numpy(b.pts).to(dev).requires_grad_(True)
+    obj = torch.from_numpy(b.obj).to(dev).requires_grad_(True)
+    src = torch.from_numpy(b.src).to(dev)
+    dst = torch.from_numpy(b.dst).to(dev)
+    ids = torch.from_numpy(b.ids).to(dev)
+    opts = fpt.Opts(scale=b.S, iters=128)
+    x, L, st = fermat_paths(pts, obj, src, dst, ids, None, solver, opts)
+    g_len, g_x = scenes.upstream_grads(b.N, b.n_max, seed=5501)
+    w_len = torch.from_numpy(g_len).to(dev)
+    w_x = torch.from_numpy(g_x).to(dev)
+    loss = (w_len * L).sum() + (w_x * x).sum()
+    loss.backward()
+    # same as the direct fpt_grad call
+    o, g_slot, g_end, g_pts, g_obj = _fwd_grad(solver, b, g_len, g_x, with_order=False)
+    np.testing.assert_allclose(obj.grad.cpu().numpy(), g_obj, rtol=1e-4,
+                               atol=1e-4 * (1 + np.abs(g_obj).max()))
+    np.testing.assert_allclose(pts.grad.cpu().numpy(), g_pts, rtol=1e-4,
+                               atol=1e-4 * (1 + np.abs(g_pts).max()))

@@ -199,3 +199,34 @@ def test_full_canyon_order2_sampled(solver, oracle_mod):
     g = {k: (v.cpu().numpy()[..., idx] if v.dim() > 1 else v.cpu().numpy()[idx])
          for k, v in out.items()}
     _check_common(sub, g, ref, min_ok=0.98)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6])
+def test_early_exit_refill_parity(solver, oracle_mod, n):
+    """Per-lane early exit with refill: each lane stops its path after two
+    small steps and takes the next one; same accuracy bar as fixed counts."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 3000, seed=4100 + n, n=n)
+    ref = oracle_mod.solve(b, threads=8)
+    g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=128, early_exit=True))
+    _check_common(b, g, ref, min_ok={1: 0.999, 2: 0.98, 3: 0.93, 4: 0.85,
+                                     5: 0.75, 6: 0.65}[n])
+    it = g["iters"].astype(np.int64)
+    assert it.max() <= 128 and it.min() >= 1
+    print(f"mean iterations {it.mean():.1f}", flush=True)
+    assert it.mean() < 100
+
+
+def test_early_exit_deterministic_and_mixed(solver):
+    """Which lane runs a path depends on timing, the path's arithmetic does
+    not: two runs are bit-identical, also with mixed orders and a ragged
+    bucket tail."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 9999, seed=4200, n=None, n_max=6)
+    opts = _opts(b.S, iters=96, early_exit=True, refill_min=3, refill_every=2)
+    g1 = gpu_util.run_gpu(solver, b, opts)
+    g2 = gpu_util.run_gpu(solver, b, opts)
+    for k in g1:
+        np.testing.assert_array_equal(g1[k], g2[k])
+    from paper_2510_16172_amd import fpt
+    assert np.all(g1["status"] & (fpt.ST_INVALID | fpt.ST_NONFINITE) == 0)
