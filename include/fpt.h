@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-enum { FPT_NMAX = 6, FPT_MAX_LEVELS = 8 };
+enum { FPT_NMAX = 6, FPT_MAX_LEVELS = 8, FPT_MAX_STAGES = 4 };
 
 typedef enum {
   FPT_OK = 0,
@@ -101,7 +101,10 @@ typedef struct {
   int32_t early_exit;   /* 0: every path runs exactly `iters` iterations.
                            1: a path stops after two consecutive steps that
                            move no point by more than exit_rtol * scale (or
-                           after `iters`), and its lane takes the next path */
+                           after `iters` in total); the solver runs in stages
+                           of stage_iters[k] iterations, and the paths still
+                           running after a stage are compacted (with their
+                           BFGS state) for the next one */
   float exit_rtol;
   float scale;          /* scene size S (> 0): unit of every tolerance */
   int32_t n_levels;     /* FP64 refinement levels, 0..FPT_MAX_LEVELS */
@@ -109,13 +112,13 @@ typedef struct {
                                        (0 = exact length) */
   int32_t level_steps[FPT_MAX_LEVELS]; /* Newton steps at each level */
   float cert_rtol;      /* certificate threshold / scale */
-  int32_t refill_min;   /* early exit: refill once this many lanes of a
-                           wavefront are idle (1..64) ... */
-  int32_t refill_every; /* ... or this many iterations have passed (>= 1) */
+  int32_t stage_iters[FPT_MAX_STAGES]; /* early exit: iterations per stage,
+                           0-terminated; the last stage hands over every
+                           path that is still running */
 } fpt_opts;
 
 /* Defaults: 64 iterations, 1 fixed-point iteration, no early exit
- * (exit_rtol = 1e-6, refill_min = 8, refill_every = 4), refinement levels
+ * (exit_rtol = 1e-6, stages of 16, 16 and 32 iterations), refinement levels
  * eps/S = 1e-3, 1e-5, 1e-7 (2 steps each) and 1e-9 (3 steps),
  * cert_rtol = 1e-5, scale = 1. */
 void fpt_default_opts(fpt_opts* opts);
@@ -158,6 +161,36 @@ fpt_status fpt_grad(fpt_handle* h, const fpt_scene* scene,
                     float* g_obj, float* g_slot, float* g_end,
                     void* hip_stream);
 
+/* Launch configuration of the FP32 solver kernel of one order (what the
+ * autotuner chooses). wg_per_cu: resident workgroups per compute unit for
+ * the persistent launches (0 = as many as the kernel's register use allows);
+ * early_exit / stage_iters override the corresponding fpt_opts fields for
+ * paths of that order when use_override is 1. */
+typedef struct {
+  int32_t wg_per_cu;
+  int32_t use_override;
+  int32_t early_exit;
+  int32_t stage_iters[FPT_MAX_STAGES];
+} fpt_launch_cfg;
+
+/* Sets (cfg != NULL) or resets to defaults (cfg == NULL) the configuration
+ * of order `order` (1..6) on this handle. */
+fpt_status fpt_set_launch(fpt_handle* h, int order, const fpt_launch_cfg* cfg);
+
+/* HIP-graph capture of one complete fpt_solve (order bucketing, every
+ * per-order launch, refinement) on a non-default stream. The graph records
+ * the given pointers and options: replays read and write the same buffers.
+ * The handle's workspace is sized before the capture; counters are cleared
+ * by kernels inside the graph (no memset nodes), so a replay can follow any
+ * other work. fpt_graph_launch replays it on `hip_stream`. */
+typedef struct fpt_graph fpt_graph;
+fpt_status fpt_graph_capture(fpt_handle* h, const fpt_scene* scene,
+                             const fpt_paths* paths, const fpt_opts* opts,
+                             const fpt_out* out, void* hip_stream,
+                             fpt_graph** g);
+fpt_status fpt_graph_launch(fpt_graph* g, void* hip_stream);
+fpt_status fpt_graph_destroy(fpt_graph* g);
+
 /* Optional per-kernel timing. While enabled, every kernel (group) that
  * fpt_solve and fpt_grad launch is bracketed by a pair of HIP events recorded
  * on the caller's stream, into a ring of 32 event pairs per slot (no host
@@ -170,6 +203,7 @@ fpt_status fpt_grad(fpt_handle* h, const fpt_scene* scene,
  *   FPT_T_REFINE + n - 1   FP64 refinement kernel of order n
  *   FPT_T_GRAD             implicit-differentiation kernel
  *   FPT_T_REDUCE           per-object gradient reduction
+ *   FPT_T_MLP              learned-initialiser inference
  * Enabling allocates the events (returns FPT_EHIP if that fails). */
 enum {
   FPT_T_BUCKET = 0,
@@ -177,10 +211,47 @@ enum {
   FPT_T_REFINE = 7,
   FPT_T_GRAD = 13,
   FPT_T_REDUCE = 14,
+  FPT_T_MLP = 15,
   FPT_TIMERS = 16
 };
 fpt_status fpt_set_timing(fpt_handle* h, int enable);
 fpt_status fpt_kernel_times(fpt_handle* h, float* ms);
+
+/* Learned initialiser (a better initial candidate, which Sec. V names as
+ * future work): an MLP 66 -> 256 -> 256 -> 256 -> 8 with ReLU that maps the
+ * geometry of an order-4 path to starting parameters for fpt_solve. BF16
+ * MFMA products with FP32 accumulation; FP32 master weights and Adam.
+ * Inputs, per path, all lengths divided by `scale`: TX, RX, and for each of
+ * the 4 interactions b, a1/|a1|, a2/|a2| (0 for an edge), b - TX, b - RX.
+ * Outputs: the 8 parameters in unit-basis coordinates divided by `scale`.
+ *
+ * `state` is a caller-owned device buffer of fpt_mlp_state_floats() floats,
+ * 16-byte aligned (weights, Adam moments, gradient, bf16 copies); its layout
+ * is private. The handle keeps an activation workspace (hipMalloc on growth).
+ * Paths: n_max must be 4; `order` is ignored (every path has order 4). */
+int64_t fpt_mlp_state_floats(void);
+
+/* He-normal weights from a counter-based hash of `seed`, zero biases and
+ * Adam moments. */
+fpt_status fpt_mlp_init(fpt_handle* h, float* state, uint64_t seed,
+                        void* hip_stream);
+
+/* One Adam step (lr, step = 1, 2, ... for the bias correction) on a batch of
+ * N paths (N a multiple of 64, at most 65536). The target is a solver output
+ * on the same paths (`target->t`, `target->status`): the loss is the mean
+ * squared error between prediction and T* (unit-basis coordinates / scale)
+ * over certified paths and non-padded parameters; *loss (a device float) is
+ * incremented by the batch loss. */
+fpt_status fpt_mlp_train_step(fpt_handle* h, float* state,
+                              const fpt_scene* scene, const fpt_paths* paths,
+                              const fpt_out* target, float scale, float lr,
+                              int32_t step, float* loss, void* hip_stream);
+
+/* Predicted start t_init [4][2][N] (caller's parametrisation) for every
+ * path, to pass as paths->t_init to fpt_solve. */
+fpt_status fpt_mlp_infer(fpt_handle* h, const float* state,
+                         const fpt_scene* scene, const fpt_paths* paths,
+                         float scale, float* t_init, void* hip_stream);
 
 /* Thread-local description of the last non-OK status of this thread. */
 const char* fpt_last_error(void);

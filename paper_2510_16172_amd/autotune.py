@@ -1,0 +1,91 @@
+"""Autotuner of the per-order launch configuration of the FP32 solver.
+
+For each order present in a workload it times candidate configurations
+(resident workgroups per CU; fixed iteration count vs per-lane early exit
+in stages) on a sample of that order's paths and keeps the one
+with the most certified-converged paths per second of that order's kernels
+(BFGS + refinement, timed with the library's HIP-event timers). Results are
+cached in a JSON file keyed by GPU architecture, order, and a power-of-two
+bucket of the sample size, and applied with fpt_set_launch.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+DEFAULT_CANDIDATES = [
+    {"wg_per_cu": 0, "early_exit": 0},
+    {"wg_per_cu": 0, "early_exit": 1, "stage_iters": [16, 16, 32]},
+    {"wg_per_cu": 0, "early_exit": 1, "stage_iters": [12, 12, 16, 24]},
+    {"wg_per_cu": 0, "early_exit": 1, "stage_iters": [24, 40]},
+    {"wg_per_cu": 0, "early_exit": 1, "stage_iters": [8, 8, 16, 32]},
+    {"wg_per_cu": 2, "early_exit": 1, "stage_iters": [16, 16, 32]},
+]
+
+
+def default_cache_path() -> str:
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "fpt", "autotune.json")
+
+
+def _key(arch: str, order: int, n: int) -> str:
+    return f"{arch}/order{order}/n2^{max(0, int(np.log2(max(n, 1))))}"
+
+
+def tune(solver, batch, opts, candidates=None, sample=1 << 18, repeats=3,
+         cache_path: str | None = None, seed: int = 0):
+    """Returns {order: cfg} for the orders in `batch` and applies it."""
+    import torch
+    from . import fpt
+    candidates = candidates or DEFAULT_CANDIDATES
+    cache_path = cache_path or default_cache_path()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cache = {}
+    if os.path.exists(cache_path):
+        try:
+            cache = json.load(open(cache_path))
+        except Exception:
+            cache = {}
+    rng = np.random.default_rng(seed)
+    chosen = {}
+    for n in sorted(set(int(v) for v in np.unique(batch.order))):
+        idx = np.nonzero(batch.order == n)[0]
+        key = _key(arch, n, len(idx))
+        if key in cache:
+            chosen[n] = cache[key]["cfg"]
+            continue
+        if len(idx) > sample:
+            idx = np.sort(rng.choice(idx, sample, replace=False))
+        sub = batch.subset(idx)
+        sub = type(sub)(sub.obj, sub.pts, sub.src, sub.dst, sub.order,
+                        np.ascontiguousarray(sub.ids[:n]), sub.S, sub.meta)
+        db = fpt.DeviceBatch(sub, with_order=False)
+        out = solver.alloc_out(db)
+        best, best_rate, results = None, -1.0, []
+        for cfg in candidates:
+            solver.set_launch(n, cfg)
+            solver.solve(db, opts, out=out)  # warm-up
+            torch.cuda.synchronize()
+            solver.set_timing(True)
+            for _ in range(repeats):
+                solver.solve(db, opts, out=out)
+            kt = solver.kernel_times()
+            solver.set_timing(False)
+            ms = kt[fpt.T_BFGS + n - 1] + kt[fpt.T_REFINE + n - 1]
+            cert = int(((out["status"] & fpt.ST_CONVERGED) != 0).sum().item())
+            rate = cert / (ms * 1e-3)
+            results.append({"cfg": cfg, "ms": ms, "certified": cert, "rate": rate})
+            if rate > best_rate:
+                best, best_rate = cfg, rate
+        chosen[n] = best
+        cache[key] = {"cfg": best, "rate": best_rate, "trials": results}
+    for n, cfg in chosen.items():
+        solver.set_launch(n, cfg)
+    try:
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        json.dump(cache, open(cache_path, "w"), indent=1)
+    except OSError:
+        pass
+    return chosen

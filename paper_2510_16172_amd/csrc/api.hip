@@ -10,12 +10,12 @@
 namespace fpt {
 hipError_t launch_solve(int phase, int order, const SolveArgs& A,
                         const int32_t* perm, const int64_t* bucket,
-                        unsigned long long* work, int grid, hipStream_t st);
+                        const StageArgs* stage, int grid, hipStream_t st);
+int stage_fields_for(int order);
 const void* solve_kernel_ptr(int phase, int order);
 hipError_t launch_bucketing(const uint8_t* order, int64_t N, int n_max,
-                            unsigned long long* counts,
-                            unsigned long long* cursor, int64_t* bucket,
-                            int32_t* perm, int grid, hipStream_t st);
+                            uint32_t* ccount, int64_t* bucket, int32_t* perm,
+                            hipStream_t st);
 hipError_t launch_invalid(const SolveArgs& A, const int32_t* perm,
                           const int64_t* bucket, int grid, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
@@ -26,6 +26,8 @@ const void* grad_kernel_ptr(int order);
 hipError_t launch_grad_invalid(const GradArgs& A, const int32_t* perm,
                                const int64_t* bucket, int grid, hipStream_t st);
 }  // namespace fpt
+#include "mlp_host.h"
+
 
 struct fpt_handle {
   int device;
@@ -38,11 +40,21 @@ struct fpt_handle {
   int nrec[FPT_TIMERS] = {};  // launches recorded since the last read
   // workspace
   int32_t* perm = nullptr;
+  uint32_t* ccount = nullptr;  // per-chunk order counts / offsets
   int64_t perm_cap = 0;
   unsigned long long* counts = nullptr;  // [8]
   unsigned long long* cursor = nullptr;  // [8]
   int64_t* bucket = nullptr;             // [8]
-  unsigned long long* work = nullptr;    // [8] refill cursors per order
+  // early-exit stage lists (ping-pong): region counters, indices, states
+  unsigned long long* scount = nullptr;  // [2][kRegions * kCounterStride]
+  int32_t* slist[2] = {nullptr, nullptr};
+  float* sstate[2] = {nullptr, nullptr};
+  int64_t stage_rcap = 0, stage_state_cap = 0;
+  // per-order launch configuration (autotuner)
+  fpt_launch_cfg cfg[FPT_NMAX + 1] = {};
+  // learned-initialiser activations (grown on demand)
+  fpt::MlpWork mlp = {};
+  void* mlp_mem = nullptr;
 };
 
 static thread_local std::string g_err;
@@ -76,8 +88,10 @@ extern "C" void fpt_default_opts(fpt_opts* o) {
   o->level_steps[2] = 2;
   o->level_steps[3] = 3;
   o->cert_rtol = 1e-5f;
-  o->refill_min = 8;
-  o->refill_every = 4;
+  o->stage_iters[0] = 16;
+  o->stage_iters[1] = 16;
+  o->stage_iters[2] = 32;
+  o->stage_iters[3] = 0;
 }
 
 // Keeps the caller's current device and switches to the handle's for the
@@ -132,7 +146,13 @@ extern "C" fpt_status fpt_create(int device, fpt_handle** out) {
   h->counts = (unsigned long long*)p;
   h->cursor = h->counts + 8;
   h->bucket = (int64_t*)(h->counts + 16);
-  h->work = h->counts + 24;
+  e = hipMalloc(&p, 2 * fpt::kRegions * fpt::kCounterStride * sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    (void)hipFree(h->counts);
+    delete h;
+    return fail(FPT_ENOMEM, "fpt_create: workspace allocation failed");
+  }
+  h->scount = (unsigned long long*)p;
   *out = h;
   return FPT_OK;
 }
@@ -142,7 +162,14 @@ extern "C" fpt_status fpt_destroy(fpt_handle* h) {
   DeviceGuard g(h->device);
   (void)hipDeviceSynchronize();
   if (h->perm) (void)hipFree(h->perm);
+  if (h->ccount) (void)hipFree(h->ccount);
   if (h->counts) (void)hipFree(h->counts);
+  if (h->scount) (void)hipFree(h->scount);
+  if (h->mlp_mem) (void)hipFree(h->mlp_mem);
+  for (int k = 0; k < 2; ++k) {
+    if (h->slist[k]) (void)hipFree(h->slist[k]);
+    if (h->sstate[k]) (void)hipFree(h->sstate[k]);
+  }
   for (int i = 0; i < FPT_TIMERS; ++i)
     for (int r = 0; r < fpt_handle::kRing; ++r)
       for (int k = 0; k < 2; ++k)
@@ -193,25 +220,67 @@ static fpt_status check_opts(const fpt_opts* o) {
   }
   if (!(o->cert_rtol >= 0.f) || !(o->exit_rtol >= 0.f))
     return fail(FPT_EINVAL, "fpt_solve: negative tolerance");
-  if (o->early_exit &&
-      (o->refill_min < 1 || o->refill_min > 64 || o->refill_every < 1))
-    return fail(FPT_EINVAL, "fpt_solve: refill_min outside 1..64 or refill_every < 1");
+  if (o->early_exit) {
+    if (o->stage_iters[0] < 1)
+      return fail(FPT_EINVAL, "fpt_solve: early exit needs stage_iters[0] >= 1");
+    for (int k = 0; k < FPT_MAX_STAGES; ++k)
+      if (o->stage_iters[k] < 0 || o->stage_iters[k] > 65535)
+        return fail(FPT_EINVAL, "fpt_solve: stage_iters outside 0..65535");
+  }
   return FPT_OK;
 }
 
 static fpt_status ensure_perm(fpt_handle* h, int64_t N) {
   if (h->perm_cap >= N) return FPT_OK;
-  if (h->perm) {
-    (void)hipFree(h->perm);
-    h->perm = nullptr;
-    h->perm_cap = 0;
-  }
+  if (h->perm) (void)hipFree(h->perm);
+  if (h->ccount) (void)hipFree(h->ccount);
+  h->perm = nullptr;
+  h->ccount = nullptr;
+  h->perm_cap = 0;
   void* p = nullptr;
   int64_t cap = N < 1024 ? 1024 : N;
   if (hipMalloc(&p, (size_t)cap * sizeof(int32_t)) != hipSuccess)
     return fail(FPT_ENOMEM, "workspace allocation failed");
   h->perm = (int32_t*)p;
+  int64_t nchunks = (cap + fpt::kSortChunk - 1) / fpt::kSortChunk;
+  if (hipMalloc(&p, (size_t)nchunks * 8 * sizeof(uint32_t)) != hipSuccess)
+    return fail(FPT_ENOMEM, "workspace allocation failed");
+  h->ccount = (uint32_t*)p;
   h->perm_cap = cap;
+  return FPT_OK;
+}
+
+// Lists and states of the early-exit stages. A list has kRegions regions
+// of rcap slots; a stage's input chunk of 64 paths appends to one region, so
+// rcap = 64 (ceil(N / 4096) + 1) holds every path. The state is sized for
+// the largest order.
+static int64_t stage_rcap(int64_t N) {
+  return 64 * ((N + 64 * fpt::kRegions - 1) / (64 * fpt::kRegions) + 1);
+}
+
+static fpt_status ensure_stage(fpt_handle* h, int64_t N, int n_max) {
+  const int64_t rcap = stage_rcap(N);
+  const int64_t slots = rcap * fpt::kRegions;
+  const int64_t need = (int64_t)fpt::stage_fields_for(n_max) * slots;
+  if (h->stage_rcap >= rcap && h->stage_state_cap >= need) return FPT_OK;
+  for (int k = 0; k < 2; ++k) {
+    if (h->slist[k]) (void)hipFree(h->slist[k]);
+    if (h->sstate[k]) (void)hipFree(h->sstate[k]);
+    h->slist[k] = nullptr;
+    h->sstate[k] = nullptr;
+  }
+  h->stage_rcap = h->stage_state_cap = 0;
+  for (int k = 0; k < 2; ++k) {
+    void* p = nullptr;
+    if (hipMalloc(&p, (size_t)slots * sizeof(int32_t)) != hipSuccess)
+      return fail(FPT_ENOMEM, "early-exit workspace allocation failed");
+    h->slist[k] = (int32_t*)p;
+    if (hipMalloc(&p, (size_t)need * sizeof(float)) != hipSuccess)
+      return fail(FPT_ENOMEM, "early-exit workspace allocation failed");
+    h->sstate[k] = (float*)p;
+  }
+  h->stage_rcap = rcap;
+  h->stage_state_cap = need;
   return FPT_OK;
 }
 
@@ -318,8 +387,6 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
   A.n_iter = o->iters;
   A.fp_iters = o->fp_iters;
   A.early_exit = o->early_exit ? 1 : 0;
-  A.refill_min = o->refill_min;
-  A.refill_every = o->refill_every;
   float ed = o->exit_rtol * o->scale;
   A.exit_d2 = ed * ed;
   A.scale = o->scale;
@@ -331,48 +398,85 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
   A.cert_abs = o->cert_rtol * o->scale;
 
   hipError_t e;
-  const int p1 = A.early_exit ? 2 : 0;  // phase-1 kernel variant
   int64_t cap = (pa->N + fpt::kBlock - 1) / fpt::kBlock;
-  auto persistent = [&](int ph, int n) -> int {
-    int64_t g = (int64_t)h->num_cu * h->occ[ph][n];
+  auto persistent = [&](int ph, int n, int wg_per_cu) -> int {
+    int64_t g = (int64_t)h->num_cu * (wg_per_cu > 0 ? wg_per_cu : h->occ[ph][n]);
     return (int)(g < cap ? g : cap);
   };
-  if (A.early_exit) {
-    e = fpt::launch_zero_u64(h->work, 8, st);
-    if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
-  }
-  if (!pa->order) {
-    for (int ph : {p1, 1}) {
-      SlotTimer tm(h, (ph == 1 ? FPT_T_REFINE : FPT_T_BFGS) + pa->n_max - 1, st);
-      int grid = (ph == 2) ? persistent(2, pa->n_max) : (int)cap;
-      e = fpt::launch_solve(ph, pa->n_max, A, nullptr, nullptr, h->work, grid, st);
-      if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
-    }
-    return FPT_OK;
-  }
-  s = ensure_perm(h, pa->N);
-  if (s != FPT_OK) return s;
-  int sgrid = h->num_cu * 4;
-  {
-    SlotTimer tm(h, FPT_T_BUCKET, st);
-    e = fpt::launch_zero_u64(h->counts, 8, st);
-    if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
-    e = fpt::launch_bucketing(pa->order, pa->N, pa->n_max, h->counts,
-                              h->cursor, h->bucket, h->perm, sgrid, st);
-    if (e != hipSuccess) return hip_fail(e, "fpt_solve: bucketing launch");
-  }
+  bool any_ee = false;
   for (int n = 1; n <= pa->n_max; ++n) {
-    for (int ph : {p1, 1}) {
-      // persistent: one resident set of workgroups strides over the bucket,
-      // whose size is only known on the device
-      SlotTimer tm(h, (ph == 1 ? FPT_T_REFINE : FPT_T_BFGS) + n - 1, st);
-      e = fpt::launch_solve(ph, n, A, h->perm, h->bucket, h->work,
-                            persistent(ph, n), st);
+    const fpt_launch_cfg& c = h->cfg[n];
+    if (c.use_override ? c.early_exit : A.early_exit) any_ee = true;
+  }
+  if (any_ee) {
+    s = ensure_stage(h, pa->N, pa->n_max);
+    if (s != FPT_OK) return s;
+  }
+  const int32_t* perm = nullptr;
+  const int64_t* bucket = nullptr;
+  if (pa->order) {
+    s = ensure_perm(h, pa->N);
+    if (s != FPT_OK) return s;
+    SlotTimer tm(h, FPT_T_BUCKET, st);
+    e = fpt::launch_bucketing(pa->order, pa->N, pa->n_max, h->ccount,
+                              h->bucket, h->perm, st);
+    if (e != hipSuccess) return hip_fail(e, "fpt_solve: bucketing launch");
+    perm = h->perm;
+    bucket = h->bucket;
+  }
+  // orders to run: all buckets, or only n_max when every path has it
+  const int n_lo = pa->order ? 1 : pa->n_max;
+  for (int n = n_lo; n <= pa->n_max; ++n) {
+    const fpt_launch_cfg& c = h->cfg[n];
+    const bool ee = c.use_override ? c.early_exit != 0 : A.early_exit != 0;
+    const int32_t* stages = (c.use_override && ee) ? c.stage_iters : o->stage_iters;
+    {
+      SlotTimer tm(h, FPT_T_BFGS + n - 1, st);
+      if (!ee) {
+        // one path per thread over the whole input, or persistent over the
+        // bucket (its size is only known on the device)
+        int grid = perm ? persistent(0, n, c.wg_per_cu) : (int)cap;
+        e = fpt::launch_solve(0, n, A, perm, bucket, nullptr, grid, st);
+        if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+      } else {
+        int ns = 0;
+        while (ns < FPT_MAX_STAGES && stages[ns] > 0) ++ns;
+        const int nc = fpt::kRegions * fpt::kCounterStride;
+        for (int k = 0; k < ns; ++k) {
+          fpt::StageArgs S;
+          memset(&S, 0, sizeof(S));
+          S.rcap = h->stage_rcap;
+          S.cap = h->stage_rcap * fpt::kRegions;
+          S.iters = stages[k];
+          if (k > 0) {
+            S.in_list = h->slist[(k - 1) & 1];
+            S.in_count = h->scount + ((k - 1) & 1) * nc;
+            S.state_in = h->sstate[(k - 1) & 1];
+          }
+          if (k + 1 < ns) {
+            S.out_list = h->slist[k & 1];
+            S.out_count = h->scount + (k & 1) * nc;
+            S.state_out = h->sstate[k & 1];
+            e = fpt::launch_zero_u64(S.out_count, nc, st);
+            if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+          }
+          int grid = (k == 0 && !perm) ? (int)cap : persistent(2, n, c.wg_per_cu);
+          e = fpt::launch_solve(2, n, A, perm, bucket, &S, grid, st);
+          if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+        }
+      }
+    }
+    {
+      SlotTimer tm(h, FPT_T_REFINE + n - 1, st);
+      int grid = perm ? persistent(1, n, 0) : (int)cap;
+      e = fpt::launch_solve(1, n, A, perm, bucket, nullptr, grid, st);
       if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
     }
   }
-  e = fpt::launch_invalid(A, h->perm, h->bucket, sgrid, st);
-  if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+  if (pa->order) {
+    e = fpt::launch_invalid(A, h->perm, h->bucket, h->num_cu * 4, st);
+    if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+  }
   return FPT_OK;
 }
 
@@ -448,10 +552,8 @@ extern "C" fpt_status fpt_grad(fpt_handle* h, const fpt_scene* sc,
   int sgrid = h->num_cu * 4;
   {
     SlotTimer tm(h, FPT_T_BUCKET, st);
-    e = fpt::launch_zero_u64(h->counts, 8, st);
-    if (e != hipSuccess) return hip_fail(e, "fpt_grad: launch");
-    e = fpt::launch_bucketing(pa->order, pa->N, pa->n_max, h->counts,
-                              h->cursor, h->bucket, h->perm, sgrid, st);
+    e = fpt::launch_bucketing(pa->order, pa->N, pa->n_max, h->ccount,
+                              h->bucket, h->perm, st);
     if (e != hipSuccess) return hip_fail(e, "fpt_grad: bucketing launch");
   }
   {
@@ -465,5 +567,219 @@ extern "C" fpt_status fpt_grad(fpt_handle* h, const fpt_scene* sc,
     e = fpt::launch_grad_invalid(A, h->perm, h->bucket, sgrid, st);
     if (e != hipSuccess) return hip_fail(e, "fpt_grad: launch");
   }
+  return FPT_OK;
+}
+
+// ------------------------------------------------- learned initialiser ----
+
+static const int64_t kMlpTrainMax = 65536;   // rows per training step
+static const int64_t kMlpInferChunk = 262144;
+
+static fpt_status ensure_mlp(fpt_handle* h, int64_t rows) {
+  if (h->mlp.cap >= rows) return FPT_OK;
+  if (h->mlp_mem) {
+    (void)hipFree(h->mlp_mem);
+    h->mlp_mem = nullptr;
+    h->mlp = fpt::MlpWork{};
+  }
+  size_t b16 = fpt::mlp_work_bf16_per_row() * (size_t)rows;
+  size_t f32 = fpt::mlp_work_f32_per_row() * (size_t)rows;
+  void* p = nullptr;
+  if (hipMalloc(&p, b16 * 2 + f32 * 4 + 256) != hipSuccess)
+    return fail(FPT_ENOMEM, "learned-initialiser workspace allocation failed");
+  h->mlp_mem = p;
+  fpt::mlp_carve(p, rows, h->mlp);
+  return FPT_OK;
+}
+
+static fpt_status check_mlp_paths(const fpt_scene* sc, const fpt_paths* pa,
+                                  const char* fn) {
+  fpt_status s = check_common(sc, pa, fn);
+  if (s != FPT_OK) return s;
+  if (pa->n_max != fpt::kMlpOrder)
+    return fail(FPT_EINVAL, std::string(fn) + ": the initialiser is for order-4 paths (n_max = 4)");
+  return FPT_OK;
+}
+
+extern "C" int64_t fpt_mlp_state_floats(void) { return 5 * fpt::kParams; }
+
+extern "C" fpt_status fpt_mlp_init(fpt_handle* h, float* state, uint64_t seed,
+                                   void* stream) {
+  if (!h || !state) return fail(FPT_EINVAL, "fpt_mlp_init: NULL argument");
+  if (!aligned(state, 16)) return fail(FPT_EINVAL, "fpt_mlp_init: state not 16-byte aligned");
+  DeviceGuard g(h->device);
+  hipStream_t st = (hipStream_t)stream;
+  fpt::MlpState S = fpt::mlp_state(state);
+  hipError_t e = fpt::launch_mlp_init(S.w, S.m, S.v, seed, st);
+  if (e != hipSuccess) return hip_fail(e, "fpt_mlp_init: launch");
+  fpt::AdamArgs A = fpt::adam_args(S, nullptr, 0.f, 1);
+  e = fpt::launch_mlp_adam(A, st);
+  if (e != hipSuccess) return hip_fail(e, "fpt_mlp_init: launch");
+  return FPT_OK;
+}
+
+extern "C" fpt_status fpt_mlp_train_step(fpt_handle* h, float* state,
+                                         const fpt_scene* sc,
+                                         const fpt_paths* pa,
+                                         const fpt_out* target, float scale,
+                                         float lr, int32_t step, float* loss,
+                                         void* stream) {
+  if (!h || !state || !target || !loss)
+    return fail(FPT_EINVAL, "fpt_mlp_train_step: NULL argument");
+  fpt_status s = check_mlp_paths(sc, pa, "fpt_mlp_train_step");
+  if (s != FPT_OK) return s;
+  if (pa->N < 64 || pa->N % 64 != 0 || pa->N > kMlpTrainMax)
+    return fail(FPT_EINVAL, "fpt_mlp_train_step: batch must be a multiple of 64 in 64..65536");
+  if (!target->t || !target->status)
+    return fail(FPT_EINVAL, "fpt_mlp_train_step: target.t and target.status are required");
+  if (!(scale > 0.f) || !(lr > 0.f) || step < 1)
+    return fail(FPT_EINVAL, "fpt_mlp_train_step: scale, lr must be > 0 and step >= 1");
+  if (!aligned(state, 16)) return fail(FPT_EINVAL, "fpt_mlp_train_step: state not 16-byte aligned");
+  DeviceGuard g(h->device);
+  hipStream_t st = (hipStream_t)stream;
+  s = ensure_mlp(h, pa->N);
+  if (s != FPT_OK) return s;
+  fpt::MlpState S = fpt::mlp_state(state);
+  fpt::MlpPrepArgs P = fpt::prep_args(sc, pa, 0, pa->N, scale, h->mlp, true);
+  P.t = target->t;
+  P.status = target->status;
+  hipError_t e = fpt::launch_mlp_prep(P, st);
+  if (e == hipSuccess) e = fpt::mlp_forward(S.w, S.wb, h->mlp, pa->N, true, st);
+  if (e == hipSuccess) e = fpt::launch_mlp_loss(h->mlp, pa->N, loss, st);
+  if (e == hipSuccess) e = fpt::mlp_backward(S.wbT, h->mlp, pa->N, S.grad, st);
+  if (e == hipSuccess) {
+    fpt::AdamArgs A = fpt::adam_args(S, S.grad, lr, step);
+    e = fpt::launch_mlp_adam(A, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "fpt_mlp_train_step: launch");
+  return FPT_OK;
+}
+
+extern "C" fpt_status fpt_mlp_infer(fpt_handle* h, const float* state,
+                                    const fpt_scene* sc, const fpt_paths* pa,
+                                    float scale, float* t_init, void* stream) {
+  if (!h || !state || !t_init) return fail(FPT_EINVAL, "fpt_mlp_infer: NULL argument");
+  fpt_status s = check_mlp_paths(sc, pa, "fpt_mlp_infer");
+  if (s != FPT_OK) return s;
+  if (!(scale > 0.f)) return fail(FPT_EINVAL, "fpt_mlp_infer: scale must be > 0");
+  if (!aligned(state, 16) || !aligned(t_init, 4))
+    return fail(FPT_EINVAL, "fpt_mlp_infer: misaligned pointer");
+  if (pa->N == 0) return FPT_OK;
+  DeviceGuard g(h->device);
+  hipStream_t st = (hipStream_t)stream;
+  int64_t chunk = pa->N < kMlpInferChunk ? pa->N : kMlpInferChunk;
+  chunk = (chunk + 63) / 64 * 64;
+  s = ensure_mlp(h, chunk);
+  if (s != FPT_OK) return s;
+  fpt::MlpState S = fpt::mlp_state(const_cast<float*>(state));
+  SlotTimer tm(h, FPT_T_MLP, st);
+  for (int64_t base = 0; base < pa->N; base += chunk) {
+    int64_t cnt = pa->N - base < chunk ? pa->N - base : chunk;
+    int64_t rows = (cnt + 63) / 64 * 64;  // GEMM rows (tail rows are zero)
+    fpt::MlpPrepArgs P = fpt::prep_args(sc, pa, base, cnt, scale, h->mlp, false);
+    hipError_t e = hipSuccess;
+    if (rows != cnt)
+      e = fpt::launch_zero_rows(h->mlp, cnt, rows, st);
+    if (e == hipSuccess) e = fpt::launch_mlp_prep(P, st);
+    if (e == hipSuccess) e = fpt::mlp_forward(S.w, S.wb, h->mlp, rows, false, st);
+    if (e == hipSuccess)
+      e = fpt::launch_mlp_to_tinit(h->mlp.Yp, sc->obj, pa->ids, pa->N, base, cnt,
+                                   sc->K, scale, t_init, st);
+    if (e != hipSuccess) return hip_fail(e, "fpt_mlp_infer: launch");
+  }
+  return FPT_OK;
+}
+
+// ------------------------------------------------ launch configuration ----
+
+extern "C" fpt_status fpt_set_launch(fpt_handle* h, int order,
+                                     const fpt_launch_cfg* cfg) {
+  if (!h) return fail(FPT_EINVAL, "fpt_set_launch: handle is NULL");
+  if (order < 1 || order > FPT_NMAX)
+    return fail(FPT_EINVAL, "fpt_set_launch: order outside 1..6");
+  if (!cfg) {
+    h->cfg[order] = fpt_launch_cfg{};
+    return FPT_OK;
+  }
+  if (cfg->wg_per_cu < 0 || cfg->wg_per_cu > 32)
+    return fail(FPT_EINVAL, "fpt_set_launch: wg_per_cu outside 0..32");
+  if (cfg->use_override && cfg->early_exit) {
+    if (cfg->stage_iters[0] < 1)
+      return fail(FPT_EINVAL, "fpt_set_launch: early exit needs stage_iters[0] >= 1");
+    for (int k = 0; k < FPT_MAX_STAGES; ++k)
+      if (cfg->stage_iters[k] < 0 || cfg->stage_iters[k] > 65535)
+        return fail(FPT_EINVAL, "fpt_set_launch: stage_iters outside 0..65535");
+  }
+  h->cfg[order] = *cfg;
+  return FPT_OK;
+}
+
+// -------------------------------------------------------- graph capture ----
+
+struct fpt_graph {
+  int device;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" fpt_status fpt_graph_capture(fpt_handle* h, const fpt_scene* sc,
+                                        const fpt_paths* pa,
+                                        const fpt_opts* o, const fpt_out* out,
+                                        void* stream, fpt_graph** g) {
+  if (!h || !g) return fail(FPT_EINVAL, "fpt_graph_capture: NULL argument");
+  *g = nullptr;
+  if (!stream) return fail(FPT_EINVAL, "fpt_graph_capture: needs a non-default stream");
+  fpt_status s = check_common(sc, pa, "fpt_graph_capture");
+  if (s != FPT_OK) return s;
+  s = check_opts(o);
+  if (s != FPT_OK) return s;
+  if (h->timing) return fail(FPT_EINVAL, "fpt_graph_capture: disable timing first");
+  DeviceGuard dg(h->device);
+  hipStream_t st = (hipStream_t)stream;
+  // no allocation inside the capture
+  if (pa->order) {
+    s = ensure_perm(h, pa->N);
+    if (s != FPT_OK) return s;
+  }
+  s = ensure_stage(h, pa->N, pa->n_max);
+  if (s != FPT_OK) return s;
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return hip_fail(e, "fpt_graph_capture: begin");
+  fpt_status rs = fpt_solve(h, sc, pa, o, out, stream);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(st, &graph);
+  if (rs != FPT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rs;
+  }
+  if (e != hipSuccess) return hip_fail(e, "fpt_graph_capture: end");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(e, "fpt_graph_capture: instantiate");
+  }
+  fpt_graph* G = new fpt_graph();
+  G->device = h->device;
+  G->graph = graph;
+  G->exec = exec;
+  *g = G;
+  return FPT_OK;
+}
+
+extern "C" fpt_status fpt_graph_launch(fpt_graph* g, void* stream) {
+  if (!g) return fail(FPT_EINVAL, "fpt_graph_launch: graph is NULL");
+  DeviceGuard dg(g->device);
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "fpt_graph_launch");
+  return FPT_OK;
+}
+
+extern "C" fpt_status fpt_graph_destroy(fpt_graph* g) {
+  if (!g) return FPT_OK;
+  DeviceGuard dg(g->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
   return FPT_OK;
 }

@@ -9,6 +9,9 @@
 namespace fpt {
 
 constexpr int kBlock = 256;  // threads per workgroup: four wave64s
+constexpr int kSortChunk = 8192;  // paths per workgroup in the order sort
+constexpr int kRegions = 64;      // list regions of an early-exit stage
+constexpr int kCounterStride = 16;  // u64 counters 128 bytes apart
 
 // Hardware reciprocal square root (v_rsq_f32), about 1 ulp.
 __device__ __forceinline__ float rsq32(float x) {
@@ -64,13 +67,25 @@ struct SolveArgs {
   int32_t K, Q, n_max;
   // options
   int32_t n_iter, fp_iters, early_exit;
-  int32_t refill_min, refill_every;  // early-exit refill policy
   float exit_d2;  // (exit_rtol * scale)^2
   float scale;
   int32_t n_levels;
   float level_eps[FPT_MAX_LEVELS];
   int32_t level_steps[FPT_MAX_LEVELS];
   float cert_abs;  // cert_rtol * scale
+};
+
+// One early-exit stage of the FP32 solver (see bfgs_stage_kernel).
+struct StageArgs {
+  const int32_t* in_list;               // null in the first stage
+  const unsigned long long* in_count;   // kRegions counters, kCounterStride apart
+  int32_t* out_list;                    // null in the last stage
+  unsigned long long* out_count;
+  const float* state_in;
+  float* state_out;
+  int64_t cap;                          // kRegions * rcap: state field stride
+  int64_t rcap;                         // slots per region
+  int32_t iters;
 };
 
 // Arguments of one fpt_grad call.

@@ -188,6 +188,28 @@ __device__ __forceinline__ RefineOut refine64(const Geo64<NO>& G, double* t,
   }
   double cert = (double)A.cert_abs;
   o.certified = A.n_levels > 0 && last_full && (last_d2 <= cert * cert);
+  if (o.certified) {
+    // Nonsmooth check. At the smoothed optimum v_i = r_i / l_i plays the role
+    // of the subgradient of |r_i|: a genuine collapse (r_i -> 0) has |v_i|
+    // bounded away from 1, while a short segment with |v_i| close to 1 is a
+    // degenerate configuration in which the length is nearly flat along the
+    // segment and the smoothing can pull the points together. Such a path is
+    // not certified.
+    const double eps = (double)A.level_eps[A.n_levels - 1] * (double)A.scale;
+    const double short2 = 1e-6 * (double)A.scale * (double)A.scale;  // (1e-3 S)^2
+    double x[NO][3];
+    points64<NO>(G, t, x);
+#pragma unroll
+    for (int i = 0; i <= NO; ++i) {
+      double r[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
+      double q = dot3d(r, r);
+      double v2 = q / (q + eps * eps);
+      if (q < short2 && v2 > 0.98 * 0.98) o.certified = false;
+    }
+  }
   return o;
 }
 
@@ -431,71 +453,120 @@ __global__ __launch_bounds__(kBlock) void bfgs_kernel(
   }
 }
 
-// Phase 1 with per-lane early exit and refill. Each lane runs its path until
-// two consecutive steps move no point by more than exit_rtol * scale (or the
-// iteration cap), hands it over, and takes the next unclaimed path of the
-// bucket. Claims are made per wavefront: a ballot counts the idle lanes and
-// one atomic on the bucket's work cursor reserves that many consecutive
-// paths. Idle lanes wait until at least refill_min of them are idle or
-// refill_every iterations have passed, so that the divergent reload is
-// amortised. A wavefront leaves when the cursor is past the bucket and none
-// of its lanes holds a path; every path takes at most n_iter iterations, so
-// every wavefront reaches that point.
+// Phase 1 with early exit, in stages. A stage runs every path of its input
+// for at most `iters` more iterations, all lanes of a wavefront in lockstep.
+// A path leaves once two consecutive steps moved no point by more than
+// exit_rtol * scale, or after n_iter iterations in total; the others are
+// appended to a compact list for the next stage, together with their BFGS
+// state (T, P, packed H, iteration count, streak), so that the next stage
+// runs dense wavefronts again. The first stage reads the order bucket, the
+// following ones the previous stage's list (its length is read on the
+// device); the last stage hands over every path. The state is stored as
+// structure-of-arrays over list slots: [field][cap].
+
 template <int NO>
-__global__ __launch_bounds__(kBlock) void bfgs_refill_kernel(
+constexpr int stage_fields() {
+  return 4 * NO + (2 * NO) * (2 * NO + 1) / 2 + 2;
+}
+
+template <int NO>
+__global__ __launch_bounds__(kBlock) void bfgs_stage_kernel(
     SolveArgs A, const int32_t* __restrict__ perm,
-    const int64_t* __restrict__ bucket, unsigned long long* __restrict__ work) {
+    const int64_t* __restrict__ bucket, StageArgs St) {
+  constexpr int M = 2 * NO, HP = M * (M + 1) / 2;
+  // input: the bucket, or the previous list (kRegions regions of St.rcap
+  // slots; pre[] = prefix sums of the region lengths)
+  __shared__ int64_t pre[kRegions + 1];
   int64_t begin = 0, count = A.N;
-  if (bucket) {
+  if (St.in_list) {
+    if (threadIdx.x == 0) {
+      int64_t acc = 0;
+      for (int r = 0; r < kRegions; ++r) {
+        pre[r] = acc;
+        acc += (int64_t)St.in_count[r * kCounterStride];
+      }
+      pre[kRegions] = acc;
+    }
+    __syncthreads();
+    count = pre[kRegions];
+  } else if (bucket) {
     begin = bucket[NO - 1];
     count = bucket[NO] - begin;
   }
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  Geo32<NO> G;
-  State32<NO> S;
-  bool have = false, valid = false, exhausted = false;
-  int64_t p = 0;
-  int it = 0, streak = 0, since = 0;
-  while (true) {
-    const unsigned long long idle = __ballot(!have);
-    const int n_idle = __popcll(idle);
-    if (n_idle > 0 && !exhausted &&
-        (n_idle >= A.refill_min || since >= A.refill_every || n_idle == 64)) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
+       idx += stride) {
+    int64_t slot_in = idx;
+    if (St.in_list) {
+      int lo = 0, hi = kRegions;  // largest r with pre[r] <= idx
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= idx) lo = mid; else hi = mid;
+      }
+      slot_in = (int64_t)lo * St.rcap + (idx - pre[lo]);
+    }
+    const int64_t p = St.in_list ? (int64_t)St.in_list[slot_in]
+                                 : (perm ? (int64_t)perm[begin + idx] : idx);
+    Geo32<NO> G;
+    float t0[NO][2];
+    const bool valid = load_path32<NO>(A, p, G, t0);
+    State32<NO> S;
+    int it = 0, streak = 0;
+    if (!St.in_list) {
+      init_state<NO>(G, t0, S);
+    } else {
+      const float* src = St.state_in + slot_in;
+      const int64_t c = St.cap;
+#pragma unroll
+      for (int k = 0; k < M; ++k) S.T[k] = src[k * c];
+#pragma unroll
+      for (int k = 0; k < M; ++k) S.P[k] = src[(M + k) * c];
+#pragma unroll
+      for (int k = 0; k < HP; ++k) S.H[k] = src[(2 * M + k) * c];
+      it = __float_as_int(src[(2 * M + HP) * c]);
+      streak = __float_as_int(src[(2 * M + HP + 1) * c]);
+      grad32<NO>(G, S.T, S.g, S.r, S.l2, S.il);
+    }
+    bool done = it >= A.n_iter;
+    for (int k = 0; k < St.iters; ++k) {
+      if (__all(done)) break;
+      if (!done) {
+        float d2 = bfgs_iter<NO>(G, S, A.fp_iters);
+        ++it;
+        streak = (d2 <= A.exit_d2) ? streak + 1 : 0;
+        done = streak >= 2 || it >= A.n_iter;
+      }
+    }
+    const bool fin = done || !St.out_list || !valid;
+    if (fin) store_phase1<NO>(A, p, S, it, valid);
+    const unsigned long long more = __ballot(!fin);
+    if (more) {
+      // region of this 64-path chunk of the input: chunks are spread over
+      // kRegions counters, each on its own cache line
+      const int region = (int)((idx >> 6) % kRegions);
       unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(work + NO, (unsigned long long)n_idle);
+      if (lane == 0)
+        base = atomicAdd(St.out_count + region * kCounterStride,
+                         (unsigned long long)__popcll(more));
       base = __shfl(base, 0);
-      if (base + (unsigned long long)n_idle >= (unsigned long long)count)
-        exhausted = true;
-      if (!have) {
-        unsigned long long idx = base + (unsigned long long)__popcll(idle & below);
-        if (idx < (unsigned long long)count) {
-          p = perm ? (int64_t)perm[begin + (int64_t)idx] : (int64_t)idx;
-          float t0[NO][2];
-          valid = load_path32<NO>(A, p, G, t0);
-          init_state<NO>(G, t0, S);
-          have = true;
-          it = 0;
-          streak = 0;
-        }
-      }
-      since = 0;
-    }
-    if (!__any(have)) break;
-    if (have && it >= A.n_iter) {
-      store_phase1<NO>(A, p, S, it, valid);
-      have = false;
-    }
-    if (have) {
-      float d2 = bfgs_iter<NO>(G, S, A.fp_iters);
-      ++it;
-      streak = (d2 <= A.exit_d2) ? streak + 1 : 0;
-      if (streak >= 2 || it >= A.n_iter) {
-        store_phase1<NO>(A, p, S, it, valid);
-        have = false;
+      if (!fin) {
+        const int64_t slot = (int64_t)region * St.rcap +
+                             (int64_t)(base + (unsigned long long)__popcll(more & below));
+        St.out_list[slot] = (int32_t)p;
+        float* dst = St.state_out + slot;
+        const int64_t c = St.cap;
+#pragma unroll
+        for (int k = 0; k < M; ++k) dst[k * c] = S.T[k];
+#pragma unroll
+        for (int k = 0; k < M; ++k) dst[(M + k) * c] = S.P[k];
+#pragma unroll
+        for (int k = 0; k < HP; ++k) dst[(2 * M + k) * c] = S.H[k];
+        dst[(2 * M + HP) * c] = __int_as_float(it);
+        dst[(2 * M + HP + 1) * c] = __int_as_float(streak);
       }
     }
-    ++since;
   }
 }
 
@@ -574,72 +645,123 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
 }
 
 // ------------------------------------------------------ order bucketing ---
-// counts[0] collects paths whose order is outside 1..n_max, counts[n] those
-// of order n. bucket offsets: bucket[n-1] .. bucket[n] is the range of order
-// n in perm; bucket[n_max] .. bucket[n_max+1] holds the invalid ones.
+// A counting sort of the path indices by order, without global atomics:
+// (1) each workgroup counts the orders of its chunk of kSortChunk paths,
+// (2) one workgroup turns the per-chunk counts into per-chunk output
+//     offsets (bucket of order n first for n = 1..n_max, invalid orders
+//     last), (3) each workgroup scatters its chunk in input order.
+// bucket[n-1] .. bucket[n] is the range of order n in perm;
+// bucket[n_max] .. bucket[n_max+1] holds the paths with an invalid order.
+
+__device__ __forceinline__ int order_bin(const uint8_t* order, int64_t i,
+                                         int64_t N, int n_max) {
+  if (i >= N) return -1;
+  int o = order[i];
+  return (o >= 1 && o <= n_max) ? o : 0;
+}
 
 __global__ __launch_bounds__(kBlock) void bucket_count_kernel(
     const uint8_t* __restrict__ order, int64_t N, int n_max,
-    unsigned long long* __restrict__ counts) {
-  __shared__ unsigned int loc[FPT_NMAX + 1];
-  if (threadIdx.x <= FPT_NMAX) loc[threadIdx.x] = 0;
+    uint32_t* __restrict__ ccount) {
+  __shared__ unsigned int loc[8];
+  if (threadIdx.x < 8) loc[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += stride) {
-    int o = order[i];
-    int b = (o >= 1 && o <= n_max) ? o : 0;
-    atomicAdd(&loc[b], 1u);
+  const int lane = threadIdx.x & 63;
+  const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
+  const int64_t c1 = min(N, c0 + (int64_t)kSortChunk);
+  for (int64_t i0 = c0; i0 < c1; i0 += kBlock) {
+    int b = order_bin(order, i0 + threadIdx.x, c1, n_max);
+    for (int k = 0; k <= n_max; ++k) {
+      unsigned long long m = __ballot(b == k);
+      if (lane == 0 && m) atomicAdd(&loc[k], (unsigned int)__popcll(m));
+    }
   }
   __syncthreads();
-  if (threadIdx.x <= FPT_NMAX && loc[threadIdx.x])
-    atomicAdd(&counts[threadIdx.x], (unsigned long long)loc[threadIdx.x]);
+  if (threadIdx.x < 8) ccount[(int64_t)blockIdx.x * 8 + threadIdx.x] = loc[threadIdx.x];
 }
 
-// bucket[0..n_max+1] from counts; cursor[] = running insert positions
-__global__ void bucket_scan_kernel(const unsigned long long* __restrict__ counts,
-                                   int n_max, int64_t* __restrict__ bucket,
-                                   unsigned long long* __restrict__ cursor) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    int64_t acc = 0;
+// One workgroup: per-chunk offsets (in place over ccount) and bucket bounds.
+__global__ __launch_bounds__(kBlock) void bucket_scan_kernel(
+    uint32_t* __restrict__ ccount, int64_t nchunks, int n_max,
+    int64_t* __restrict__ bucket) {
+  __shared__ unsigned long long part[kBlock][8];
+  __shared__ unsigned long long start[8];
+  const int64_t per = (nchunks + kBlock - 1) / kBlock;
+  const int64_t c0 = (int64_t)threadIdx.x * per;
+  const int64_t c1 = min(nchunks, c0 + per);
+  unsigned long long sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t c = c0; c < c1; ++c)
+    for (int k = 0; k <= n_max; ++k) sum[k] += ccount[c * 8 + k];
+  for (int k = 0; k < 8; ++k) part[threadIdx.x][k] = sum[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // exclusive scan over threads, per bin; bin totals
+    unsigned long long tot[8];
+    for (int k = 0; k <= n_max; ++k) {
+      unsigned long long acc = 0;
+      for (int t = 0; t < kBlock; ++t) {
+        unsigned long long v = part[t][k];
+        part[t][k] = acc;
+        acc += v;
+      }
+      tot[k] = acc;
+    }
+    unsigned long long acc = 0;
     bucket[0] = 0;
     for (int n = 1; n <= n_max; ++n) {
-      cursor[n] = (unsigned long long)acc;
-      acc += (int64_t)counts[n];
-      bucket[n] = acc;
+      start[n] = acc;
+      acc += tot[n];
+      bucket[n] = (int64_t)acc;
     }
-    cursor[0] = (unsigned long long)acc;
-    acc += (int64_t)counts[0];
-    bucket[n_max + 1] = acc;
+    start[0] = acc;
+    acc += tot[0];
+    bucket[n_max + 1] = (int64_t)acc;
   }
+  __syncthreads();
+  unsigned long long run[8];
+  for (int k = 0; k <= n_max; ++k) run[k] = start[k] + part[threadIdx.x][k];
+  for (int64_t c = c0; c < c1; ++c)
+    for (int k = 0; k <= n_max; ++k) {
+      uint32_t v = ccount[c * 8 + k];
+      ccount[c * 8 + k] = (uint32_t)run[k];
+      run[k] += v;
+    }
 }
 
-// Scatter path indices into their order bucket. Each workgroup reserves one
-// contiguous range per order, so paths keep their relative order inside a
-// workgroup's chunk.
+// Scatter: within a chunk, slices of 256 paths in order; inside a slice,
+// wavefronts in order and lanes by rank (ballot + popcount): a stable sort.
 __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
     const uint8_t* __restrict__ order, int64_t N, int n_max,
-    unsigned long long* __restrict__ cursor, int32_t* __restrict__ perm) {
-  __shared__ unsigned int loc[FPT_NMAX + 1];
-  __shared__ unsigned long long base[FPT_NMAX + 1];
-  const int64_t chunk = (int64_t)kBlock;
-  for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < N; c0 += (int64_t)gridDim.x * chunk) {
-    if (threadIdx.x <= FPT_NMAX) loc[threadIdx.x] = 0;
-    __syncthreads();
-    int64_t i = c0 + threadIdx.x;
-    int b = -1;
-    unsigned int rank = 0;
-    if (i < N) {
-      int o = order[i];
-      b = (o >= 1 && o <= n_max) ? o : 0;
-      rank = atomicAdd(&loc[b], 1u);
+    const uint32_t* __restrict__ coff, int32_t* __restrict__ perm) {
+  __shared__ unsigned int run[8];
+  __shared__ unsigned int wcnt[kBlock / 64][8];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  if (threadIdx.x < 8) run[threadIdx.x] = coff[(int64_t)blockIdx.x * 8 + threadIdx.x];
+  __syncthreads();
+  const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
+  const int64_t c1 = min(N, c0 + (int64_t)kSortChunk);
+  for (int64_t i0 = c0; i0 < c1; i0 += kBlock) {
+    const int64_t i = i0 + threadIdx.x;
+    const int b = order_bin(order, i, c1, n_max);
+    unsigned int my_rank = 0;
+    for (int k = 0; k <= n_max; ++k) {
+      unsigned long long m = __ballot(b == k);
+      if (lane == 0) wcnt[w][k] = (unsigned int)__popcll(m);
+      if (b == k) my_rank = (unsigned int)__popcll(m & below);
     }
     __syncthreads();
-    if (threadIdx.x <= FPT_NMAX)
-      base[threadIdx.x] = loc[threadIdx.x]
-                              ? atomicAdd(&cursor[threadIdx.x], (unsigned long long)loc[threadIdx.x])
-                              : 0ull;
+    if (b >= 0) {
+      unsigned int off = run[b] + my_rank;
+      for (int v = 0; v < w; ++v) off += wcnt[v][b];
+      perm[off] = (int32_t)i;
+    }
     __syncthreads();
-    if (b >= 0) perm[base[b] + rank] = (int32_t)i;
+    if (threadIdx.x <= n_max) {
+      unsigned int add = 0;
+      for (int v = 0; v < kBlock / 64; ++v) add += wcnt[v][threadIdx.x];
+      run[threadIdx.x] += add;
+    }
     __syncthreads();
   }
 }
@@ -668,7 +790,7 @@ __global__ __launch_bounds__(kBlock) void invalid_kernel(
 template <int NO>
 static hipError_t launch_phase(int phase, const SolveArgs& A,
                                const int32_t* perm, const int64_t* bucket,
-                               unsigned long long* work, int grid,
+                               const StageArgs* stage, int grid,
                                hipStream_t st) {
   if (phase == 0)
     hipLaunchKernelGGL(bfgs_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
@@ -677,32 +799,44 @@ static hipError_t launch_phase(int phase, const SolveArgs& A,
     hipLaunchKernelGGL(refine_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
                        perm, bucket);
   else
-    hipLaunchKernelGGL(bfgs_refill_kernel<NO>, dim3(grid), dim3(kBlock), 0,
-                       st, A, perm, bucket, work);
+    hipLaunchKernelGGL(bfgs_stage_kernel<NO>, dim3(grid), dim3(kBlock), 0,
+                       st, A, perm, bucket, *stage);
   return hipGetLastError();
 }
 
 // phase 0: bfgs_kernel<order>, 1: refine_kernel<order>,
-// 2: bfgs_refill_kernel<order> (needs the zeroed work cursors)
+// 2: bfgs_stage_kernel<order> (one early-exit stage, `stage` describes it)
 hipError_t launch_solve(int phase, int order, const SolveArgs& A,
                         const int32_t* perm, const int64_t* bucket,
-                        unsigned long long* work, int grid, hipStream_t st) {
+                        const StageArgs* stage, int grid, hipStream_t st) {
   switch (order) {
-    case 1: return launch_phase<1>(phase, A, perm, bucket, work, grid, st);
-    case 2: return launch_phase<2>(phase, A, perm, bucket, work, grid, st);
-    case 3: return launch_phase<3>(phase, A, perm, bucket, work, grid, st);
-    case 4: return launch_phase<4>(phase, A, perm, bucket, work, grid, st);
-    case 5: return launch_phase<5>(phase, A, perm, bucket, work, grid, st);
-    case 6: return launch_phase<6>(phase, A, perm, bucket, work, grid, st);
+    case 1: return launch_phase<1>(phase, A, perm, bucket, stage, grid, st);
+    case 2: return launch_phase<2>(phase, A, perm, bucket, stage, grid, st);
+    case 3: return launch_phase<3>(phase, A, perm, bucket, stage, grid, st);
+    case 4: return launch_phase<4>(phase, A, perm, bucket, stage, grid, st);
+    case 5: return launch_phase<5>(phase, A, perm, bucket, stage, grid, st);
+    case 6: return launch_phase<6>(phase, A, perm, bucket, stage, grid, st);
   }
   return hipErrorInvalidValue;
+}
+
+int stage_fields_for(int order) {
+  switch (order) {
+    case 1: return stage_fields<1>();
+    case 2: return stage_fields<2>();
+    case 3: return stage_fields<3>();
+    case 4: return stage_fields<4>();
+    case 5: return stage_fields<5>();
+    case 6: return stage_fields<6>();
+  }
+  return 0;
 }
 
 template <int NO>
 static const void* phase_ptr(int phase) {
   return phase == 0 ? (const void*)bfgs_kernel<NO>
          : phase == 1 ? (const void*)refine_kernel<NO>
-                      : (const void*)bfgs_refill_kernel<NO>;
+                      : (const void*)bfgs_stage_kernel<NO>;
 }
 
 const void* solve_kernel_ptr(int phase, int order) {
@@ -718,14 +852,15 @@ const void* solve_kernel_ptr(int phase, int order) {
 }
 
 hipError_t launch_bucketing(const uint8_t* order, int64_t N, int n_max,
-                            unsigned long long* counts, unsigned long long* cursor,
-                            int64_t* bucket, int32_t* perm, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(bucket_count_kernel, dim3(grid), dim3(kBlock), 0, st,
-                     order, N, n_max, counts);
-  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(64), 0, st, counts,
-                     n_max, bucket, cursor);
-  hipLaunchKernelGGL(bucket_scatter_kernel, dim3(grid), dim3(kBlock), 0, st,
-                     order, N, n_max, cursor, perm);
+                            uint32_t* ccount, int64_t* bucket, int32_t* perm,
+                            hipStream_t st) {
+  const int64_t nchunks = (N + kSortChunk - 1) / kSortChunk;
+  hipLaunchKernelGGL(bucket_count_kernel, dim3((unsigned)nchunks), dim3(kBlock), 0, st,
+                     order, N, n_max, ccount);
+  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(kBlock), 0, st, ccount,
+                     nchunks, n_max, bucket);
+  hipLaunchKernelGGL(bucket_scatter_kernel, dim3((unsigned)nchunks), dim3(kBlock), 0, st,
+                     order, N, n_max, ccount, perm);
   return hipGetLastError();
 }
 
@@ -741,14 +876,13 @@ hipError_t launch_invalid(const SolveArgs& A, const int32_t* perm,
 namespace fpt {
 
 __global__ void zero_u64_kernel(unsigned long long* p, int n) {
-  int i = threadIdx.x;
-  if (i < n) p[i] = 0ull;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
 }
 
 // clears small counters with a kernel rather than a memset node, so that the
 // sequence can be captured into a HIP graph
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st) {
-  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, p, n);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

@@ -42,7 +42,12 @@ class _Opts(ctypes.Structure):
                 ("level_eps", ctypes.c_float * FPT_MAX_LEVELS),
                 ("level_steps", ctypes.c_int32 * FPT_MAX_LEVELS),
                 ("cert_rtol", ctypes.c_float),
-                ("refill_min", ctypes.c_int32), ("refill_every", ctypes.c_int32)]
+                ("stage_iters", ctypes.c_int32 * 4)]
+
+
+class _LaunchCfg(ctypes.Structure):
+    _fields_ = [("wg_per_cu", ctypes.c_int32), ("use_override", ctypes.c_int32),
+                ("early_exit", ctypes.c_int32), ("stage_iters", ctypes.c_int32 * 4)]
 
 
 class _Out(ctypes.Structure):
@@ -51,10 +56,14 @@ class _Out(ctypes.Structure):
 
 
 EXPORTED = ["fpt_default_opts", "fpt_create", "fpt_destroy", "fpt_solve",
-            "fpt_grad", "fpt_last_error", "fpt_set_timing", "fpt_kernel_times"]
+            "fpt_grad", "fpt_last_error", "fpt_set_timing", "fpt_kernel_times",
+            "fpt_mlp_state_floats", "fpt_mlp_init", "fpt_mlp_train_step",
+            "fpt_mlp_infer", "fpt_set_launch", "fpt_graph_capture",
+            "fpt_graph_launch", "fpt_graph_destroy"]
 
 # timer slots of fpt_kernel_times
-T_BUCKET, T_BFGS, T_REFINE, T_GRAD, T_REDUCE, TIMERS = 0, 1, 7, 13, 14, 16
+T_BUCKET, T_BFGS, T_REFINE, T_GRAD, T_REDUCE, T_MLP, TIMERS = 0, 1, 7, 13, 14, 15, 16
+MLP_PARAMS = 172864  # padded parameter count: state[0:MLP_PARAMS] = weights
 
 _lib = None
 
@@ -87,6 +96,28 @@ def load_library(path: str = LIB_PATH):
     lib.fpt_set_timing.restype = ctypes.c_int
     lib.fpt_kernel_times.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
     lib.fpt_kernel_times.restype = ctypes.c_int
+    lib.fpt_mlp_state_floats.argtypes = []
+    lib.fpt_mlp_state_floats.restype = ctypes.c_int64
+    lib.fpt_mlp_init.argtypes = [_P, _P, ctypes.c_uint64, _P]
+    lib.fpt_mlp_init.restype = ctypes.c_int
+    lib.fpt_mlp_train_step.argtypes = [_P, _P, ctypes.POINTER(_Scene),
+                                       ctypes.POINTER(_Paths),
+                                       ctypes.POINTER(_Out), ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_int32, _P, _P]
+    lib.fpt_mlp_train_step.restype = ctypes.c_int
+    lib.fpt_mlp_infer.argtypes = [_P, _P, ctypes.POINTER(_Scene),
+                                  ctypes.POINTER(_Paths), ctypes.c_float, _P, _P]
+    lib.fpt_mlp_infer.restype = ctypes.c_int
+    lib.fpt_set_launch.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_LaunchCfg)]
+    lib.fpt_set_launch.restype = ctypes.c_int
+    lib.fpt_graph_capture.argtypes = [_P, ctypes.POINTER(_Scene),
+                                      ctypes.POINTER(_Paths), ctypes.POINTER(_Opts),
+                                      ctypes.POINTER(_Out), _P, ctypes.POINTER(_P)]
+    lib.fpt_graph_capture.restype = ctypes.c_int
+    lib.fpt_graph_launch.argtypes = [_P, _P]
+    lib.fpt_graph_launch.restype = ctypes.c_int
+    lib.fpt_graph_destroy.argtypes = [_P]
+    lib.fpt_graph_destroy.restype = ctypes.c_int
     lib.fpt_last_error.argtypes = []
     lib.fpt_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -114,8 +145,7 @@ class Opts:
     level_eps: list = field(default_factory=lambda: [1e-3, 1e-5, 1e-7, 1e-9])
     level_steps: list = field(default_factory=lambda: [2, 2, 2, 3])
     cert_rtol: float = 1e-5
-    refill_min: int = 8
-    refill_every: int = 4
+    stage_iters: list = field(default_factory=lambda: [16, 16, 32])
 
     def to_c(self) -> _Opts:
         o = _Opts()
@@ -134,8 +164,10 @@ class Opts:
             o.level_eps[i] = float(self.level_eps[i]) if i < o.n_levels else 0.0
             o.level_steps[i] = int(self.level_steps[i]) if i < o.n_levels else 0
         o.cert_rtol = float(self.cert_rtol)
-        o.refill_min = int(self.refill_min)
-        o.refill_every = int(self.refill_every)
+        if len(self.stage_iters) > 4:
+            raise ValueError("at most 4 early-exit stages")
+        for i in range(4):
+            o.stage_iters[i] = int(self.stage_iters[i]) if i < len(self.stage_iters) else 0
         return o
 
 
@@ -230,6 +262,32 @@ class Solver:
         _check(load_library().fpt_kernel_times(self._h, ms), "fpt_kernel_times")
         return [float(v) for v in ms]
 
+    def set_launch(self, order: int, cfg: dict | None):
+        """Per-order launch configuration (see fpt_launch_cfg); None resets."""
+        lib = load_library()
+        if cfg is None:
+            _check(lib.fpt_set_launch(self._h, int(order), None), "fpt_set_launch")
+            return
+        c = _LaunchCfg()
+        c.wg_per_cu = int(cfg.get("wg_per_cu", 0))
+        c.use_override = 1 if "early_exit" in cfg else 0
+        c.early_exit = int(cfg.get("early_exit", 0))
+        st = list(cfg.get("stage_iters", [16, 16, 32]))
+        for i in range(4):
+            c.stage_iters[i] = int(st[i]) if i < len(st) else 0
+        _check(lib.fpt_set_launch(self._h, int(order), ctypes.byref(c)), "fpt_set_launch")
+
+    def capture(self, db: DeviceBatch, opts, out, stream):
+        """HIP graph of one fpt_solve on `stream` (a torch.cuda.Stream that
+        is not the default stream); returns a Graph."""
+        sc, pa, oc, ou = db.c_scene(), db.c_paths(), opts.to_c(), self.c_out(out)
+        g = ctypes.c_void_p()
+        _check(load_library().fpt_graph_capture(
+            self._h, ctypes.byref(sc), ctypes.byref(pa), ctypes.byref(oc),
+            ctypes.byref(ou), _stream_ptr(stream), ctypes.byref(g)),
+            "fpt_graph_capture")
+        return Graph(g, keep=(db, opts, out))
+
     def alloc_out(self, db: DeviceBatch):
         import torch
         dev = db.obj.device
@@ -276,3 +334,68 @@ class Solver:
             _ptr(g_len), _ptr(g_x), _ptr(g_pts), _ptr(g_obj), _ptr(g_slot),
             _ptr(g_end), _stream_ptr(stream)), "fpt_grad")
         return g_pts, g_obj
+
+
+class Mlp:
+    """Learned initialiser state on the device (fpt_mlp_*)."""
+
+    def __init__(self, solver: Solver, seed: int = 0, stream=None):
+        import torch
+        lib = load_library()
+        self.solver = solver
+        n = int(lib.fpt_mlp_state_floats())
+        self.state = torch.empty(n, dtype=torch.float32, device="cuda")
+        _check(lib.fpt_mlp_init(solver._h, _ptr(self.state), int(seed),
+                                _stream_ptr(stream)), "fpt_mlp_init")
+        self.step = 0
+
+    def weights(self):
+        return self.state[:MLP_PARAMS]
+
+    def grad(self):
+        return self.state[3 * MLP_PARAMS:4 * MLP_PARAMS]
+
+    def train_step(self, db: DeviceBatch, target, scale: float, lr: float,
+                   loss_acc, stream=None):
+        """One Adam step on the batch db (order 4) against solver output
+        `target`; adds the batch loss to the device scalar loss_acc."""
+        self.step += 1
+        sc, pa, ou = db.c_scene(), db.c_paths(), Solver.c_out(target)
+        _check(load_library().fpt_mlp_train_step(
+            self.solver._h, _ptr(self.state), ctypes.byref(sc), ctypes.byref(pa),
+            ctypes.byref(ou), float(scale), float(lr), int(self.step),
+            _ptr(loss_acc), _stream_ptr(stream)), "fpt_mlp_train_step")
+
+    def infer(self, db: DeviceBatch, scale: float, out=None, stream=None):
+        """t_init [4][2][N] for db's paths."""
+        import torch
+        if out is None:
+            out = torch.empty((4, 2, db.N), dtype=torch.float32, device="cuda")
+        sc, pa = db.c_scene(), db.c_paths()
+        _check(load_library().fpt_mlp_infer(
+            self.solver._h, _ptr(self.state), ctypes.byref(sc), ctypes.byref(pa),
+            float(scale), _ptr(out), _stream_ptr(stream)), "fpt_mlp_infer")
+        return out
+
+
+class Graph:
+    """A captured fpt_solve (fpt_graph_*)."""
+
+    def __init__(self, handle, keep):
+        self._g = handle
+        self._keep = keep  # buffers the graph reads and writes
+
+    def launch(self, stream=None):
+        _check(load_library().fpt_graph_launch(self._g, _stream_ptr(stream)),
+               "fpt_graph_launch")
+
+    def close(self):
+        if getattr(self, "_g", None):
+            load_library().fpt_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -41,8 +41,8 @@ def test_default_opts_and_struct_layout():
     assert ctypes.sizeof(fpt._Scene) == 32
     assert ctypes.sizeof(fpt._Paths) == 56
     assert ctypes.sizeof(fpt._Out) == 40
-    assert ctypes.sizeof(fpt._Opts) == 4 * 6 + 4 * 8 * 2 + 4 + 8
-    assert o.refill_min == 8 and o.refill_every == 4
+    assert ctypes.sizeof(fpt._Opts) == 4 * 6 + 4 * 8 * 2 + 4 + 16
+    assert list(o.stage_iters) == [16, 16, 32, 0]
 
 
 def test_create_without_gpu_fails_cleanly():

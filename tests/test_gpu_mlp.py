@@ -1,0 +1,103 @@
+"""BF16 MFMA kernels of the learned initialiser vs the FP64 numpy reference
+(tests/mlp_ref.py), and its training behaviour."""
+import numpy as np
+import pytest
+
+import mlp_ref
+from paper_2510_16172_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16(a):
+    """Round to bfloat16 (nearest even), as the kernels store operands."""
+    a = np.asarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2510_16172_amd import fpt
+    s = fpt.Solver(0)
+    yield s
+    s.close()
+
+
+def _batch(N, seed):
+    sc = scenes.canyon_scene()
+    return scenes.canyon_sample_paths(sc, N, seed=seed, n=4)
+
+
+def test_infer_matches_reference(solver):
+    import torch
+    from paper_2510_16172_amd import fpt
+    b = _batch(1000, 6000)   # ragged: 1000 is not a multiple of 64
+    mlp = fpt.Mlp(solver, seed=3)
+    db = fpt.DeviceBatch(b)
+    t_init = mlp.infer(db, b.S)
+    torch.cuda.synchronize()
+    W = mlp_ref.unpack(mlp.weights().cpu().numpy())
+    Wb = {k: (_bf16(v) if k.startswith("W") else v) for k, v in W.items()}
+    X = _bf16(mlp_ref.features(b, b.S))
+    Y, _ = mlp_ref.forward(Wb, X)
+    # back to the caller's parametrisation
+    want = np.zeros((4, 2, b.N))
+    for j in range(4):
+        k = b.ids[j]
+        n1 = np.linalg.norm(b.obj[3:6, k].astype(np.float64), axis=0)
+        n2 = np.linalg.norm(b.obj[6:9, k].astype(np.float64), axis=0)
+        want[j, 0] = Y[:, 2 * j] * b.S / n1
+        want[j, 1] = np.where(n2 > 0, Y[:, 2 * j + 1] * b.S / np.where(n2 > 0, n2, 1), 0)
+    got = t_init.cpu().numpy().astype(np.float64)
+    scale = np.abs(want).max()
+    # bf16 activations between layers: ~1e-2 relative
+    assert np.abs(got - want).max() <= 3e-2 * scale
+    assert np.corrcoef(got.ravel(), want.ravel())[0, 1] > 0.9995
+
+
+def test_train_step_gradient_matches_reference(solver):
+    import torch
+    from paper_2510_16172_amd import fpt
+    b = _batch(1024, 6100)
+    db = fpt.DeviceBatch(b, with_order=False)
+    out = solver.solve(db, fpt.Opts(scale=b.S, iters=96))
+    mlp = fpt.Mlp(solver, seed=4)
+    W = mlp_ref.unpack(mlp.weights().cpu().numpy().copy())
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    mlp.train_step(db, out, b.S, lr=1e-3, loss_acc=loss)
+    torch.cuda.synchronize()
+    g_gpu = mlp_ref.unpack(mlp.grad().cpu().numpy())
+    Wb = {k: (_bf16(v) if k.startswith("W") else v) for k, v in W.items()}
+    X = _bf16(mlp_ref.features(b, b.S))
+    t = out["t"].cpu().numpy().astype(np.float64)
+    T, M = mlp_ref.targets(b, t, out["status"].cpu().numpy(), b.S)
+    L, g = mlp_ref.loss_and_grad(Wb, X, T, M)
+    assert abs(loss.item() - L) <= 2e-2 * L
+    for k in g:
+        a, w = g_gpu[k].ravel(), g[k].ravel()
+        cos = np.dot(a, w) / (np.linalg.norm(a) * np.linalg.norm(w) + 1e-30)
+        rel = np.linalg.norm(a - w) / (np.linalg.norm(w) + 1e-30)
+        print(f"{k}: cos {cos:.5f} rel {rel:.3e}", flush=True)
+        assert cos > 0.995 and rel < 0.1, k
+
+
+def test_training_reduces_loss(solver):
+    import torch
+    from paper_2510_16172_amd import fpt
+    b = _batch(16384, 6200)
+    db = fpt.DeviceBatch(b, with_order=False)
+    out = solver.solve(db, fpt.Opts(scale=b.S, iters=96))
+    mlp = fpt.Mlp(solver, seed=5)
+    losses = []
+    for epoch in range(30):
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        mlp.train_step(db, out, b.S, lr=2e-3, loss_acc=loss)
+        losses.append(loss.item())
+    print("losses", losses[0], losses[-1], flush=True)
+    assert losses[-1] < 0.5 * losses[0]
+    assert np.all(np.isfinite(losses))

@@ -202,9 +202,9 @@ def test_full_canyon_order2_sampled(solver, oracle_mod):
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 6])
-def test_early_exit_refill_parity(solver, oracle_mod, n):
-    """Per-lane early exit with refill: each lane stops its path after two
-    small steps and takes the next one; same accuracy bar as fixed counts."""
+def test_early_exit_stages_parity(solver, oracle_mod, n):
+    """Early exit in stages: a path stops after two small steps, the others
+    are compacted for the next stage; same accuracy bar as fixed counts."""
     sc = scenes.canyon_scene()
     b = scenes.canyon_sample_paths(sc, 3000, seed=4100 + n, n=n)
     ref = oracle_mod.solve(b, threads=8)
@@ -218,15 +218,62 @@ def test_early_exit_refill_parity(solver, oracle_mod, n):
 
 
 def test_early_exit_deterministic_and_mixed(solver):
-    """Which lane runs a path depends on timing, the path's arithmetic does
-    not: two runs are bit-identical, also with mixed orders and a ragged
-    bucket tail."""
+    """Which list slot holds a path depends on timing, the path's arithmetic
+    does not: two runs are bit-identical, also with mixed orders, ragged
+    buckets and four stages."""
     sc = scenes.canyon_scene()
     b = scenes.canyon_sample_paths(sc, 9999, seed=4200, n=None, n_max=6)
-    opts = _opts(b.S, iters=96, early_exit=True, refill_min=3, refill_every=2)
+    opts = _opts(b.S, iters=96, early_exit=True, stage_iters=[8, 8, 16, 64])
     g1 = gpu_util.run_gpu(solver, b, opts)
     g2 = gpu_util.run_gpu(solver, b, opts)
     for k in g1:
         np.testing.assert_array_equal(g1[k], g2[k])
     from paper_2510_16172_amd import fpt
     assert np.all(g1["status"] & (fpt.ST_INVALID | fpt.ST_NONFINITE) == 0)
+
+
+def test_graph_capture_replays_match_eager(solver):
+    """A captured fpt_solve (bucketing + persistent per-order launches with
+    early exit + refinement) replayed several times, with other work and
+    synchronisations in between, gives the eager result every time."""
+    import torch
+    from paper_2510_16172_amd import fpt
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 20000, seed=4300, n=None, n_max=6)
+    opts = _opts(b.S, iters=64, early_exit=True)
+    db = fpt.DeviceBatch(b)
+    eager = solver.solve(db, opts)
+    torch.cuda.synchronize()
+    eager = {k: v.cpu().numpy() for k, v in eager.items()}
+    st = torch.cuda.Stream()
+    out = solver.alloc_out(db)
+    with torch.cuda.stream(st):
+        graph = solver.capture(db, opts, out, st)
+    for rep in range(3):
+        for v in out.values():
+            v.zero_()
+        torch.cuda.synchronize()
+        graph.launch(st)
+        st.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        for k in eager:
+            np.testing.assert_array_equal(got[k], eager[k], err_msg=f"replay {rep} {k}")
+        # unrelated eager work between replays
+        solver.solve(fpt.DeviceBatch(b.subset(np.arange(100))), opts)
+        torch.cuda.synchronize()
+    graph.close()
+
+
+def test_autotuner_choices_keep_parity(solver, oracle_mod, tmp_path):
+    from paper_2510_16172_amd import autotune
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 12000, seed=4400, n=None, n_max=3)
+    opts = _opts(b.S, iters=64)
+    chosen = autotune.tune(solver, b, opts, sample=4096, repeats=2,
+                           cache_path=str(tmp_path / "tune.json"))
+    assert set(chosen) == {1, 2, 3}
+    ref = oracle_mod.solve(b, threads=8)
+    g = gpu_util.run_gpu(solver, b, opts)
+    _check_common(b, g, ref, min_ok=0.9)
+    for n in (1, 2, 3):
+        solver.set_launch(n, None)
