@@ -116,6 +116,169 @@ def cpu_baseline(batch, out_np, seconds: float, threads: int, seed: int = 7):
             "gpu_certified_but_wrong_on_sample": n_fp}
 
 
+def grad_bytes_per_path(n: int) -> int:
+    """Algorithmic HBM bytes of grad_kernel<n> per path: reads T* (8n),
+    status (1), g_len (4), g_x (12n), src/dst (8), ids (4n); the scene
+    tables and the reduced gradient stay in cache / LDS."""
+    return 8 * n + 1 + 4 + 12 * n + 8 + 4 * n
+
+
+def run_fwd_grad(args, fpt, scenes, torch):
+    """1,048,576 order-3 canyon paths: fpt_solve + fpt_grad (implicit
+    differentiation), and autodiff through 64 unrolled BFGS iterations on a
+    262,144-path subset for comparison."""
+    from paper_2510_16172_amd.unrolled_ad import gather_paths, unrolled_bfgs
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 1 << 20, seed=1004, n=3)
+    g_len, g_x = scenes.upstream_grads(b.N, b.n_max, seed=1104)
+    solver = fpt.Solver(0)
+    db = fpt.DeviceBatch(b, with_order=False)
+    opts = fpt.Opts(scale=b.S, iters=args.iters, fp_iters=args.fp_iters,
+                    early_exit=args.early_exit)
+    out = solver.alloc_out(db)
+    gl = torch.from_numpy(g_len).cuda()
+    gx = torch.from_numpy(g_x).cuda()
+    g_pts = torch.zeros((3, b.Q), dtype=torch.float32, device="cuda")
+    g_obj = torch.zeros((9, b.K), dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        solver.solve(db, opts, out=out)
+        solver.grad(db, out, g_len=gl, g_x=gx, g_pts=g_pts, g_obj=g_obj)
+    torch.cuda.synchronize()
+    solver.set_timing(True)
+    steps = max(3, args.steps // 2)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    t_f = t_g = 0.0
+    for _ in range(steps):
+        e0.record(st)
+        solver.solve(db, opts, out=out)
+        e1.record(st)
+        g_pts.zero_()
+        g_obj.zero_()
+        solver.grad(db, out, g_len=gl, g_x=gx, g_pts=g_pts, g_obj=g_obj)
+        e2.record(st)
+        torch.cuda.synchronize()
+        t_f += e0.elapsed_time(e1)
+        t_g += e1.elapsed_time(e2)
+    kt = solver.kernel_times()
+    solver.set_timing(False)
+    t_f /= steps
+    t_g /= steps
+    cert = int(((out["status"] & fpt.ST_CONVERGED) != 0).sum().item())
+    tg_kernel = kt[fpt.T_GRAD]
+    res = {
+        "workload": "street canyon: 1,048,576 sampled order-3 paths, "
+                    "upstream gradients N(0,1)",
+        "ms_fwd": t_f, "ms_grad": t_g, "grad_kernel_ms": tg_kernel,
+        "certified_fraction": cert / b.N,
+        "converged_paths_per_s_fwd_grad": cert / ((t_f + t_g) * 1e-3),
+        "grad_roofline": {
+            "kernel": "grad_kernel<3>", "bound": "hbm",
+            "achieved": grad_bytes_per_path(3) * b.N / (tg_kernel * 1e-3) / 1e9,
+            "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": grad_bytes_per_path(3) * b.N / (tg_kernel * 1e-3) / PEAK_HBM},
+    }
+    # autodiff through unrolled iterations vs implicit, same subset
+    M = 1 << 18
+    sub = b.subset(np.arange(M))
+    pts = torch.from_numpy(sub.pts).cuda().requires_grad_(True)
+    obj = torch.from_numpy(sub.obj).cuda().requires_grad_(True)
+    src, dst = torch.from_numpy(sub.src).cuda(), torch.from_numpy(sub.dst).cuda()
+    ids = torch.from_numpy(sub.ids).cuda()
+    wl = gl[:M]
+    wx = gx[:, :, :M].permute(2, 0, 1).contiguous()
+
+    def ad_once():
+        pts.grad = None
+        obj.grad = None
+        tx, rx, B, A1, A2 = gather_paths(pts, obj, src, dst, ids)
+        X, L = unrolled_bfgs(tx, rx, B, A1, A2, iters=64)
+        loss = (wl * L).sum() + (wx * X).sum()
+        loss.backward()
+
+    ad_once()
+    torch.cuda.synchronize()
+    e0.record(st)
+    ad_once()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ad_ms = e0.elapsed_time(e1)
+    dbs = fpt.DeviceBatch(sub, with_order=False)
+    outs = solver.solve(dbs, opts)
+    gps = torch.zeros_like(g_pts)
+    gos = torch.zeros_like(g_obj)
+    solver.grad(dbs, outs, g_len=wl.contiguous(), g_x=gx[:, :, :M].contiguous(),
+                g_pts=gps, g_obj=gos)
+    torch.cuda.synchronize()
+    e0.record(st)
+    solver.grad(dbs, outs, g_len=wl.contiguous(), g_x=gx[:, :, :M].contiguous(),
+                g_pts=gps, g_obj=gos)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ift_ms = e0.elapsed_time(e1)
+    e0.record(st)
+    solver.solve(dbs, opts, out=outs)
+    e1.record(st)
+    torch.cuda.synchronize()
+    solve_ms = e0.elapsed_time(e1)
+    res["unrolled_ad"] = {"paths": M, "iters": 64,
+                          "ms_fwd_plus_backprop": ad_ms,
+                          "ms_implicit_grad": ift_ms,
+                          "ms_solve_plus_implicit_grad": solve_ms + ift_ms,
+                          "speedup_of_implicit_grad": ad_ms / ift_ms,
+                          "speedup_of_solve_plus_implicit": ad_ms / (solve_ms + ift_ms)}
+    solver.close()
+    return res
+
+
+def run_uneven(args, fpt, scenes, torch):
+    """8,388,608 canyon paths, orders 1..6 with P(n) ~ 2^-n, one captured
+    HIP graph per step, per-order launch configuration from the autotuner."""
+    from paper_2510_16172_amd import autotune
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 1 << 23, seed=1003, n=None, n_max=6)
+    solver = fpt.Solver(0)
+    opts = fpt.Opts(scale=b.S, iters=64)
+    chosen = autotune.tune(solver, b, opts, sample=1 << 17, repeats=2)
+    db = fpt.DeviceBatch(b)
+    out = solver.alloc_out(db)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        solver.solve(db, opts, out=out, stream=st)
+        st.synchronize()
+        graph = solver.capture(db, opts, out, st)
+        for _ in range(2):
+            graph.launch(st)
+        st.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        steps = max(3, args.steps // 2)
+        e0.record(st)
+        for _ in range(steps):
+            graph.launch(st)
+        e1.record(st)
+        st.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    cert = int(((out["status"] & fpt.ST_CONVERGED) != 0).sum().item())
+    graph.close()
+    solver.close()
+    return {"workload": "street canyon: 8,388,608 paths, orders 1..6 with "
+                        "P(n) proportional to 2^-n, one HIP graph per step",
+            "ms_per_step": ms, "certified_fraction": cert / b.N,
+            "converged_paths_per_s": cert / (ms * 1e-3),
+            "autotuned": {str(k): v for k, v in chosen.items()},
+            "order_counts": {str(n): int((b.order == n).sum()) for n in range(1, 7)}}
+
+
+def run_learned(args, fpt, torch):
+    from paper_2510_16172_amd import learned_init
+    solver = fpt.Solver(0)
+    res, _ = learned_init.run(solver, n_train=1 << 22, n_test=1 << 20,
+                              epochs=args.mlp_epochs,
+                              log=lambda m: print(m, file=sys.stderr, flush=True))
+    solver.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +289,13 @@ def main():
     ap.add_argument("--early-exit", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the forward+gradient leg")
+    ap.add_argument("--uneven", action="store_true",
+                    help="also run the mixed-order (1..6) graph workload")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train and evaluate the learned initialiser")
+    ap.add_argument("--mlp-epochs", type=int, default=4)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of known size (for "
                          "calibrating the HBM byte counters)")
@@ -195,7 +365,7 @@ def main():
         "refine_order2": kt[fpt.T_REFINE + 1],
     }
     res = {
-        "metric": "converged paths/s (fwd) at <=1e-4 rel error",
+        "metric": "converged paths/s (fwd, fwd+grad) at <=1e-4 rel error",
         "value": value,
         "unit": "paths/s",
         "n_gpus": 1,
@@ -232,8 +402,18 @@ def main():
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
         res["cpu_baseline"] = cpu_baseline(batch, out_np, args.cpu_seconds, threads)
-    print(json.dumps(res), flush=True)
     solver.close()
+    del db, out
+    torch.cuda.empty_cache()
+    if not args.no_grad:
+        res["fwd_grad"] = run_fwd_grad(args, fpt, scenes, torch)
+        torch.cuda.empty_cache()
+    if args.uneven:
+        res["uneven_orders"] = run_uneven(args, fpt, scenes, torch)
+        torch.cuda.empty_cache()
+    if args.learned:
+        res["learned_init"] = run_learned(args, fpt, torch)
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

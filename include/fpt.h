@@ -68,8 +68,10 @@ typedef enum {
 
 /* per-path status bits */
 enum {
-  FPT_ST_CONVERGED = 1, /* FP64 Newton certificate: the last full Newton step
-                           moved no point by more than cert_rtol * scale */
+  FPT_ST_CONVERGED = 1, /* FP64 Newton certificate: the last two Newton steps
+                           were taken in full and each moved no point by
+                           more than cert_rtol * scale; no short segment
+                           with a near-unit smoothed direction remains */
   FPT_ST_REFINED = 2,   /* at least one FP64 refinement step was accepted */
   FPT_ST_COLLAPSED = 4, /* two consecutive points closer than 1e-6 * scale */
   FPT_ST_NONFINITE = 8, /* the solve produced a non-finite value */
@@ -115,12 +117,18 @@ typedef struct {
   int32_t stage_iters[FPT_MAX_STAGES]; /* early exit: iterations per stage,
                            0-terminated; the last stage hands over every
                            path that is still running */
+  int32_t quick_steps;  /* > 0: refinement in two passes; first quick_steps
+                           Newton steps at the last level for every path,
+                           then the full schedule for the paths that pass
+                           did not certify (the certificate needs two steps,
+                           so 1 certifies nothing in the first pass).
+                           0: the full schedule for all */
 } fpt_opts;
 
 /* Defaults: 64 iterations, 1 fixed-point iteration, no early exit
  * (exit_rtol = 1e-6, stages of 16, 16 and 32 iterations), refinement levels
- * eps/S = 1e-3, 1e-5, 1e-7 (2 steps each) and 1e-9 (3 steps),
- * cert_rtol = 1e-5, scale = 1. */
+ * eps/S = 1e-3, 1e-5, 1e-7 (2 steps each) and 1e-9 (3 steps) after a quick
+ * pass of 3 steps at 1e-9, cert_rtol = 1e-5, scale = 1. */
 void fpt_default_opts(fpt_opts* opts);
 
 typedef struct {

@@ -92,6 +92,7 @@ extern "C" void fpt_default_opts(fpt_opts* o) {
   o->stage_iters[1] = 16;
   o->stage_iters[2] = 32;
   o->stage_iters[3] = 0;
+  o->quick_steps = 3;
 }
 
 // Keeps the caller's current device and switches to the handle's for the
@@ -220,6 +221,8 @@ static fpt_status check_opts(const fpt_opts* o) {
   }
   if (!(o->cert_rtol >= 0.f) || !(o->exit_rtol >= 0.f))
     return fail(FPT_EINVAL, "fpt_solve: negative tolerance");
+  if (o->quick_steps < 0 || o->quick_steps > 64)
+    return fail(FPT_EINVAL, "fpt_solve: quick_steps outside 0..64");
   if (o->early_exit) {
     if (o->stage_iters[0] < 1)
       return fail(FPT_EINVAL, "fpt_solve: early exit needs stage_iters[0] >= 1");
@@ -261,7 +264,7 @@ static int64_t stage_rcap(int64_t N) {
 static fpt_status ensure_stage(fpt_handle* h, int64_t N, int n_max) {
   const int64_t rcap = stage_rcap(N);
   const int64_t slots = rcap * fpt::kRegions;
-  const int64_t need = (int64_t)fpt::stage_fields_for(n_max) * slots;
+  const int64_t need = n_max > 0 ? (int64_t)fpt::stage_fields_for(n_max) * slots : 0;
   if (h->stage_rcap >= rcap && h->stage_state_cap >= need) return FPT_OK;
   for (int k = 0; k < 2; ++k) {
     if (h->slist[k]) (void)hipFree(h->slist[k]);
@@ -275,13 +278,24 @@ static fpt_status ensure_stage(fpt_handle* h, int64_t N, int n_max) {
     if (hipMalloc(&p, (size_t)slots * sizeof(int32_t)) != hipSuccess)
       return fail(FPT_ENOMEM, "early-exit workspace allocation failed");
     h->slist[k] = (int32_t*)p;
-    if (hipMalloc(&p, (size_t)need * sizeof(float)) != hipSuccess)
-      return fail(FPT_ENOMEM, "early-exit workspace allocation failed");
-    h->sstate[k] = (float*)p;
+    if (need > 0) {
+      if (hipMalloc(&p, (size_t)need * sizeof(float)) != hipSuccess)
+        return fail(FPT_ENOMEM, "early-exit workspace allocation failed");
+      h->sstate[k] = (float*)p;
+    }
   }
   h->stage_rcap = rcap;
   h->stage_state_cap = need;
   return FPT_OK;
+}
+
+// Does any order of this call run the early-exit stages?
+static bool uses_early_exit(const fpt_handle* h, const fpt_opts* o, int n_max) {
+  for (int n = 1; n <= n_max; ++n) {
+    const fpt_launch_cfg& c = h->cfg[n];
+    if (c.use_override ? c.early_exit != 0 : o->early_exit != 0) return true;
+  }
+  return false;
 }
 
 // Event pair around the launches of one timer slot (no-op unless enabled).
@@ -396,6 +410,7 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     A.level_steps[i] = o->level_steps[i];
   }
   A.cert_abs = o->cert_rtol * o->scale;
+  A.quick_steps = o->n_levels > 0 ? o->quick_steps : 0;
 
   hipError_t e;
   int64_t cap = (pa->N + fpt::kBlock - 1) / fpt::kBlock;
@@ -403,13 +418,9 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     int64_t g = (int64_t)h->num_cu * (wg_per_cu > 0 ? wg_per_cu : h->occ[ph][n]);
     return (int)(g < cap ? g : cap);
   };
-  bool any_ee = false;
-  for (int n = 1; n <= pa->n_max; ++n) {
-    const fpt_launch_cfg& c = h->cfg[n];
-    if (c.use_override ? c.early_exit : A.early_exit) any_ee = true;
-  }
-  if (any_ee) {
-    s = ensure_stage(h, pa->N, pa->n_max);
+  const bool any_ee = uses_early_exit(h, o, pa->n_max);
+  if (any_ee || A.quick_steps > 0) {
+    s = ensure_stage(h, pa->N, any_ee ? pa->n_max : 0);
     if (s != FPT_OK) return s;
   }
   const int32_t* perm = nullptr;
@@ -468,8 +479,31 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     }
     {
       SlotTimer tm(h, FPT_T_REFINE + n - 1, st);
+      fpt::StageArgs R;
+      memset(&R, 0, sizeof(R));
       int grid = perm ? persistent(1, n, 0) : (int)cap;
-      e = fpt::launch_solve(1, n, A, perm, bucket, nullptr, grid, st);
+      if (A.quick_steps > 0) {
+        // pass 1: quick steps for all, list the uncertified paths
+        const int nc = fpt::kRegions * fpt::kCounterStride;
+        R.rcap = h->stage_rcap;
+        R.cap = h->stage_rcap * fpt::kRegions;
+        R.out_list = h->slist[0];
+        R.out_count = h->scount;
+        e = fpt::launch_zero_u64(R.out_count, nc, st);
+        if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+        e = fpt::launch_solve(1, n, A, perm, bucket, &R, grid, st);
+        if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+        // pass 2: the full schedule on the list
+        fpt::StageArgs R2;
+        memset(&R2, 0, sizeof(R2));
+        R2.rcap = R.rcap;
+        R2.cap = R.cap;
+        R2.in_list = h->slist[0];
+        R2.in_count = h->scount;
+        e = fpt::launch_solve(1, n, A, perm, bucket, &R2, persistent(1, n, 0), st);
+      } else {
+        e = fpt::launch_solve(1, n, A, perm, bucket, &R, grid, st);
+      }
       if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
     }
   }
@@ -741,7 +775,7 @@ extern "C" fpt_status fpt_graph_capture(fpt_handle* h, const fpt_scene* sc,
     s = ensure_perm(h, pa->N);
     if (s != FPT_OK) return s;
   }
-  s = ensure_stage(h, pa->N, pa->n_max);
+  s = ensure_stage(h, pa->N, uses_early_exit(h, o, pa->n_max) ? pa->n_max : 0);
   if (s != FPT_OK) return s;
   hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return hip_fail(e, "fpt_graph_capture: begin");

@@ -73,6 +73,7 @@ struct SolveArgs {
   float level_eps[FPT_MAX_LEVELS];
   int32_t level_steps[FPT_MAX_LEVELS];
   float cert_abs;  // cert_rtol * scale
+  int32_t quick_steps;  // > 0: two-pass refinement (see refine_kernel)
 };
 
 // One early-exit stage of the FP32 solver (see bfgs_stage_kernel).

@@ -149,22 +149,25 @@ __device__ __forceinline__ double max_disp64(const Geo64<NO>& G,
 // does not lengthen the smoothed path beyond the rounding of L itself.
 template <int NO>
 __device__ __forceinline__ RefineOut refine64(const Geo64<NO>& G, double* t,
-                                              const SolveArgs& A) {
+                                              const SolveArgs& A, bool quick) {
   RefineOut o{false, false, true};
-  bool last_full = false;
-  double last_d2 = INFINITY;
-  for (int lv = 0; lv < A.n_levels; ++lv) {
+  // the last two Newton steps: each taken in full and moving no point by more
+  // than the certificate radius
+  const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
+  bool prev_small = false, last_small = false;
+  // quick: only the last level, with quick_steps steps
+  const int lv0 = quick ? A.n_levels - 1 : 0;
+  for (int lv = lv0; lv < A.n_levels; ++lv) {
     double eps = (double)A.level_eps[lv] * (double)A.scale;
     double eps2 = eps * eps;
-    for (int st = 0; st < A.level_steps[lv]; ++st) {
+    const int nsteps = quick ? A.quick_steps : A.level_steps[lv];
+    for (int st = 0; st < nsteps; ++st) {
       double d[2 * NO];
       bool ok = newton_dir64<NO>(G, t, eps2, d);
-      if (!ok) {
-        last_full = false;
-        last_d2 = INFINITY;
-        continue;
-      }
-      last_d2 = max_disp64<NO>(G, d);
+      prev_small = last_small;
+      last_small = false;
+      if (!ok) continue;
+      const double d2 = max_disp64<NO>(G, d);
       double L0 = length64<NO>(G, t, eps2);
       double slack = 1e-15 * fabs(L0);
       double s = 1.0;
@@ -182,12 +185,15 @@ __device__ __forceinline__ RefineOut refine64(const Geo64<NO>& G, double* t,
         }
         s *= 0.25;
       }
-      last_full = acc && (s == 1.0);
+      last_small = acc && (s == 1.0) && (d2 <= cert2);
       o.refined = o.refined || acc;
     }
   }
-  double cert = (double)A.cert_abs;
-  o.certified = A.n_levels > 0 && last_full && (last_d2 <= cert * cert);
+  // One small full step is not enough: along a nearly flat valley of the
+  // length a Newton step taken from well outside its quadratic region can be
+  // short and still leave the point far from the minimiser (the next step
+  // then jumps). Two consecutive small full steps are required.
+  o.certified = A.n_levels > 0 && prev_small && last_small;
   if (o.certified) {
     // Nonsmooth check. At the smoothed optimum v_i = r_i / l_i plays the role
     // of the subgradient of |r_i|: a genuine collapse (r_i -> 0) has |v_i|
@@ -572,20 +578,51 @@ __global__ __launch_bounds__(kBlock) void bfgs_stage_kernel(
 
 // Phase 2: FP64 refinement of the parameters left by bfgs_kernel in A.t
 // (unit-vector coordinates), certificate, and the final outputs.
+// With quick_steps > 0 the refinement runs in two passes: the first takes
+// quick_steps Newton steps at the last smoothing level for every path of the
+// bucket and hands over the certified ones; the others are listed (by the
+// same region scheme as the early-exit stages: St.out_list) and the second
+// pass (St.in_list) runs the full schedule on them from the FP32 result.
+// St.in_list == St.out_list == null: one pass with the full schedule.
 template <int NO>
 __global__ __launch_bounds__(kBlock) void refine_kernel(
     SolveArgs A, const int32_t* __restrict__ perm,
-    const int64_t* __restrict__ bucket) {
+    const int64_t* __restrict__ bucket, StageArgs St) {
+  __shared__ int64_t pre[kRegions + 1];
   int64_t begin = 0, count = A.N;
-  if (bucket) {
+  if (St.in_list) {
+    if (threadIdx.x == 0) {
+      int64_t acc = 0;
+      for (int r = 0; r < kRegions; ++r) {
+        pre[r] = acc;
+        acc += (int64_t)St.in_count[r * kCounterStride];
+      }
+      pre[kRegions] = acc;
+    }
+    __syncthreads();
+    count = pre[kRegions];
+  } else if (bucket) {
     begin = bucket[NO - 1];
     count = bucket[NO] - begin;
   }
+  const bool quick = St.out_list != nullptr;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const float qnan = __builtin_nanf("");
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
        idx += stride) {
-    const int64_t p = perm ? (int64_t)perm[begin + idx] : idx;
+    int64_t p;
+    if (St.in_list) {
+      int lo = 0, hi = kRegions;
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= idx) lo = mid; else hi = mid;
+      }
+      p = St.in_list[(int64_t)lo * St.rcap + (idx - pre[lo])];
+    } else {
+      p = perm ? (int64_t)perm[begin + idx] : idx;
+    }
     const bool valid = (A.status[p] & FPT_ST_INVALID) == 0;
     Geo64<NO> D;
     float inv[NO][2];
@@ -598,7 +635,22 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
       td[2 * j] = (double)t0 * (double)inv[j][0];
       td[2 * j + 1] = D.edge[j] ? 0.0 : (double)t1 * (double)inv[j][1];
     }
-    RefineOut ro = refine64<NO>(D, td, A);
+    RefineOut ro = refine64<NO>(D, td, A, quick);
+    // first pass: defer the paths it does not certify
+    const bool defer = quick && valid && !ro.certified;
+    const unsigned long long more = __ballot(defer);
+    if (more) {
+      const int region = (int)((idx >> 6) % kRegions);
+      unsigned long long base = 0;
+      if (lane == 0)
+        base = atomicAdd(St.out_count + region * kCounterStride,
+                         (unsigned long long)__popcll(more));
+      base = __shfl(base, 0);
+      if (defer)
+        St.out_list[(int64_t)region * St.rcap +
+                    (int64_t)(base + (unsigned long long)__popcll(more & below))] = (int32_t)p;
+    }
+    if (defer) continue;
     double xs[NO][3];
     points64<NO>(D, td, xs);
     double Lx = 0.0, minl2 = INFINITY;
@@ -797,7 +849,7 @@ static hipError_t launch_phase(int phase, const SolveArgs& A,
                        perm, bucket);
   else if (phase == 1)
     hipLaunchKernelGGL(refine_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
-                       perm, bucket);
+                       perm, bucket, *stage);
   else
     hipLaunchKernelGGL(bfgs_stage_kernel<NO>, dim3(grid), dim3(kBlock), 0,
                        st, A, perm, bucket, *stage);
