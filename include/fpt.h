@@ -172,13 +172,14 @@ fpt_status fpt_grad(fpt_handle* h, const fpt_scene* scene,
 /* Launch configuration of the FP32 solver kernel of one order (what the
  * autotuner chooses). wg_per_cu: resident workgroups per compute unit for
  * the persistent launches (0 = as many as the kernel's register use allows);
- * early_exit / stage_iters override the corresponding fpt_opts fields for
- * paths of that order when use_override is 1. */
+ * early_exit / stage_iters / iters (if > 0) override the corresponding
+ * fpt_opts fields for paths of that order when use_override is 1. */
 typedef struct {
   int32_t wg_per_cu;
   int32_t use_override;
   int32_t early_exit;
   int32_t stage_iters[FPT_MAX_STAGES];
+  int32_t iters;        /* 0..65535; 0 = fpt_opts.iters */
 } fpt_launch_cfg;
 
 /* Sets (cfg != NULL) or resets to defaults (cfg == NULL) the configuration
@@ -224,6 +225,15 @@ enum {
 };
 fpt_status fpt_set_timing(fpt_handle* h, int enable);
 fpt_status fpt_kernel_times(fpt_handle* h, float* ms);
+
+/* Work done by the FP64 refinement while timing is enabled, for the
+ * algorithmic operation count of its kernel: for order n = 1..6,
+ * counts[2(n-1)] = evaluations of the (smoothed) path (points, segment
+ * lengths, unit vectors, total length) and counts[2(n-1)+1] = Newton solves
+ * (gradient and block-tridiagonal Hessian solve), summed over the refinement
+ * launches since the previous read; the counters are then cleared.
+ * Synchronises the device. All zero if timing was never enabled. */
+fpt_status fpt_work_counts(fpt_handle* h, uint64_t counts[2 * FPT_NMAX]);
 
 /* Learned initialiser (a better initial candidate, which Sec. V names as
  * future work): an MLP 66 -> 256 -> 256 -> 256 -> 8 with ReLU that maps the

@@ -1,10 +1,12 @@
 """Autotuner of the per-order launch configuration of the FP32 solver.
 
 For each order present in a workload it times candidate configurations
-(resident workgroups per CU; fixed iteration count vs per-lane early exit
-in stages) on a sample of that order's paths and keeps the one
-with the most certified-converged paths per second of that order's kernels
-(BFGS + refinement, timed with the library's HIP-event timers). Results are
+(resident workgroups per CU; the number of fixed BFGS iterations, or
+per-lane early exit in stages) on a sample of that order's paths and keeps
+the one with the most certified-converged paths per second of that order's
+kernels (BFGS + refinement, timed with the library's HIP-event timers). The
+iteration count trades FP32 BFGS time against FP64 refinement time: paths
+the BFGS leaves further from the minimiser need more Newton steps. Results are
 cached in a JSON file keyed by GPU architecture, order, and a power-of-two
 bucket of the sample size, and applied with fpt_set_launch.
 """
@@ -15,14 +17,12 @@ import os
 
 import numpy as np
 
-DEFAULT_CANDIDATES = [
-    {"wg_per_cu": 0, "early_exit": 0},
-    {"wg_per_cu": 0, "early_exit": 1, "stage_iters": [16, 16, 32]},
-    {"wg_per_cu": 0, "early_exit": 1, "stage_iters": [12, 12, 16, 24]},
-    {"wg_per_cu": 0, "early_exit": 1, "stage_iters": [24, 40]},
-    {"wg_per_cu": 0, "early_exit": 1, "stage_iters": [8, 8, 16, 32]},
-    {"wg_per_cu": 2, "early_exit": 1, "stage_iters": [16, 16, 32]},
-]
+DEFAULT_CANDIDATES = (
+    [{"wg_per_cu": 0, "early_exit": 0, "iters": k}
+     for k in (8, 10, 12, 14, 16, 20, 24, 32, 48, 64)]
+    + [{"wg_per_cu": 0, "early_exit": 1, "iters": 64, "stage_iters": s}
+       for s in ([16, 16, 32], [12, 12, 16, 24], [8, 8, 16, 32])]
+)
 
 
 def default_cache_path() -> str:
@@ -31,7 +31,7 @@ def default_cache_path() -> str:
 
 
 def _key(arch: str, order: int, n: int) -> str:
-    return f"{arch}/order{order}/n2^{max(0, int(np.log2(max(n, 1))))}"
+    return f"v2/{arch}/order{order}/n2^{max(0, int(np.log2(max(n, 1))))}"
 
 
 def tune(solver, batch, opts, candidates=None, sample=1 << 18, repeats=3,

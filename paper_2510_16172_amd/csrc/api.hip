@@ -38,6 +38,7 @@ struct fpt_handle {
   bool timing = false;
   hipEvent_t ev[FPT_TIMERS][kRing][2] = {};
   int nrec[FPT_TIMERS] = {};  // launches recorded since the last read
+  unsigned long long* work = nullptr;  // [FPT_NMAX][2] refinement counters
   // workspace
   int32_t* perm = nullptr;
   uint32_t* ccount = nullptr;  // per-chunk order counts / offsets
@@ -165,6 +166,7 @@ extern "C" fpt_status fpt_destroy(fpt_handle* h) {
   if (h->perm) (void)hipFree(h->perm);
   if (h->ccount) (void)hipFree(h->ccount);
   if (h->counts) (void)hipFree(h->counts);
+  if (h->work) (void)hipFree(h->work);
   if (h->scount) (void)hipFree(h->scount);
   if (h->mlp_mem) (void)hipFree(h->mlp_mem);
   for (int k = 0; k < 2; ++k) {
@@ -332,8 +334,28 @@ extern "C" fpt_status fpt_set_timing(fpt_handle* h, int enable) {
             return hip_fail(e, "fpt_set_timing: hipEventCreate");
         }
   }
+  if (enable && !h->work) {
+    hipError_t e = hipMalloc(&h->work, 2 * FPT_NMAX * sizeof(unsigned long long));
+    if (e != hipSuccess) return hip_fail(e, "fpt_set_timing: hipMalloc");
+    e = hipMemset(h->work, 0, 2 * FPT_NMAX * sizeof(unsigned long long));
+    if (e != hipSuccess) return hip_fail(e, "fpt_set_timing: hipMemset");
+  }
   h->timing = enable != 0;
   for (int i = 0; i < FPT_TIMERS; ++i) h->nrec[i] = 0;
+  return FPT_OK;
+}
+
+extern "C" fpt_status fpt_work_counts(fpt_handle* h, uint64_t* counts) {
+  if (!h || !counts) return fail(FPT_EINVAL, "fpt_work_counts: NULL argument");
+  DeviceGuard g(h->device);
+  for (int i = 0; i < 2 * FPT_NMAX; ++i) counts[i] = 0;
+  if (!h->work) return FPT_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess)
+    e = hipMemcpy(counts, h->work, 2 * FPT_NMAX * sizeof(uint64_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemset(h->work, 0, 2 * FPT_NMAX * sizeof(unsigned long long));
+  if (e != hipSuccess) return hip_fail(e, "fpt_work_counts");
   return FPT_OK;
 }
 
@@ -441,13 +463,16 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     const fpt_launch_cfg& c = h->cfg[n];
     const bool ee = c.use_override ? c.early_exit != 0 : A.early_exit != 0;
     const int32_t* stages = (c.use_override && ee) ? c.stage_iters : o->stage_iters;
+    fpt::SolveArgs An = A;
+    if (c.use_override && c.iters > 0) An.n_iter = c.iters;
+    An.work = (h->timing && h->work) ? h->work + 2 * (n - 1) : nullptr;
     {
       SlotTimer tm(h, FPT_T_BFGS + n - 1, st);
       if (!ee) {
         // one path per thread over the whole input, or persistent over the
         // bucket (its size is only known on the device)
         int grid = perm ? persistent(0, n, c.wg_per_cu) : (int)cap;
-        e = fpt::launch_solve(0, n, A, perm, bucket, nullptr, grid, st);
+        e = fpt::launch_solve(0, n, An, perm, bucket, nullptr, grid, st);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
       } else {
         int ns = 0;
@@ -472,7 +497,7 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
             if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
           }
           int grid = (k == 0 && !perm) ? (int)cap : persistent(2, n, c.wg_per_cu);
-          e = fpt::launch_solve(2, n, A, perm, bucket, &S, grid, st);
+          e = fpt::launch_solve(2, n, An, perm, bucket, &S, grid, st);
           if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         }
       }
@@ -491,7 +516,7 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
         R.out_count = h->scount;
         e = fpt::launch_zero_u64(R.out_count, nc, st);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
-        e = fpt::launch_solve(1, n, A, perm, bucket, &R, grid, st);
+        e = fpt::launch_solve(1, n, An, perm, bucket, &R, grid, st);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         // pass 2: the full schedule on the list
         fpt::StageArgs R2;
@@ -500,9 +525,9 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
         R2.cap = R.cap;
         R2.in_list = h->slist[0];
         R2.in_count = h->scount;
-        e = fpt::launch_solve(1, n, A, perm, bucket, &R2, persistent(1, n, 0), st);
+        e = fpt::launch_solve(1, n, An, perm, bucket, &R2, persistent(1, n, 0), st);
       } else {
-        e = fpt::launch_solve(1, n, A, perm, bucket, &R, grid, st);
+        e = fpt::launch_solve(1, n, An, perm, bucket, &R, grid, st);
       }
       if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
     }
@@ -737,6 +762,8 @@ extern "C" fpt_status fpt_set_launch(fpt_handle* h, int order,
   }
   if (cfg->wg_per_cu < 0 || cfg->wg_per_cu > 32)
     return fail(FPT_EINVAL, "fpt_set_launch: wg_per_cu outside 0..32");
+  if (cfg->use_override && (cfg->iters < 0 || cfg->iters > 65535))
+    return fail(FPT_EINVAL, "fpt_set_launch: iters outside 0..65535");
   if (cfg->use_override && cfg->early_exit) {
     if (cfg->stage_iters[0] < 1)
       return fail(FPT_EINVAL, "fpt_set_launch: early exit needs stage_iters[0] >= 1");

@@ -74,6 +74,9 @@ struct SolveArgs {
   int32_t level_steps[FPT_MAX_LEVELS];
   float cert_abs;  // cert_rtol * scale
   int32_t quick_steps;  // > 0: two-pass refinement (see refine_kernel)
+  // null, or two counters of the launch's order: FP64 path evaluations and
+  // Newton solves made by refine_kernel (work accounting while timing)
+  unsigned long long* work;
 };
 
 // One early-exit stage of the FP32 solver (see bfgs_stage_kernel).

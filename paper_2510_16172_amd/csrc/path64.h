@@ -85,12 +85,18 @@ __device__ __forceinline__ void segments64(const Geo64<NO>& G,
   }
 }
 
+// Segments of the (smoothed) length at t and the length itself.
 template <int NO>
-__device__ __forceinline__ double length64(const Geo64<NO>& G,
-                                           const double* t, double eps2) {
+struct Seg64 {
+  double v[NO + 1][3], il[NO + 1], L;
+};
+
+template <int NO>
+__device__ __forceinline__ void eval64(const Geo64<NO>& G, const double* t,
+                                       double eps2, Seg64<NO>& s) {
   double x[NO][3];
   points64<NO>(G, t, x);
-  double L = 0.0;
+  s.L = 0.0;
 #pragma unroll
   for (int i = 0; i <= NO; ++i) {
     double r[3];
@@ -98,9 +104,11 @@ __device__ __forceinline__ double length64(const Geo64<NO>& G,
     for (int c = 0; c < 3; ++c)
       r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
     double q = fmax(dot3d(r, r) + eps2, 1e-300);
-    L += q * rsq64(q);
+    s.il[i] = rsq64(q);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s.v[i][c] = r[c] * s.il[i];
+    s.L += q * s.il[i];
   }
-  return L;
 }
 
 // Gradient of the (smoothed) length: g_j = A_j^T (v_j - v_{j+1}); the padded

@@ -116,19 +116,6 @@ __device__ __forceinline__ void load_geo64(const SolveArgs& A, int64_t p,
   }
 }
 
-// Newton direction d = -H^{-1} g of the eps-smoothed length at t.
-template <int NO>
-__device__ __forceinline__ bool newton_dir64(const Geo64<NO>& G,
-                                             const double* t, double eps2,
-                                             double* d) {
-  double v[NO + 1][3], il[NO + 1], g[2 * NO];
-  segments64<NO>(G, t, eps2, v, il);
-  gradient64<NO>(G, v, g);
-#pragma unroll
-  for (int k = 0; k < 2 * NO; ++k) g[k] = -g[k];
-  return hess_solve64<NO>(G, v, il, g, d);
-}
-
 template <int NO>
 __device__ __forceinline__ double max_disp64(const Geo64<NO>& G,
                                              const double* d) {
@@ -146,10 +133,13 @@ __device__ __forceinline__ double max_disp64(const Geo64<NO>& G,
 
 // Damped Newton refinement, level by level. t is in the caller's
 // parametrisation. A trial step s*d (s = 1, 1/4, 1/16, ...) is taken if it
-// does not lengthen the smoothed path beyond the rounding of L itself.
+// does not lengthen the smoothed path beyond the rounding of L itself. The
+// segments of an accepted trial are those of the next step, so each step
+// evaluates the path once per trial.
 template <int NO>
 __device__ __forceinline__ RefineOut refine64(const Geo64<NO>& G, double* t,
-                                              const SolveArgs& A, bool quick) {
+                                              const SolveArgs& A, bool quick,
+                                              uint32_t& n_eval, uint32_t& n_solve) {
   RefineOut o{false, false, true};
   // the last two Newton steps: each taken in full and moving no point by more
   // than the certificate radius
@@ -161,29 +151,44 @@ __device__ __forceinline__ RefineOut refine64(const Geo64<NO>& G, double* t,
     double eps = (double)A.level_eps[lv] * (double)A.scale;
     double eps2 = eps * eps;
     const int nsteps = quick ? A.quick_steps : A.level_steps[lv];
+    Seg64<NO> cur;
+    eval64<NO>(G, t, eps2, cur);
+    ++n_eval;
     for (int st = 0; st < nsteps; ++st) {
-      double d[2 * NO];
-      bool ok = newton_dir64<NO>(G, t, eps2, d);
+      double g[2 * NO], d[2 * NO];
+      gradient64<NO>(G, cur.v, g);
+#pragma unroll
+      for (int k = 0; k < 2 * NO; ++k) g[k] = -g[k];
+      const double bound = cur.L + 1e-15 * fabs(cur.L);
+      const bool ok = hess_solve64<NO>(G, cur.v, cur.il, g, d);
+      ++n_solve;
       prev_small = last_small;
       last_small = false;
       if (!ok) continue;
       const double d2 = max_disp64<NO>(G, d);
-      double L0 = length64<NO>(G, t, eps2);
-      double slack = 1e-15 * fabs(L0);
       double s = 1.0;
       bool acc = false;
       for (int h = 0; h < 7; ++h) {
         double tn[2 * NO];
 #pragma unroll
         for (int k = 0; k < 2 * NO; ++k) tn[k] = fma(s, d[k], t[k]);
-        double L1 = length64<NO>(G, tn, eps2);
-        if (L1 <= L0 + slack) {
+        Seg64<NO> nx;
+        eval64<NO>(G, tn, eps2, nx);
+        ++n_eval;
+        if (nx.L <= bound) {
 #pragma unroll
           for (int k = 0; k < 2 * NO; ++k) t[k] = tn[k];
+          cur = nx;
           acc = true;
           break;
         }
         s *= 0.25;
+      }
+      // (the segments at t are not kept across the trials: recomputed here
+      // in the rare case that every trial failed)
+      if (!acc) {
+        eval64<NO>(G, t, eps2, cur);
+        ++n_eval;
       }
       last_small = acc && (s == 1.0) && (d2 <= cert2);
       o.refined = o.refined || acc;
@@ -211,9 +216,9 @@ __device__ __forceinline__ RefineOut refine64(const Geo64<NO>& G, double* t,
 #pragma unroll
       for (int c = 0; c < 3; ++c)
         r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
+      // |v_i|^2 = q / (q + eps^2) > 0.98^2
       double q = dot3d(r, r);
-      double v2 = q / (q + eps * eps);
-      if (q < short2 && v2 > 0.98 * 0.98) o.certified = false;
+      if (q < short2 && q > (0.98 * 0.98) * (q + eps * eps)) o.certified = false;
     }
   }
   return o;
@@ -610,6 +615,7 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const float qnan = __builtin_nanf("");
+  uint32_t n_eval = 0, n_solve = 0;
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
        idx += stride) {
     int64_t p;
@@ -635,7 +641,7 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
       td[2 * j] = (double)t0 * (double)inv[j][0];
       td[2 * j + 1] = D.edge[j] ? 0.0 : (double)t1 * (double)inv[j][1];
     }
-    RefineOut ro = refine64<NO>(D, td, A, quick);
+    RefineOut ro = refine64<NO>(D, td, A, quick, n_eval, n_solve);
     // first pass: defer the paths it does not certify
     const bool defer = quick && valid && !ro.certified;
     const unsigned long long more = __ballot(defer);
@@ -693,6 +699,18 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
     }
     A.len[p] = valid ? (float)Lx : qnan;
     A.status[p] = st;
+  }
+  if (A.work) {
+    // wave sums, one atomic per wave
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      n_eval += __shfl_xor(n_eval, off);
+      n_solve += __shfl_xor(n_solve, off);
+    }
+    if (lane == 0) {
+      atomicAdd(A.work, (unsigned long long)n_eval);
+      atomicAdd(A.work + 1, (unsigned long long)n_solve);
+    }
   }
 }
 

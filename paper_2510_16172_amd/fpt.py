@@ -48,7 +48,8 @@ class _Opts(ctypes.Structure):
 
 class _LaunchCfg(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("use_override", ctypes.c_int32),
-                ("early_exit", ctypes.c_int32), ("stage_iters", ctypes.c_int32 * 4)]
+                ("early_exit", ctypes.c_int32), ("stage_iters", ctypes.c_int32 * 4),
+                ("iters", ctypes.c_int32)]
 
 
 class _Out(ctypes.Structure):
@@ -119,6 +120,8 @@ def load_library(path: str = LIB_PATH):
     lib.fpt_graph_launch.restype = ctypes.c_int
     lib.fpt_graph_destroy.argtypes = [_P]
     lib.fpt_graph_destroy.restype = ctypes.c_int
+    lib.fpt_work_counts.argtypes = [_P, ctypes.POINTER(ctypes.c_uint64)]
+    lib.fpt_work_counts.restype = ctypes.c_int
     lib.fpt_last_error.argtypes = []
     lib.fpt_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -265,6 +268,13 @@ class Solver:
         _check(load_library().fpt_kernel_times(self._h, ms), "fpt_kernel_times")
         return [float(v) for v in ms]
 
+    def work_counts(self):
+        """{order: (path evaluations, Newton solves)} of the FP64 refinement
+        since the previous read (counted while timing is enabled)."""
+        c = (ctypes.c_uint64 * 12)()
+        _check(load_library().fpt_work_counts(self._h, c), "fpt_work_counts")
+        return {n: (int(c[2 * n - 2]), int(c[2 * n - 1])) for n in range(1, 7)}
+
     def set_launch(self, order: int, cfg: dict | None):
         """Per-order launch configuration (see fpt_launch_cfg); None resets."""
         lib = load_library()
@@ -273,8 +283,9 @@ class Solver:
             return
         c = _LaunchCfg()
         c.wg_per_cu = int(cfg.get("wg_per_cu", 0))
-        c.use_override = 1 if "early_exit" in cfg else 0
+        c.use_override = 1 if ("early_exit" in cfg or "iters" in cfg) else 0
         c.early_exit = int(cfg.get("early_exit", 0))
+        c.iters = int(cfg.get("iters", 0))
         st = list(cfg.get("stage_iters", [16, 16, 32]))
         for i in range(4):
             c.stage_iters[i] = int(st[i]) if i < len(st) else 0

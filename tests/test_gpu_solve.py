@@ -277,3 +277,53 @@ def test_autotuner_choices_keep_parity(solver, oracle_mod, tmp_path):
     _check_common(b, g, ref, min_ok=0.9)
     for n in (1, 2, 3):
         solver.set_launch(n, None)
+
+
+def test_launch_iters_override_matches_opts(solver):
+    """A per-order iteration count set with fpt_set_launch gives the same
+    result as the same count in fpt_opts."""
+    from paper_2510_16172_amd import fpt
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 20000, seed=4500, n=None, n_max=3)
+    want = gpu_util.run_gpu(solver, b, _opts(b.S, iters=12))
+    for n in (1, 2, 3):
+        solver.set_launch(n, {"iters": 12})
+    try:
+        got = gpu_util.run_gpu(solver, b, _opts(b.S, iters=64))
+    finally:
+        for n in (1, 2, 3):
+            solver.set_launch(n, None)
+    for k in want:
+        np.testing.assert_array_equal(got[k], want[k], err_msg=k)
+    with pytest.raises(fpt.FptError):
+        solver.set_launch(2, {"iters": -1})
+
+
+def test_refine_work_counts(solver):
+    """The refinement's evaluation / Newton-solve counters: every path of an
+    order starts one level and takes at least quick_steps solves; nothing is
+    counted while timing is off."""
+    import torch
+    from paper_2510_16172_amd import fpt
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 30000, seed=4600, n=None, n_max=3)
+    opts = _opts(b.S, iters=16)
+    db = fpt.DeviceBatch(b)
+    solver.set_timing(True)
+    solver.work_counts()
+    out = solver.solve(db, opts)
+    torch.cuda.synchronize()
+    wc = solver.work_counts()
+    solver.kernel_times()
+    solver.set_timing(False)
+    total_levels = sum(opts.level_steps)
+    for n in (1, 2, 3):
+        cnt = int((b.order == n).sum())
+        ev, so = wc[n]
+        assert so >= opts.quick_steps * cnt
+        assert so <= (opts.quick_steps + total_levels) * cnt
+        assert ev >= cnt + so // 2
+    assert wc[4] == (0, 0)
+    solver.solve(db, opts, out=out)
+    torch.cuda.synchronize()
+    assert all(v == (0, 0) for v in solver.work_counts().values())
