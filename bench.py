@@ -77,8 +77,10 @@ def refine_solve_flops(n: int) -> int:
     and projection dot products 35, diagonal blocks 21, determinant 3,
     reciprocal 7, inverse 3, back substitution 14 per slot; off-diagonal
     block 42 and Schur complement 38 per coupling; largest displacement 14n;
-    bound 2; trial point 4n."""
-    return 13 * n + 83 * n + 80 * (n - 1) + 14 * n + 2 + 4 * n
+    bound 2; trial point 4n; majorant step along d: point changes 9n,
+    segment changes 3(n+1), two sums 12(n+1), reciprocal and product 8."""
+    return (13 * n + 83 * n + 80 * (n - 1) + 14 * n + 2 + 4 * n
+            + 9 * n + 15 * (n + 1) + 8)
 
 
 def refine_final_flops(n: int) -> int:
@@ -394,8 +396,7 @@ def main():
     for _ in range(args.warmup):
         solver.solve(db, opts, out=out, stream=stream)
     torch.cuda.synchronize()
-    solver.set_timing(True)
-    solver.work_counts()  # clear
+    # the timed steps (no library instrumentation)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     ev[0].record(stream)
@@ -405,6 +406,12 @@ def main():
     torch.cuda.synchronize()
     ms_step = ev[0].elapsed_time(ev[-1]) / args.steps
     per_step = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    # the same steps again with the per-kernel HIP-event timers and the
+    # refinement work counters on, for the kernel breakdown and rooflines
+    solver.set_timing(True)
+    solver.work_counts()  # clear
+    for k in range(args.steps):
+        solver.solve(db, opts, out=out, stream=stream)
     kt = solver.kernel_times()
     work = solver.work_counts()
     solver.set_timing(False)
@@ -424,8 +431,10 @@ def main():
             + int(o2.sum()) * bfgs_init_flops(2))
     t_b = kt[fpt.T_BFGS + 1] * 1e-3
     kname_b = "bfgs_stage_kernel<2>" if ee2 else "bfgs_kernel<2>"
-    n_eval, n_solve = (v / args.steps for v in work[2])
+    n_eval, n_solve, m_eval, m_solve = (v / args.steps for v in work[2])
+    # refinement passes at order 2, reduced paths of the collapse step at 1
     fl_r = (n_eval * refine_eval_flops(2) + n_solve * refine_solve_flops(2)
+            + m_eval * refine_eval_flops(1) + m_solve * refine_solve_flops(1)
             + int(o2.sum()) * refine_final_flops(2))
     t_r = kt[fpt.T_REFINE + 1] * 1e-3
     roof_b = {
@@ -437,12 +446,14 @@ def main():
         "traffic": read_traffic(kname_b.split("<")[0] + "_2", workload),
     }
     roof_r = {
-        "kernel": "refine_kernel<2> (both passes)",
+        "kernel": "refine_kernel<2> (both passes) + merge_kernel<2>",
         "bound": "alu", "achieved": fl_r / t_r / 1e12, "peak": PEAK_FP64 / 1e12,
         "unit": "TFLOP/s", "frac": fl_r / t_r / PEAK_FP64,
         "flops_per_launch": fl_r, "ms": t_r * 1e3,
         "evaluations_per_path": n_eval / int(o2.sum()),
         "newton_solves_per_path": n_solve / int(o2.sum()),
+        "collapse_step_evaluations_per_path": m_eval / int(o2.sum()),
+        "collapse_step_solves_per_path": m_solve / int(o2.sum()),
         "traffic": read_traffic("refine_kernel_2", workload),
     }
     dominant, other = (roof_b, roof_r) if t_b >= t_r else (roof_r, roof_b)

@@ -71,7 +71,14 @@ enum {
   FPT_ST_CONVERGED = 1, /* FP64 Newton certificate: the last two Newton steps
                            were taken in full and each moved no point by
                            more than cert_rtol * scale; no short segment
-                           with a near-unit smoothed direction remains */
+                           with a near-unit smoothed direction remains. Or,
+                           for a minimiser where two consecutive interaction
+                           points coincide (with FPT_ST_COLLAPSED): the path
+                           with the two merged on the intersection of their
+                           objects passed that certificate, and a subgradient
+                           of the zero-length segment of norm below 1
+                           (squared norm <= 1 - 1e-6)
+                           satisfies the stationarity of both points */
   FPT_ST_REFINED = 2,   /* at least one FP64 refinement step was accepted */
   FPT_ST_COLLAPSED = 4, /* two consecutive points closer than 1e-6 * scale */
   FPT_ST_NONFINITE = 8, /* the solve produced a non-finite value */
@@ -147,7 +154,11 @@ fpt_status fpt_create(int device, fpt_handle** h);
 fpt_status fpt_destroy(fpt_handle* h);
 
 /* Solves every path (Sec. III-B Eq. 4 by the BFGS / fixed-point method of
- * Sec. III-C, then FP64 refinement). See the layout notes above. */
+ * Sec. III-C, then FP64 refinement). See the layout notes above. With
+ * quick_steps > 0, the paths of order >= 2 that the quick pass does not
+ * certify and that have exactly one short interior segment are first tried
+ * as collapsed minimisers (see FPT_ST_CONVERGED); the rest get the full
+ * schedule. */
 fpt_status fpt_solve(fpt_handle* h, const fpt_scene* scene,
                      const fpt_paths* paths, const fpt_opts* opts,
                      const fpt_out* out, void* hip_stream);
@@ -227,13 +238,15 @@ fpt_status fpt_set_timing(fpt_handle* h, int enable);
 fpt_status fpt_kernel_times(fpt_handle* h, float* ms);
 
 /* Work done by the FP64 refinement while timing is enabled, for the
- * algorithmic operation count of its kernel: for order n = 1..6,
- * counts[2(n-1)] = evaluations of the (smoothed) path (points, segment
- * lengths, unit vectors, total length) and counts[2(n-1)+1] = Newton solves
- * (gradient and block-tridiagonal Hessian solve), summed over the refinement
+ * algorithmic operation count of its kernels: for order n = 1..6,
+ * counts[4(n-1)] = evaluations of the (smoothed) path (points, segment
+ * lengths, unit vectors, total length) and counts[4(n-1)+1] = Newton solves
+ * (gradient and block-tridiagonal Hessian solve) of the two refinement
+ * passes; counts[4(n-1)+2], counts[4(n-1)+3] = the same for the reduced
+ * paths of order n-1 solved by the collapse (merge) step. Summed over the
  * launches since the previous read; the counters are then cleared.
  * Synchronises the device. All zero if timing was never enabled. */
-fpt_status fpt_work_counts(fpt_handle* h, uint64_t counts[2 * FPT_NMAX]);
+fpt_status fpt_work_counts(fpt_handle* h, uint64_t counts[4 * FPT_NMAX]);
 
 /* Learned initialiser (a better initial candidate, which Sec. V names as
  * future work): an MLP 66 -> 256 -> 256 -> 256 -> 8 with ReLU that maps the

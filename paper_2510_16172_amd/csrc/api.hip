@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "common.h"
 
@@ -32,13 +33,13 @@ hipError_t launch_grad_invalid(const GradArgs& A, const int32_t* perm,
 struct fpt_handle {
   int device;
   int num_cu;
-  int occ[3][FPT_NMAX + 1];  // resident workgroups per CU, per phase/order
+  int occ[4][FPT_NMAX + 1];  // resident workgroups per CU, per phase/order
   // optional per-kernel timing
   static constexpr int kRing = 32;
   bool timing = false;
   hipEvent_t ev[FPT_TIMERS][kRing][2] = {};
   int nrec[FPT_TIMERS] = {};  // launches recorded since the last read
-  unsigned long long* work = nullptr;  // [FPT_NMAX][2] refinement counters
+  unsigned long long* work = nullptr;  // [FPT_NMAX][4][kWorkSlots] counters
   // workspace
   int32_t* perm = nullptr;
   uint32_t* ccount = nullptr;  // per-chunk order counts / offsets
@@ -131,7 +132,7 @@ extern "C" fpt_status fpt_create(int device, fpt_handle** out) {
   fpt_handle* h = new fpt_handle();
   h->device = device;
   h->num_cu = prop.multiProcessorCount;
-  for (int ph = 0; ph < 3; ++ph)
+  for (int ph = 0; ph < 4; ++ph)
     for (int n = 1; n <= FPT_NMAX; ++n) {
       int occ = 0;
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -335,9 +336,10 @@ extern "C" fpt_status fpt_set_timing(fpt_handle* h, int enable) {
         }
   }
   if (enable && !h->work) {
-    hipError_t e = hipMalloc(&h->work, 2 * FPT_NMAX * sizeof(unsigned long long));
+    const size_t bytes = 4 * FPT_NMAX * fpt::kWorkSlots * sizeof(unsigned long long);
+    hipError_t e = hipMalloc(&h->work, bytes);
     if (e != hipSuccess) return hip_fail(e, "fpt_set_timing: hipMalloc");
-    e = hipMemset(h->work, 0, 2 * FPT_NMAX * sizeof(unsigned long long));
+    e = hipMemset(h->work, 0, bytes);
     if (e != hipSuccess) return hip_fail(e, "fpt_set_timing: hipMemset");
   }
   h->timing = enable != 0;
@@ -348,14 +350,17 @@ extern "C" fpt_status fpt_set_timing(fpt_handle* h, int enable) {
 extern "C" fpt_status fpt_work_counts(fpt_handle* h, uint64_t* counts) {
   if (!h || !counts) return fail(FPT_EINVAL, "fpt_work_counts: NULL argument");
   DeviceGuard g(h->device);
-  for (int i = 0; i < 2 * FPT_NMAX; ++i) counts[i] = 0;
+  for (int i = 0; i < 4 * FPT_NMAX; ++i) counts[i] = 0;
   if (!h->work) return FPT_OK;
+  const int nw = 4 * FPT_NMAX * fpt::kWorkSlots;
+  std::vector<uint64_t> slots(nw);
+  const size_t bytes = nw * sizeof(uint64_t);
   hipError_t e = hipDeviceSynchronize();
-  if (e == hipSuccess)
-    e = hipMemcpy(counts, h->work, 2 * FPT_NMAX * sizeof(uint64_t), hipMemcpyDeviceToHost);
-  if (e == hipSuccess)
-    e = hipMemset(h->work, 0, 2 * FPT_NMAX * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemcpy(slots.data(), h->work, bytes, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemset(h->work, 0, bytes);
   if (e != hipSuccess) return hip_fail(e, "fpt_work_counts");
+  for (int i = 0; i < 4 * FPT_NMAX; ++i)
+    for (int s = 0; s < fpt::kWorkSlots; ++s) counts[i] += slots[i * fpt::kWorkSlots + s];
   return FPT_OK;
 }
 
@@ -465,7 +470,7 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     const int32_t* stages = (c.use_override && ee) ? c.stage_iters : o->stage_iters;
     fpt::SolveArgs An = A;
     if (c.use_override && c.iters > 0) An.n_iter = c.iters;
-    An.work = (h->timing && h->work) ? h->work + 2 * (n - 1) : nullptr;
+    An.work = (h->timing && h->work) ? h->work + 4 * fpt::kWorkSlots * (n - 1) : nullptr;
     {
       SlotTimer tm(h, FPT_T_BFGS + n - 1, st);
       if (!ee) {
@@ -518,13 +523,27 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         e = fpt::launch_solve(1, n, An, perm, bucket, &R, grid, st);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
-        // pass 2: the full schedule on the list
         fpt::StageArgs R2;
         memset(&R2, 0, sizeof(R2));
         R2.rcap = R.rcap;
         R2.cap = R.cap;
         R2.in_list = h->slist[0];
         R2.in_count = h->scount;
+        if (n >= 2) {
+          // collapsed minimisers: merge attempt on the list, the rest listed
+          // again for pass 2
+          fpt::StageArgs Mg = R2;
+          Mg.out_list = h->slist[1];
+          Mg.out_count = h->scount + nc;
+          e = fpt::launch_zero_u64(Mg.out_count, nc, st);
+          if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+          e = fpt::launch_solve(3, n, An, nullptr, nullptr, &Mg,
+                                persistent(3, n, 0), st);
+          if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+          R2.in_list = h->slist[1];
+          R2.in_count = Mg.out_count;
+        }
+        // pass 2: the full schedule on the list
         e = fpt::launch_solve(1, n, An, perm, bucket, &R2, persistent(1, n, 0), st);
       } else {
         e = fpt::launch_solve(1, n, An, perm, bucket, &R, grid, st);

@@ -11,7 +11,8 @@ namespace fpt {
 constexpr int kBlock = 256;  // threads per workgroup: four wave64s
 constexpr int kSortChunk = 8192;  // paths per workgroup in the order sort
 constexpr int kRegions = 64;      // list regions of an early-exit stage
-constexpr int kCounterStride = 16;  // u64 counters 128 bytes apart
+constexpr int kCounterStride = 16;
+constexpr int kWorkSlots = 64;  // u64 counters 128 bytes apart
 
 // Hardware reciprocal square root (v_rsq_f32), about 1 ulp.
 __device__ __forceinline__ float rsq32(float x) {
@@ -74,8 +75,10 @@ struct SolveArgs {
   int32_t level_steps[FPT_MAX_LEVELS];
   float cert_abs;  // cert_rtol * scale
   int32_t quick_steps;  // > 0: two-pass refinement (see refine_kernel)
-  // null, or two counters of the launch's order: FP64 path evaluations and
-  // Newton solves made by refine_kernel (work accounting while timing)
+  // null, or the work counters of the launch's order (accounting while
+  // timing): [4][kWorkSlots] FP64 path evaluations and Newton solves of
+  // refine_kernel, then of merge_kernel's reduced paths; a wave adds to
+  // slot blockIdx.x % kWorkSlots so that the atomics do not contend
   unsigned long long* work;
 };
 

@@ -16,7 +16,8 @@ struct Geo64 {
   double tx[3], rx[3];
   double b[NO][3];
   double a[NO][2][3];  // caller's basis vectors (a[j][1] = 0 for an edge)
-  bool edge[NO];
+  bool edge[NO];   // second parameter masked (padding)
+  bool fixed[NO];  // both parameters masked: a fixed point (reduced paths)
 };
 
 // Geometry of path p in FP64 (exact widening of the FP32 tables). Indices out
@@ -48,6 +49,7 @@ __device__ __forceinline__ void load_geo64(const float* __restrict__ obj,
     }
     bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
     D.edge[j] = edge;
+    D.fixed[j] = false;
 #pragma unroll
     for (int c = 0; c < 3; ++c) D.a[j][1][c] = edge ? 0.0 : (double)a2[c];
   }
@@ -121,7 +123,7 @@ __device__ __forceinline__ void gradient64(const Geo64<NO>& G,
     double du[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) du[c] = v[j][c] - v[j + 1][c];
-    g[2 * j] = dot3d(G.a[j][0], du);
+    g[2 * j] = G.fixed[j] ? 0.0 : dot3d(G.a[j][0], du);
     g[2 * j + 1] = G.edge[j] ? 0.0 : dot3d(G.a[j][1], du);
   }
 }
@@ -134,7 +136,8 @@ __device__ __forceinline__ void gradient64(const Geo64<NO>& G,
 // and is solved by block-Thomas elimination (forward Schur complements
 // S_j = D_j - E_{j-1}^T S_{j-1}^{-1} E_{j-1}, then back substitution).
 // The padded parameter of an edge has a zero row and column in H; its
-// diagonal is set to 1 and its right-hand side to 0, so its d is 0.
+// diagonal is set to 1 and its right-hand side to 0, so its d is 0. A fixed
+// slot has both parameters masked that way.
 // Returns false if a pivot block is not positive definite or d is not finite.
 template <int NO>
 __device__ __forceinline__ bool hess_solve64(const Geo64<NO>& G,
@@ -159,6 +162,11 @@ __device__ __forceinline__ bool hess_solve64(const Geo64<NO>& G,
       D01 = 0.0;
       D11 = 1.0;
       rhs1 = 0.0;
+    }
+    if (G.fixed[j]) {
+      D00 = 1.0;
+      D01 = 0.0;
+      rhs0 = 0.0;
     }
     if (j > 0) {
       // W = S_{j-1}^{-1} E_{j-1}; E rows: parameters of slot j-1
@@ -193,6 +201,8 @@ __device__ __forceinline__ bool hess_solve64(const Geo64<NO>& G,
       E[j][3] = -(dot3d(a1, b1) - pout1 * qn1) * il1;
       if (G.edge[j]) E[j][2] = E[j][3] = 0.0;
       if (G.edge[j + 1]) E[j][1] = E[j][3] = 0.0;
+      if (G.fixed[j]) E[j][0] = E[j][1] = 0.0;
+      if (G.fixed[j + 1]) E[j][0] = E[j][2] = 0.0;
     } else {
       E[j][0] = E[j][1] = E[j][2] = E[j][3] = 0.0;
     }
@@ -211,6 +221,7 @@ __device__ __forceinline__ bool hess_solve64(const Geo64<NO>& G,
     double d0 = Sinv[j][0] * c0 + Sinv[j][1] * c1;
     double d1 = Sinv[j][1] * c0 + Sinv[j][2] * c1;
     if (G.edge[j]) d1 = 0.0;
+    if (G.fixed[j]) d0 = 0.0;
     d[2 * j] = d0;
     d[2 * j + 1] = d1;
     n0 = d0;

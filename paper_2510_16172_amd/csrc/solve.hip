@@ -131,97 +131,618 @@ __device__ __forceinline__ double max_disp64(const Geo64<NO>& G,
   return m;  // squared
 }
 
-// Damped Newton refinement, level by level. t is in the caller's
-// parametrisation. A trial step s*d (s = 1, 1/4, 1/16, ...) is taken if it
-// does not lengthen the smoothed path beyond the rounding of L itself. The
-// segments of an accepted trial are those of the next step, so each step
-// evaluates the path once per trial.
+// Newton run on the eps-smoothed length. The full step t + d is taken if it
+// does not lengthen the smoothed path beyond the rounding of L itself. Else,
+// with majorant = true, the step along d that minimises the quadratic
+// majorant of the smoothed length, sum_i |r_i + a D_i|^2 / (2 l_i) (the
+// iteration of Eq. 6 started at a = 0, which cannot lengthen the path), is
+// tried: one evaluation, where near a collapsed minimiser a backtracking
+// search from the (overshooting) Newton step takes many; with majorant =
+// false the step is backtracked by factors of 4 (up to 6 times), which
+// makes more progress per step on such paths. The segments of an accepted
+// trial are those of the next step. prev_small / last_small track whether
+// the last two steps were taken in full and moved no point by more than
+// sqrt(cert2).
+struct NewtonTrack {
+  bool prev_small, last_small, refined;
+  uint32_t n_eval, n_solve;
+};
+
+template <int NO>
+__device__ __forceinline__ void newton_run64(const Geo64<NO>& G, double* t,
+                                             double eps2, int nsteps,
+                                             double cert2, bool majorant,
+                                             NewtonTrack& k) {
+  Seg64<NO> cur;
+  eval64<NO>(G, t, eps2, cur);
+  ++k.n_eval;
+  for (int st = 0; st < nsteps; ++st) {
+    double g[2 * NO], d[2 * NO];
+    gradient64<NO>(G, cur.v, g);
+#pragma unroll
+    for (int q = 0; q < 2 * NO; ++q) g[q] = -g[q];
+    const double bound = cur.L + 1e-15 * fabs(cur.L);
+    const bool ok = hess_solve64<NO>(G, cur.v, cur.il, g, d);
+    ++k.n_solve;
+    k.prev_small = k.last_small;
+    k.last_small = false;
+    if (!ok) continue;
+    const double d2 = max_disp64<NO>(G, d);
+    // majorant step: a = -sum D_i.v_i / sum |D_i|^2 il_i (v_i = r_i il_i),
+    // D_i = A_i d_i - A_{i-1} d_{i-1} the change of segment i along d
+    double num = 0.0, den = 0.0;
+    {
+      double qp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i <= NO; ++i) {
+        double qn[3], D[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          qn[c] = (i == NO) ? 0.0 : fma(d[2 * i + 1], G.a[i][1][c], d[2 * i] * G.a[i][0][c]);
+          D[c] = qn[c] - qp[c];
+          qp[c] = qn[c];
+        }
+        num += dot3d(D, cur.v[i]);
+        den = fma(dot3d(D, D), cur.il[i], den);
+      }
+    }
+    const double amm = (den > 0.0) ? -num * rcp64(den) : 0.0;
+    double s = 1.0;
+    bool acc = false;
+    const int trials = majorant ? 2 : 7;
+    for (int h = 0; h < trials; ++h) {
+      double tn[2 * NO];
+#pragma unroll
+      for (int q = 0; q < 2 * NO; ++q) tn[q] = fma(s, d[q], t[q]);
+      Seg64<NO> nx;
+      eval64<NO>(G, tn, eps2, nx);
+      ++k.n_eval;
+      if (nx.L <= bound) {
+#pragma unroll
+        for (int q = 0; q < 2 * NO; ++q) t[q] = tn[q];
+        cur = nx;
+        acc = true;
+        break;
+      }
+      if (majorant) {
+        // (the majorant step cannot lengthen the path in exact arithmetic,
+        // whatever its size)
+        if (!(amm > 0.0) || !isfinite(amm) || amm == 1.0) break;
+        s = amm;
+      } else {
+        s *= 0.25;
+      }
+    }
+    // (the segments at t are not kept across the trials: recomputed here in
+    // the rare case that every trial failed)
+    if (!acc) {
+      eval64<NO>(G, t, eps2, cur);
+      ++k.n_eval;
+    }
+    k.last_small = acc && (s == 1.0) && (d2 <= cert2);
+    k.refined = k.refined || acc;
+  }
+}
+
+// Nonsmooth check. At the smoothed optimum v_i = r_i / l_i plays the role of
+// the subgradient of |r_i|: a genuine collapse (r_i -> 0) has |v_i| bounded
+// away from 1, while a short segment (< 1e-3 S) with |v_i| close to 1 is a
+// degenerate configuration in which the length is nearly flat along the
+// segment and the smoothing can pull the points together. Such a path is not
+// certified.
+template <int NO>
+__device__ __forceinline__ bool nonsmooth_ok64(const Geo64<NO>& G,
+                                               const double* t, double eps,
+                                               double scale) {
+  const double short2 = 1e-6 * scale * scale;
+  double x[NO][3];
+  points64<NO>(G, t, x);
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
+    // |v_i|^2 = q / (q + eps^2) > 0.98^2
+    double q = dot3d(r, r);
+    if (q < short2 && q > (0.98 * 0.98) * (q + eps * eps)) ok = false;
+  }
+  return ok;
+}
+
+// Damped Newton refinement, level by level (quick: only the last level, with
+// quick_steps steps). t is in the caller's parametrisation.
 template <int NO>
 __device__ __forceinline__ RefineOut refine64(const Geo64<NO>& G, double* t,
                                               const SolveArgs& A, bool quick,
                                               uint32_t& n_eval, uint32_t& n_solve) {
-  RefineOut o{false, false, true};
-  // the last two Newton steps: each taken in full and moving no point by more
-  // than the certificate radius
   const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
-  bool prev_small = false, last_small = false;
-  // quick: only the last level, with quick_steps steps
+  NewtonTrack k{false, false, false, 0, 0};
   const int lv0 = quick ? A.n_levels - 1 : 0;
   for (int lv = lv0; lv < A.n_levels; ++lv) {
     double eps = (double)A.level_eps[lv] * (double)A.scale;
-    double eps2 = eps * eps;
-    const int nsteps = quick ? A.quick_steps : A.level_steps[lv];
-    Seg64<NO> cur;
-    eval64<NO>(G, t, eps2, cur);
-    ++n_eval;
-    for (int st = 0; st < nsteps; ++st) {
-      double g[2 * NO], d[2 * NO];
-      gradient64<NO>(G, cur.v, g);
-#pragma unroll
-      for (int k = 0; k < 2 * NO; ++k) g[k] = -g[k];
-      const double bound = cur.L + 1e-15 * fabs(cur.L);
-      const bool ok = hess_solve64<NO>(G, cur.v, cur.il, g, d);
-      ++n_solve;
-      prev_small = last_small;
-      last_small = false;
-      if (!ok) continue;
-      const double d2 = max_disp64<NO>(G, d);
-      double s = 1.0;
-      bool acc = false;
-      for (int h = 0; h < 7; ++h) {
-        double tn[2 * NO];
-#pragma unroll
-        for (int k = 0; k < 2 * NO; ++k) tn[k] = fma(s, d[k], t[k]);
-        Seg64<NO> nx;
-        eval64<NO>(G, tn, eps2, nx);
-        ++n_eval;
-        if (nx.L <= bound) {
-#pragma unroll
-          for (int k = 0; k < 2 * NO; ++k) t[k] = tn[k];
-          cur = nx;
-          acc = true;
-          break;
-        }
-        s *= 0.25;
-      }
-      // (the segments at t are not kept across the trials: recomputed here
-      // in the rare case that every trial failed)
-      if (!acc) {
-        eval64<NO>(G, t, eps2, cur);
-        ++n_eval;
-      }
-      last_small = acc && (s == 1.0) && (d2 <= cert2);
-      o.refined = o.refined || acc;
-    }
+    // (the quick pass, which every path takes, uses the one-evaluation
+    // majorant fallback; the paths left for the full schedule backtrack)
+    newton_run64<NO>(G, t, eps * eps, quick ? A.quick_steps : A.level_steps[lv],
+                     cert2, quick, k);
   }
+  n_eval += k.n_eval;
+  n_solve += k.n_solve;
+  RefineOut o{false, k.refined, true};
   // One small full step is not enough: along a nearly flat valley of the
   // length a Newton step taken from well outside its quadratic region can be
   // short and still leave the point far from the minimiser (the next step
   // then jumps). Two consecutive small full steps are required.
-  o.certified = A.n_levels > 0 && prev_small && last_small;
-  if (o.certified) {
-    // Nonsmooth check. At the smoothed optimum v_i = r_i / l_i plays the role
-    // of the subgradient of |r_i|: a genuine collapse (r_i -> 0) has |v_i|
-    // bounded away from 1, while a short segment with |v_i| close to 1 is a
-    // degenerate configuration in which the length is nearly flat along the
-    // segment and the smoothing can pull the points together. Such a path is
-    // not certified.
-    const double eps = (double)A.level_eps[A.n_levels - 1] * (double)A.scale;
-    const double short2 = 1e-6 * (double)A.scale * (double)A.scale;  // (1e-3 S)^2
-    double x[NO][3];
-    points64<NO>(G, t, x);
+  o.certified = A.n_levels > 0 && k.prev_small && k.last_small;
+  if (o.certified)
+    o.certified = nonsmooth_ok64<NO>(
+        G, t, (double)A.level_eps[A.n_levels - 1] * (double)A.scale, (double)A.scale);
+  return o;
+}
+
+// ------------------------------------------------ collapsed minimisers ---
+// At many minimisers two consecutive interaction points coincide (e.g. a
+// reflection on a face at the edge that bounds it). The length is not
+// differentiable there and the smoothed Newton iteration approaches such a
+// point slowly, so refine64 does not certify it. merge64 handles a single
+// such collapse: if exactly one interior segment is short, its two points a,
+// b = a + 1 become one point on the intersection of their objects (a line, a
+// point, or a plane for two coplanar planes), the reduced path of order
+// NO - 1 is solved by the same Newton iteration and certificate, and the
+// collapse is certified optimal if some w with |w| < 1 (|w|^2 <= 1 - 1e-6)
+// satisfies the stationarity of both original points,
+//   A_a^T (u_in - w) = 0,   A_b^T (w - u_out) = 0,
+// where u_in, u_out are the unit vectors of the segments entering a and
+// leaving b. Such a w is a subgradient of the zero-length segment's length,
+// so 0 lies in the subdifferential of L; L is convex in T, so the point is a
+// global minimiser (Sec. III-B, Eq. 5 as a sum of norms of affine maps).
+
+__device__ __forceinline__ void cross3d(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Orthonormal basis of an object's directions; n = unit normal of a plane.
+struct Basis64 {
+  double q[2][3], n[3];
+  bool line;
+};
+
+__device__ __forceinline__ Basis64 basis64(const double (*a)[3], bool edge) {
+  Basis64 B;
+  double i0 = rsq64(dot3d(a[0], a[0]));
 #pragma unroll
-    for (int i = 0; i <= NO; ++i) {
-      double r[3];
+  for (int c = 0; c < 3; ++c) B.q[0][c] = a[0][c] * i0;
+  double pr = dot3d(a[1], B.q[0]);
+  double w[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
-      // |v_i|^2 = q / (q + eps^2) > 0.98^2
-      double q = dot3d(r, r);
-      if (q < short2 && q > (0.98 * 0.98) * (q + eps * eps)) o.certified = false;
+  for (int c = 0; c < 3; ++c) w[c] = a[1][c] - pr * B.q[0][c];
+  double ww = dot3d(w, w);
+  B.line = edge || !(ww > 0.0);
+  double i1 = B.line ? 0.0 : rsq64(ww);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) B.q[1][c] = w[c] * i1;
+  cross3d(B.q[0], B.q[1], B.n);
+  return B;
+}
+
+// The intersection of two objects near ymid: point y0 and an orthonormal
+// basis e of its directions (dim 0, 1 or 2), and an orthonormal basis of the
+// directions orthogonal to both objects (nnul of them: the common normal of
+// two coplanar objects). False if they do not meet within tol of each other
+// or the meeting point is further than sqrt(far2) from ymid.
+struct Virt64 {
+  double y0[3], e[2][3], nul[2][3];
+  int dim, nnul;
+};
+
+__device__ __forceinline__ bool intersect64(const Basis64& U, const double* bu,
+                                            const Basis64& V, const double* bv,
+                                            const double* ymid, double tol,
+                                            double far2, Virt64& X) {
+  constexpr double kPar = 1e-12;  // sin^2 of the angle below which: parallel
+#pragma unroll
+  for (int c = 0; c < 3; ++c) X.e[0][c] = X.e[1][c] = X.nul[0][c] = X.nul[1][c] = 0.0;
+  X.dim = -1;
+  X.nnul = 0;
+  if (!U.line && !V.line) {
+    double d[3];
+    cross3d(U.n, V.n, d);
+    double dd = dot3d(d, d);
+    if (dd > kPar) {
+      // line: rows n_u, n_v, e of a 3x3 system (Cramer)
+      double il = rsq64(dd), e[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) e[c] = d[c] * il;
+      double h0 = dot3d(U.n, bu), h1 = dot3d(V.n, bv), h2 = dot3d(e, ymid);
+      double c12[3], c20[3], c01[3];
+      cross3d(V.n, e, c12);
+      cross3d(e, U.n, c20);
+      cross3d(U.n, V.n, c01);
+      double det = dot3d(U.n, c12);
+      double idet = rcp64(det);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        X.y0[c] = (h0 * c12[c] + h1 * c20[c] + h2 * c01[c]) * idet;
+        X.e[0][c] = e[c];
+      }
+      X.dim = 1;
+    } else {
+      double g[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g[c] = bv[c] - bu[c];
+      if (!(fabs(dot3d(U.n, g)) < tol)) return false;
+      double h = dot3d(U.n, ymid) - dot3d(U.n, bu);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        X.y0[c] = ymid[c] - h * U.n[c];
+        X.e[0][c] = U.q[0][c];
+        X.e[1][c] = U.q[1][c];
+        X.nul[0][c] = U.n[c];
+      }
+      X.dim = 2;
+      X.nnul = 1;
+    }
+  } else if (U.line != V.line) {
+    const Basis64& P = U.line ? V : U;
+    const Basis64& Lb = U.line ? U : V;
+    const double* bp = U.line ? bv : bu;
+    const double* bl = U.line ? bu : bv;
+    double sn = dot3d(P.n, Lb.q[0]);
+    double g[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[c] = bp[c] - bl[c];
+    if (sn * sn > kPar) {
+      double tt = dot3d(P.n, g) * rcp64(sn);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) X.y0[c] = bl[c] + tt * Lb.q[0][c];
+      X.dim = 0;
+    } else {
+      if (!(fabs(dot3d(P.n, g)) < tol)) return false;
+      double m[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) m[c] = ymid[c] - bl[c];
+      double tt = dot3d(Lb.q[0], m);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        X.y0[c] = bl[c] + tt * Lb.q[0][c];
+        X.e[0][c] = Lb.q[0][c];
+        X.nul[0][c] = P.n[c];
+      }
+      X.dim = 1;
+      X.nnul = 1;
+    }
+  } else {
+    double d[3], w0[3];
+    cross3d(U.q[0], V.q[0], d);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w0[c] = bu[c] - bv[c];
+    double dd = dot3d(d, d);
+    if (dd > kPar) {
+      // closest points of the two lines
+      double cab = dot3d(U.q[0], V.q[0]);
+      double du = dot3d(U.q[0], w0), dv = dot3d(V.q[0], w0);
+      double iden = rcp64(1.0 - cab * cab);
+      double su = (cab * dv - du) * iden, sv = (dv - cab * du) * iden;
+      double pu[3], pv[3], g[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        pu[c] = bu[c] + su * U.q[0][c];
+        pv[c] = bv[c] + sv * V.q[0][c];
+        g[c] = pu[c] - pv[c];
+      }
+      if (!(dot3d(g, g) < tol * tol)) return false;
+      double il = rsq64(dd);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        X.y0[c] = 0.5 * (pu[c] + pv[c]);
+        X.nul[0][c] = d[c] * il;
+      }
+      X.dim = 0;
+      X.nnul = 1;
+    } else {
+      double pr = dot3d(w0, U.q[0]), g[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g[c] = w0[c] - pr * U.q[0][c];
+      if (!(dot3d(g, g) < tol * tol)) return false;
+      double m[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) m[c] = ymid[c] - bu[c];
+      double tt = dot3d(U.q[0], m);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        X.y0[c] = bu[c] + tt * U.q[0][c];
+        X.e[0][c] = U.q[0][c];
+      }
+      X.dim = 1;
+      // two unit vectors orthogonal to the common line
+      const double* q = U.q[0];
+      double h[3] = {fabs(q[0]) < 0.6 ? 1.0 : 0.0, fabs(q[0]) < 0.6 ? 0.0 : 1.0, 0.0};
+      double n0[3], n1[3];
+      cross3d(q, h, n0);
+      double i0 = rsq64(dot3d(n0, n0));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) n0[c] *= i0;
+      cross3d(q, n0, n1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        X.nul[0][c] = n0[c];
+        X.nul[1][c] = n1[c];
+      }
+      X.nnul = 2;
     }
   }
-  return o;
+  // the meeting point must be near the two collapsing points
+  double m[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) m[c] = ymid[c] - X.y0[c];
+  double pe0 = dot3d(m, X.e[0]), pe1 = dot3d(m, X.e[1]);
+  double dist2 = dot3d(m, m) - pe0 * pe0 - pe1 * pe1;
+  return isfinite(dist2) && dist2 < far2;
+}
+
+// Parameters of point y on an object (caller's basis a, origin b).
+__device__ __forceinline__ void coords64(const double (*a)[3], const double* b,
+                                         bool edge, const double* y, double* t) {
+  double m[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) m[c] = y[c] - b[c];
+  double g00 = dot3d(a[0], a[0]), h0 = dot3d(a[0], m);
+  if (edge) {
+    t[0] = h0 * rcp64(g00);
+    t[1] = 0.0;
+    return;
+  }
+  double g01 = dot3d(a[0], a[1]), g11 = dot3d(a[1], a[1]), h1 = dot3d(a[1], m);
+  double idet = rcp64(g00 * g11 - g01 * g01);
+  t[0] = (g11 * h0 - g01 * h1) * idet;
+  t[1] = (g00 * h1 - g01 * h0) * idet;
+}
+
+// The objects of slots a and a + 1 (selected without dynamic register
+// indexing).
+template <int NO>
+__device__ __forceinline__ void pair64(const Geo64<NO>& G, int a,
+                                       double (*aa)[3], double* ba, bool& ea,
+                                       double (*ab)[3], double* bb, bool& eb) {
+#pragma unroll
+  for (int j = 0; j + 1 < NO; ++j) {
+    const bool s = (j == a);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      aa[0][c] = s ? G.a[j][0][c] : aa[0][c];
+      aa[1][c] = s ? G.a[j][1][c] : aa[1][c];
+      ba[c] = s ? G.b[j][c] : ba[c];
+      ab[0][c] = s ? G.a[j + 1][0][c] : ab[0][c];
+      ab[1][c] = s ? G.a[j + 1][1][c] : ab[1][c];
+      bb[c] = s ? G.b[j + 1][c] : bb[c];
+    }
+    ea = s ? G.edge[j] : ea;
+    eb = s ? G.edge[j + 1] : eb;
+  }
+}
+
+template <int NO>
+__device__ __forceinline__ bool merge64(const Geo64<NO>& G, double* t,
+                                        const SolveArgs& A, uint32_t& n_eval,
+                                        uint32_t& n_solve) {
+  if constexpr (NO < 2) {
+    return false;
+  } else {
+    const double S = (double)A.scale;
+    // candidates: exactly one segment shorter than 6e-2 S, and it is
+    // interior (segment a + 1 joins slots a and a + 1); the start point may
+    // be far from converged on such paths, the certificate decides
+    const double short2 = 3.6e-3 * S * S;
+    int nshort = 0, a = 0;
+    double ymid[3] = {0.0, 0.0, 0.0};
+    {
+      double x[NO][3];
+      points64<NO>(G, t, x);
+#pragma unroll
+      for (int i = 0; i <= NO; ++i) {
+        double r[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
+        bool sh = dot3d(r, r) < short2;
+        nshort += sh ? ((i == 0 || i == NO) ? 2 : 1) : 0;
+        a = sh ? i - 1 : a;
+        if (i >= 1 && i < NO) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            ymid[c] = sh ? 0.5 * (x[i - 1][c] + x[i][c]) : ymid[c];
+        }
+      }
+    }
+    if (nshort != 1) return false;
+    // intersection of the two objects; the reduced path: slot a is the
+    // intersection, slots after a + 1 shift down
+    Geo64<NO - 1> R;
+    double tr[2 * (NO - 1)];
+    double nul[2][3];
+    {
+      double aa[2][3] = {}, ab[2][3] = {}, ba[3] = {}, bb[3] = {};
+      bool ea = false, eb = false;
+      pair64<NO>(G, a, aa, ba, ea, ab, bb, eb);
+      const Basis64 U = basis64(aa, ea), V = basis64(ab, eb);
+      Virt64 X;
+      if (!intersect64(U, ba, V, bb, ymid, 1e-6 * S, 1.44e-2 * S * S, X)) return false;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        R.tx[c] = G.tx[c];
+        R.rx[c] = G.rx[c];
+        nul[0][c] = X.nul[0][c];
+        nul[1][c] = X.nul[1][c];
+      }
+#pragma unroll
+      for (int j = 0; j < NO - 1; ++j) {
+        const bool lo = j < a, vi = j == a;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          R.b[j][c] = vi ? X.y0[c] : (lo ? G.b[j][c] : G.b[j + 1][c]);
+          R.a[j][0][c] = vi ? X.e[0][c] : (lo ? G.a[j][0][c] : G.a[j + 1][0][c]);
+          R.a[j][1][c] = vi ? X.e[1][c] : (lo ? G.a[j][1][c] : G.a[j + 1][1][c]);
+        }
+        R.edge[j] = vi ? (X.dim < 2) : (lo ? G.edge[j] : G.edge[j + 1]);
+        R.fixed[j] = vi && X.dim == 0;
+        double m[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) m[c] = ymid[c] - X.y0[c];
+        tr[2 * j] = vi ? dot3d(m, X.e[0]) : (lo ? t[2 * j] : t[2 * j + 2]);
+        tr[2 * j + 1] = vi ? dot3d(m, X.e[1]) : (lo ? t[2 * j + 1] : t[2 * j + 3]);
+      }
+    }
+    const double eps = (double)A.level_eps[A.n_levels - 1] * S;
+    const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
+    NewtonTrack k{false, false, false, 0, 0};
+    newton_run64<NO - 1>(R, tr, eps * eps, 8, cert2, false, k);
+    n_eval += k.n_eval;
+    n_solve += k.n_solve;
+    if (!(k.prev_small && k.last_small)) return false;
+    if (!nonsmooth_ok64<NO - 1>(R, tr, eps, S)) return false;
+    // subgradient of the collapsed segment: least-norm w with
+    // P_U w = P_U u_in and P_V w = P_V u_out (P = projector onto the
+    // object's directions), w = (P_U + P_V)^+ (P_U u_in + P_V u_out); the
+    // pseudo-inverse by adding the projector onto the common normals (the
+    // null space of P_U + P_V, which the right-hand side does not reach)
+    double uin[3] = {}, uout[3] = {}, y[3] = {};
+    {
+      Seg64<NO - 1> sg;
+      eval64<NO - 1>(R, tr, 0.0, sg);
+      ++n_eval;
+      double xr[NO - 1][3];
+      points64<NO - 1>(R, tr, xr);
+#pragma unroll
+      for (int j = 0; j < NO - 1; ++j) {
+        const bool s = (j == a);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          uin[c] = s ? sg.v[j][c] : uin[c];
+          uout[c] = s ? sg.v[j + 1][c] : uout[c];
+          y[c] = s ? xr[j][c] : y[c];
+        }
+      }
+    }
+    double aa[2][3] = {}, ab[2][3] = {}, ba[3] = {}, bb[3] = {};
+    bool ea = false, eb = false;
+    pair64<NO>(G, a, aa, ba, ea, ab, bb, eb);
+    {
+      const Basis64 U = basis64(aa, ea), V = basis64(ab, eb);
+      double M[3][3], rhs[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        rhs[r] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          M[r][c] = nul[0][r] * nul[0][c] + nul[1][r] * nul[1][c];
+      }
+#pragma unroll
+      for (int k2 = 0; k2 < 2; ++k2) {
+        const double* qu = U.q[k2];
+        const double* qv = V.q[k2];
+        double pu = dot3d(qu, uin), pv = dot3d(qv, uout);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          rhs[r] += qu[r] * pu + qv[r] * pv;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) M[r][c] += qu[r] * qu[c] + qv[r] * qv[c];
+        }
+      }
+      double C0[3], C1[3], C2[3];
+      cross3d(M[1], M[2], C0);
+      cross3d(M[2], M[0], C1);
+      cross3d(M[0], M[1], C2);
+      double idet = rcp64(dot3d(M[0], C0));
+      double w[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        w[c] = (C0[c] * rhs[0] + C1[c] * rhs[1] + C2[c] * rhs[2]) * idet;
+      // consistency (the reduced stationarity) and |w| < 1
+      double res = 0.0;
+#pragma unroll
+      for (int k2 = 0; k2 < 2; ++k2) {
+        double dd[3], ee[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          dd[c] = uin[c] - w[c];
+          ee[c] = w[c] - uout[c];
+        }
+        double ru = dot3d(U.q[k2], dd), rv = dot3d(V.q[k2], ee);
+        res += ru * ru + rv * rv;
+      }
+      if (!(res <= 1e-10) || !(dot3d(w, w) <= 1.0 - 1e-6)) return false;
+    }
+    // back to the caller's parameters of the full path
+    double ta[2], tb[2];
+    coords64(aa, ba, ea, y, ta);
+    coords64(ab, bb, eb, y, tb);
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      const bool lo = j < a, isa = j == a, isb = j == a + 1;
+      const int jr = (j >= 1) ? j - 1 : 0;  // reduced slot of j > a + 1
+      const int jl = (j < NO - 1) ? j : 0;  // reduced slot of j < a
+      t[2 * j] = isa ? ta[0] : (isb ? tb[0] : (lo ? tr[2 * jl] : tr[2 * jr]));
+      t[2 * j + 1] = isa ? ta[1] : (isb ? tb[1] : (lo ? tr[2 * jl + 1] : tr[2 * jr + 1]));
+    }
+    return true;
+  }
+}
+
+// Final outputs of path p from the FP64 parameters td (caller's
+// parametrisation): points, exact length, parameters, status (collapsed:
+// set FPT_ST_COLLAPSED whatever the segment lengths).
+template <int NO>
+__device__ __forceinline__ void write_path64(const SolveArgs& A,
+                                             const Geo64<NO>& D,
+                                             const double* td, int64_t p,
+                                             bool valid, bool certified,
+                                             bool refined, bool collapsed = false) {
+  const float qnan = __builtin_nanf("");
+  double xs[NO][3];
+  points64<NO>(D, td, xs);
+  double Lx = 0.0, minl2 = INFINITY;
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+    double rr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      rr[c] = ((i == NO) ? D.rx[c] : xs[i][c]) - ((i == 0) ? D.tx[c] : xs[i - 1][c]);
+    double q2 = dot3d(rr, rr);
+    minl2 = fmin(minl2, q2);
+    Lx += (q2 > 0.0) ? q2 * rsq64(q2) : 0.0;
+  }
+  bool finite = isfinite(Lx);
+#pragma unroll
+  for (int k = 0; k < 2 * NO; ++k) finite = finite && isfinite(td[k]);
+  uint8_t st = 0;
+  if (!valid) {
+    st = FPT_ST_INVALID;
+  } else {
+    double cs = 1e-6 * (double)A.scale;
+    if (certified && finite) st |= FPT_ST_CONVERGED;
+    if (refined) st |= FPT_ST_REFINED;
+    if (minl2 < cs * cs || collapsed) st |= FPT_ST_COLLAPSED;
+    if (!finite) st |= FPT_ST_NONFINITE;
+  }
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      A.x[(int64_t)(3 * j + c) * A.N + p] = valid ? (float)xs[j][c] : qnan;
+    A.t[(int64_t)(2 * j) * A.N + p] = valid ? (float)td[2 * j] : qnan;
+    A.t[(int64_t)(2 * j + 1) * A.N + p] = valid ? (float)td[2 * j + 1] : qnan;
+  }
+  for (int j = NO; j < A.n_max; ++j) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) A.x[(int64_t)(3 * j + c) * A.N + p] = qnan;
+    A.t[(int64_t)(2 * j) * A.N + p] = qnan;
+    A.t[(int64_t)(2 * j + 1) * A.N + p] = qnan;
+  }
+  A.len[p] = valid ? (float)Lx : qnan;
+  A.status[p] = st;
 }
 
 // ------------------------------------------------------------- kernel -----
@@ -585,9 +1106,10 @@ __global__ __launch_bounds__(kBlock) void bfgs_stage_kernel(
 // (unit-vector coordinates), certificate, and the final outputs.
 // With quick_steps > 0 the refinement runs in two passes: the first takes
 // quick_steps Newton steps at the last smoothing level for every path of the
-// bucket and hands over the certified ones; the others are listed (by the
-// same region scheme as the early-exit stages: St.out_list) and the second
-// pass (St.in_list) runs the full schedule on them from the FP32 result.
+// bucket and writes the certified ones; the others are listed (by the same
+// region scheme as the early-exit stages: St.out_list) with their point
+// left in A.t, and the second pass (St.in_list) runs the full schedule on
+// them from there (after merge_kernel for orders >= 2).
 // St.in_list == St.out_list == null: one pass with the full schedule.
 template <int NO>
 __global__ __launch_bounds__(kBlock) void refine_kernel(
@@ -614,7 +1136,6 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  const float qnan = __builtin_nanf("");
   uint32_t n_eval = 0, n_solve = 0;
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
        idx += stride) {
@@ -656,49 +1177,18 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
         St.out_list[(int64_t)region * St.rcap +
                     (int64_t)(base + (unsigned long long)__popcll(more & below))] = (int32_t)p;
     }
-    if (defer) continue;
-    double xs[NO][3];
-    points64<NO>(D, td, xs);
-    double Lx = 0.0, minl2 = INFINITY;
+    if (defer) {
+      // hand the quick pass's point to the collapse step and the second pass
+      // (unit-vector coordinates, as the FP32 phase left them)
 #pragma unroll
-    for (int i = 0; i <= NO; ++i) {
-      double rr[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        rr[c] = ((i == NO) ? D.rx[c] : xs[i][c]) - ((i == 0) ? D.tx[c] : xs[i - 1][c]);
-      double q2 = dot3d(rr, rr);
-      minl2 = fmin(minl2, q2);
-      Lx += (q2 > 0.0) ? q2 * rsq64(q2) : 0.0;
+      for (int j = 0; j < NO; ++j) {
+        A.t[(int64_t)(2 * j) * A.N + p] = (float)(td[2 * j] * rcp64((double)inv[j][0]));
+        A.t[(int64_t)(2 * j + 1) * A.N + p] =
+            D.edge[j] ? 0.f : (float)(td[2 * j + 1] * rcp64((double)inv[j][1]));
+      }
+      continue;
     }
-    bool finite = isfinite(Lx);
-#pragma unroll
-    for (int k = 0; k < 2 * NO; ++k) finite = finite && isfinite(td[k]);
-    uint8_t st = 0;
-    if (!valid) {
-      st = FPT_ST_INVALID;
-    } else {
-      double cs = 1e-6 * (double)A.scale;
-      if (ro.certified && finite) st |= FPT_ST_CONVERGED;
-      if (ro.refined) st |= FPT_ST_REFINED;
-      if (minl2 < cs * cs) st |= FPT_ST_COLLAPSED;
-      if (!finite) st |= FPT_ST_NONFINITE;
-    }
-#pragma unroll
-    for (int j = 0; j < NO; ++j) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        A.x[(int64_t)(3 * j + c) * A.N + p] = valid ? (float)xs[j][c] : qnan;
-      A.t[(int64_t)(2 * j) * A.N + p] = valid ? (float)td[2 * j] : qnan;
-      A.t[(int64_t)(2 * j + 1) * A.N + p] = valid ? (float)td[2 * j + 1] : qnan;
-    }
-    for (int j = NO; j < A.n_max; ++j) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) A.x[(int64_t)(3 * j + c) * A.N + p] = qnan;
-      A.t[(int64_t)(2 * j) * A.N + p] = qnan;
-      A.t[(int64_t)(2 * j + 1) * A.N + p] = qnan;
-    }
-    A.len[p] = valid ? (float)Lx : qnan;
-    A.status[p] = st;
+    write_path64<NO>(A, D, td, p, valid, ro.certified, ro.refined);
   }
   if (A.work) {
     // wave sums, one atomic per wave
@@ -708,8 +1198,81 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
       n_solve += __shfl_xor(n_solve, off);
     }
     if (lane == 0) {
-      atomicAdd(A.work, (unsigned long long)n_eval);
-      atomicAdd(A.work + 1, (unsigned long long)n_solve);
+      const int slot = blockIdx.x % kWorkSlots;
+      atomicAdd(A.work + slot, (unsigned long long)n_eval);
+      atomicAdd(A.work + kWorkSlots + slot, (unsigned long long)n_solve);
+    }
+  }
+}
+
+// Between the two refinement passes: the paths the quick pass did not
+// certify (St.in_list) get one attempt of merge64 from the FP32 result;
+// those it certifies are written, the others are listed (St.out_list) for
+// the second pass.
+template <int NO>
+__global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St) {
+  __shared__ int64_t pre[kRegions + 1];
+  if (threadIdx.x == 0) {
+    int64_t acc = 0;
+    for (int r = 0; r < kRegions; ++r) {
+      pre[r] = acc;
+      acc += (int64_t)St.in_count[r * kCounterStride];
+    }
+    pre[kRegions] = acc;
+  }
+  __syncthreads();
+  const int64_t count = pre[kRegions];
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  uint32_t n_eval = 0, n_solve = 0;
+  for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
+       idx += stride) {
+    int lo = 0, hi = kRegions;
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (pre[mid] <= idx) lo = mid; else hi = mid;
+    }
+    const int64_t p = St.in_list[(int64_t)lo * St.rcap + (idx - pre[lo])];
+    Geo64<NO> D;
+    float inv[NO][2];
+    load_geo64<NO>(A, p, D, inv);
+    double td[2 * NO];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      float t0 = A.t[(int64_t)(2 * j) * A.N + p];
+      float t1 = A.t[(int64_t)(2 * j + 1) * A.N + p];
+      td[2 * j] = (double)t0 * (double)inv[j][0];
+      td[2 * j + 1] = D.edge[j] ? 0.0 : (double)t1 * (double)inv[j][1];
+    }
+    uint32_t me = 0, ms = 0;
+    const bool ok = merge64<NO>(D, td, A, me, ms);
+    n_eval += me;
+    n_solve += ms;
+    const unsigned long long more = __ballot(!ok);
+    if (more) {
+      const int region = (int)((idx >> 6) % kRegions);
+      unsigned long long base = 0;
+      if (lane == 0)
+        base = atomicAdd(St.out_count + region * kCounterStride,
+                         (unsigned long long)__popcll(more));
+      base = __shfl(base, 0);
+      if (!ok)
+        St.out_list[(int64_t)region * St.rcap +
+                    (int64_t)(base + (unsigned long long)__popcll(more & below))] = (int32_t)p;
+    }
+    if (ok) write_path64<NO>(A, D, td, p, true, true, true, true);
+  }
+  if (A.work) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      n_eval += __shfl_xor(n_eval, off);
+      n_solve += __shfl_xor(n_solve, off);
+    }
+    if (lane == 0) {
+      const int slot = blockIdx.x % kWorkSlots;
+      atomicAdd(A.work + 2 * kWorkSlots + slot, (unsigned long long)n_eval);
+      atomicAdd(A.work + 3 * kWorkSlots + slot, (unsigned long long)n_solve);
     }
   }
 }
@@ -868,14 +1431,18 @@ static hipError_t launch_phase(int phase, const SolveArgs& A,
   else if (phase == 1)
     hipLaunchKernelGGL(refine_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
                        perm, bucket, *stage);
-  else
+  else if (phase == 2)
     hipLaunchKernelGGL(bfgs_stage_kernel<NO>, dim3(grid), dim3(kBlock), 0,
                        st, A, perm, bucket, *stage);
+  else
+    hipLaunchKernelGGL(merge_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
+                       *stage);
   return hipGetLastError();
 }
 
 // phase 0: bfgs_kernel<order>, 1: refine_kernel<order>,
-// 2: bfgs_stage_kernel<order> (one early-exit stage, `stage` describes it)
+// 2: bfgs_stage_kernel<order> (one early-exit stage, `stage` describes it),
+// 3: merge_kernel<order> (between the refinement passes)
 hipError_t launch_solve(int phase, int order, const SolveArgs& A,
                         const int32_t* perm, const int64_t* bucket,
                         const StageArgs* stage, int grid, hipStream_t st) {
@@ -906,7 +1473,8 @@ template <int NO>
 static const void* phase_ptr(int phase) {
   return phase == 0 ? (const void*)bfgs_kernel<NO>
          : phase == 1 ? (const void*)refine_kernel<NO>
-                      : (const void*)bfgs_stage_kernel<NO>;
+         : phase == 2 ? (const void*)bfgs_stage_kernel<NO>
+                      : (const void*)merge_kernel<NO>;
 }
 
 const void* solve_kernel_ptr(int phase, int order) {

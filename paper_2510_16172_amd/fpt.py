@@ -269,11 +269,12 @@ class Solver:
         return [float(v) for v in ms]
 
     def work_counts(self):
-        """{order: (path evaluations, Newton solves)} of the FP64 refinement
+        """{order: (path evaluations, Newton solves, reduced-path evaluations,
+        reduced-path Newton solves)} of the FP64 refinement and collapse step
         since the previous read (counted while timing is enabled)."""
-        c = (ctypes.c_uint64 * 12)()
+        c = (ctypes.c_uint64 * 24)()
         _check(load_library().fpt_work_counts(self._h, c), "fpt_work_counts")
-        return {n: (int(c[2 * n - 2]), int(c[2 * n - 1])) for n in range(1, 7)}
+        return {n: tuple(int(c[4 * (n - 1) + k]) for k in range(4)) for n in range(1, 7)}
 
     def set_launch(self, order: int, cfg: dict | None):
         """Per-order launch configuration (see fpt_launch_cfg); None resets."""

@@ -319,11 +319,34 @@ def test_refine_work_counts(solver):
     total_levels = sum(opts.level_steps)
     for n in (1, 2, 3):
         cnt = int((b.order == n).sum())
-        ev, so = wc[n]
+        ev, so, mev, mso = wc[n]
         assert so >= opts.quick_steps * cnt
         assert so <= (opts.quick_steps + total_levels) * cnt
         assert ev >= cnt + so // 2
-    assert wc[4] == (0, 0)
+        if n == 1:
+            assert (mev, mso) == (0, 0)
+        assert mso <= 5 * cnt and mev <= 5 * 9 * cnt
+    assert wc[4] == (0, 0, 0, 0)
     solver.solve(db, opts, out=out)
     torch.cuda.synchronize()
-    assert all(v == (0, 0) for v in solver.work_counts().values())
+    assert all(v == (0, 0, 0, 0) for v in solver.work_counts().values())
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_collapsed_minimisers_certified(solver, oracle_mod, n):
+    """Minimisers where two consecutive interaction points coincide (the
+    oracle's COLLAPSED flag): the collapse step certifies most of them, every
+    certified one lies within 1e-4 S of the oracle and carries the
+    COLLAPSED status (the backward pass skips such paths)."""
+    from paper_2510_16172_amd import fpt
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 6000, seed=4700 + n, n=n)
+    ref = oracle_mod.solve(b, threads=8)
+    g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=16), with_order=False)
+    s = _check_common(b, g, ref, min_ok={2: 0.95, 3: 0.85}[n])
+    col = s["col"] & ~s["ill"]
+    cc = s["cert"] & col
+    print(f"n={n} collapsed={col.sum()} certified={cc.sum()}", flush=True)
+    assert col.sum() > 300
+    assert cc.sum() >= {2: 0.9, 3: 0.75}[n] * col.sum()
+    assert np.all((g["status"][cc] & fpt.ST_COLLAPSED) != 0)
