@@ -355,7 +355,7 @@ def main():
                     help="also run the mixed-order (1..6) graph workload")
     ap.add_argument("--learned", action="store_true",
                     help="also train and evaluate the learned initialiser")
-    ap.add_argument("--mlp-epochs", type=int, default=4)
+    ap.add_argument("--mlp-epochs", type=int, default=40)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of known size (for "
                          "calibrating the HBM byte counters)")

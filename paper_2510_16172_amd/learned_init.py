@@ -32,8 +32,9 @@ def dedup_against(train: scenes.Batch, test: scenes.Batch) -> scenes.Batch:
 
 def train(solver, mlp, db: fpt.DeviceBatch, target, scale: float, epochs: int,
           batch: int = 16384, lr: float = 1e-3, seed: int = 0, log=None):
-    """Adam epochs over the paths of db against the solver output `target`.
-    Returns the mean training loss of each epoch."""
+    """Adam epochs over the paths of db against the solver output `target`,
+    the step size decaying linearly to 0.1 lr. Returns the mean training
+    loss of each epoch."""
     import torch
     N = db.N
     rng = np.random.default_rng(seed)
@@ -123,8 +124,51 @@ def evaluate(solver, mlp, db: fpt.DeviceBatch, opts, repeats: int = 3):
     return res, out0, out1
 
 
-def run(solver, n_train: int = 1 << 22, n_test: int = 1 << 20, epochs: int = 4,
-        opts_kw=None, log=None, seed: int = 0):
+def compare_fixed(solver, mlp, db: fpt.DeviceBatch, scale: float,
+                  iters=(8, 16, 24), repeats: int = 3):
+    """Zero vs learned start at equal fixed iteration counts: certified
+    fraction, solve time, and certified paths/s with and without the
+    network's inference time (HIP events on the current stream)."""
+    import torch
+    tinit = torch.empty((4, 2, db.N), dtype=torch.float32, device="cuda")
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(repeats):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        return r, best
+
+    _, ms_inf = timed(lambda: mlp.infer(db, scale, out=tinit))
+    rows = []
+    for k in iters:
+        o = fpt.Opts(scale=scale, iters=int(k))
+        db.t_init = None
+        o0, ms0 = timed(lambda: solver.solve(db, o))
+        db.t_init = tinit
+        o1, ms1 = timed(lambda: solver.solve(db, o))
+        db.t_init = None
+        c0 = int(((o0["status"] & fpt.ST_CONVERGED) != 0).sum().item())
+        c1 = int(((o1["status"] & fpt.ST_CONVERGED) != 0).sum().item())
+        rows.append({"iters": int(k),
+                     "zero": {"certified": c0 / db.N, "ms": ms0,
+                              "converged_paths_per_s": c0 / (ms0 * 1e-3)},
+                     "learned": {"certified": c1 / db.N, "ms_solve": ms1,
+                                 "converged_paths_per_s_solve_only": c1 / (ms1 * 1e-3),
+                                 "converged_paths_per_s_with_inference":
+                                     c1 / ((ms1 + ms_inf) * 1e-3)}})
+    return {"ms_inference": ms_inf, "fixed_iterations": rows}
+
+
+def run(solver, n_train: int = 1 << 22, n_test: int = 1 << 20, epochs: int = 40,
+        opts_kw=None, log=None, seed: int = 0, lr: float = 2e-3):
     """The full experiment on the street canyon, order-4 paths."""
     import torch
     sc = scenes.canyon_scene()
@@ -138,12 +182,13 @@ def run(solver, n_train: int = 1 << 22, n_test: int = 1 << 20, epochs: int = 4,
     torch.cuda.synchronize()
     mlp = fpt.Mlp(solver, seed=seed)
     t1 = time.perf_counter()
-    losses = train(solver, mlp, dbt, target, sc.S, epochs, log=log, seed=seed)
+    losses = train(solver, mlp, dbt, target, sc.S, epochs, lr=lr, log=log, seed=seed)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     dbe = fpt.DeviceBatch(test, with_order=False)
     opts = fpt.Opts(scale=sc.S, **{**dict(iters=64, early_exit=True), **opts_kw})
     res, _, _ = evaluate(solver, mlp, dbe, opts)
+    res["equal_iterations"] = compare_fixed(solver, mlp, dbe, sc.S)
     res.update({"train_paths": trainb.N, "train_certified": float(
         ((target["status"] & fpt.ST_CONVERGED) != 0).float().mean().item()),
         "epochs": epochs, "train_loss": losses, "train_s": t_train,

@@ -101,3 +101,42 @@ def test_training_reduces_loss(solver):
     print("losses", losses[0], losses[-1], flush=True)
     assert losses[-1] < 0.5 * losses[0]
     assert np.all(np.isfinite(losses))
+
+
+def test_learned_init_gains_over_zero_start(solver):
+    """What the trained network gains: on held-out order-4 canyon paths and
+    at the same fixed number of BFGS iterations, the solver started from the
+    network's prediction certifies more paths than from T = 0, and needs
+    fewer iterations to stop under early exit (the plain solver is the
+    teacher and the fallback)."""
+    import torch
+    from paper_2510_16172_amd import fpt, learned_init
+    sc = scenes.canyon_scene()
+    test = scenes.canyon_sample_paths(sc, 1 << 16, seed=6300, n=4)
+    train = learned_init.dedup_against(
+        scenes.canyon_sample_paths(sc, 1 << 19, seed=6301, n=4), test)
+    dbt = fpt.DeviceBatch(train, with_order=False)
+    target = solver.solve(dbt, fpt.Opts(scale=sc.S, iters=96))
+    mlp = fpt.Mlp(solver, seed=1)
+    losses = learned_init.train(solver, mlp, dbt, target, sc.S, epochs=24,
+                                lr=2e-3, batch=8192)
+    assert losses[-1] < 0.5 * losses[0]
+    dbe = fpt.DeviceBatch(test, with_order=False)
+    t0 = mlp.infer(dbe, sc.S)
+
+    def run(t_init, **kw):
+        dbe.t_init = t_init
+        out = solver.solve(dbe, fpt.Opts(scale=sc.S, **kw))
+        torch.cuda.synchronize()
+        dbe.t_init = None
+        return {k: v.cpu().numpy() for k, v in out.items()}
+
+    z, l = run(None, iters=8), run(t0, iters=8)
+    cz = ((z["status"] & fpt.ST_CONVERGED) != 0).mean()
+    cl = ((l["status"] & fpt.ST_CONVERGED) != 0).mean()
+    print(f"certified at 8 iterations: zero {cz:.4f} learned {cl:.4f}", flush=True)
+    assert cl >= cz + 0.01
+    ze, le = run(None, iters=64, early_exit=True), run(t0, iters=64, early_exit=True)
+    iz, il = ze["iters"].astype(np.float64).mean(), le["iters"].astype(np.float64).mean()
+    print(f"mean iterations under early exit: zero {iz:.2f} learned {il:.2f}", flush=True)
+    assert il < iz
