@@ -78,9 +78,9 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(
     }
 #pragma unroll
     for (int j = 0; j < NO; ++j)
-      if (G.edge[j]) t[2 * j + 1] = 0.0;
+      if (G.edge(j)) t[2 * j + 1] = 0.0;
     double u[NO + 1][3], il[NO + 1];
-    segments64<NO>(G, t, 0.0, u, il);
+    segments64(G, t, 0.0, u, il);
     const double gl = A.g_len ? (double)A.g_len[p] : 0.0;
     double gx[NO][3], w[2 * NO];
 #pragma unroll
@@ -88,11 +88,11 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(
 #pragma unroll
       for (int c = 0; c < 3; ++c)
         gx[j][c] = A.g_x ? (double)A.g_x[(int64_t)(3 * j + c) * A.N + p] : 0.0;
-      w[2 * j] = dot3d(G.a[j][0], gx[j]);
-      w[2 * j + 1] = dot3d(G.a[j][1], gx[j]);
+      w[2 * j] = G.a(j, 0, 0) * gx[j][0] + G.a(j, 0, 1) * gx[j][1] + G.a(j, 0, 2) * gx[j][2];
+      w[2 * j + 1] = G.a(j, 1, 0) * gx[j][0] + G.a(j, 1, 1) * gx[j][1] + G.a(j, 1, 2) * gx[j][2];
     }
     double lam[2 * NO];
-    bool ok = hess_solve64<NO>(G, u, il, w, lam);
+    bool ok = hess_solve64(G, u, il, w, lam);
     use = use && ok;
     // c_i = P_i delta_i for every segment
     double cseg[NO + 1][3];
@@ -102,10 +102,10 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         double qi = (i == NO) ? 0.0
-                              : lam[2 * i] * G.a[i][0][c] + lam[2 * i + 1] * G.a[i][1][c];
+                              : lam[2 * i] * G.a(i, 0, c) + lam[2 * i + 1] * G.a(i, 1, c);
         double qm = (i == 0) ? 0.0
-                             : lam[2 * i - 2] * G.a[i - 1][0][c] +
-                                   lam[2 * i - 1] * G.a[i - 1][1][c];
+                             : lam[2 * i - 2] * G.a(i - 1, 0, c) +
+                                   lam[2 * i - 1] * G.a(i - 1, 1, c);
         dl[c] = qi - qm;
       }
       double ud = dot3d(u[i], dl);
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(
       for (int c = 0; c < 3; ++c) {
         val[c] = (float)gb[c];
         val[3 + c] = (float)(t[2 * j] * gb[c] - lam[2 * j] * du[c]);
-        val[6 + c] = G.edge[j] ? 0.f
+        val[6 + c] = G.edge(j) ? 0.f
                                : (float)(t[2 * j + 1] * gb[c] - lam[2 * j + 1] * du[c]);
       }
 #pragma unroll

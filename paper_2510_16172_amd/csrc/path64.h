@@ -11,14 +11,50 @@
 
 namespace fpt {
 
+// The FP64 helpers below take the geometry of one path through accessors,
+// so that it can live in registers (Geo64) or in LDS (GeoLds).
 template <int NO>
 struct Geo64 {
-  double tx[3], rx[3];
-  double b[NO][3];
-  double a[NO][2][3];  // caller's basis vectors (a[j][1] = 0 for an edge)
-  bool edge[NO];   // second parameter masked (padding)
-  bool fixed[NO];  // both parameters masked: a fixed point (reduced paths)
+  static constexpr int kOrder = NO;
+  double tx_[3], rx_[3];
+  double b_[NO][3];
+  double a_[NO][2][3];  // caller's basis vectors (a[j][1] = 0 for an edge)
+  bool edge_[NO];   // second parameter masked (padding)
+  bool fixed_[NO];  // both parameters masked: a fixed point (reduced paths)
+  __device__ __forceinline__ double tx(int c) const { return tx_[c]; }
+  __device__ __forceinline__ double rx(int c) const { return rx_[c]; }
+  __device__ __forceinline__ double b(int j, int c) const { return b_[j][c]; }
+  __device__ __forceinline__ double a(int j, int k, int c) const { return a_[j][k][c]; }
+  __device__ __forceinline__ bool edge(int j) const { return edge_[j]; }
+  __device__ __forceinline__ bool fixed(int j) const { return fixed_[j]; }
 };
+
+// Geometry of one lane in LDS: the FP32 scene values (exact in FP64, widened
+// on use) in one column of a [geo_lds_rows(NO)][kBlock] float array, so that
+// the FP64 kernels keep fewer live registers. Rows: TX, RX, then b, a1, a2
+// per slot.
+__host__ __device__ constexpr int geo_lds_rows(int NO) { return 6 + 9 * NO; }
+
+template <int NO>
+struct GeoLds {
+  static constexpr int kOrder = NO;
+  const float* col;  // this lane's column: &lds[threadIdx.x]
+  bool edge_[NO];
+  __device__ __forceinline__ double tx(int c) const { return (double)col[c * kBlock]; }
+  __device__ __forceinline__ double rx(int c) const { return (double)col[(3 + c) * kBlock]; }
+  __device__ __forceinline__ double b(int j, int c) const {
+    return (double)col[(6 + 9 * j + c) * kBlock];
+  }
+  __device__ __forceinline__ double a(int j, int k, int c) const {
+    return (double)col[(9 + 9 * j + 3 * k + c) * kBlock];
+  }
+  __device__ __forceinline__ bool edge(int j) const { return edge_[j]; }
+  __device__ __forceinline__ bool fixed(int) const { return false; }
+};
+
+// Loads of a GeoLds are not to be hoisted or merged across this point: it
+// bounds how long the widened values stay in registers (no instruction).
+__device__ __forceinline__ void geo_fence() { asm volatile("" ::: "memory"); }
 
 // Geometry of path p in FP64 (exact widening of the FP32 tables). Indices out
 // of range are clamped to 0 (the caller has flagged such a path invalid).
@@ -33,8 +69,8 @@ __device__ __forceinline__ void load_geo64(const float* __restrict__ obj,
   e = (e >= 0 && e < Q) ? e : 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    D.tx[c] = pts[(int64_t)c * Q + s];
-    D.rx[c] = pts[(int64_t)c * Q + e];
+    D.tx_[c] = pts[(int64_t)c * Q + s];
+    D.rx_[c] = pts[(int64_t)c * Q + e];
   }
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
@@ -43,43 +79,45 @@ __device__ __forceinline__ void load_geo64(const float* __restrict__ obj,
     float a2[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      D.b[j][c] = obj[(int64_t)c * K + k];
-      D.a[j][0][c] = obj[(int64_t)(3 + c) * K + k];
+      D.b_[j][c] = obj[(int64_t)c * K + k];
+      D.a_[j][0][c] = obj[(int64_t)(3 + c) * K + k];
       a2[c] = obj[(int64_t)(6 + c) * K + k];
     }
     bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
-    D.edge[j] = edge;
-    D.fixed[j] = false;
+    D.edge_[j] = edge;
+    D.fixed_[j] = false;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) D.a[j][1][c] = edge ? 0.0 : (double)a2[c];
+    for (int c = 0; c < 3; ++c) D.a_[j][1][c] = edge ? 0.0 : (double)a2[c];
   }
 }
 
-template <int NO>
-__device__ __forceinline__ void points64(const Geo64<NO>& G, const double* t,
+template <class GEO>
+__device__ __forceinline__ void points64(const GEO& G, const double* t,
                                          double (*x)[3]) {
+  constexpr int NO = GEO::kOrder;
 #pragma unroll
   for (int j = 0; j < NO; ++j)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      x[j][c] = fma(t[2 * j + 1], G.a[j][1][c],
-                    fma(t[2 * j], G.a[j][0][c], G.b[j][c]));
+      x[j][c] = fma(t[2 * j + 1], G.a(j, 1, c),
+                    fma(t[2 * j], G.a(j, 0, c), G.b(j, c)));
 }
 
 // Segments at t: v_i = r_i / l_i and il_i = 1 / l_i with
 // l_i = sqrt(|r_i|^2 + eps^2) (eps = 0: the exact length of Eq. 5).
-template <int NO>
-__device__ __forceinline__ void segments64(const Geo64<NO>& G,
+template <class GEO>
+__device__ __forceinline__ void segments64(const GEO& G,
                                            const double* t, double eps2,
                                            double (*v)[3], double* il) {
+  constexpr int NO = GEO::kOrder;
   double x[NO][3];
-  points64<NO>(G, t, x);
+  points64(G, t, x);
 #pragma unroll
   for (int i = 0; i <= NO; ++i) {
     double r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
+      r[c] = ((i == NO) ? G.rx(c) : x[i][c]) - ((i == 0) ? G.tx(c) : x[i - 1][c]);
     double q = fmax(dot3d(r, r) + eps2, 1e-300);
     il[i] = rsq64(q);
 #pragma unroll
@@ -93,18 +131,19 @@ struct Seg64 {
   double v[NO + 1][3], il[NO + 1], L;
 };
 
-template <int NO>
-__device__ __forceinline__ void eval64(const Geo64<NO>& G, const double* t,
-                                       double eps2, Seg64<NO>& s) {
+template <class GEO>
+__device__ __forceinline__ void eval64(const GEO& G, const double* t,
+                                       double eps2, Seg64<GEO::kOrder>& s) {
+  constexpr int NO = GEO::kOrder;
   double x[NO][3];
-  points64<NO>(G, t, x);
+  points64(G, t, x);
   s.L = 0.0;
 #pragma unroll
   for (int i = 0; i <= NO; ++i) {
     double r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
+      r[c] = ((i == NO) ? G.rx(c) : x[i][c]) - ((i == 0) ? G.tx(c) : x[i - 1][c]);
     double q = fmax(dot3d(r, r) + eps2, 1e-300);
     s.il[i] = rsq64(q);
 #pragma unroll
@@ -115,16 +154,23 @@ __device__ __forceinline__ void eval64(const Geo64<NO>& G, const double* t,
 
 // Gradient of the (smoothed) length: g_j = A_j^T (v_j - v_{j+1}); the padded
 // parameter of an edge gets 0.
-template <int NO>
-__device__ __forceinline__ void gradient64(const Geo64<NO>& G,
+template <class GEO>
+__device__ __forceinline__ void gradient64(const GEO& G,
                                            const double (*v)[3], double* g) {
+  constexpr int NO = GEO::kOrder;
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
     double du[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) du[c] = v[j][c] - v[j + 1][c];
-    g[2 * j] = G.fixed[j] ? 0.0 : dot3d(G.a[j][0], du);
-    g[2 * j + 1] = G.edge[j] ? 0.0 : dot3d(G.a[j][1], du);
+    double a0[3], a1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a0[c] = G.a(j, 0, c);
+      a1[c] = G.a(j, 1, c);
+    }
+    g[2 * j] = G.fixed(j) ? 0.0 : dot3d(a0, du);
+    g[2 * j + 1] = G.edge(j) ? 0.0 : dot3d(a1, du);
   }
 }
 
@@ -139,18 +185,23 @@ __device__ __forceinline__ void gradient64(const Geo64<NO>& G,
 // diagonal is set to 1 and its right-hand side to 0, so its d is 0. A fixed
 // slot has both parameters masked that way.
 // Returns false if a pivot block is not positive definite or d is not finite.
-template <int NO>
-__device__ __forceinline__ bool hess_solve64(const Geo64<NO>& G,
+template <class GEO>
+__device__ __forceinline__ bool hess_solve64(const GEO& G,
                                              const double (*v)[3],
                                              const double* il,
                                              const double* rhs, double* d) {
+  constexpr int NO = GEO::kOrder;
   double Sinv[NO][3], E[NO][4], z[NO][2];
   double pSinv[3] = {0, 0, 0}, pE[4] = {0, 0, 0, 0}, pz[2] = {0, 0};
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
-    const double* a0 = G.a[j][0];
-    const double* a1 = G.a[j][1];
+    double a0[3], a1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a0[c] = G.a(j, 0, c);
+      a1[c] = G.a(j, 1, c);
+    }
     double pin0 = dot3d(a0, v[j]), pin1 = dot3d(a1, v[j]);
     double pout0 = dot3d(a0, v[j + 1]), pout1 = dot3d(a1, v[j + 1]);
     double G00 = dot3d(a0, a0), G01 = dot3d(a0, a1), G11 = dot3d(a1, a1);
@@ -158,12 +209,12 @@ __device__ __forceinline__ bool hess_solve64(const Geo64<NO>& G,
     double D01 = (G01 - pin0 * pin1) * il[j] + (G01 - pout0 * pout1) * il[j + 1];
     double D11 = (G11 - pin1 * pin1) * il[j] + (G11 - pout1 * pout1) * il[j + 1];
     double rhs0 = rhs[2 * j], rhs1 = rhs[2 * j + 1];
-    if (G.edge[j]) {
+    if (G.edge(j)) {
       D01 = 0.0;
       D11 = 1.0;
       rhs1 = 0.0;
     }
-    if (G.fixed[j]) {
+    if (G.fixed(j)) {
       D00 = 1.0;
       D01 = 0.0;
       rhs0 = 0.0;
@@ -191,18 +242,22 @@ __device__ __forceinline__ bool hess_solve64(const Geo64<NO>& G,
     z[j][0] = rhs0;
     z[j][1] = rhs1;
     if (j + 1 < NO) {
-      const double* b0 = G.a[j + 1][0];
-      const double* b1 = G.a[j + 1][1];
+      double b0[3], b1[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        b0[c] = G.a(j + 1, 0, c);
+        b1[c] = G.a(j + 1, 1, c);
+      }
       double qn0 = dot3d(b0, v[j + 1]), qn1 = dot3d(b1, v[j + 1]);
       double il1 = il[j + 1];
       E[j][0] = -(dot3d(a0, b0) - pout0 * qn0) * il1;
       E[j][1] = -(dot3d(a0, b1) - pout0 * qn1) * il1;
       E[j][2] = -(dot3d(a1, b0) - pout1 * qn0) * il1;
       E[j][3] = -(dot3d(a1, b1) - pout1 * qn1) * il1;
-      if (G.edge[j]) E[j][2] = E[j][3] = 0.0;
-      if (G.edge[j + 1]) E[j][1] = E[j][3] = 0.0;
-      if (G.fixed[j]) E[j][0] = E[j][1] = 0.0;
-      if (G.fixed[j + 1]) E[j][0] = E[j][2] = 0.0;
+      if (G.edge(j)) E[j][2] = E[j][3] = 0.0;
+      if (G.edge(j + 1)) E[j][1] = E[j][3] = 0.0;
+      if (G.fixed(j)) E[j][0] = E[j][1] = 0.0;
+      if (G.fixed(j + 1)) E[j][0] = E[j][2] = 0.0;
     } else {
       E[j][0] = E[j][1] = E[j][2] = E[j][3] = 0.0;
     }
@@ -220,8 +275,8 @@ __device__ __forceinline__ bool hess_solve64(const Geo64<NO>& G,
     double c1 = z[j][1] - (E[j][2] * n0 + E[j][3] * n1);
     double d0 = Sinv[j][0] * c0 + Sinv[j][1] * c1;
     double d1 = Sinv[j][1] * c0 + Sinv[j][2] * c1;
-    if (G.edge[j]) d1 = 0.0;
-    if (G.fixed[j]) d0 = 0.0;
+    if (G.edge(j)) d1 = 0.0;
+    if (G.fixed(j)) d0 = 0.0;
     d[2 * j] = d0;
     d[2 * j + 1] = d1;
     n0 = d0;

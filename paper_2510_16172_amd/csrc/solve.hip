@@ -109,23 +109,62 @@ __device__ __forceinline__ void load_geo64(const SolveArgs& A, int64_t p,
     float a1[3], a2[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      a1[c] = (float)D.a[j][0][c];
-      a2[c] = (float)D.a[j][1][c];
+      a1[c] = (float)D.a(j, 0, c);
+      a2[c] = (float)D.a(j, 1, c);
     }
-    basis_inv32(a1, a2, D.edge[j], inv[j][0], inv[j][1]);
+    basis_inv32(a1, a2, D.edge(j), inv[j][0], inv[j][1]);
   }
 }
 
+// The same into this lane's LDS column (see GeoLds): the table values as
+// they are (FP32), plus the edge flags and 1/|a| factors in registers.
 template <int NO>
-__device__ __forceinline__ double max_disp64(const Geo64<NO>& G,
+__device__ __forceinline__ void load_geo_lds(const SolveArgs& A, int64_t p,
+                                             float* col, GeoLds<NO>& D,
+                                             float (*inv)[2]) {
+  int32_t s = A.src[p], e = A.dst[p];
+  s = (s >= 0 && s < A.Q) ? s : 0;
+  e = (e >= 0 && e < A.Q) ? e : 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    col[c * kBlock] = A.pts[(int64_t)c * A.Q + s];
+    col[(3 + c) * kBlock] = A.pts[(int64_t)c * A.Q + e];
+  }
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    int32_t k = A.ids[(int64_t)j * A.N + p];
+    k = (k >= 0 && k < A.K) ? k : 0;
+    float bb[3], a1[3], a2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bb[c] = A.obj[(int64_t)c * A.K + k];
+      a1[c] = A.obj[(int64_t)(3 + c) * A.K + k];
+      a2[c] = A.obj[(int64_t)(6 + c) * A.K + k];
+    }
+    const bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      col[(6 + 9 * j + c) * kBlock] = bb[c];
+      col[(9 + 9 * j + c) * kBlock] = a1[c];
+      col[(12 + 9 * j + c) * kBlock] = edge ? 0.f : a2[c];
+    }
+    D.edge_[j] = edge;
+    basis_inv32(a1, a2, edge, inv[j][0], inv[j][1]);
+  }
+  D.col = col;
+}
+
+template <class GEO>
+__device__ __forceinline__ double max_disp64(const GEO& G,
                                              const double* d) {
+  constexpr int NO = GEO::kOrder;
   double m = 0.0;
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
     double w[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      w[c] = d[2 * j] * G.a[j][0][c] + d[2 * j + 1] * G.a[j][1][c];
+      w[c] = d[2 * j] * G.a(j, 0, c) + d[2 * j + 1] * G.a(j, 1, c);
     m = fmax(m, dot3d(w, w));
   }
   return m;  // squared
@@ -148,26 +187,28 @@ struct NewtonTrack {
   uint32_t n_eval, n_solve;
 };
 
-template <int NO>
-__device__ __forceinline__ void newton_run64(const Geo64<NO>& G, double* t,
+template <class GEO>
+__device__ __forceinline__ void newton_run64(const GEO& G, double* t,
                                              double eps2, int nsteps,
                                              double cert2, bool majorant,
                                              NewtonTrack& k) {
+  constexpr int NO = GEO::kOrder;
   Seg64<NO> cur;
-  eval64<NO>(G, t, eps2, cur);
+  eval64(G, t, eps2, cur);
   ++k.n_eval;
   for (int st = 0; st < nsteps; ++st) {
+    geo_fence();
     double g[2 * NO], d[2 * NO];
-    gradient64<NO>(G, cur.v, g);
+    gradient64(G, cur.v, g);
 #pragma unroll
     for (int q = 0; q < 2 * NO; ++q) g[q] = -g[q];
     const double bound = cur.L + 1e-15 * fabs(cur.L);
-    const bool ok = hess_solve64<NO>(G, cur.v, cur.il, g, d);
+    const bool ok = hess_solve64(G, cur.v, cur.il, g, d);
     ++k.n_solve;
     k.prev_small = k.last_small;
     k.last_small = false;
     if (!ok) continue;
-    const double d2 = max_disp64<NO>(G, d);
+    const double d2 = max_disp64(G, d);
     // majorant step: a = -sum D_i.v_i / sum |D_i|^2 il_i (v_i = r_i il_i),
     // D_i = A_i d_i - A_{i-1} d_{i-1} the change of segment i along d
     double num = 0.0, den = 0.0;
@@ -178,7 +219,7 @@ __device__ __forceinline__ void newton_run64(const Geo64<NO>& G, double* t,
         double qn[3], D[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          qn[c] = (i == NO) ? 0.0 : fma(d[2 * i + 1], G.a[i][1][c], d[2 * i] * G.a[i][0][c]);
+          qn[c] = (i == NO) ? 0.0 : fma(d[2 * i + 1], G.a(i, 1, c), d[2 * i] * G.a(i, 0, c));
           D[c] = qn[c] - qp[c];
           qp[c] = qn[c];
         }
@@ -191,11 +232,12 @@ __device__ __forceinline__ void newton_run64(const Geo64<NO>& G, double* t,
     bool acc = false;
     const int trials = majorant ? 2 : 7;
     for (int h = 0; h < trials; ++h) {
+      geo_fence();
       double tn[2 * NO];
 #pragma unroll
       for (int q = 0; q < 2 * NO; ++q) tn[q] = fma(s, d[q], t[q]);
       Seg64<NO> nx;
-      eval64<NO>(G, tn, eps2, nx);
+      eval64(G, tn, eps2, nx);
       ++k.n_eval;
       if (nx.L <= bound) {
 #pragma unroll
@@ -216,7 +258,7 @@ __device__ __forceinline__ void newton_run64(const Geo64<NO>& G, double* t,
     // (the segments at t are not kept across the trials: recomputed here in
     // the rare case that every trial failed)
     if (!acc) {
-      eval64<NO>(G, t, eps2, cur);
+      eval64(G, t, eps2, cur);
       ++k.n_eval;
     }
     k.last_small = acc && (s == 1.0) && (d2 <= cert2);
@@ -230,20 +272,21 @@ __device__ __forceinline__ void newton_run64(const Geo64<NO>& G, double* t,
 // degenerate configuration in which the length is nearly flat along the
 // segment and the smoothing can pull the points together. Such a path is not
 // certified.
-template <int NO>
-__device__ __forceinline__ bool nonsmooth_ok64(const Geo64<NO>& G,
+template <class GEO>
+__device__ __forceinline__ bool nonsmooth_ok64(const GEO& G,
                                                const double* t, double eps,
                                                double scale) {
+  constexpr int NO = GEO::kOrder;
   const double short2 = 1e-6 * scale * scale;
   double x[NO][3];
-  points64<NO>(G, t, x);
+  points64(G, t, x);
   bool ok = true;
 #pragma unroll
   for (int i = 0; i <= NO; ++i) {
     double r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
+      r[c] = ((i == NO) ? G.rx(c) : x[i][c]) - ((i == 0) ? G.tx(c) : x[i - 1][c]);
     // |v_i|^2 = q / (q + eps^2) > 0.98^2
     double q = dot3d(r, r);
     if (q < short2 && q > (0.98 * 0.98) * (q + eps * eps)) ok = false;
@@ -253,10 +296,11 @@ __device__ __forceinline__ bool nonsmooth_ok64(const Geo64<NO>& G,
 
 // Damped Newton refinement, level by level (quick: only the last level, with
 // quick_steps steps). t is in the caller's parametrisation.
-template <int NO>
-__device__ __forceinline__ RefineOut refine64(const Geo64<NO>& G, double* t,
+template <class GEO>
+__device__ __forceinline__ RefineOut refine64(const GEO& G, double* t,
                                               const SolveArgs& A, bool quick,
                                               uint32_t& n_eval, uint32_t& n_solve) {
+  constexpr int NO = GEO::kOrder;
   const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
   NewtonTrack k{false, false, false, 0, 0};
   const int lv0 = quick ? A.n_levels - 1 : 0;
@@ -264,7 +308,7 @@ __device__ __forceinline__ RefineOut refine64(const Geo64<NO>& G, double* t,
     double eps = (double)A.level_eps[lv] * (double)A.scale;
     // (the quick pass, which every path takes, uses the one-evaluation
     // majorant fallback; the paths left for the full schedule backtrack)
-    newton_run64<NO>(G, t, eps * eps, quick ? A.quick_steps : A.level_steps[lv],
+    newton_run64(G, t, eps * eps, quick ? A.quick_steps : A.level_steps[lv],
                      cert2, quick, k);
   }
   n_eval += k.n_eval;
@@ -276,7 +320,7 @@ __device__ __forceinline__ RefineOut refine64(const Geo64<NO>& G, double* t,
   // then jumps). Two consecutive small full steps are required.
   o.certified = A.n_levels > 0 && k.prev_small && k.last_small;
   if (o.certified)
-    o.certified = nonsmooth_ok64<NO>(
+    o.certified = nonsmooth_ok64(
         G, t, (double)A.level_eps[A.n_levels - 1] * (double)A.scale, (double)A.scale);
   return o;
 }
@@ -503,31 +547,33 @@ __device__ __forceinline__ void coords64(const double (*a)[3], const double* b,
 
 // The objects of slots a and a + 1 (selected without dynamic register
 // indexing).
-template <int NO>
-__device__ __forceinline__ void pair64(const Geo64<NO>& G, int a,
+template <class GEO>
+__device__ __forceinline__ void pair64(const GEO& G, int a,
                                        double (*aa)[3], double* ba, bool& ea,
                                        double (*ab)[3], double* bb, bool& eb) {
+  constexpr int NO = GEO::kOrder;
 #pragma unroll
   for (int j = 0; j + 1 < NO; ++j) {
     const bool s = (j == a);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      aa[0][c] = s ? G.a[j][0][c] : aa[0][c];
-      aa[1][c] = s ? G.a[j][1][c] : aa[1][c];
-      ba[c] = s ? G.b[j][c] : ba[c];
-      ab[0][c] = s ? G.a[j + 1][0][c] : ab[0][c];
-      ab[1][c] = s ? G.a[j + 1][1][c] : ab[1][c];
-      bb[c] = s ? G.b[j + 1][c] : bb[c];
+      aa[0][c] = s ? G.a(j, 0, c) : aa[0][c];
+      aa[1][c] = s ? G.a(j, 1, c) : aa[1][c];
+      ba[c] = s ? G.b(j, c) : ba[c];
+      ab[0][c] = s ? G.a(j + 1, 0, c) : ab[0][c];
+      ab[1][c] = s ? G.a(j + 1, 1, c) : ab[1][c];
+      bb[c] = s ? G.b(j + 1, c) : bb[c];
     }
-    ea = s ? G.edge[j] : ea;
-    eb = s ? G.edge[j + 1] : eb;
+    ea = s ? G.edge(j) : ea;
+    eb = s ? G.edge(j + 1) : eb;
   }
 }
 
-template <int NO>
-__device__ __forceinline__ bool merge64(const Geo64<NO>& G, double* t,
+template <class GEO>
+__device__ __forceinline__ bool merge64(const GEO& G, double* t,
                                         const SolveArgs& A, uint32_t& n_eval,
                                         uint32_t& n_solve) {
+  constexpr int NO = GEO::kOrder;
   if constexpr (NO < 2) {
     return false;
   } else {
@@ -540,13 +586,13 @@ __device__ __forceinline__ bool merge64(const Geo64<NO>& G, double* t,
     double ymid[3] = {0.0, 0.0, 0.0};
     {
       double x[NO][3];
-      points64<NO>(G, t, x);
+      points64(G, t, x);
 #pragma unroll
       for (int i = 0; i <= NO; ++i) {
         double r[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          r[c] = ((i == NO) ? G.rx[c] : x[i][c]) - ((i == 0) ? G.tx[c] : x[i - 1][c]);
+          r[c] = ((i == NO) ? G.rx(c) : x[i][c]) - ((i == 0) ? G.tx(c) : x[i - 1][c]);
         bool sh = dot3d(r, r) < short2;
         nshort += sh ? ((i == 0 || i == NO) ? 2 : 1) : 0;
         a = sh ? i - 1 : a;
@@ -566,14 +612,14 @@ __device__ __forceinline__ bool merge64(const Geo64<NO>& G, double* t,
     {
       double aa[2][3] = {}, ab[2][3] = {}, ba[3] = {}, bb[3] = {};
       bool ea = false, eb = false;
-      pair64<NO>(G, a, aa, ba, ea, ab, bb, eb);
+      pair64(G, a, aa, ba, ea, ab, bb, eb);
       const Basis64 U = basis64(aa, ea), V = basis64(ab, eb);
       Virt64 X;
       if (!intersect64(U, ba, V, bb, ymid, 1e-6 * S, 1.44e-2 * S * S, X)) return false;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        R.tx[c] = G.tx[c];
-        R.rx[c] = G.rx[c];
+        R.tx_[c] = G.tx(c);
+        R.rx_[c] = G.rx(c);
         nul[0][c] = X.nul[0][c];
         nul[1][c] = X.nul[1][c];
       }
@@ -582,12 +628,12 @@ __device__ __forceinline__ bool merge64(const Geo64<NO>& G, double* t,
         const bool lo = j < a, vi = j == a;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          R.b[j][c] = vi ? X.y0[c] : (lo ? G.b[j][c] : G.b[j + 1][c]);
-          R.a[j][0][c] = vi ? X.e[0][c] : (lo ? G.a[j][0][c] : G.a[j + 1][0][c]);
-          R.a[j][1][c] = vi ? X.e[1][c] : (lo ? G.a[j][1][c] : G.a[j + 1][1][c]);
+          R.b_[j][c] = vi ? X.y0[c] : (lo ? G.b(j, c) : G.b(j + 1, c));
+          R.a_[j][0][c] = vi ? X.e[0][c] : (lo ? G.a(j, 0, c) : G.a(j + 1, 0, c));
+          R.a_[j][1][c] = vi ? X.e[1][c] : (lo ? G.a(j, 1, c) : G.a(j + 1, 1, c));
         }
-        R.edge[j] = vi ? (X.dim < 2) : (lo ? G.edge[j] : G.edge[j + 1]);
-        R.fixed[j] = vi && X.dim == 0;
+        R.edge_[j] = vi ? (X.dim < 2) : (lo ? G.edge(j) : G.edge(j + 1));
+        R.fixed_[j] = vi && X.dim == 0;
         double m[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) m[c] = ymid[c] - X.y0[c];
@@ -598,11 +644,11 @@ __device__ __forceinline__ bool merge64(const Geo64<NO>& G, double* t,
     const double eps = (double)A.level_eps[A.n_levels - 1] * S;
     const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
     NewtonTrack k{false, false, false, 0, 0};
-    newton_run64<NO - 1>(R, tr, eps * eps, 8, cert2, false, k);
+    newton_run64(R, tr, eps * eps, 8, cert2, false, k);
     n_eval += k.n_eval;
     n_solve += k.n_solve;
     if (!(k.prev_small && k.last_small)) return false;
-    if (!nonsmooth_ok64<NO - 1>(R, tr, eps, S)) return false;
+    if (!nonsmooth_ok64(R, tr, eps, S)) return false;
     // subgradient of the collapsed segment: least-norm w with
     // P_U w = P_U u_in and P_V w = P_V u_out (P = projector onto the
     // object's directions), w = (P_U + P_V)^+ (P_U u_in + P_V u_out); the
@@ -611,10 +657,10 @@ __device__ __forceinline__ bool merge64(const Geo64<NO>& G, double* t,
     double uin[3] = {}, uout[3] = {}, y[3] = {};
     {
       Seg64<NO - 1> sg;
-      eval64<NO - 1>(R, tr, 0.0, sg);
+      eval64(R, tr, 0.0, sg);
       ++n_eval;
       double xr[NO - 1][3];
-      points64<NO - 1>(R, tr, xr);
+      points64(R, tr, xr);
 #pragma unroll
       for (int j = 0; j < NO - 1; ++j) {
         const bool s = (j == a);
@@ -628,7 +674,7 @@ __device__ __forceinline__ bool merge64(const Geo64<NO>& G, double* t,
     }
     double aa[2][3] = {}, ab[2][3] = {}, ba[3] = {}, bb[3] = {};
     bool ea = false, eb = false;
-    pair64<NO>(G, a, aa, ba, ea, ab, bb, eb);
+    pair64(G, a, aa, ba, ea, ab, bb, eb);
     {
       const Basis64 U = basis64(aa, ea), V = basis64(ab, eb);
       double M[3][3], rhs[3];
@@ -694,22 +740,23 @@ __device__ __forceinline__ bool merge64(const Geo64<NO>& G, double* t,
 // Final outputs of path p from the FP64 parameters td (caller's
 // parametrisation): points, exact length, parameters, status (collapsed:
 // set FPT_ST_COLLAPSED whatever the segment lengths).
-template <int NO>
+template <class GEO>
 __device__ __forceinline__ void write_path64(const SolveArgs& A,
-                                             const Geo64<NO>& D,
+                                             const GEO& D,
                                              const double* td, int64_t p,
                                              bool valid, bool certified,
                                              bool refined, bool collapsed = false) {
+  constexpr int NO = GEO::kOrder;
   const float qnan = __builtin_nanf("");
   double xs[NO][3];
-  points64<NO>(D, td, xs);
+  points64(D, td, xs);
   double Lx = 0.0, minl2 = INFINITY;
 #pragma unroll
   for (int i = 0; i <= NO; ++i) {
     double rr[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      rr[c] = ((i == NO) ? D.rx[c] : xs[i][c]) - ((i == 0) ? D.tx[c] : xs[i - 1][c]);
+      rr[c] = ((i == NO) ? D.rx(c) : xs[i][c]) - ((i == 0) ? D.tx(c) : xs[i - 1][c]);
     double q2 = dot3d(rr, rr);
     minl2 = fmin(minl2, q2);
     Lx += (q2 > 0.0) ? q2 * rsq64(q2) : 0.0;
@@ -1133,6 +1180,7 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
     count = bucket[NO] - begin;
   }
   const bool quick = St.out_list != nullptr;
+  __shared__ float geo[geo_lds_rows(NO) * kBlock];
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -1151,18 +1199,18 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
       p = perm ? (int64_t)perm[begin + idx] : idx;
     }
     const bool valid = (A.status[p] & FPT_ST_INVALID) == 0;
-    Geo64<NO> D;
+    GeoLds<NO> D;
     float inv[NO][2];
-    load_geo64<NO>(A, p, D, inv);
+    load_geo_lds<NO>(A, p, geo + threadIdx.x, D, inv);
     double td[2 * NO];
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
       float t0 = A.t[(int64_t)(2 * j) * A.N + p];
       float t1 = A.t[(int64_t)(2 * j + 1) * A.N + p];
       td[2 * j] = (double)t0 * (double)inv[j][0];
-      td[2 * j + 1] = D.edge[j] ? 0.0 : (double)t1 * (double)inv[j][1];
+      td[2 * j + 1] = D.edge(j) ? 0.0 : (double)t1 * (double)inv[j][1];
     }
-    RefineOut ro = refine64<NO>(D, td, A, quick, n_eval, n_solve);
+    RefineOut ro = refine64(D, td, A, quick, n_eval, n_solve);
     // first pass: defer the paths it does not certify
     const bool defer = quick && valid && !ro.certified;
     const unsigned long long more = __ballot(defer);
@@ -1184,11 +1232,11 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
       for (int j = 0; j < NO; ++j) {
         A.t[(int64_t)(2 * j) * A.N + p] = (float)(td[2 * j] * rcp64((double)inv[j][0]));
         A.t[(int64_t)(2 * j + 1) * A.N + p] =
-            D.edge[j] ? 0.f : (float)(td[2 * j + 1] * rcp64((double)inv[j][1]));
+            D.edge(j) ? 0.f : (float)(td[2 * j + 1] * rcp64((double)inv[j][1]));
       }
       continue;
     }
-    write_path64<NO>(A, D, td, p, valid, ro.certified, ro.refined);
+    write_path64(A, D, td, p, valid, ro.certified, ro.refined);
   }
   if (A.work) {
     // wave sums, one atomic per wave
@@ -1222,6 +1270,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St
   }
   __syncthreads();
   const int64_t count = pre[kRegions];
+  __shared__ float geo[geo_lds_rows(NO) * kBlock];
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -1234,19 +1283,19 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St
       if (pre[mid] <= idx) lo = mid; else hi = mid;
     }
     const int64_t p = St.in_list[(int64_t)lo * St.rcap + (idx - pre[lo])];
-    Geo64<NO> D;
+    GeoLds<NO> D;
     float inv[NO][2];
-    load_geo64<NO>(A, p, D, inv);
+    load_geo_lds<NO>(A, p, geo + threadIdx.x, D, inv);
     double td[2 * NO];
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
       float t0 = A.t[(int64_t)(2 * j) * A.N + p];
       float t1 = A.t[(int64_t)(2 * j + 1) * A.N + p];
       td[2 * j] = (double)t0 * (double)inv[j][0];
-      td[2 * j + 1] = D.edge[j] ? 0.0 : (double)t1 * (double)inv[j][1];
+      td[2 * j + 1] = D.edge(j) ? 0.0 : (double)t1 * (double)inv[j][1];
     }
     uint32_t me = 0, ms = 0;
-    const bool ok = merge64<NO>(D, td, A, me, ms);
+    const bool ok = merge64(D, td, A, me, ms);
     n_eval += me;
     n_solve += ms;
     const unsigned long long more = __ballot(!ok);
@@ -1261,7 +1310,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St
         St.out_list[(int64_t)region * St.rcap +
                     (int64_t)(base + (unsigned long long)__popcll(more & below))] = (int32_t)p;
     }
-    if (ok) write_path64<NO>(A, D, td, p, true, true, true, true);
+    if (ok) write_path64(A, D, td, p, true, true, true, true);
   }
   if (A.work) {
 #pragma unroll
