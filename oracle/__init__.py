@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libfermat_oracle.so")
 SOURCES = [os.path.join(HERE, "fermat_oracle.c")]
 
 COLLAPSED, ILL, NOCONV, INVALID = 1, 2, 4, 8
+EXTENT, SPECULAR, VISIBLE = 1, 2, 4
 
 
 def build(force: bool = True) -> str:
@@ -57,6 +58,9 @@ def _load():
         lib.oracle_length.argtypes = [I64, I32, P, I64, P, I64, P, P, P, P, P,
                                       P]
         lib.oracle_length.restype = I32
+        lib.oracle_validate.argtypes = [I64, I32, P, I64, P, I64, P, P, P, P,
+                                        D, P, P, D, P, I32]
+        lib.oracle_validate.restype = I32
         _lib = lib
     return _lib
 
@@ -140,5 +144,25 @@ def length(b, t):
                            t.ctypes.data, out.ctypes.data)
     if rc != 0:
         raise ValueError("oracle_length rejected the sizes")
+    del keep
+    return out
+
+
+def validate(b, t, x, tol: float = 0.0, threads: int = 0):
+    """Validity bits (EXTENT, SPECULAR, VISIBLE) of solved paths on the finite
+    objects of the scene, for parameters ``t [N][n_max][2]`` and points
+    ``x [N][n_max][3]``; ``tol`` widens (> 0) or narrows the tests (see
+    ``fermat_oracle.c``)."""
+    lib = _load()
+    t = np.ascontiguousarray(t, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    assert t.shape == (b.N, b.n_max, 2) and x.shape == (b.N, b.n_max, 3)
+    out = np.empty(b.N, np.uint8)
+    keep, (po, K, pp, Q, ps, pd, pn, pi) = _tables(b)
+    rc = lib.oracle_validate(b.N, b.n_max, po, K, pp, Q, ps, pd, pn, pi,
+                             float(b.S), t.ctypes.data, x.ctypes.data,
+                             float(tol), out.ctypes.data, int(threads))
+    if rc != 0:
+        raise ValueError("oracle_validate rejected the sizes")
     del keep
     return out

@@ -508,3 +508,115 @@ int oracle_length(int64_t N, int n_max, const float *obj, int64_t K,
   }
   return 0;
 }
+
+/* ------------------------------------------------------------- validity -- */
+/*
+ * Post-processing of solved paths on finite objects (the step after the
+ * solve that Sec. III names but does not study). A face is the
+ * parallelogram b + s a1 + u a2, s, u in [0, 1]; an edge the segment
+ * b + s a1, s in [0, 1]. For tolerance tol (may be negative):
+ *   EXTENT   every interaction parameter lies in [-tol, 1 + tol]
+ *   SPECULAR at every face, the previous and next points are on the same
+ *            side: with d = n.(x_prev - x) / S and n the unit normal,
+ *            both d_in, d_out > tol or both < -tol
+ *   VISIBLE  no segment crosses a face of the scene other than the faces of
+ *            its own end points: a crossing is a point of the segment at
+ *            parameter s in (1e-6, 1 - 1e-6) on the face's plane with both
+ *            face parameters in [tol, 1 - tol]; segments parallel to a face
+ *            do not cross it; edges occlude nothing.
+ * Points and parameters are the caller's (x [N][n_max][3], t
+ * [N][n_max][2]); flags[i] gets the bits of the tests that pass.
+ */
+static int crosses_face(const double *p, const double *q, const double *b,
+                        const double *u, const double *v, double tol) {
+  double d[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+  double w[3] = {b[0] - p[0], b[1] - p[1], b[2] - p[2]};
+  /* p + s d = b + al u + be v: Cramer's rule on [d, -u, -v] (s, al, be) = w */
+  double m[3][3] = {{d[0], -u[0], -v[0]}, {d[1], -u[1], -v[1]}, {d[2], -u[2], -v[2]}};
+  double det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+               m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+               m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+  double nd = sqrt(dot3(d, d));
+  double nu = sqrt(dot3(u, u)), nv = sqrt(dot3(v, v));
+  if (fabs(det) <= 1e-12 * nd * nu * nv) return 0;
+  double sol[3];
+  for (int k = 0; k < 3; ++k) {
+    double mk[3][3];
+    memcpy(mk, m, sizeof mk);
+    for (int r = 0; r < 3; ++r) mk[r][k] = w[r];
+    sol[k] = (mk[0][0] * (mk[1][1] * mk[2][2] - mk[1][2] * mk[2][1]) -
+              mk[0][1] * (mk[1][0] * mk[2][2] - mk[1][2] * mk[2][0]) +
+              mk[0][2] * (mk[1][0] * mk[2][1] - mk[1][1] * mk[2][0])) / det;
+  }
+  return sol[0] > 1e-6 && sol[0] < 1.0 - 1e-6 && sol[1] >= tol &&
+         sol[1] <= 1.0 - tol && sol[2] >= tol && sol[2] <= 1.0 - tol;
+}
+
+int oracle_validate(int64_t N, int n_max, const float *obj, int64_t K,
+                    const float *pts, int64_t Q, const int32_t *src,
+                    const int32_t *dst, const uint8_t *order, const int32_t *ids,
+                    double S, const double *t_in, const double *x_in,
+                    double tol, uint8_t *flags, int nthreads) {
+  if (N < 0 || n_max < 1 || n_max > NMAX || K < 0 || Q < 0 || !(S > 0)) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; ++i) {
+    path_t p;
+    if (load_path(&p, i, N, n_max, obj, K, pts, Q, src, dst, order, ids)) {
+      flags[i] = 0;
+      continue;
+    }
+    const int n = p.n;
+    /* points x[0] = TX, x[1..n], x[n+1] = RX */
+    double x[NMAX + 2][3];
+    memcpy(x[0], p.x0, sizeof p.x0);
+    memcpy(x[n + 1], p.xe, sizeof p.xe);
+    for (int j = 0; j < n; ++j)
+      for (int c = 0; c < 3; ++c) x[j + 1][c] = x_in[(i * n_max + j) * 3 + c];
+    int extent = 1, specular = 1, visible = 1;
+    for (int j = 0; j < n; ++j) {
+      for (int k = 0; k < p.d[j]; ++k) {
+        double tk = t_in[(i * n_max + j) * 2 + k];
+        if (!(tk >= -tol && tk <= 1.0 + tol)) extent = 0;
+      }
+      if (p.d[j] == 2) {
+        const double *u = p.a[j][0], *v = p.a[j][1];
+        double nrm[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2],
+                         u[0] * v[1] - u[1] * v[0]};
+        double ln = sqrt(dot3(nrm, nrm));
+        double din = 0.0, dout = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          din += nrm[c] * (x[j][c] - x[j + 1][c]);
+          dout += nrm[c] * (x[j + 2][c] - x[j + 1][c]);
+        }
+        din /= ln * S;
+        dout /= ln * S;
+        if (!((din > tol && dout > tol) || (din < -tol && dout < -tol))) specular = 0;
+      }
+    }
+    for (int s = 0; s <= n && visible; ++s) {
+      /* segment s from point s to point s + 1; own faces: slots s-1 and s */
+      int64_t own0 = s >= 1 ? ids[(int64_t)(s - 1) * N + i] : -1;
+      int64_t own1 = s < n ? ids[(int64_t)s * N + i] : -1;
+      for (int64_t f = 0; f < K && visible; ++f) {
+        if (f == own0 || f == own1) continue;
+        double b[3], u[3], v[3];
+        for (int c = 0; c < 3; ++c) {
+          b[c] = obj[c * K + f];
+          u[c] = obj[(3 + c) * K + f];
+          v[c] = obj[(6 + c) * K + f];
+        }
+        if (v[0] == 0.0 && v[1] == 0.0 && v[2] == 0.0) continue;
+        if (crosses_face(x[s], x[s + 1], b, u, v, tol)) visible = 0;
+      }
+    }
+    flags[i] = (uint8_t)((extent ? ORACLE_EXTENT : 0) |
+                         (specular ? ORACLE_SPECULAR : 0) |
+                         (visible ? ORACLE_VISIBLE : 0));
+  }
+  return 0;
+}

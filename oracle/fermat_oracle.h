@@ -33,6 +33,9 @@ enum {
   ORACLE_INVALID = 8    /* bad id / order / point index or non-finite input */
 };
 
+/* validity bits of oracle_validate */
+enum { ORACLE_EXTENT = 1, ORACLE_SPECULAR = 2, ORACLE_VISIBLE = 4 };
+
 int oracle_solve(int64_t N, int n_max, const float *obj, int64_t K,
                  const float *pts, int64_t Q, const int32_t *src,
                  const int32_t *dst, const uint8_t *order, const int32_t *ids,
@@ -56,5 +59,13 @@ int oracle_length(int64_t N, int n_max, const float *obj, int64_t K,
                   const float *pts, int64_t Q, const int32_t *src,
                   const int32_t *dst, const uint8_t *order, const int32_t *ids,
                   const double *t_in, double *len_out);
+
+/* Validity of solved paths on finite objects (see fermat_oracle.c):
+ * t_in [N][n_max][2], x_in [N][n_max][3] path-major; flags [N]. */
+int oracle_validate(int64_t N, int n_max, const float *obj, int64_t K,
+                    const float *pts, int64_t Q, const int32_t *src,
+                    const int32_t *dst, const uint8_t *order, const int32_t *ids,
+                    double S, const double *t_in, const double *x_in,
+                    double tol, uint8_t *flags, int nthreads);
 
 #endif

@@ -340,3 +340,100 @@ def test_gradient_structure(oracle_mod):
         u, _ = pins.segment_dirs(xs)
         np.testing.assert_allclose(g0["g_tx"][i], -gl[i] * u[0], atol=1e-9)
         np.testing.assert_allclose(g0["g_rx"][i], gl[i] * u[-1], atol=1e-9)
+
+
+# ------------------------------------------------------------ validity ----
+# Post-processing on finite objects (faces are parallelograms b + s a1 + u a2,
+# edges segments b + s a1, parameters in [0, 1]).
+
+def _validity_batch(paths, extra_objs, S=10.0):
+    """Batch of explicit order-n paths whose object table also holds
+    `extra_objs` (occluder candidates that no path uses)."""
+    from paper_2510_16172_amd.scenes import Batch
+    b = pins.batch_from_paths(paths, S)
+    if extra_objs:
+        ext = np.array([np.concatenate(o) for o in extra_objs], np.float32).T
+        obj = np.concatenate([b.obj, ext], axis=1)
+        b = Batch(np.ascontiguousarray(obj), b.pts, b.src, b.dst, b.order, b.ids, b.S)
+    return b
+
+
+def _flags_for(oracle_mod, paths, t_list, extra=(), tol=0.0):
+    b = _validity_batch(paths, list(extra))
+    n = b.n_max
+    t = np.zeros((b.N, n, 2))
+    x = np.zeros((b.N, n, 3))
+    for i, ((tx, rx, objs), ts) in enumerate(zip(paths, t_list)):
+        for j, ((bb, a1, a2), tj) in enumerate(zip(objs, ts)):
+            t[i, j] = tj
+            x[i, j] = np.asarray(bb) + tj[0] * np.asarray(a1) + tj[1] * np.asarray(a2)
+    return oracle_mod.validate(b, t, x, tol=tol)
+
+
+def test_validity_hand_cases(oracle_mod):
+    """Reflection at (1,0,0) of TX (0,0,1) -> RX (2,0,1) on the floor z = 0."""
+    E, SP, V = oracle_mod.EXTENT, oracle_mod.SPECULAR, oracle_mod.VISIBLE
+    tx, rx = (0.0, 0.0, 1.0), (2.0, 0.0, 1.0)
+    floor = ((-1.0, -1.0, 0.0), (4.0, 0.0, 0.0), (0.0, 2.0, 0.0))   # x in [-1,3]
+    small = ((-1.0, -1.0, 0.0), (1.0, 0.0, 0.0), (0.0, 2.0, 0.0))   # x in [-1,0]
+    wall = ((0.5, -1.0, 0.0), (0.0, 2.0, 0.0), (0.0, 0.0, 2.0))     # x = 0.5
+    wall_off = ((0.5, 2.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 2.0))  # y in [2,3]
+    edge = ((0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+    paths = [(tx, rx, [floor]), (tx, rx, [small]), (tx, (2.0, 0.0, -1.0), [floor]),
+             (tx, rx, [floor]), (tx, rx, [edge]), (tx, rx, [edge])]
+    t_list = [[(0.5, 0.5)], [(2.0, 0.5)], [(0.5, 0.5)], [(0.5, 0.5)],
+              [(0.5, 0.0)], [(1.5, 0.0)]]
+    f = _flags_for(oracle_mod, paths[:3], t_list[:3])
+    assert list(f) == [E | SP | V, SP | V, E | V]
+    # the wall at x = 0.5 cuts TX -> (1,0,0) at (0.5, 0, 0.5), inside it
+    f = _flags_for(oracle_mod, paths[3:4], t_list[3:4], extra=[wall])
+    assert list(f) == [E | SP]
+    f = _flags_for(oracle_mod, paths[3:4], t_list[3:4], extra=[wall_off])
+    assert list(f) == [E | SP | V]
+    # an edge has no side test; its one parameter must lie in [0, 1]
+    f = _flags_for(oracle_mod, paths[4:], t_list[4:])
+    assert list(f) == [E | SP | V, SP | V]
+
+
+def test_validity_crossing_vs_linear_solve(oracle_mod):
+    """VISIBLE against an independent crossing test: each segment-face pair
+    solved with numpy.linalg.solve (LU) instead of Cramer's rule; pairs
+    within 1e-7 of a decision boundary are left out."""
+    rng = np.random.default_rng(77)
+    faces = []
+    for _ in range(40):
+        b = rng.uniform(-5, 5, 3)
+        q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+        faces.append((b, q[:, 0] * rng.uniform(1, 4), q[:, 1] * rng.uniform(1, 4)))
+    dummy = ((50.0, 50.0, 50.0), (1.0, 0.0, 0.0), (0.0, 0.0, 0.0))  # an edge
+    paths, t_list, want, keep = [], [], [], []
+    for i in range(400):
+        tx = rng.uniform(-6, 6, 3)
+        rx = rng.uniform(-6, 6, 3)
+        xm = rng.uniform(-6, 6, 3)
+        # order-1 path TX -> xm -> RX with xm placed on the dummy edge's line
+        obj = ((xm - np.array([0.5, 0, 0])), (1.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+        paths.append((tx, rx, [obj]))
+        t_list.append([(0.5, 0.0)])
+        hit, tie = False, False
+        for p, q in ((tx, xm), (xm, rx)):
+            for (b, u, v) in faces:
+                M = np.stack([q - p, -u, -v], 1)
+                if abs(np.linalg.det(M)) <= 1e-12 * np.linalg.norm(q - p) * np.linalg.norm(u) * np.linalg.norm(v):
+                    continue
+                s, al, be = np.linalg.solve(M, b - p)
+                margins = [s - 1e-6, 1 - 1e-6 - s, al, 1 - al, be, 1 - be]
+                inside = all(m > 0 for m in margins)
+                if min(abs(m) for m in margins) < 1e-7:
+                    tie = True
+                hit = hit or inside
+        want.append(not hit)
+        keep.append(not tie)
+    b = _validity_batch(paths, faces)
+    t = np.array([[tl[0]] for tl in t_list])
+    x = np.array([[p[2][0][0] + 0.5 * np.asarray(p[2][0][1])] for p in paths])
+    f = oracle_mod.validate(b, t, x)
+    got = (f & oracle_mod.VISIBLE) != 0
+    keep = np.array(keep)
+    assert keep.sum() > 390 and 0.2 < np.mean(want) < 0.9
+    np.testing.assert_array_equal(got[keep], np.array(want)[keep])
