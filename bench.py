@@ -416,6 +416,19 @@ def main():
     work = solver.work_counts()
     solver.set_timing(False)
 
+    # post-processing (not part of the metric): validity of the solved paths
+    # on the scene's finite objects
+    vflags = solver.validate(db, out, stream=stream)
+    torch.cuda.synchronize()
+    v0, v1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    v0.record(stream)
+    for _ in range(3):
+        solver.validate(db, out, flags=vflags, stream=stream)
+    v1.record(stream)
+    torch.cuda.synchronize()
+    ms_val = v0.elapsed_time(v1) / 3
+    vf = vflags.cpu().numpy()
+
     out_np = {k: v.cpu().numpy() for k, v in out.items()}
     st = out_np["status"]
     certified = int(((st & fpt.ST_CONVERGED) != 0).sum())
@@ -493,6 +506,14 @@ def main():
         "kernel_ms": kernels_ms,
         "roofline": dominant,
         "roofline_other": other,
+        "validate": {
+            "ms": ms_val, "paths_per_s": N / (ms_val * 1e-3),
+            "extent": float(((vf & fpt.VALID_EXTENT) != 0).mean()),
+            "specular": float(((vf & fpt.VALID_SPECULAR) != 0).mean()),
+            "visible": float(((vf & fpt.VALID_VISIBLE) != 0).mean()),
+            "valid": float((vf == 7).mean()),
+            "valid_and_certified": float(((vf == 7) & ((st & fpt.ST_CONVERGED) != 0)).mean()),
+        },
     }
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))

@@ -180,6 +180,29 @@ fpt_status fpt_grad(fpt_handle* h, const fpt_scene* scene,
                     float* g_obj, float* g_slot, float* g_end,
                     void* hip_stream);
 
+/* Validity of solved paths on finite objects: the post-processing step
+ * after the solve (Sec. III names finite objects and obstruction but leaves
+ * them out; the solver treats every object as its infinite plane or line).
+ * A face is the parallelogram b + s a1 + u a2 with s, u in [0, 1]; an edge
+ * the segment b + s a1 with s in [0, 1]. For every path, flags[i] gets
+ *   FPT_VALID_EXTENT    every interaction parameter (fwd->t) in [0, 1];
+ *   FPT_VALID_SPECULAR  at every face, the previous and next points lie
+ *                       strictly on the same side of its plane (a reflection,
+ *                       not a pass-through);
+ *   FPT_VALID_VISIBLE   no segment crosses a face of the scene other than
+ *                       the faces of its own end points (a crossing: at
+ *                       segment parameter in (1e-6, 1 - 1e-6), face
+ *                       parameters in [0, 1]; edges occlude nothing).
+ * A path is valid when all three are set. Paths with FPT_ST_INVALID or
+ * FPT_ST_NONFINITE in fwd->status, or an order outside 1..n_max, get 0.
+ * Needs fwd->x, fwd->t, fwd->status (device pointers) and flags [N] (device).
+ * The work is every segment against every face: O(N n K). Uses tables of
+ * 18 K + 64 floats in the handle's workspace (hipMalloc on growth). */
+enum { FPT_VALID_EXTENT = 1, FPT_VALID_SPECULAR = 2, FPT_VALID_VISIBLE = 4 };
+fpt_status fpt_validate(fpt_handle* h, const fpt_scene* scene,
+                        const fpt_paths* paths, const fpt_out* fwd,
+                        uint8_t* flags, void* hip_stream);
+
 /* Launch configuration of the FP32 solver kernel of one order (what the
  * autotuner chooses). wg_per_cu: resident workgroups per compute unit for
  * the persistent launches (0 = as many as the kernel's register use allows);
@@ -224,6 +247,7 @@ fpt_status fpt_graph_destroy(fpt_graph* g);
  *   FPT_T_GRAD             implicit-differentiation kernel
  *   FPT_T_REDUCE           per-object gradient reduction
  *   FPT_T_MLP              learned-initialiser inference
+ *   FPT_T_VALIDATE         path validity (fpt_validate)
  * Enabling allocates the events (returns FPT_EHIP if that fails). */
 enum {
   FPT_T_BUCKET = 0,
@@ -232,7 +256,8 @@ enum {
   FPT_T_GRAD = 13,
   FPT_T_REDUCE = 14,
   FPT_T_MLP = 15,
-  FPT_TIMERS = 16
+  FPT_T_VALIDATE = 16,
+  FPT_TIMERS = 17
 };
 fpt_status fpt_set_timing(fpt_handle* h, int enable);
 fpt_status fpt_kernel_times(fpt_handle* h, float* ms);

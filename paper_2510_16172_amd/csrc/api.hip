@@ -24,6 +24,12 @@ hipError_t launch_grad(int order, const GradArgs& A, const int32_t* perm,
                        const int64_t* bucket, int grid, size_t shmem,
                        hipStream_t st);
 const void* grad_kernel_ptr(int order);
+hipError_t launch_face_table(const float* obj, int32_t K, float* tab, float* nrm,
+                             int32_t* nfaces, hipStream_t st);
+hipError_t launch_validate(int order, const ValidateArgs& A, const int32_t* perm,
+                           const int64_t* bucket, int grid, hipStream_t st);
+hipError_t launch_validate_invalid(const ValidateArgs& A, const int32_t* perm,
+                                   const int64_t* bucket, int grid, hipStream_t st);
 hipError_t launch_grad_invalid(const GradArgs& A, const int32_t* perm,
                                const int64_t* bucket, int grid, hipStream_t st);
 }  // namespace fpt
@@ -40,6 +46,8 @@ struct fpt_handle {
   hipEvent_t ev[FPT_TIMERS][kRing][2] = {};
   int nrec[FPT_TIMERS] = {};  // launches recorded since the last read
   unsigned long long* work = nullptr;  // [FPT_NMAX][4][kWorkSlots] counters
+  float* faces = nullptr;  // validity tables: faces [15][K], normals [3][K], count
+  int64_t faces_cap = 0;
   // workspace
   int32_t* perm = nullptr;
   uint32_t* ccount = nullptr;  // per-chunk order counts / offsets
@@ -168,6 +176,7 @@ extern "C" fpt_status fpt_destroy(fpt_handle* h) {
   if (h->ccount) (void)hipFree(h->ccount);
   if (h->counts) (void)hipFree(h->counts);
   if (h->work) (void)hipFree(h->work);
+  if (h->faces) (void)hipFree(h->faces);
   if (h->scount) (void)hipFree(h->scount);
   if (h->mlp_mem) (void)hipFree(h->mlp_mem);
   for (int k = 0; k < 2; ++k) {
@@ -645,6 +654,79 @@ extern "C" fpt_status fpt_grad(fpt_handle* h, const fpt_scene* sc,
     e = fpt::launch_grad_invalid(A, h->perm, h->bucket, sgrid, st);
     if (e != hipSuccess) return hip_fail(e, "fpt_grad: launch");
   }
+  return FPT_OK;
+}
+
+// ------------------------------------------------------------ validity ----
+
+extern "C" fpt_status fpt_validate(fpt_handle* h, const fpt_scene* sc,
+                                   const fpt_paths* pa, const fpt_out* fwd,
+                                   uint8_t* flags, void* stream) {
+  if (!h) return fail(FPT_EINVAL, "fpt_validate: handle is NULL");
+  fpt_status s = check_common(sc, pa, "fpt_validate");
+  if (s != FPT_OK) return s;
+  if (!fwd || !flags) return fail(FPT_EINVAL, "fpt_validate: fwd and flags are required");
+  if (pa->N == 0) return FPT_OK;
+  if (!fwd->x || !fwd->t || !fwd->status)
+    return fail(FPT_EINVAL, "fpt_validate: fwd.x, fwd.t and fwd.status are required");
+  if (!aligned(fwd->x, 4) || !aligned(fwd->t, 4))
+    return fail(FPT_EINVAL, "fpt_validate: misaligned pointer");
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(FPT_EHIP, "fpt_validate: hipSetDevice failed");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t kk = sc->K > 0 ? sc->K : 1;
+  const int64_t need = 18 * kk + 64;
+  if (h->faces_cap < need) {
+    if (h->faces) (void)hipFree(h->faces);
+    h->faces = nullptr;
+    h->faces_cap = 0;
+    void* p = nullptr;
+    if (hipMalloc(&p, (size_t)need * sizeof(float)) != hipSuccess)
+      return fail(FPT_ENOMEM, "fpt_validate: face table allocation failed");
+    h->faces = (float*)p;
+    h->faces_cap = need;
+  }
+  fpt::ValidateArgs A;
+  memset(&A, 0, sizeof(A));
+  A.obj = sc->obj;
+  A.pts = sc->pts;
+  A.src = pa->src;
+  A.dst = pa->dst;
+  A.ids = pa->ids;
+  A.x = fwd->x;
+  A.t = fwd->t;
+  A.status = fwd->status;
+  A.tab = h->faces;
+  A.nrm = h->faces + 15 * kk;
+  A.nfaces = (const int32_t*)(h->faces + 18 * kk);
+  A.flags = flags;
+  A.N = pa->N;
+  A.K = sc->K;
+  A.Q = sc->Q;
+  A.n_max = pa->n_max;
+  hipError_t e;
+  SlotTimer tm(h, FPT_T_VALIDATE, st);
+  e = fpt::launch_face_table(sc->obj, sc->K, h->faces, h->faces + 15 * kk,
+                             (int32_t*)(h->faces + 18 * kk), st);
+  if (e != hipSuccess) return hip_fail(e, "fpt_validate: launch");
+  const int64_t cap = (pa->N + fpt::kBlock - 1) / fpt::kBlock;
+  const int64_t pg = (int64_t)h->num_cu * 8;
+  const int grid = (int)(cap < pg ? cap : pg);
+  if (!pa->order) {
+    e = fpt::launch_validate(pa->n_max, A, nullptr, nullptr, grid, st);
+    if (e != hipSuccess) return hip_fail(e, "fpt_validate: launch");
+    return FPT_OK;
+  }
+  s = ensure_perm(h, pa->N);
+  if (s != FPT_OK) return s;
+  e = fpt::launch_bucketing(pa->order, pa->N, pa->n_max, h->ccount, h->bucket, h->perm, st);
+  if (e != hipSuccess) return hip_fail(e, "fpt_validate: bucketing launch");
+  for (int n = 1; n <= pa->n_max; ++n) {
+    e = fpt::launch_validate(n, A, h->perm, h->bucket, grid, st);
+    if (e != hipSuccess) return hip_fail(e, "fpt_validate: launch");
+  }
+  e = fpt::launch_validate_invalid(A, h->perm, h->bucket, h->num_cu * 4, st);
+  if (e != hipSuccess) return hip_fail(e, "fpt_validate: launch");
   return FPT_OK;
 }
 

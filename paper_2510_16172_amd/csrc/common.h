@@ -116,4 +116,22 @@ struct GradArgs {
   int32_t lds;            // accumulate per workgroup in LDS first
 };
 
+// Arguments of one fpt_validate call.
+struct ValidateArgs {
+  const float* obj;
+  const float* pts;
+  const int32_t* src;
+  const int32_t* dst;
+  const int32_t* ids;
+  const float* x;         // forward X* [n_max][3][N]
+  const float* t;         // forward T* [n_max][2][N] (caller's parametrisation)
+  const uint8_t* status;  // forward status [N]
+  const float* tab;       // compact face table [15][K] (face_table_kernel)
+  const float* nrm;       // normals of every object [3][K] (0 for an edge)
+  const int32_t* nfaces;  // number of faces in tab
+  uint8_t* flags;         // [N]
+  int64_t N;
+  int32_t K, Q, n_max;
+};
+
 }  // namespace fpt

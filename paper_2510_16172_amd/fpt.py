@@ -64,7 +64,9 @@ EXPORTED = ["fpt_default_opts", "fpt_create", "fpt_destroy", "fpt_solve",
             "fpt_graph_launch", "fpt_graph_destroy"]
 
 # timer slots of fpt_kernel_times
-T_BUCKET, T_BFGS, T_REFINE, T_GRAD, T_REDUCE, T_MLP, TIMERS = 0, 1, 7, 13, 14, 15, 16
+T_BUCKET, T_BFGS, T_REFINE, T_GRAD, T_REDUCE, T_MLP, T_VALIDATE, TIMERS = (
+    0, 1, 7, 13, 14, 15, 16, 17)
+VALID_EXTENT, VALID_SPECULAR, VALID_VISIBLE = 1, 2, 4
 MLP_PARAMS = 172864  # padded parameter count: state[0:MLP_PARAMS] = weights
 
 _lib = None
@@ -120,6 +122,9 @@ def load_library(path: str = LIB_PATH):
     lib.fpt_graph_launch.restype = ctypes.c_int
     lib.fpt_graph_destroy.argtypes = [_P]
     lib.fpt_graph_destroy.restype = ctypes.c_int
+    lib.fpt_validate.argtypes = [_P, ctypes.POINTER(_Scene), ctypes.POINTER(_Paths),
+                                 ctypes.POINTER(_Out), _P, _P]
+    lib.fpt_validate.restype = ctypes.c_int
     lib.fpt_work_counts.argtypes = [_P, ctypes.POINTER(ctypes.c_uint64)]
     lib.fpt_work_counts.restype = ctypes.c_int
     lib.fpt_last_error.argtypes = []
@@ -267,6 +272,18 @@ class Solver:
         ms = (ctypes.c_float * TIMERS)()
         _check(load_library().fpt_kernel_times(self._h, ms), "fpt_kernel_times")
         return [float(v) for v in ms]
+
+    def validate(self, db: DeviceBatch, out, flags=None, stream=None):
+        """fpt_validate: uint8 [N] validity bits (VALID_*) of the solved
+        paths `out` on the scene's finite objects."""
+        import torch
+        if flags is None:
+            flags = torch.empty(db.N, dtype=torch.uint8, device="cuda")
+        sc, pa, ou = db.c_scene(), db.c_paths(), self.c_out(out)
+        _check(load_library().fpt_validate(
+            self._h, ctypes.byref(sc), ctypes.byref(pa), ctypes.byref(ou),
+            _ptr(flags), _stream_ptr(stream)), "fpt_validate")
+        return flags
 
     def work_counts(self):
         """{order: (path evaluations, Newton solves, reduced-path evaluations,
