@@ -90,7 +90,7 @@ def refine_final_flops(n: int) -> int:
 
 def source_digest() -> str:
     h = hashlib.sha256()
-    for f in ("solve.hip", "common.h"):
+    for f in ("solve.hip", "path64.h", "common.h", "api.hip"):
         with open(os.path.join(ROOT, "paper_2510_16172_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -500,6 +500,7 @@ def main():
             "autotuned": not args.no_autotune,
             "refine_levels": list(zip(opts.level_eps, opts.level_steps)),
             "quick_steps": opts.quick_steps,
+            "quick_passes": opts.quick_passes,
         },
         "certified_fraction": certified / N,
         "paths_per_s_all": N / (ms_step / 1e3),

@@ -130,12 +130,16 @@ typedef struct {
                            did not certify (the certificate needs two steps,
                            so 1 certifies nothing in the first pass).
                            0: the full schedule for all */
+  int32_t quick_passes; /* 1 or 2: with 2, the paths the first quick pass
+                           does not certify get a second quick pass of
+                           quick_steps more steps (compacted) before the
+                           rest of the pipeline */
 } fpt_opts;
 
 /* Defaults: 64 iterations, 1 fixed-point iteration, no early exit
  * (exit_rtol = 1e-6, stages of 16, 16 and 32 iterations), refinement levels
  * eps/S = 1e-3, 1e-5, 1e-7 (2 steps each) and 1e-9 (3 steps) after a quick
- * pass of 3 steps at 1e-9, cert_rtol = 1e-5, scale = 1. */
+ * pass of 2 steps at 1e-9 (twice: quick_passes = 2), cert_rtol = 1e-5, scale = 1. */
 void fpt_default_opts(fpt_opts* opts);
 
 typedef struct {

@@ -102,7 +102,8 @@ extern "C" void fpt_default_opts(fpt_opts* o) {
   o->stage_iters[1] = 16;
   o->stage_iters[2] = 32;
   o->stage_iters[3] = 0;
-  o->quick_steps = 3;
+  o->quick_steps = 2;
+  o->quick_passes = 2;
 }
 
 // Keeps the caller's current device and switches to the handle's for the
@@ -235,6 +236,8 @@ static fpt_status check_opts(const fpt_opts* o) {
     return fail(FPT_EINVAL, "fpt_solve: negative tolerance");
   if (o->quick_steps < 0 || o->quick_steps > 64)
     return fail(FPT_EINVAL, "fpt_solve: quick_steps outside 0..64");
+  if (o->quick_passes < 1 || o->quick_passes > 2)
+    return fail(FPT_EINVAL, "fpt_solve: quick_passes outside 1..2");
   if (o->early_exit) {
     if (o->stage_iters[0] < 1)
       return fail(FPT_EINVAL, "fpt_solve: early exit needs stage_iters[0] >= 1");
@@ -532,26 +535,40 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         e = fpt::launch_solve(1, n, An, perm, bucket, &R, grid, st);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+        // the current list (ping-pong between the two list buffers)
+        int cur = 0;
+        auto next_stage = [&](int phase, int grid_x) -> hipError_t {
+          fpt::StageArgs Q;
+          memset(&Q, 0, sizeof(Q));
+          Q.rcap = R.rcap;
+          Q.cap = R.cap;
+          Q.in_list = h->slist[cur];
+          Q.in_count = h->scount + cur * nc;
+          Q.out_list = h->slist[cur ^ 1];
+          Q.out_count = h->scount + (cur ^ 1) * nc;
+          hipError_t ez = fpt::launch_zero_u64(Q.out_count, nc, st);
+          if (ez != hipSuccess) return ez;
+          ez = fpt::launch_solve(phase, n, An, nullptr, nullptr, &Q, grid_x, st);
+          cur ^= 1;
+          return ez;
+        };
+        if (o->quick_passes > 1) {
+          // second quick pass on the paths the first did not certify
+          e = next_stage(1, persistent(1, n, 0));
+          if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+        }
+        if (n >= 2) {
+          // collapsed minimisers: merge attempt on the list, the rest listed
+          // again for pass 2
+          e = next_stage(3, persistent(3, n, 0));
+          if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+        }
         fpt::StageArgs R2;
         memset(&R2, 0, sizeof(R2));
         R2.rcap = R.rcap;
         R2.cap = R.cap;
-        R2.in_list = h->slist[0];
-        R2.in_count = h->scount;
-        if (n >= 2) {
-          // collapsed minimisers: merge attempt on the list, the rest listed
-          // again for pass 2
-          fpt::StageArgs Mg = R2;
-          Mg.out_list = h->slist[1];
-          Mg.out_count = h->scount + nc;
-          e = fpt::launch_zero_u64(Mg.out_count, nc, st);
-          if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
-          e = fpt::launch_solve(3, n, An, nullptr, nullptr, &Mg,
-                                persistent(3, n, 0), st);
-          if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
-          R2.in_list = h->slist[1];
-          R2.in_count = Mg.out_count;
-        }
+        R2.in_list = h->slist[cur];
+        R2.in_count = h->scount + cur * nc;
         // pass 2: the full schedule on the list
         e = fpt::launch_solve(1, n, An, perm, bucket, &R2, persistent(1, n, 0), st);
       } else {

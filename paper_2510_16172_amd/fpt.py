@@ -43,7 +43,7 @@ class _Opts(ctypes.Structure):
                 ("level_steps", ctypes.c_int32 * FPT_MAX_LEVELS),
                 ("cert_rtol", ctypes.c_float),
                 ("stage_iters", ctypes.c_int32 * 4),
-                ("quick_steps", ctypes.c_int32)]
+                ("quick_steps", ctypes.c_int32), ("quick_passes", ctypes.c_int32)]
 
 
 class _LaunchCfg(ctypes.Structure):
@@ -155,7 +155,8 @@ class Opts:
     level_steps: list = field(default_factory=lambda: [2, 2, 2, 3])
     cert_rtol: float = 1e-5
     stage_iters: list = field(default_factory=lambda: [16, 16, 32])
-    quick_steps: int = 3
+    quick_steps: int = 2
+    quick_passes: int = 2
 
     def to_c(self) -> _Opts:
         o = _Opts()
@@ -179,6 +180,7 @@ class Opts:
         for i in range(4):
             o.stage_iters[i] = int(self.stage_iters[i]) if i < len(self.stage_iters) else 0
         o.quick_steps = int(self.quick_steps)
+        o.quick_passes = int(self.quick_passes)
         return o
 
 

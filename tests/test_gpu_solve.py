@@ -321,7 +321,7 @@ def test_refine_work_counts(solver):
         cnt = int((b.order == n).sum())
         ev, so, mev, mso = wc[n]
         assert so >= opts.quick_steps * cnt
-        assert so <= (opts.quick_steps + total_levels) * cnt
+        assert so <= (opts.quick_passes * opts.quick_steps + total_levels) * cnt
         assert ev >= cnt + so // 2
         if n == 1:
             assert (mev, mso) == (0, 0)
