@@ -134,6 +134,10 @@ typedef struct {
                            does not certify get a second quick pass of
                            quick_steps more steps (compacted) before the
                            rest of the pipeline */
+  int32_t concurrent_orders; /* 1: with several orders (and no early exit),
+                           each order's kernels run on a stream of their own
+                           (forked from and joined back into hip_stream);
+                           0: one after the other on hip_stream */
 } fpt_opts;
 
 /* Defaults: 64 iterations, 1 fixed-point iteration, no early exit
@@ -210,14 +214,17 @@ fpt_status fpt_validate(fpt_handle* h, const fpt_scene* scene,
 /* Launch configuration of the FP32 solver kernel of one order (what the
  * autotuner chooses). wg_per_cu: resident workgroups per compute unit for
  * the persistent launches (0 = as many as the kernel's register use allows);
- * early_exit / stage_iters / iters (if > 0) override the corresponding
- * fpt_opts fields for paths of that order when use_override is 1. */
+ * early_exit / stage_iters / iters / quick_steps / quick_passes (each if
+ * > 0) override the corresponding fpt_opts fields for paths of that order
+ * when use_override is 1. */
 typedef struct {
   int32_t wg_per_cu;
   int32_t use_override;
   int32_t early_exit;
   int32_t stage_iters[FPT_MAX_STAGES];
   int32_t iters;        /* 0..65535; 0 = fpt_opts.iters */
+  int32_t quick_steps;  /* 0..64; 0 = fpt_opts.quick_steps */
+  int32_t quick_passes; /* 0..2; 0 = fpt_opts.quick_passes */
 } fpt_launch_cfg;
 
 /* Sets (cfg != NULL) or resets to defaults (cfg == NULL) the configuration

@@ -1,8 +1,8 @@
 """Autotuner of the per-order launch configuration of the FP32 solver.
 
 For each order present in a workload it times candidate configurations
-(resident workgroups per CU; the number of fixed BFGS iterations, or
-per-lane early exit in stages) on a sample of that order's paths and keeps
+(the number of fixed BFGS iterations, or per-lane early exit in stages;
+the quick FP64 refinement passes) on a sample of that order's paths and keeps
 the one with the most certified-converged paths per second of that order's
 kernels (BFGS + refinement, timed with the library's HIP-event timers). The
 iteration count trades FP32 BFGS time against FP64 refinement time: paths
@@ -18,10 +18,12 @@ import os
 import numpy as np
 
 DEFAULT_CANDIDATES = (
-    [{"wg_per_cu": 0, "early_exit": 0, "iters": k}
-     for k in (8, 10, 12, 14, 16, 20, 24, 32, 48, 64)]
-    + [{"wg_per_cu": 0, "early_exit": 1, "iters": 64, "stage_iters": s}
-       for s in ([16, 16, 32], [12, 12, 16, 24], [8, 8, 16, 32])]
+    [{"wg_per_cu": 0, "early_exit": 0, "iters": k, "quick_steps": qs, "quick_passes": qp}
+     for k in (8, 10, 12, 14, 16, 20, 24, 32, 48)
+     for (qs, qp) in ((2, 2), (3, 1))]
+    + [{"wg_per_cu": 0, "early_exit": 1, "iters": 64, "stage_iters": s,
+        "quick_steps": 2, "quick_passes": 2}
+       for s in ([16, 16, 32], [12, 12, 16, 24])]
 )
 
 
@@ -31,7 +33,7 @@ def default_cache_path() -> str:
 
 
 def _key(arch: str, order: int, n: int) -> str:
-    return f"v2/{arch}/order{order}/n2^{max(0, int(np.log2(max(n, 1))))}"
+    return f"v3/{arch}/order{order}/n2^{max(0, int(np.log2(max(n, 1))))}"
 
 
 def tune(solver, batch, opts, candidates=None, sample=1 << 18, repeats=3,

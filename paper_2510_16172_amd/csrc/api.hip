@@ -55,11 +55,20 @@ struct fpt_handle {
   unsigned long long* counts = nullptr;  // [8]
   unsigned long long* cursor = nullptr;  // [8]
   int64_t* bucket = nullptr;             // [8]
-  // early-exit stage lists (ping-pong): region counters, indices, states
-  unsigned long long* scount = nullptr;  // [2][kRegions * kCounterStride]
-  int32_t* slist[2] = {nullptr, nullptr};
+  // path lists between the stages of the solve (early-exit BFGS stages,
+  // refinement passes): per list set (one per order when the orders run on
+  // their own streams, else set 0) two ping-pong index lists and four
+  // counter blocks (kRegions counters kCounterStride apart, one block per
+  // stage, all cleared by one launch); the early-exit BFGS states (set 0)
+  unsigned long long* scount = nullptr;  // [FPT_NMAX + 1][4][kRegions * kCounterStride]
+  int32_t* slist[FPT_NMAX + 1][2] = {};
   float* sstate[2] = {nullptr, nullptr};
-  int64_t stage_rcap = 0, stage_state_cap = 0;
+  int64_t list_cap[FPT_NMAX + 1] = {};  // rcap the lists of a set were sized for
+  int64_t stage_state_cap = 0, state_rcap = 0;
+  // one stream per order (default priority) with fork / join events
+  hipStream_t ostream[FPT_NMAX + 1] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[FPT_NMAX + 1] = {};
   // per-order launch configuration (autotuner)
   fpt_launch_cfg cfg[FPT_NMAX + 1] = {};
   // learned-initialiser activations (grown on demand)
@@ -104,6 +113,7 @@ extern "C" void fpt_default_opts(fpt_opts* o) {
   o->stage_iters[3] = 0;
   o->quick_steps = 2;
   o->quick_passes = 2;
+  o->concurrent_orders = 0;
 }
 
 // Keeps the caller's current device and switches to the handle's for the
@@ -158,7 +168,8 @@ extern "C" fpt_status fpt_create(int device, fpt_handle** out) {
   h->counts = (unsigned long long*)p;
   h->cursor = h->counts + 8;
   h->bucket = (int64_t*)(h->counts + 16);
-  e = hipMalloc(&p, 2 * fpt::kRegions * fpt::kCounterStride * sizeof(unsigned long long));
+  e = hipMalloc(&p, (size_t)(FPT_NMAX + 1) * 4 * fpt::kRegions * fpt::kCounterStride *
+                       sizeof(unsigned long long));
   if (e != hipSuccess) {
     (void)hipFree(h->counts);
     delete h;
@@ -180,10 +191,16 @@ extern "C" fpt_status fpt_destroy(fpt_handle* h) {
   if (h->faces) (void)hipFree(h->faces);
   if (h->scount) (void)hipFree(h->scount);
   if (h->mlp_mem) (void)hipFree(h->mlp_mem);
-  for (int k = 0; k < 2; ++k) {
-    if (h->slist[k]) (void)hipFree(h->slist[k]);
+  for (int k = 0; k < 2; ++k)
     if (h->sstate[k]) (void)hipFree(h->sstate[k]);
+  for (int w = 0; w <= FPT_NMAX; ++w)
+    for (int k = 0; k < 2; ++k)
+      if (h->slist[w][k]) (void)hipFree(h->slist[w][k]);
+  for (int w = 0; w <= FPT_NMAX; ++w) {
+    if (h->ostream[w]) (void)hipStreamDestroy(h->ostream[w]);
+    if (h->ev_join[w]) (void)hipEventDestroy(h->ev_join[w]);
   }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   for (int i = 0; i < FPT_TIMERS; ++i)
     for (int r = 0; r < fpt_handle::kRing; ++r)
       for (int k = 0; k < 2; ++k)
@@ -276,31 +293,55 @@ static int64_t stage_rcap(int64_t N) {
   return 64 * ((N + 64 * fpt::kRegions - 1) / (64 * fpt::kRegions) + 1);
 }
 
-static fpt_status ensure_stage(fpt_handle* h, int64_t N, int n_max) {
+// Lists of set w for N paths; the early-exit states (set 0) for order
+// n_state (0: none).
+static fpt_status ensure_lists(fpt_handle* h, int64_t N, int w) {
   const int64_t rcap = stage_rcap(N);
-  const int64_t slots = rcap * fpt::kRegions;
-  const int64_t need = n_max > 0 ? (int64_t)fpt::stage_fields_for(n_max) * slots : 0;
-  if (h->stage_rcap >= rcap && h->stage_state_cap >= need) return FPT_OK;
+  if (h->list_cap[w] >= rcap) return FPT_OK;
   for (int k = 0; k < 2; ++k) {
-    if (h->slist[k]) (void)hipFree(h->slist[k]);
-    if (h->sstate[k]) (void)hipFree(h->sstate[k]);
-    h->slist[k] = nullptr;
-    h->sstate[k] = nullptr;
+    if (h->slist[w][k]) (void)hipFree(h->slist[w][k]);
+    h->slist[w][k] = nullptr;
   }
-  h->stage_rcap = h->stage_state_cap = 0;
+  h->list_cap[w] = 0;
   for (int k = 0; k < 2; ++k) {
     void* p = nullptr;
-    if (hipMalloc(&p, (size_t)slots * sizeof(int32_t)) != hipSuccess)
-      return fail(FPT_ENOMEM, "early-exit workspace allocation failed");
-    h->slist[k] = (int32_t*)p;
-    if (need > 0) {
-      if (hipMalloc(&p, (size_t)need * sizeof(float)) != hipSuccess)
-        return fail(FPT_ENOMEM, "early-exit workspace allocation failed");
-      h->sstate[k] = (float*)p;
-    }
+    if (hipMalloc(&p, (size_t)rcap * fpt::kRegions * sizeof(int32_t)) != hipSuccess)
+      return fail(FPT_ENOMEM, "path-list workspace allocation failed");
+    h->slist[w][k] = (int32_t*)p;
   }
-  h->stage_rcap = rcap;
+  h->list_cap[w] = rcap;
+  return FPT_OK;
+}
+
+static fpt_status ensure_states(fpt_handle* h, int64_t N, int n_state) {
+  const int64_t rcap = stage_rcap(N);
+  const int64_t need = n_state > 0 ? (int64_t)fpt::stage_fields_for(n_state) * rcap * fpt::kRegions : 0;
+  if (h->stage_state_cap >= need && h->state_rcap >= rcap) return FPT_OK;
+  for (int k = 0; k < 2; ++k) {
+    if (h->sstate[k]) (void)hipFree(h->sstate[k]);
+    h->sstate[k] = nullptr;
+  }
+  h->stage_state_cap = h->state_rcap = 0;
+  for (int k = 0; k < 2; ++k) {
+    void* p = nullptr;
+    if (hipMalloc(&p, (size_t)need * sizeof(float)) != hipSuccess)
+      return fail(FPT_ENOMEM, "early-exit workspace allocation failed");
+    h->sstate[k] = (float*)p;
+  }
   h->stage_state_cap = need;
+  h->state_rcap = rcap;
+  return FPT_OK;
+}
+
+static fpt_status ensure_streams(fpt_handle* h) {
+  if (h->ev_fork) return FPT_OK;
+  for (int w = 1; w <= FPT_NMAX; ++w) {
+    if (hipStreamCreateWithFlags(&h->ostream[w], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_join[w], hipEventDisableTiming) != hipSuccess)
+      return fail(FPT_EHIP, "fpt_solve: stream creation failed");
+  }
+  if (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess)
+    return fail(FPT_EHIP, "fpt_solve: event creation failed");
   return FPT_OK;
 }
 
@@ -400,6 +441,32 @@ extern "C" fpt_status fpt_kernel_times(fpt_handle* h, float* ms) {
   return FPT_OK;
 }
 
+// Workspace of one fpt_solve, allocated before any launch (also before a
+// graph capture): order buckets, path lists per list set, early-exit
+// states, and the per-order streams.
+static fpt_status prepare_solve(fpt_handle* h, const fpt_paths* pa, const fpt_opts* o,
+                                bool any_ee, bool concurrent) {
+  fpt_status s;
+  if (pa->order) {
+    s = ensure_perm(h, pa->N);
+    if (s != FPT_OK) return s;
+  }
+  const bool lists = any_ee || (o->n_levels > 0 && o->quick_steps > 0);
+  if (!lists) return FPT_OK;
+  if (concurrent) {
+    s = ensure_streams(h);
+    if (s != FPT_OK) return s;
+    for (int n = 1; n <= pa->n_max; ++n) {
+      s = ensure_lists(h, pa->N, n);
+      if (s != FPT_OK) return s;
+    }
+  } else {
+    s = ensure_lists(h, pa->N, 0);
+    if (s != FPT_OK) return s;
+  }
+  return ensure_states(h, pa->N, any_ee ? pa->n_max : 0);
+}
+
 extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
                                 const fpt_paths* pa, const fpt_opts* o,
                                 const fpt_out* out, void* stream) {
@@ -458,15 +525,17 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     return (int)(g < cap ? g : cap);
   };
   const bool any_ee = uses_early_exit(h, o, pa->n_max);
-  if (any_ee || A.quick_steps > 0) {
-    s = ensure_stage(h, pa->N, any_ee ? pa->n_max : 0);
-    if (s != FPT_OK) return s;
-  }
+  const int n_lo = pa->order ? 1 : pa->n_max;  // all buckets, or only n_max
+  // The orders are independent: with several orders (and no early-exit
+  // states, which are shared) each runs on its own stream with its own path
+  // lists, so that the small orders and the latency-bound tails of each
+  // order's passes overlap.
+  const bool concurrent = o->concurrent_orders && n_lo < pa->n_max && !any_ee;
+  s = prepare_solve(h, pa, o, any_ee, concurrent);
+  if (s != FPT_OK) return s;
   const int32_t* perm = nullptr;
   const int64_t* bucket = nullptr;
   if (pa->order) {
-    s = ensure_perm(h, pa->N);
-    if (s != FPT_OK) return s;
     SlotTimer tm(h, FPT_T_BUCKET, st);
     e = fpt::launch_bucketing(pa->order, pa->N, pa->n_max, h->ccount,
                               h->bucket, h->perm, st);
@@ -474,85 +543,94 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     perm = h->perm;
     bucket = h->bucket;
   }
-  // orders to run: all buckets, or only n_max when every path has it
-  const int n_lo = pa->order ? 1 : pa->n_max;
+  if (concurrent) {
+    e = hipEventRecord(h->ev_fork, st);
+    if (e != hipSuccess) return hip_fail(e, "fpt_solve: event record");
+  }
+  const int nc = fpt::kRegions * fpt::kCounterStride;
+  const int64_t rcap = stage_rcap(pa->N);
   for (int n = n_lo; n <= pa->n_max; ++n) {
+    const int w = concurrent ? n : 0;               // list set
+    hipStream_t sn = concurrent ? h->ostream[n] : st;
+    if (concurrent) {
+      e = hipStreamWaitEvent(sn, h->ev_fork, 0);
+      if (e != hipSuccess) return hip_fail(e, "fpt_solve: stream wait");
+    }
+    unsigned long long* cnt = h->scount + (size_t)w * 4 * nc;  // 4 stage blocks
     const fpt_launch_cfg& c = h->cfg[n];
     const bool ee = c.use_override ? c.early_exit != 0 : A.early_exit != 0;
     const int32_t* stages = (c.use_override && ee) ? c.stage_iters : o->stage_iters;
     fpt::SolveArgs An = A;
     if (c.use_override && c.iters > 0) An.n_iter = c.iters;
+    if (c.use_override && c.quick_steps > 0 && A.quick_steps > 0) An.quick_steps = c.quick_steps;
+    const int qpasses = (c.use_override && c.quick_passes > 0) ? c.quick_passes : o->quick_passes;
     An.work = (h->timing && h->work) ? h->work + 4 * fpt::kWorkSlots * (n - 1) : nullptr;
     {
-      SlotTimer tm(h, FPT_T_BFGS + n - 1, st);
+      SlotTimer tm(h, FPT_T_BFGS + n - 1, sn);
       if (!ee) {
         // one path per thread over the whole input, or persistent over the
         // bucket (its size is only known on the device)
         int grid = perm ? persistent(0, n, c.wg_per_cu) : (int)cap;
-        e = fpt::launch_solve(0, n, An, perm, bucket, nullptr, grid, st);
+        e = fpt::launch_solve(0, n, An, perm, bucket, nullptr, grid, sn);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
       } else {
         int ns = 0;
         while (ns < FPT_MAX_STAGES && stages[ns] > 0) ++ns;
-        const int nc = fpt::kRegions * fpt::kCounterStride;
         for (int k = 0; k < ns; ++k) {
           fpt::StageArgs S;
           memset(&S, 0, sizeof(S));
-          S.rcap = h->stage_rcap;
-          S.cap = h->stage_rcap * fpt::kRegions;
+          S.rcap = rcap;
+          S.cap = rcap * fpt::kRegions;
           S.iters = stages[k];
           if (k > 0) {
-            S.in_list = h->slist[(k - 1) & 1];
-            S.in_count = h->scount + ((k - 1) & 1) * nc;
+            S.in_list = h->slist[w][(k - 1) & 1];
+            S.in_count = cnt + ((k - 1) & 1) * nc;
             S.state_in = h->sstate[(k - 1) & 1];
           }
           if (k + 1 < ns) {
-            S.out_list = h->slist[k & 1];
-            S.out_count = h->scount + (k & 1) * nc;
+            S.out_list = h->slist[w][k & 1];
+            S.out_count = cnt + (k & 1) * nc;
             S.state_out = h->sstate[k & 1];
-            e = fpt::launch_zero_u64(S.out_count, nc, st);
+            e = fpt::launch_zero_u64(S.out_count, nc, sn);
             if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
           }
           int grid = (k == 0 && !perm) ? (int)cap : persistent(2, n, c.wg_per_cu);
-          e = fpt::launch_solve(2, n, An, perm, bucket, &S, grid, st);
+          e = fpt::launch_solve(2, n, An, perm, bucket, &S, grid, sn);
           if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         }
       }
     }
     {
-      SlotTimer tm(h, FPT_T_REFINE + n - 1, st);
+      SlotTimer tm(h, FPT_T_REFINE + n - 1, sn);
       fpt::StageArgs R;
       memset(&R, 0, sizeof(R));
       int grid = perm ? persistent(1, n, 0) : (int)cap;
-      if (A.quick_steps > 0) {
+      if (An.quick_steps > 0) {
+        // stage k lists its uncertified paths in list k & 1 with counter
+        // block k; the blocks are cleared together first
+        e = fpt::launch_zero_u64(cnt, 4 * nc, sn);
+        if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+        R.rcap = rcap;
+        R.cap = rcap * fpt::kRegions;
         // pass 1: quick steps for all, list the uncertified paths
-        const int nc = fpt::kRegions * fpt::kCounterStride;
-        R.rcap = h->stage_rcap;
-        R.cap = h->stage_rcap * fpt::kRegions;
-        R.out_list = h->slist[0];
-        R.out_count = h->scount;
-        e = fpt::launch_zero_u64(R.out_count, nc, st);
+        R.out_list = h->slist[w][0];
+        R.out_count = cnt;
+        e = fpt::launch_solve(1, n, An, perm, bucket, &R, grid, sn);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
-        e = fpt::launch_solve(1, n, An, perm, bucket, &R, grid, st);
-        if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
-        // the current list (ping-pong between the two list buffers)
-        int cur = 0;
+        int k = 0;  // the stage whose list is current
         auto next_stage = [&](int phase, int grid_x) -> hipError_t {
           fpt::StageArgs Q;
           memset(&Q, 0, sizeof(Q));
           Q.rcap = R.rcap;
           Q.cap = R.cap;
-          Q.in_list = h->slist[cur];
-          Q.in_count = h->scount + cur * nc;
-          Q.out_list = h->slist[cur ^ 1];
-          Q.out_count = h->scount + (cur ^ 1) * nc;
-          hipError_t ez = fpt::launch_zero_u64(Q.out_count, nc, st);
-          if (ez != hipSuccess) return ez;
-          ez = fpt::launch_solve(phase, n, An, nullptr, nullptr, &Q, grid_x, st);
-          cur ^= 1;
-          return ez;
+          Q.in_list = h->slist[w][k & 1];
+          Q.in_count = cnt + k * nc;
+          Q.out_list = h->slist[w][(k + 1) & 1];
+          Q.out_count = cnt + (k + 1) * nc;
+          ++k;
+          return fpt::launch_solve(phase, n, An, nullptr, nullptr, &Q, grid_x, sn);
         };
-        if (o->quick_passes > 1) {
+        if (qpasses > 1) {
           // second quick pass on the paths the first did not certify
           e = next_stage(1, persistent(1, n, 0));
           if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
@@ -567,14 +645,20 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
         memset(&R2, 0, sizeof(R2));
         R2.rcap = R.rcap;
         R2.cap = R.cap;
-        R2.in_list = h->slist[cur];
-        R2.in_count = h->scount + cur * nc;
+        R2.in_list = h->slist[w][k & 1];
+        R2.in_count = cnt + k * nc;
         // pass 2: the full schedule on the list
-        e = fpt::launch_solve(1, n, An, perm, bucket, &R2, persistent(1, n, 0), st);
+        e = fpt::launch_solve(1, n, An, perm, bucket, &R2, persistent(1, n, 0), sn);
       } else {
-        e = fpt::launch_solve(1, n, An, perm, bucket, &R, grid, st);
+        e = fpt::launch_solve(1, n, An, perm, bucket, &R, grid, sn);
       }
       if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+    }
+    if (concurrent) {
+      e = hipEventRecord(h->ev_join[n], sn);
+      if (e != hipSuccess) return hip_fail(e, "fpt_solve: event record");
+      e = hipStreamWaitEvent(st, h->ev_join[n], 0);
+      if (e != hipSuccess) return hip_fail(e, "fpt_solve: stream wait");
     }
   }
   if (pa->order) {
@@ -882,6 +966,9 @@ extern "C" fpt_status fpt_set_launch(fpt_handle* h, int order,
     return fail(FPT_EINVAL, "fpt_set_launch: wg_per_cu outside 0..32");
   if (cfg->use_override && (cfg->iters < 0 || cfg->iters > 65535))
     return fail(FPT_EINVAL, "fpt_set_launch: iters outside 0..65535");
+  if (cfg->use_override && (cfg->quick_steps < 0 || cfg->quick_steps > 64 ||
+                            cfg->quick_passes < 0 || cfg->quick_passes > 2))
+    return fail(FPT_EINVAL, "fpt_set_launch: quick_steps / quick_passes out of range");
   if (cfg->use_override && cfg->early_exit) {
     if (cfg->stage_iters[0] < 1)
       return fail(FPT_EINVAL, "fpt_set_launch: early exit needs stage_iters[0] >= 1");
@@ -916,12 +1003,12 @@ extern "C" fpt_status fpt_graph_capture(fpt_handle* h, const fpt_scene* sc,
   DeviceGuard dg(h->device);
   hipStream_t st = (hipStream_t)stream;
   // no allocation inside the capture
-  if (pa->order) {
-    s = ensure_perm(h, pa->N);
+  {
+    const bool any_ee = uses_early_exit(h, o, pa->n_max);
+    const bool concurrent = o->concurrent_orders && pa->order && pa->n_max > 1 && !any_ee;
+    s = prepare_solve(h, pa, o, any_ee, concurrent);
     if (s != FPT_OK) return s;
   }
-  s = ensure_stage(h, pa->N, uses_early_exit(h, o, pa->n_max) ? pa->n_max : 0);
-  if (s != FPT_OK) return s;
   hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return hip_fail(e, "fpt_graph_capture: begin");
   fpt_status rs = fpt_solve(h, sc, pa, o, out, stream);

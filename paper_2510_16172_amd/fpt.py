@@ -43,13 +43,15 @@ class _Opts(ctypes.Structure):
                 ("level_steps", ctypes.c_int32 * FPT_MAX_LEVELS),
                 ("cert_rtol", ctypes.c_float),
                 ("stage_iters", ctypes.c_int32 * 4),
-                ("quick_steps", ctypes.c_int32), ("quick_passes", ctypes.c_int32)]
+                ("quick_steps", ctypes.c_int32), ("quick_passes", ctypes.c_int32),
+                ("concurrent_orders", ctypes.c_int32)]
 
 
 class _LaunchCfg(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("use_override", ctypes.c_int32),
                 ("early_exit", ctypes.c_int32), ("stage_iters", ctypes.c_int32 * 4),
-                ("iters", ctypes.c_int32)]
+                ("iters", ctypes.c_int32), ("quick_steps", ctypes.c_int32),
+                ("quick_passes", ctypes.c_int32)]
 
 
 class _Out(ctypes.Structure):
@@ -157,6 +159,7 @@ class Opts:
     stage_iters: list = field(default_factory=lambda: [16, 16, 32])
     quick_steps: int = 2
     quick_passes: int = 2
+    concurrent_orders: bool = False
 
     def to_c(self) -> _Opts:
         o = _Opts()
@@ -181,6 +184,7 @@ class Opts:
             o.stage_iters[i] = int(self.stage_iters[i]) if i < len(self.stage_iters) else 0
         o.quick_steps = int(self.quick_steps)
         o.quick_passes = int(self.quick_passes)
+        o.concurrent_orders = 1 if self.concurrent_orders else 0
         return o
 
 
@@ -303,9 +307,12 @@ class Solver:
             return
         c = _LaunchCfg()
         c.wg_per_cu = int(cfg.get("wg_per_cu", 0))
-        c.use_override = 1 if ("early_exit" in cfg or "iters" in cfg) else 0
+        c.use_override = 1 if any(k in cfg for k in (
+            "early_exit", "iters", "quick_steps", "quick_passes")) else 0
         c.early_exit = int(cfg.get("early_exit", 0))
         c.iters = int(cfg.get("iters", 0))
+        c.quick_steps = int(cfg.get("quick_steps", 0))
+        c.quick_passes = int(cfg.get("quick_passes", 0))
         st = list(cfg.get("stage_iters", [16, 16, 32]))
         for i in range(4):
             c.stage_iters[i] = int(st[i]) if i < len(st) else 0

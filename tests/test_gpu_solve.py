@@ -350,3 +350,29 @@ def test_collapsed_minimisers_certified(solver, oracle_mod, n):
     assert col.sum() > 300
     assert cc.sum() >= {2: 0.9, 3: 0.75}[n] * col.sum()
     assert np.all((g["status"][cc] & fpt.ST_COLLAPSED) != 0)
+
+
+def test_concurrent_orders_equal_sequential(solver):
+    """Each order on its own stream gives the same result as the orders one
+    after the other (eager and through a captured graph)."""
+    import torch
+    from paper_2510_16172_amd import fpt
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 30000, seed=4800, n=None, n_max=6)
+    want = gpu_util.run_gpu(solver, b, _opts(b.S, iters=16))
+    got = gpu_util.run_gpu(solver, b, _opts(b.S, iters=16, concurrent_orders=True))
+    for k in want:
+        np.testing.assert_array_equal(got[k], want[k], err_msg=k)
+    db = fpt.DeviceBatch(b)
+    opts = _opts(b.S, iters=16, concurrent_orders=True)
+    out = solver.alloc_out(db)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        g = solver.capture(db, opts, out, st)
+        for _ in range(2):
+            g.launch(st)
+            st.synchronize()
+            rep = {k: v.cpu().numpy() for k, v in out.items()}
+            for k in want:
+                np.testing.assert_array_equal(rep[k], want[k], err_msg=k)
+    g.close()
