@@ -834,7 +834,6 @@ extern "C" fpt_status fpt_validate(fpt_handle* h, const fpt_scene* sc,
 // ------------------------------------------------- learned initialiser ----
 
 static const int64_t kMlpTrainMax = 65536;   // rows per training step
-static const int64_t kMlpInferChunk = 262144;
 
 static fpt_status ensure_mlp(fpt_handle* h, int64_t rows) {
   if (h->mlp.cap >= rows) return FPT_OK;
@@ -928,26 +927,11 @@ extern "C" fpt_status fpt_mlp_infer(fpt_handle* h, const float* state,
   if (pa->N == 0) return FPT_OK;
   DeviceGuard g(h->device);
   hipStream_t st = (hipStream_t)stream;
-  int64_t chunk = pa->N < kMlpInferChunk ? pa->N : kMlpInferChunk;
-  chunk = (chunk + 63) / 64 * 64;
-  s = ensure_mlp(h, chunk);
-  if (s != FPT_OK) return s;
   fpt::MlpState S = fpt::mlp_state(const_cast<float*>(state));
   SlotTimer tm(h, FPT_T_MLP, st);
-  for (int64_t base = 0; base < pa->N; base += chunk) {
-    int64_t cnt = pa->N - base < chunk ? pa->N - base : chunk;
-    int64_t rows = (cnt + 63) / 64 * 64;  // GEMM rows (tail rows are zero)
-    fpt::MlpPrepArgs P = fpt::prep_args(sc, pa, base, cnt, scale, h->mlp, false);
-    hipError_t e = hipSuccess;
-    if (rows != cnt)
-      e = fpt::launch_zero_rows(h->mlp, cnt, rows, st);
-    if (e == hipSuccess) e = fpt::launch_mlp_prep(P, st);
-    if (e == hipSuccess) e = fpt::mlp_forward(S.w, S.wb, h->mlp, rows, false, st);
-    if (e == hipSuccess)
-      e = fpt::launch_mlp_to_tinit(h->mlp.Yp, sc->obj, pa->ids, pa->N, base, cnt,
-                                   sc->K, scale, t_init, st);
-    if (e != hipSuccess) return hip_fail(e, "fpt_mlp_infer: launch");
-  }
+  // one fused kernel (features, layers, output): no workspace
+  hipError_t e = fpt::launch_mlp_infer(sc, pa, S.w, S.wb, scale, t_init, st);
+  if (e != hipSuccess) return hip_fail(e, "fpt_mlp_infer: launch");
   return FPT_OK;
 }
 

@@ -141,56 +141,73 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
 // edge), b - TX and b - RX: 6 + 4 * 15 = 66 values, zero-padded to 96.
 // Target: the solver's parameters in unit-vector coordinates, / S, masked
 // where the path is not certified or the parameter is an edge's padding.
+// The 96 (padded) features of path i, and its unit-basis norms |a| of each
+// slot (for the target and for mapping the output back).
+__device__ __forceinline__ void mlp_features(
+    const float* __restrict__ obj, const float* __restrict__ pts,
+    const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+    const int32_t* __restrict__ ids, int64_t N, int32_t K, int32_t Q,
+    float inv_scale, int64_t i, float* f, float (*nrm)[2], bool* edge) {
+#pragma unroll
+  for (int k = 0; k < kInP; ++k) f[k] = 0.f;
+  int32_t s = src[i], e = dst[i];
+  s = (s >= 0 && s < Q) ? s : 0;
+  e = (e >= 0 && e < Q) ? e : 0;
+  float tx[3], rx[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    tx[c] = pts[(int64_t)c * Q + s];
+    rx[c] = pts[(int64_t)c * Q + e];
+    f[c] = tx[c] * inv_scale;
+    f[3 + c] = rx[c] * inv_scale;
+  }
+#pragma unroll
+  for (int j = 0; j < kMlpOrder; ++j) {
+    int32_t k = ids[(int64_t)j * N + i];
+    k = (k >= 0 && k < K) ? k : 0;
+    float bb[3], a1[3], a2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bb[c] = obj[(int64_t)c * K + k];
+      a1[c] = obj[(int64_t)(3 + c) * K + k];
+      a2[c] = obj[(int64_t)(6 + c) * K + k];
+    }
+    edge[j] = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
+    float n1 = dot3(a1, a1), n2 = dot3(a2, a2);
+    float i1 = rsq32(n1 > 0.f ? n1 : 1.f);
+    float i2 = edge[j] ? 0.f : rsq32(n2 > 0.f ? n2 : 1.f);
+    nrm[j][0] = n1 * i1;
+    nrm[j][1] = n2 * i2;
+    const int o = 6 + 15 * j;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      f[o + c] = bb[c] * inv_scale;
+      f[o + 3 + c] = a1[c] * i1;
+      f[o + 6 + c] = a2[c] * i2;
+      f[o + 9 + c] = (bb[c] - tx[c]) * inv_scale;
+      f[o + 12 + c] = (bb[c] - rx[c]) * inv_scale;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void mlp_prep_kernel(MlpPrepArgs A) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;  // batch row
   if (r >= A.count) return;
   const int64_t i = A.base + r;  // path
-  float f[kInP];
-#pragma unroll
-  for (int k = 0; k < kInP; ++k) f[k] = 0.f;
-  int32_t s = A.src[i], e = A.dst[i];
-  s = (s >= 0 && s < A.Q) ? s : 0;
-  e = (e >= 0 && e < A.Q) ? e : 0;
-  float tx[3], rx[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    tx[c] = A.pts[(int64_t)c * A.Q + s];
-    rx[c] = A.pts[(int64_t)c * A.Q + e];
-    f[c] = tx[c] * A.inv_scale;
-    f[3 + c] = rx[c] * A.inv_scale;
-  }
+  float f[kInP], nrm[kMlpOrder][2];
+  bool edge[kMlpOrder];
+  mlp_features(A.obj, A.pts, A.src, A.dst, A.ids, A.N, A.K, A.Q, A.inv_scale, i, f,
+               nrm, edge);
   bool cert = A.status ? (A.status[i] & FPT_ST_CONVERGED) != 0 : false;
+  if (A.Y) {
 #pragma unroll
-  for (int j = 0; j < kMlpOrder; ++j) {
-    int32_t k = A.ids[(int64_t)j * A.N + i];
-    k = (k >= 0 && k < A.K) ? k : 0;
-    float bb[3], a1[3], a2[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      bb[c] = A.obj[(int64_t)c * A.K + k];
-      a1[c] = A.obj[(int64_t)(3 + c) * A.K + k];
-      a2[c] = A.obj[(int64_t)(6 + c) * A.K + k];
-    }
-    bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
-    float n1 = dot3(a1, a1), n2 = dot3(a2, a2);
-    float i1 = rsq32(n1 > 0.f ? n1 : 1.f);
-    float i2 = edge ? 0.f : rsq32(n2 > 0.f ? n2 : 1.f);
-    const int o = 6 + 15 * j;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      f[o + c] = bb[c] * A.inv_scale;
-      f[o + 3 + c] = a1[c] * i1;
-      f[o + 6 + c] = a2[c] * i2;
-      f[o + 9 + c] = (bb[c] - tx[c]) * A.inv_scale;
-      f[o + 12 + c] = (bb[c] - rx[c]) * A.inv_scale;
-    }
-    if (A.Y) {
+    for (int j = 0; j < kMlpOrder; ++j) {
       float t0 = A.t[(int64_t)(2 * j) * A.N + i];
       float t1 = A.t[(int64_t)(2 * j + 1) * A.N + i];
       // unit-vector coordinates: that = t * |a|
-      float y0 = t0 * (n1 * i1) * A.inv_scale;
-      float y1 = edge ? 0.f : t1 * (n2 * i2) * A.inv_scale;
-      bool ok0 = cert && isfinite(y0), ok1 = cert && !edge && isfinite(y1);
+      float y0 = t0 * nrm[j][0] * A.inv_scale;
+      float y1 = edge[j] ? 0.f : t1 * nrm[j][1] * A.inv_scale;
+      bool ok0 = cert && isfinite(y0), ok1 = cert && !edge[j] && isfinite(y1);
       A.Y[r * kOut + 2 * j] = ok0 ? y0 : 0.f;
       A.Y[r * kOut + 2 * j + 1] = ok1 ? y1 : 0.f;
       A.Ym[r * kOut + 2 * j] = ok0 ? 1.f : 0.f;
@@ -205,31 +222,158 @@ __global__ __launch_bounds__(kBlock) void mlp_prep_kernel(MlpPrepArgs A) {
   }
 }
 
-// Network output (unit-vector coordinates / S) -> t_init in the caller's
-// parametrisation, [4][2][N].
-__global__ __launch_bounds__(kBlock) void mlp_to_tinit_kernel(
-    const float* __restrict__ Yp, const float* __restrict__ obj,
-    const int32_t* __restrict__ ids, int64_t N, int64_t base, int64_t count,
-    int32_t K, float scale, float* __restrict__ t_init) {
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (r >= count) return;
-  const int64_t i = base + r;
+// ------------------------------------------------------ fused inference ----
+// One workgroup of 8 wavefronts per tile of kTM = 128 paths computes the
+// features, the three hidden layers and the output layer, with the
+// activations in LDS, and writes t_init: no activation goes through HBM. A
+// layer's products stay in the accumulators until every wave has read the
+// layer's input, so one LDS buffer holds the input features and then each
+// hidden activation in turn. Weights are read as MFMA fragments from global
+// memory (344 KB of bf16, L2-resident; the tile size sets how often they are
+// re-read). Wave w computes rows 64 (w / 4) .. + 63 and output columns
+// 64 (w % 4) .. + 63 of each hidden layer (4 x 4 tiles of 16 x 16).
+constexpr int kTM = 128, kLdH = kHid + 8;  // +8: fewer LDS bank conflicts
+constexpr int kInferThreads = 512;
+
+struct MlpInferArgs {
+  const float* obj;
+  const float* pts;
+  const int32_t* src;
+  const int32_t* dst;
+  const int32_t* ids;
+  const float* w32;  // biases (fp32 master copy)
+  const bf16* wb;    // bf16 weights [out][in]
+  int64_t N;
+  int32_t K, Q;
+  float scale, inv_scale;
+  float* t_init;     // [4][2][N]
+};
+
+__device__ __forceinline__ bf16x8 load8s(const bf16* p) {
+  return *reinterpret_cast<const bf16x8*>(p);
+}
+
+__global__ __launch_bounds__(kInferThreads) void mlp_infer_kernel(MlpInferArgs A) {
+  __shared__ __align__(16) bf16 sH[kTM * kLdH];  // features, then H1, H2, H3
+  __shared__ float sY[kTM * kOut];
+  __shared__ float sN[kTM * kOut];  // |a| per output, 0 for an edge's padding
+  const int64_t row0 = (int64_t)blockIdx.x * kTM;
+  if (threadIdx.x < kTM) {
+    const int64_t i = row0 + threadIdx.x;
+    float f[kInP], nrm[kMlpOrder][2];
+    bool edge[kMlpOrder];
+    if (i < A.N) {
+      mlp_features(A.obj, A.pts, A.src, A.dst, A.ids, A.N, A.K, A.Q, A.inv_scale, i,
+                   f, nrm, edge);
+    } else {
 #pragma unroll
-  for (int j = 0; j < kMlpOrder; ++j) {
-    int32_t k = ids[(int64_t)j * N + i];
-    k = (k >= 0 && k < K) ? k : 0;
-    float a1[3], a2[3];
+      for (int k = 0; k < kInP; ++k) f[k] = 0.f;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      a1[c] = obj[(int64_t)(3 + c) * K + k];
-      a2[c] = obj[(int64_t)(6 + c) * K + k];
+      for (int j = 0; j < kMlpOrder; ++j) {
+        nrm[j][0] = nrm[j][1] = 1.f;
+        edge[j] = false;
+      }
     }
-    bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
-    float i1 = rsq32(fmaxf(dot3(a1, a1), 1e-30f));
-    float i2 = edge ? 0.f : rsq32(fmaxf(dot3(a2, a2), 1e-30f));
-    t_init[(int64_t)(2 * j) * N + i] = Yp[r * kOutP + 2 * j] * scale * i1;
-    t_init[(int64_t)(2 * j + 1) * N + i] = Yp[r * kOutP + 2 * j + 1] * scale * i2;
+#pragma unroll
+    for (int k = 0; k < kInP; ++k) sH[threadIdx.x * kLdH + k] = (bf16)f[k];
+#pragma unroll
+    for (int j = 0; j < kMlpOrder; ++j) {
+      sN[threadIdx.x * kOut + 2 * j] = nrm[j][0];
+      sN[threadIdx.x * kOut + 2 * j + 1] = edge[j] ? 0.f : nrm[j][1];
+    }
   }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = (lane >> 4) * 8;
+  const int mr = 64 * (w >> 2), nc = 64 * (w & 3);
+#pragma unroll 1
+  for (int layer = 0; layer < 3; ++layer) {
+    const int K = layer == 0 ? kInP : kHid;
+    const bf16* W = A.wb + (layer == 0 ? oW1 : layer == 1 ? oW2 : oW3);
+    const float* bias = A.w32 + (layer == 0 ? oB1 : layer == 1 ? oB2 : oB3);
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < K; k += 32) {
+      bf16x8 fa[4], fb[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        fb[b] = load8(W + (int64_t)(nc + 16 * b + li) * K + k + lk);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) fa[a] = load8s(sH + (mr + 16 * a + li) * kLdH + k + lk);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();  // every wave has read this layer's input
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int n = nc + 16 * b + li;
+      const float bn = bias[n];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = mr + 16 * a + (lane >> 4) * 4 + r;
+          sH[m * kLdH + n] = (bf16)fmaxf(acc[a][b][r] + bn, 0.f);
+        }
+    }
+    __syncthreads();
+  }
+  // output layer: wave w takes rows 16 w .. 16 w + 15, the first 16 outputs
+  {
+    const bf16* W4 = A.wb + oW4;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < kHid; k += 32) {
+      bf16x8 fa = load8s(sH + (16 * w + li) * kLdH + k + lk);
+      bf16x8 fb = load8(W4 + (int64_t)li * kHid + k + lk);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc, 0, 0, 0);
+    }
+    if (li < kOut) {
+      const float b4 = A.w32[oB4 + li];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        sY[(16 * w + (lane >> 4) * 4 + r) * kOut + li] = acc[r] + b4;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kTM) {
+    const int64_t i = row0 + threadIdx.x;
+    if (i < A.N) {
+#pragma unroll
+      for (int q = 0; q < kOut; ++q) {
+        const float nq = sN[threadIdx.x * kOut + q];
+        // unit-vector coordinates / S -> the caller's parametrisation
+        A.t_init[(int64_t)q * A.N + i] =
+            nq > 0.f ? sY[threadIdx.x * kOut + q] * A.scale / nq : 0.f;
+      }
+    }
+  }
+}
+
+hipError_t launch_mlp_infer(const fpt_scene* sc, const fpt_paths* pa, const float* w32,
+                            const bf16* wb, float scale, float* t_init, hipStream_t st) {
+  MlpInferArgs A;
+  A.obj = sc->obj;
+  A.pts = sc->pts;
+  A.src = pa->src;
+  A.dst = pa->dst;
+  A.ids = pa->ids;
+  A.w32 = w32;
+  A.wb = wb;
+  A.N = pa->N;
+  A.K = sc->K;
+  A.Q = sc->Q;
+  A.scale = scale;
+  A.inv_scale = 1.f / scale;
+  A.t_init = t_init;
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)((pa->N + kTM - 1) / kTM)),
+                     dim3(kInferThreads), 0, st, A);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------- loss, Adam ------
@@ -474,28 +618,8 @@ hipError_t launch_mlp_init(float* w, float* m, float* v, uint64_t seed, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_to_tinit(const float* Yp, const float* obj, const int32_t* ids,
-                               int64_t N, int64_t base, int64_t count, int32_t K,
-                               float scale, float* t_init, hipStream_t st) {
-  hipLaunchKernelGGL(mlp_to_tinit_kernel, dim3(cdiv(count, kBlock)), dim3(kBlock), 0, st,
-                     Yp, obj, ids, N, base, count, K, scale, t_init);
-  return hipGetLastError();
-}
-
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
   hipLaunchKernelGGL(fill_f32_kernel, dim3(256), dim3(kBlock), 0, st, p, n, v);
-  return hipGetLastError();
-}
-
-// zero the input rows from..to-1 of a forward batch (GEMM tail rows)
-__global__ __launch_bounds__(kBlock) void zero_rows_kernel(bf16* X, int64_t from, int64_t to) {
-  const int64_t i = from * kInP + (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < to * kInP) X[i] = (bf16)0.f;
-}
-
-hipError_t launch_zero_rows(const MlpWork& W, int64_t from, int64_t to, hipStream_t st) {
-  int64_t n = (to - from) * kInP;
-  hipLaunchKernelGGL(zero_rows_kernel, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, W.X, from, to);
   return hipGetLastError();
 }
 

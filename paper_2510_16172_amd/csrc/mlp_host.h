@@ -127,12 +127,9 @@ hipError_t mlp_forward(const float* w32, const bf16* wb, const MlpWork& W,
 hipError_t mlp_backward(const bf16* wbT, const MlpWork& W, int64_t Bn,
                         float* grad, hipStream_t st);
 hipError_t launch_mlp_prep(const MlpPrepArgs& A, hipStream_t st);
+hipError_t launch_mlp_infer(const fpt_scene* sc, const fpt_paths* pa, const float* w32,
+                            const bf16* wb, float scale, float* t_init, hipStream_t st);
 hipError_t launch_mlp_loss(const MlpWork& W, int64_t Bn, float* loss, hipStream_t st);
 hipError_t launch_mlp_adam(const AdamArgs& A, hipStream_t st);
 hipError_t launch_mlp_init(float* w, float* m, float* v, uint64_t seed, hipStream_t st);
-hipError_t launch_mlp_to_tinit(const float* Yp, const float* obj, const int32_t* ids,
-                               int64_t N, int64_t base, int64_t count, int32_t K,
-                               float scale, float* t_init, hipStream_t st);
-hipError_t launch_zero_rows(const MlpWork& W, int64_t from, int64_t to, hipStream_t st);
-
 }  // namespace fpt
