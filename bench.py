@@ -430,6 +430,16 @@ def main():
     torch.cuda.synchronize()
     ms_val = v0.elapsed_time(v1) / 3
     vf = vflags.cpu().numpy()
+    # lazy mode: occlusion only for paths that pass the extent and side tests
+    lflags = solver.validate(db, out, lazy=True, stream=stream)
+    torch.cuda.synchronize()
+    v0.record(stream)
+    for _ in range(3):
+        solver.validate(db, out, flags=lflags, lazy=True, stream=stream)
+    v1.record(stream)
+    torch.cuda.synchronize()
+    ms_val_lazy = v0.elapsed_time(v1) / 3
+    lazy_same_valid = bool(np.array_equal(lflags.cpu().numpy() == 7, vf == 7))
 
     out_np = {k: v.cpu().numpy() for k, v in out.items()}
     st = out_np["status"]
@@ -511,6 +521,7 @@ def main():
         "roofline_other": other,
         "validate": {
             "ms": ms_val, "paths_per_s": N / (ms_val * 1e-3),
+            "ms_lazy": ms_val_lazy, "lazy_same_valid_set": lazy_same_valid,
             "extent": float(((vf & fpt.VALID_EXTENT) != 0).mean()),
             "specular": float(((vf & fpt.VALID_SPECULAR) != 0).mean()),
             "visible": float(((vf & fpt.VALID_VISIBLE) != 0).mean()),

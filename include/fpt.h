@@ -204,12 +204,17 @@ fpt_status fpt_grad(fpt_handle* h, const fpt_scene* scene,
  * A path is valid when all three are set. Paths with FPT_ST_INVALID or
  * FPT_ST_NONFINITE in fwd->status, or an order outside 1..n_max, get 0.
  * Needs fwd->x, fwd->t, fwd->status (device pointers) and flags [N] (device).
- * The work is every segment against every face: O(N n K). Uses tables of
- * 18 K + 64 floats in the handle's workspace (hipMalloc on growth). */
+ * mode FPT_VALIDATE_ALL tests every segment of every path against every
+ * face: O(N n F) for F faces. mode FPT_VALIDATE_LAZY tests occlusion only for
+ * the paths that have EXTENT and SPECULAR (gathered per workgroup first) and
+ * leaves FPT_VALID_VISIBLE clear on the others; the set of valid paths (all
+ * three bits) is the same in both modes. Uses tables of 19 K + 64 floats in
+ * the handle's workspace (hipMalloc on growth). */
 enum { FPT_VALID_EXTENT = 1, FPT_VALID_SPECULAR = 2, FPT_VALID_VISIBLE = 4 };
+enum { FPT_VALIDATE_ALL = 0, FPT_VALIDATE_LAZY = 1 };
 fpt_status fpt_validate(fpt_handle* h, const fpt_scene* scene,
                         const fpt_paths* paths, const fpt_out* fwd,
-                        uint8_t* flags, void* hip_stream);
+                        uint8_t* flags, int32_t mode, void* hip_stream);
 
 /* Launch configuration of the FP32 solver kernel of one order (what the
  * autotuner chooses). wg_per_cu: resident workgroups per compute unit for

@@ -26,7 +26,7 @@ hipError_t launch_grad(int order, const GradArgs& A, const int32_t* perm,
 const void* grad_kernel_ptr(int order);
 hipError_t launch_face_table(const float* obj, int32_t K, float* tab, float* nrm,
                              int32_t* nfaces, hipStream_t st);
-hipError_t launch_validate(int order, const ValidateArgs& A, const int32_t* perm,
+hipError_t launch_validate(int order, const ValidateArgs& A, bool lazy, const int32_t* perm,
                            const int64_t* bucket, int grid, hipStream_t st);
 hipError_t launch_validate_invalid(const ValidateArgs& A, const int32_t* perm,
                                    const int64_t* bucket, int grid, hipStream_t st);
@@ -46,7 +46,7 @@ struct fpt_handle {
   hipEvent_t ev[FPT_TIMERS][kRing][2] = {};
   int nrec[FPT_TIMERS] = {};  // launches recorded since the last read
   unsigned long long* work = nullptr;  // [FPT_NMAX][4][kWorkSlots] counters
-  float* faces = nullptr;  // validity tables: faces [15][K], normals [3][K], count
+  float* faces = nullptr;  // validity tables: faces [K][16], normals [3][K], counts
   int64_t faces_cap = 0;
   // workspace
   int32_t* perm = nullptr;
@@ -762,11 +762,14 @@ extern "C" fpt_status fpt_grad(fpt_handle* h, const fpt_scene* sc,
 
 extern "C" fpt_status fpt_validate(fpt_handle* h, const fpt_scene* sc,
                                    const fpt_paths* pa, const fpt_out* fwd,
-                                   uint8_t* flags, void* stream) {
+                                   uint8_t* flags, int32_t mode, void* stream) {
   if (!h) return fail(FPT_EINVAL, "fpt_validate: handle is NULL");
   fpt_status s = check_common(sc, pa, "fpt_validate");
   if (s != FPT_OK) return s;
   if (!fwd || !flags) return fail(FPT_EINVAL, "fpt_validate: fwd and flags are required");
+  if (mode != FPT_VALIDATE_ALL && mode != FPT_VALIDATE_LAZY)
+    return fail(FPT_EINVAL, "fpt_validate: unknown mode");
+  const bool lazy = mode == FPT_VALIDATE_LAZY;
   if (pa->N == 0) return FPT_OK;
   if (!fwd->x || !fwd->t || !fwd->status)
     return fail(FPT_EINVAL, "fpt_validate: fwd.x, fwd.t and fwd.status are required");
@@ -776,7 +779,7 @@ extern "C" fpt_status fpt_validate(fpt_handle* h, const fpt_scene* sc,
   if (!g.ok) return fail(FPT_EHIP, "fpt_validate: hipSetDevice failed");
   hipStream_t st = (hipStream_t)stream;
   const int64_t kk = sc->K > 0 ? sc->K : 1;
-  const int64_t need = 18 * kk + 64;
+  const int64_t need = 19 * kk + 64;
   if (h->faces_cap < need) {
     if (h->faces) (void)hipFree(h->faces);
     h->faces = nullptr;
@@ -798,8 +801,8 @@ extern "C" fpt_status fpt_validate(fpt_handle* h, const fpt_scene* sc,
   A.t = fwd->t;
   A.status = fwd->status;
   A.tab = h->faces;
-  A.nrm = h->faces + 15 * kk;
-  A.nfaces = (const int32_t*)(h->faces + 18 * kk);
+  A.nrm = h->faces + 16 * kk;
+  A.nfaces = (const int32_t*)(h->faces + 19 * kk);
   A.flags = flags;
   A.N = pa->N;
   A.K = sc->K;
@@ -807,14 +810,14 @@ extern "C" fpt_status fpt_validate(fpt_handle* h, const fpt_scene* sc,
   A.n_max = pa->n_max;
   hipError_t e;
   SlotTimer tm(h, FPT_T_VALIDATE, st);
-  e = fpt::launch_face_table(sc->obj, sc->K, h->faces, h->faces + 15 * kk,
-                             (int32_t*)(h->faces + 18 * kk), st);
+  e = fpt::launch_face_table(sc->obj, sc->K, h->faces, h->faces + 16 * kk,
+                             (int32_t*)(h->faces + 19 * kk), st);
   if (e != hipSuccess) return hip_fail(e, "fpt_validate: launch");
   const int64_t cap = (pa->N + fpt::kBlock - 1) / fpt::kBlock;
   const int64_t pg = (int64_t)h->num_cu * 8;
   const int grid = (int)(cap < pg ? cap : pg);
   if (!pa->order) {
-    e = fpt::launch_validate(pa->n_max, A, nullptr, nullptr, grid, st);
+    e = fpt::launch_validate(pa->n_max, A, lazy, nullptr, nullptr, grid, st);
     if (e != hipSuccess) return hip_fail(e, "fpt_validate: launch");
     return FPT_OK;
   }
@@ -823,7 +826,7 @@ extern "C" fpt_status fpt_validate(fpt_handle* h, const fpt_scene* sc,
   e = fpt::launch_bucketing(pa->order, pa->N, pa->n_max, h->ccount, h->bucket, h->perm, st);
   if (e != hipSuccess) return hip_fail(e, "fpt_validate: bucketing launch");
   for (int n = 1; n <= pa->n_max; ++n) {
-    e = fpt::launch_validate(n, A, h->perm, h->bucket, grid, st);
+    e = fpt::launch_validate(n, A, lazy, h->perm, h->bucket, grid, st);
     if (e != hipSuccess) return hip_fail(e, "fpt_validate: launch");
   }
   e = fpt::launch_validate_invalid(A, h->perm, h->bucket, h->num_cu * 4, st);

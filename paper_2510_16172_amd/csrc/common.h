@@ -126,7 +126,7 @@ struct ValidateArgs {
   const float* x;         // forward X* [n_max][3][N]
   const float* t;         // forward T* [n_max][2][N] (caller's parametrisation)
   const uint8_t* status;  // forward status [N]
-  const float* tab;       // compact face table [15][K] (face_table_kernel)
+  const float* tab;       // compact face table [K][16] (face_table_kernel)
   const float* nrm;       // normals of every object [3][K] (0 for an edge)
   const int32_t* nfaces;  // number of faces in tab
   uint8_t* flags;         // [N]

@@ -69,6 +69,7 @@ EXPORTED = ["fpt_default_opts", "fpt_create", "fpt_destroy", "fpt_solve",
 T_BUCKET, T_BFGS, T_REFINE, T_GRAD, T_REDUCE, T_MLP, T_VALIDATE, TIMERS = (
     0, 1, 7, 13, 14, 15, 16, 17)
 VALID_EXTENT, VALID_SPECULAR, VALID_VISIBLE = 1, 2, 4
+VALIDATE_ALL, VALIDATE_LAZY = 0, 1
 MLP_PARAMS = 172864  # padded parameter count: state[0:MLP_PARAMS] = weights
 
 _lib = None
@@ -125,7 +126,7 @@ def load_library(path: str = LIB_PATH):
     lib.fpt_graph_destroy.argtypes = [_P]
     lib.fpt_graph_destroy.restype = ctypes.c_int
     lib.fpt_validate.argtypes = [_P, ctypes.POINTER(_Scene), ctypes.POINTER(_Paths),
-                                 ctypes.POINTER(_Out), _P, _P]
+                                 ctypes.POINTER(_Out), _P, ctypes.c_int32, _P]
     lib.fpt_validate.restype = ctypes.c_int
     lib.fpt_work_counts.argtypes = [_P, ctypes.POINTER(ctypes.c_uint64)]
     lib.fpt_work_counts.restype = ctypes.c_int
@@ -279,16 +280,18 @@ class Solver:
         _check(load_library().fpt_kernel_times(self._h, ms), "fpt_kernel_times")
         return [float(v) for v in ms]
 
-    def validate(self, db: DeviceBatch, out, flags=None, stream=None):
+    def validate(self, db: DeviceBatch, out, flags=None, lazy=False, stream=None):
         """fpt_validate: uint8 [N] validity bits (VALID_*) of the solved
-        paths `out` on the scene's finite objects."""
+        paths `out` on the scene's finite objects. lazy: occlusion is tested
+        only for paths with VALID_EXTENT and VALID_SPECULAR (VALIDATE_LAZY)."""
         import torch
         if flags is None:
             flags = torch.empty(db.N, dtype=torch.uint8, device="cuda")
         sc, pa, ou = db.c_scene(), db.c_paths(), self.c_out(out)
         _check(load_library().fpt_validate(
             self._h, ctypes.byref(sc), ctypes.byref(pa), ctypes.byref(ou),
-            _ptr(flags), _stream_ptr(stream)), "fpt_validate")
+            _ptr(flags), ctypes.c_int32(VALIDATE_LAZY if lazy else VALIDATE_ALL),
+            _stream_ptr(stream)), "fpt_validate")
         return flags
 
     def work_counts(self):
