@@ -222,6 +222,41 @@ fpt_status fpt_validate(fpt_handle* h, const fpt_scene* scene,
  * early_exit / stage_iters / iters / quick_steps / quick_passes (each if
  * > 0) override the corresponding fpt_opts fields for paths of that order
  * when use_override is 1. */
+/* Candidate enumeration on the device (Sec. III, problem statement: the
+ * candidates with n interactions are every ordered sequence of n objects,
+ * for n = 1..n_max, per TX/RX pair). The candidates, in rank order:
+ *   for n = order_min .. order_max, for pair p = 0 .. P-1, every sequence
+ *   (k_1, .., k_n) of object indices in 0..K-1, in lexicographic order,
+ *   leaving out those with k_{j+1} == k_j when no_repeat is 1.
+ * Order n has P * M_n candidates, M_n = K (K-1)^(n-1) with no_repeat and
+ * K^n without. */
+typedef struct {
+  const int32_t* pair_src;  /* [P] device: point index (into pts) of pair p's TX */
+  const int32_t* pair_dst;  /* [P] device: point index of pair p's RX */
+  int32_t P;                /* pairs, >= 1 */
+  int32_t K;                /* objects, >= 1 */
+  int32_t order_min;        /* 1 .. order_max */
+  int32_t order_max;        /* order_min .. FPT_NMAX */
+  int32_t no_repeat;        /* 0 or 1 */
+} fpt_enum_spec;
+
+/* Number of candidates of `spec` into *total (host arithmetic only; the
+ * device pointers are not read). FPT_EINVAL for a bad spec or a total
+ * above 2^62. */
+fpt_status fpt_enum_count(const fpt_enum_spec* spec, int64_t* total);
+
+/* Writes the candidates of ranks rank0 .. rank0 + count - 1 as paths
+ * 0 .. count - 1, in the fpt_paths layout with N = count: src [count],
+ * dst [count] (from the pair tables), order [count] (u8), ids [n_max][count]
+ * (-1 past the path's order). All device pointers, caller-owned; n_max in
+ * order_max .. FPT_NMAX. rank0 < 0, count < 0 or rank0 + count above the
+ * total is FPT_EINVAL; count == 0 launches nothing. One kernel on
+ * `hip_stream`, no allocation: a caller can stream a candidate set of any
+ * size through fixed buffers, chunk by chunk. */
+fpt_status fpt_enumerate(fpt_handle* h, const fpt_enum_spec* spec, int64_t rank0,
+                         int64_t count, int32_t* src, int32_t* dst, uint8_t* order,
+                         int32_t* ids, int32_t n_max, void* hip_stream);
+
 typedef struct {
   int32_t wg_per_cu;
   int32_t use_override;

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfpt.so")
-SOURCES = ["solve.hip", "grad.hip", "validate.hip", "mlp.hip", "api.hip"]
+SOURCES = ["solve.hip", "grad.hip", "validate.hip", "enumerate.hip", "mlp.hip", "api.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions (v_pk_*_f32) anywhere in the device code

@@ -28,6 +28,7 @@ hipError_t launch_face_table(const float* obj, int32_t K, float* tab, float* nrm
                              int32_t* nfaces, hipStream_t st);
 hipError_t launch_validate(int order, const ValidateArgs& A, bool lazy, const int32_t* perm,
                            const int64_t* bucket, int grid, hipStream_t st);
+hipError_t launch_enumerate(const EnumArgs& A, int grid, hipStream_t st);
 hipError_t launch_validate_invalid(const ValidateArgs& A, const int32_t* perm,
                                    const int64_t* bucket, int grid, hipStream_t st);
 hipError_t launch_grad_invalid(const GradArgs& A, const int32_t* perm,
@@ -755,6 +756,99 @@ extern "C" fpt_status fpt_grad(fpt_handle* h, const fpt_scene* sc,
     e = fpt::launch_grad_invalid(A, h->perm, h->bucket, sgrid, st);
     if (e != hipSuccess) return hip_fail(e, "fpt_grad: launch");
   }
+  return FPT_OK;
+}
+
+// ---------------------------------------------------------- enumeration ----
+
+static const int64_t kEnumLimit = (int64_t)1 << 62;
+
+// Candidates per pair of every order of the spec, and the first rank of
+// every order; false on a total above kEnumLimit.
+static bool enum_layout(const fpt_enum_spec* sp, int64_t per_pair[FPT_NMAX + 1],
+                        int64_t first[FPT_NMAX + 1]) {
+  const int64_t radix = sp->no_repeat ? sp->K - 1 : sp->K;
+  int64_t m = sp->K, acc = 0;
+  for (int n = 1; n <= sp->order_max; ++n) {
+    if (n > 1) {
+      if (radix != 0 && m > kEnumLimit / radix) return false;
+      m *= radix;
+    }
+    per_pair[n] = m;
+    if (n >= sp->order_min) {
+      first[n - sp->order_min] = acc;
+      if (m != 0 && sp->P > (kEnumLimit - acc) / m) return false;
+      acc += (int64_t)sp->P * m;
+    }
+  }
+  first[sp->order_max - sp->order_min + 1] = acc;
+  return true;
+}
+
+static fpt_status check_enum_spec(const fpt_enum_spec* sp, const char* who) {
+  if (!sp) return fail(FPT_EINVAL, std::string(who) + ": spec is NULL");
+  if (sp->P < 1 || sp->K < 1)
+    return fail(FPT_EINVAL, std::string(who) + ": P and K must be >= 1");
+  if (sp->order_min < 1 || sp->order_min > sp->order_max || sp->order_max > FPT_NMAX)
+    return fail(FPT_EINVAL, std::string(who) + ": need 1 <= order_min <= order_max <= 6");
+  if (sp->no_repeat != 0 && sp->no_repeat != 1)
+    return fail(FPT_EINVAL, std::string(who) + ": no_repeat must be 0 or 1");
+  return FPT_OK;
+}
+
+extern "C" fpt_status fpt_enum_count(const fpt_enum_spec* sp, int64_t* total) {
+  fpt_status s = check_enum_spec(sp, "fpt_enum_count");
+  if (s != FPT_OK) return s;
+  if (!total) return fail(FPT_EINVAL, "fpt_enum_count: total is NULL");
+  int64_t per_pair[FPT_NMAX + 1], first[FPT_NMAX + 1];
+  if (!enum_layout(sp, per_pair, first))
+    return fail(FPT_EINVAL, "fpt_enum_count: more than 2^62 candidates");
+  *total = first[sp->order_max - sp->order_min + 1];
+  return FPT_OK;
+}
+
+extern "C" fpt_status fpt_enumerate(fpt_handle* h, const fpt_enum_spec* sp, int64_t rank0,
+                                    int64_t count, int32_t* src, int32_t* dst,
+                                    uint8_t* order, int32_t* ids, int32_t n_max,
+                                    void* stream) {
+  if (!h) return fail(FPT_EINVAL, "fpt_enumerate: handle is NULL");
+  fpt_status s = check_enum_spec(sp, "fpt_enumerate");
+  if (s != FPT_OK) return s;
+  if (n_max < sp->order_max || n_max > FPT_NMAX)
+    return fail(FPT_EINVAL, "fpt_enumerate: n_max must be in order_max..6");
+  fpt::EnumArgs A;
+  memset(&A, 0, sizeof(A));
+  if (!enum_layout(sp, A.per_pair, A.first))
+    return fail(FPT_EINVAL, "fpt_enumerate: more than 2^62 candidates");
+  const int64_t total = A.first[sp->order_max - sp->order_min + 1];
+  if (rank0 < 0 || count < 0 || rank0 > total || count > total - rank0)
+    return fail(FPT_EINVAL, "fpt_enumerate: ranks outside the candidate set");
+  if (count == 0) return FPT_OK;
+  if (!sp->pair_src || !sp->pair_dst || !src || !dst || !order || !ids)
+    return fail(FPT_EINVAL, "fpt_enumerate: NULL pointer");
+  if (!aligned(sp->pair_src, 4) || !aligned(sp->pair_dst, 4) || !aligned(src, 4) ||
+      !aligned(dst, 4) || !aligned(ids, 4))
+    return fail(FPT_EINVAL, "fpt_enumerate: misaligned pointer");
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(FPT_EHIP, "fpt_enumerate: hipSetDevice failed");
+  A.pair_src = sp->pair_src;
+  A.pair_dst = sp->pair_dst;
+  A.src = src;
+  A.dst = dst;
+  A.order = order;
+  A.ids = ids;
+  A.rank0 = rank0;
+  A.count = count;
+  A.omin = sp->order_min;
+  A.omax = sp->order_max;
+  A.K = sp->K;
+  A.no_repeat = sp->no_repeat;
+  A.n_max = n_max;
+  const int64_t blocks = (count + fpt::kBlock - 1) / fpt::kBlock;
+  const int64_t cap = (int64_t)h->num_cu * 8;
+  hipError_t e = fpt::launch_enumerate(A, (int)(blocks < cap ? blocks : cap),
+                                       (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "fpt_enumerate: launch");
   return FPT_OK;
 }
 

@@ -134,4 +134,18 @@ struct ValidateArgs {
   int32_t K, Q, n_max;
 };
 
+// Candidate enumeration (enumerate.hip)
+struct EnumArgs {
+  const int32_t* pair_src;
+  const int32_t* pair_dst;
+  int32_t* src;
+  int32_t* dst;
+  uint8_t* order;
+  int32_t* ids;  // [n_max][count]
+  int64_t rank0, count;
+  int64_t first[FPT_NMAX + 1];  // first rank of order omin + i; first[omax - omin + 1] = total
+  int64_t per_pair[FPT_NMAX + 1];  // sequences per pair of order n (index n)
+  int32_t omin, omax, K, no_repeat, n_max;
+};
+
 }  // namespace fpt

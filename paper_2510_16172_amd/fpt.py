@@ -54,6 +54,12 @@ class _LaunchCfg(ctypes.Structure):
                 ("quick_passes", ctypes.c_int32)]
 
 
+class _EnumSpec(ctypes.Structure):
+    _fields_ = [("pair_src", _P), ("pair_dst", _P), ("P", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("order_min", ctypes.c_int32),
+                ("order_max", ctypes.c_int32), ("no_repeat", ctypes.c_int32)]
+
+
 class _Out(ctypes.Structure):
     _fields_ = [("x", _P), ("len", _P), ("t", _P), ("status", _P),
                 ("iters", _P)]
@@ -63,7 +69,8 @@ EXPORTED = ["fpt_default_opts", "fpt_create", "fpt_destroy", "fpt_solve",
             "fpt_grad", "fpt_last_error", "fpt_set_timing", "fpt_kernel_times",
             "fpt_mlp_state_floats", "fpt_mlp_init", "fpt_mlp_train_step",
             "fpt_mlp_infer", "fpt_set_launch", "fpt_graph_capture",
-            "fpt_graph_launch", "fpt_graph_destroy"]
+            "fpt_graph_launch", "fpt_graph_destroy", "fpt_validate",
+            "fpt_work_counts", "fpt_enum_count", "fpt_enumerate"]
 
 # timer slots of fpt_kernel_times
 T_BUCKET, T_BFGS, T_REFINE, T_GRAD, T_REDUCE, T_MLP, T_VALIDATE, TIMERS = (
@@ -128,6 +135,11 @@ def load_library(path: str = LIB_PATH):
     lib.fpt_validate.argtypes = [_P, ctypes.POINTER(_Scene), ctypes.POINTER(_Paths),
                                  ctypes.POINTER(_Out), _P, ctypes.c_int32, _P]
     lib.fpt_validate.restype = ctypes.c_int
+    lib.fpt_enum_count.argtypes = [ctypes.POINTER(_EnumSpec), ctypes.POINTER(ctypes.c_int64)]
+    lib.fpt_enum_count.restype = ctypes.c_int
+    lib.fpt_enumerate.argtypes = [_P, ctypes.POINTER(_EnumSpec), ctypes.c_int64,
+                                  ctypes.c_int64, _P, _P, _P, _P, ctypes.c_int32, _P]
+    lib.fpt_enumerate.restype = ctypes.c_int
     lib.fpt_work_counts.argtypes = [_P, ctypes.POINTER(ctypes.c_uint64)]
     lib.fpt_work_counts.restype = ctypes.c_int
     lib.fpt_last_error.argtypes = []
@@ -198,6 +210,22 @@ def _stream_ptr(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _enum_spec(P, K, order_min, order_max, no_repeat=True, pair_src=None, pair_dst=None):
+    return _EnumSpec(pair_src.data_ptr() if pair_src is not None else None,
+                     pair_dst.data_ptr() if pair_dst is not None else None,
+                     int(P), int(K), int(order_min), int(order_max), 1 if no_repeat else 0)
+
+
+def enum_count(P: int, K: int, order_min: int, order_max: int, no_repeat: bool = True) -> int:
+    """fpt_enum_count: number of candidates (every ordered sequence of
+    order_min..order_max objects per pair; no immediate repeat if asked)."""
+    sp = _enum_spec(P, K, order_min, order_max, no_repeat)
+    total = ctypes.c_int64()
+    _check(load_library().fpt_enum_count(ctypes.byref(sp), ctypes.byref(total)),
+           "fpt_enum_count")
+    return int(total.value)
 
 
 class DeviceBatch:
@@ -293,6 +321,35 @@ class Solver:
             _ptr(flags), ctypes.c_int32(VALIDATE_LAZY if lazy else VALIDATE_ALL),
             _stream_ptr(stream)), "fpt_validate")
         return flags
+
+    def enumerate(self, pair_src, pair_dst, K: int, order_min: int, order_max: int,
+                  no_repeat: bool = True, rank0: int = 0, count: int | None = None,
+                  n_max: int | None = None, out=None, stream=None):
+        """fpt_enumerate: candidates of ranks rank0 .. rank0 + count - 1 as
+        device tensors {src, dst, order, ids} in the fpt_paths layout.
+        pair_src / pair_dst: int32 [P] device tensors of point indices."""
+        import torch
+        P = int(pair_src.shape[0])
+        if int(pair_dst.shape[0]) != P:
+            raise ValueError("pair_src and pair_dst differ in length")
+        for name, t in (("pair_src", pair_src), ("pair_dst", pair_dst)):
+            if t.dtype != torch.int32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{name} must be a contiguous int32 device tensor")
+        if count is None:
+            count = enum_count(P, K, order_min, order_max, no_repeat) - int(rank0)
+        n_max = int(order_max if n_max is None else n_max)
+        if out is None:
+            dev = pair_src.device
+            out = {"src": torch.empty(count, dtype=torch.int32, device=dev),
+                   "dst": torch.empty(count, dtype=torch.int32, device=dev),
+                   "order": torch.empty(count, dtype=torch.uint8, device=dev),
+                   "ids": torch.empty((n_max, count), dtype=torch.int32, device=dev)}
+        sp = _enum_spec(P, K, order_min, order_max, no_repeat, pair_src, pair_dst)
+        _check(load_library().fpt_enumerate(
+            self._h, ctypes.byref(sp), ctypes.c_int64(int(rank0)), ctypes.c_int64(int(count)),
+            _ptr(out["src"]), _ptr(out["dst"]), _ptr(out["order"]), _ptr(out["ids"]),
+            ctypes.c_int32(n_max), _stream_ptr(stream)), "fpt_enumerate")
+        return out
 
     def work_counts(self):
         """{order: (path evaluations, Newton solves, reduced-path evaluations,

@@ -76,3 +76,23 @@ def test_solve_rejects_bad_arguments_before_launch():
                        ctypes.byref(o), ctypes.byref(ou), None)
     assert rc == -1
     assert b"handle" in lib.fpt_last_error()
+
+
+def test_enum_count_host_matches_oracle():
+    """fpt_enum_count is host arithmetic: it runs without a GPU. Counts
+    equal the enumeration oracle's; bad specs and totals above 2^62 are
+    rejected."""
+    import pytest
+    from oracle import candidates as cand
+    from paper_2510_16172_amd import fpt
+    for P, K, lo, hi, nr in [(64, 313, 1, 2, True), (3, 5, 2, 4, False), (1, 1, 1, 6, True),
+                             (7, 2, 1, 6, True), (64, 313, 1, 6, True), (2, 1000, 3, 6, False)]:
+        assert fpt.enum_count(P, K, lo, hi, nr) == cand.total(P, K, lo, hi, nr)
+    for bad in [(0, 5, 1, 2), (2, 0, 1, 2), (2, 5, 0, 2), (2, 5, 3, 2), (2, 5, 1, 7),
+                (1 << 30, 1 << 20, 1, 6)]:
+        with pytest.raises(fpt.FptError):
+            fpt.enum_count(*bad)
+    lib = fpt.load_library()
+    sp = fpt._enum_spec(2, 5, 1, 2)
+    rc = lib.fpt_enumerate(None, ctypes.byref(sp), 0, 1, None, None, None, None, 2, None)
+    assert rc == -1 and b"handle" in lib.fpt_last_error()
