@@ -349,6 +349,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use --iters / --early-exit for every order instead "
                          "of the autotuned per-order schedule")
+    ap.add_argument("--schedule", type=str, default=None,
+                    help="JSON {order: launch config} applied with fpt_set_launch "
+                         "instead of autotuning (e.g. a previous run's config.schedule)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true",
@@ -381,7 +384,11 @@ def main():
     out = solver.alloc_out(db)
     stream = torch.cuda.current_stream()
     chosen = {}
-    if not args.no_autotune:
+    if args.schedule:
+        chosen = {int(k): v for k, v in json.loads(args.schedule).items()}
+        for n, cfg in chosen.items():
+            solver.set_launch(n, cfg)
+    elif not args.no_autotune:
         from paper_2510_16172_amd import autotune
         chosen = autotune.tune(solver, batch, opts, sample=1 << 20, repeats=3)
     orders = sorted(int(v) for v in np.unique(batch.order))
@@ -446,6 +453,36 @@ def main():
     certified = int(((st & fpt.ST_CONVERGED) != 0).sum())
     value = certified / (ms_step / 1e3)
 
+    # candidate enumeration on the device (the step before the solve), and
+    # the chain candidates -> solve -> validity (lazy) on one stream
+    n_pairs = scene.meta["n_pairs"]
+    tps = torch.arange(0, 2 * n_pairs, 2, dtype=torch.int32, device="cuda:0")
+    tpd = tps + 1
+    eo = solver.enumerate(tps, tpd, scene.K, 1, 2, stream=stream)
+    torch.cuda.synchronize()
+    enum_same = all(bool(torch.equal(eo[k], getattr(db, k)))
+                    for k in ("src", "dst", "order", "ids"))
+    v0.record(stream)
+    for _ in range(5):
+        solver.enumerate(tps, tpd, scene.K, 1, 2, out=eo, stream=stream)
+    v1.record(stream)
+    torch.cuda.synchronize()
+    ms_enum = v0.elapsed_time(v1) / 5
+    enum_bytes = 4 + 4 + 1 + 4 * batch.n_max  # src, dst, order, ids written per candidate
+    dbe = fpt.DeviceBatch.from_tensors(db.obj, db.pts, eo["src"], eo["dst"], eo["ids"],
+                                       eo["order"], S=batch.S)
+    cflags = solver.validate(dbe, out, lazy=True, stream=stream)
+    torch.cuda.synchronize()
+    v0.record(stream)
+    for _ in range(3):
+        solver.enumerate(tps, tpd, scene.K, 1, 2, out=eo, stream=stream)
+        solver.solve(dbe, opts, out=out, stream=stream)
+        solver.validate(dbe, out, flags=cflags, lazy=True, stream=stream)
+    v1.record(stream)
+    torch.cuda.synchronize()
+    ms_chain = v0.elapsed_time(v1) / 3
+    chain_valid = int((cflags == 7).sum().item())
+
     # rooflines of the two kernels of the order-2 bucket (99.7 % of the
     # paths): FP32 BFGS and FP64 refinement; the dominant one is `roofline`
     workload = "canyon_order2_all"
@@ -509,7 +546,7 @@ def main():
                         "of order <= 2 (313 objects, 64 TX/RX pairs)",
             "paths": N, "fp_iters": args.fp_iters,
             "schedule": schedule,
-            "autotuned": not args.no_autotune,
+            "autotuned": not args.no_autotune and not args.schedule,
             "refine_levels": list(zip(opts.level_eps, opts.level_steps)),
             "quick_steps": opts.quick_steps,
             "quick_passes": opts.quick_passes,
@@ -527,6 +564,19 @@ def main():
             "visible": float(((vf & fpt.VALID_VISIBLE) != 0).mean()),
             "valid": float((vf == 7).mean()),
             "valid_and_certified": float(((vf == 7) & ((st & fpt.ST_CONVERGED) != 0)).mean()),
+        },
+        "enumerate": {
+            "ms": ms_enum, "candidates_per_s": N / (ms_enum * 1e-3),
+            "bytes_per_candidate": enum_bytes,
+            "roofline": {"bound": "hbm", "achieved": N * enum_bytes / (ms_enum * 1e-3) / 1e9,
+                         "peak": 8000.0, "unit": "GB/s",
+                         "frac": N * enum_bytes / (ms_enum * 1e-3) / 1e9 / 8000.0},
+            "same_as_host_generator": enum_same,
+        },
+        "chain": {
+            "steps": "enumerate + solve + lazy validity, one stream",
+            "ms": ms_chain, "candidates_per_s": N / (ms_chain * 1e-3),
+            "valid_paths": chain_valid,
         },
     }
     if not args.no_cpu_baseline:
