@@ -40,7 +40,7 @@ hipError_t launch_grad_invalid(const GradArgs& A, const int32_t* perm,
 struct fpt_handle {
   int device;
   int num_cu;
-  int occ[4][FPT_NMAX + 1];  // resident workgroups per CU, per phase/order
+  int occ[5][FPT_NMAX + 1];  // resident workgroups per CU, per phase/order
   // optional per-kernel timing
   static constexpr int kRing = 32;
   bool timing = false;
@@ -152,7 +152,7 @@ extern "C" fpt_status fpt_create(int device, fpt_handle** out) {
   fpt_handle* h = new fpt_handle();
   h->device = device;
   h->num_cu = prop.multiProcessorCount;
-  for (int ph = 0; ph < 4; ++ph)
+  for (int ph = 0; ph < 5; ++ph)
     for (int n = 1; n <= FPT_NMAX; ++n) {
       int occ = 0;
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -616,7 +616,8 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
         // pass 1: quick steps for all, list the uncertified paths
         R.out_list = h->slist[w][0];
         R.out_count = cnt;
-        e = fpt::launch_solve(1, n, An, perm, bucket, &R, grid, sn);
+        e = fpt::launch_solve(1, n, An, perm, bucket, &R, perm ? persistent(4, n, 0) : (int)cap,
+                              sn);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         int k = 0;  // the stage whose list is current
         auto next_stage = [&](int phase, int grid_x) -> hipError_t {
@@ -633,7 +634,7 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
         };
         if (qpasses > 1) {
           // second quick pass on the paths the first did not certify
-          e = next_stage(1, persistent(1, n, 0));
+          e = next_stage(1, persistent(4, n, 0));
           if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         }
         if (n >= 2) {

@@ -1158,7 +1158,9 @@ __global__ __launch_bounds__(kBlock) void bfgs_stage_kernel(
 // left in A.t, and the second pass (St.in_list) runs the full schedule on
 // them from there (after merge_kernel for orders >= 2).
 // St.in_list == St.out_list == null: one pass with the full schedule.
-template <int NO>
+// QUICK (St.out_list != null) and the full schedule are separate
+// instantiations, so that each gets its own register budget.
+template <int NO, bool QUICK>
 __global__ __launch_bounds__(kBlock) void refine_kernel(
     SolveArgs A, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ bucket, StageArgs St) {
@@ -1179,7 +1181,7 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
     begin = bucket[NO - 1];
     count = bucket[NO] - begin;
   }
-  const bool quick = St.out_list != nullptr;
+  constexpr bool quick = QUICK;
   __shared__ float geo[geo_lds_rows(NO) * kBlock];
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -1477,8 +1479,11 @@ static hipError_t launch_phase(int phase, const SolveArgs& A,
   if (phase == 0)
     hipLaunchKernelGGL(bfgs_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
                        perm, bucket);
+  else if (phase == 1 && stage && stage->out_list)
+    hipLaunchKernelGGL((refine_kernel<NO, true>), dim3(grid), dim3(kBlock), 0, st, A,
+                       perm, bucket, *stage);
   else if (phase == 1)
-    hipLaunchKernelGGL(refine_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
+    hipLaunchKernelGGL((refine_kernel<NO, false>), dim3(grid), dim3(kBlock), 0, st, A,
                        perm, bucket, *stage);
   else if (phase == 2)
     hipLaunchKernelGGL(bfgs_stage_kernel<NO>, dim3(grid), dim3(kBlock), 0,
@@ -1489,7 +1494,8 @@ static hipError_t launch_phase(int phase, const SolveArgs& A,
   return hipGetLastError();
 }
 
-// phase 0: bfgs_kernel<order>, 1: refine_kernel<order>,
+// phase 0: bfgs_kernel<order>, 1: refine_kernel<order> (the quick variant
+// when stage->out_list is set),
 // 2: bfgs_stage_kernel<order> (one early-exit stage, `stage` describes it),
 // 3: merge_kernel<order> (between the refinement passes)
 hipError_t launch_solve(int phase, int order, const SolveArgs& A,
@@ -1521,9 +1527,10 @@ int stage_fields_for(int order) {
 template <int NO>
 static const void* phase_ptr(int phase) {
   return phase == 0 ? (const void*)bfgs_kernel<NO>
-         : phase == 1 ? (const void*)refine_kernel<NO>
+         : phase == 1 ? (const void*)refine_kernel<NO, false>
          : phase == 2 ? (const void*)bfgs_stage_kernel<NO>
-                      : (const void*)merge_kernel<NO>;
+         : phase == 3 ? (const void*)merge_kernel<NO>
+                      : (const void*)refine_kernel<NO, true>;
 }
 
 const void* solve_kernel_ptr(int phase, int order) {
