@@ -111,15 +111,19 @@ def read_traffic(kernel: str, workload: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(batch, out_np, seconds: float, threads: int, seed: int = 7):
+def cpu_baseline(batch, out_np, seconds: float, threads: int, seed: int = 7,
+                 others=None):
     """The FP64 oracle timed on host cores on a seeded random sample of the
     workload (chunks of 2^14 paths until `seconds` have elapsed), and the GPU
-    result checked against it on that sample."""
+    result checked against it on that sample (also each of `others`, a
+    {name: output} dict of other GPU results on the same workload)."""
     import oracle
     rng = np.random.default_rng(seed)
     perm = rng.permutation(batch.N)
     chunk = 1 << 14
-    done, t_used, n_ok, n_fp, n_cert = 0, 0.0, 0, 0, 0
+    done, t_used = 0, 0.0
+    outs = {"": out_np, **(others or {})}
+    tally = {k: [0, 0, 0] for k in outs}  # within 1e-4, certified, certified but wrong
     while t_used < seconds and done < batch.N:
         idx = np.sort(perm[done:done + chunk])
         sub = batch.subset(idx)
@@ -127,17 +131,19 @@ def cpu_baseline(batch, out_np, seconds: float, threads: int, seed: int = 7):
         ref = oracle.solve(sub, threads=threads)
         t_used += time.perf_counter() - t0
         done += len(idx)
-        x = np.transpose(out_np["x"][:, :, idx], (2, 0, 1)).astype(np.float64)
-        d = np.linalg.norm(x - ref["x"], axis=-1)
         j = np.arange(sub.n_max)[None, :]
-        d = np.where(j < sub.order[:, None].astype(np.int64), d, 0.0)
-        err = np.where(np.isfinite(d), d, np.inf).max(axis=1) / sub.S
-        ok = err <= 1e-4
-        cert = (out_np["status"][idx] & 1) != 0
         ill = (ref["flags"] & 2) != 0
-        n_ok += int(ok.sum())
-        n_cert += int(cert.sum())
-        n_fp += int((cert & ~ok & ~ill).sum())
+        for k, o in outs.items():
+            x = np.transpose(o["x"][:, :, idx], (2, 0, 1)).astype(np.float64)
+            d = np.linalg.norm(x - ref["x"], axis=-1)
+            d = np.where(j < sub.order[:, None].astype(np.int64), d, 0.0)
+            err = np.where(np.isfinite(d), d, np.inf).max(axis=1) / sub.S
+            ok = err <= 1e-4
+            cert = (o["status"][idx] & 1) != 0
+            tally[k][0] += int(ok.sum())
+            tally[k][1] += int(cert.sum())
+            tally[k][2] += int((cert & ~ok & ~ill).sum())
+    n_ok, n_cert, n_fp = tally[""]
     # one thread, on the first chunk of the same sample
     sub = batch.subset(np.sort(perm[:min(chunk, batch.N)]))
     t0 = time.perf_counter()
@@ -153,7 +159,12 @@ def cpu_baseline(batch, out_np, seconds: float, threads: int, seed: int = 7):
             "gpu_within_1e-4_on_sample": n_ok / done,
             "gpu_within_1e-4_paths": n_ok,
             "gpu_certified_on_sample": n_cert / done,
-            "gpu_certified_but_wrong_on_sample": n_fp}
+            "gpu_certified_but_wrong_on_sample": n_fp,
+            "others": {k: {"gpu_within_1e-4_on_sample": v[0] / done,
+                           "gpu_within_1e-4_paths": v[0],
+                           "gpu_certified_on_sample": v[1] / done,
+                           "gpu_certified_but_wrong_on_sample": v[2]}
+                       for k, v in tally.items() if k}}
 
 
 def _cpu_model() -> str:
@@ -352,6 +363,8 @@ def main():
     ap.add_argument("--schedule", type=str, default=None,
                     help="JSON {order: launch config} applied with fpt_set_launch "
                          "instead of autotuning (e.g. a previous run's config.schedule)")
+    ap.add_argument("--no-variant", action="store_true",
+                    help="skip the FP32 Newton solver-variant leg")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true",
@@ -483,6 +496,31 @@ def main():
     ms_chain = v0.elapsed_time(v1) / 3
     chain_valid = int((cflags == 7).sum().item())
 
+    # solver variant (not the paper's method, not in `value`): the FP32
+    # exact-Hessian Newton first phase, autotuned the same way, same steps
+    variant, others = None, {}
+    if not args.no_variant:
+        from paper_2510_16172_amd import autotune
+        opts_n = fpt.Opts(scale=batch.S, method=fpt.METHOD_NEWTON32)
+        chosen_n = autotune.tune(solver, batch, opts_n,
+                                 candidates=autotune.NEWTON32_CANDIDATES,
+                                 sample=1 << 20, repeats=3)
+        for _ in range(args.warmup):
+            solver.solve(db, opts_n, out=out, stream=stream)
+        torch.cuda.synchronize()
+        v0.record(stream)
+        for _ in range(args.steps):
+            solver.solve(db, opts_n, out=out, stream=stream)
+        v1.record(stream)
+        torch.cuda.synchronize()
+        ms_n = v0.elapsed_time(v1) / args.steps
+        others["newton32"] = {k: v.cpu().numpy() for k, v in out.items()}
+        cert_n = int(((others["newton32"]["status"] & fpt.ST_CONVERGED) != 0).sum())
+        variant = {"method": "FP32 exact-Hessian Newton first phase (fpt_opts.method = 1)",
+                   "schedule": {str(k): v for k, v in chosen_n.items()},
+                   "ms_per_step": ms_n, "certified_fraction": cert_n / N,
+                   "certified_paths_per_s": cert_n / (ms_n * 1e-3)}
+
     # rooflines of the two kernels of the order-2 bucket (99.7 % of the
     # paths): FP32 BFGS and FP64 refinement; the dominant one is `roofline`
     workload = "canyon_order2_all"
@@ -573,6 +611,7 @@ def main():
                          "frac": N * enum_bytes / (ms_enum * 1e-3) / 1e9 / 8000.0},
             "same_as_host_generator": enum_same,
         },
+        "variant_newton32": variant,
         "chain": {
             "steps": "enumerate + solve + lazy validity, one stream",
             "ms": ms_chain, "candidates_per_s": N / (ms_chain * 1e-3),
@@ -581,7 +620,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-        res["cpu_baseline"] = cpu_baseline(batch, out_np, args.cpu_seconds, threads)
+        res["cpu_baseline"] = cpu_baseline(batch, out_np, args.cpu_seconds, threads,
+                                           others=others)
         if res["cpu_baseline"]["sample"].startswith("all "):
             # every output checked against the oracle: paths within 1e-4 S per
             # second, certified or not (the certificate is conservative)

@@ -138,7 +138,18 @@ typedef struct {
                            each order's kernels run on a stream of their own
                            (forked from and joined back into hip_stream);
                            0: one after the other on hip_stream */
+  int32_t method;       /* first phase: FPT_METHOD_BFGS, the paper's FP32 BFGS
+                           with the Eq. 6 step (Sec. III-C); or
+                           FPT_METHOD_NEWTON32, a solver variant: damped
+                           Newton in FP32 on the exact block-tridiagonal
+                           Hessian of the smoothed length, `iters` steps split
+                           evenly over eps / scale = 1e-2, 1e-3, 1e-4, 1e-5,
+                           majorant step when the full step lengthens the
+                           path (no early exit). The FP64 refinement, the
+                           certificate and the outputs are the same */
 } fpt_opts;
+
+enum { FPT_METHOD_BFGS = 0, FPT_METHOD_NEWTON32 = 1 };
 
 /* Defaults: 64 iterations, 1 fixed-point iteration, no early exit
  * (exit_rtol = 1e-6, stages of 16, 16 and 32 iterations), refinement levels

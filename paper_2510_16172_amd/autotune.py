@@ -7,11 +7,13 @@ the one with the most certified-converged paths per second of that order's
 kernels (BFGS + refinement, timed with the library's HIP-event timers). The
 iteration count trades FP32 BFGS time against FP64 refinement time: paths
 the BFGS leaves further from the minimiser need more Newton steps. Results are
-cached in a JSON file keyed by GPU architecture, order, and a power-of-two
-bucket of the sample size, and applied with fpt_set_launch.
+cached in a JSON file keyed by GPU architecture, first-phase method,
+candidate set, order, and a power-of-two bucket of the sample size, and
+applied with fpt_set_launch.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 
@@ -27,13 +29,22 @@ DEFAULT_CANDIDATES = (
 )
 
 
+# The FP32 Newton variant of the first phase (fpt_opts.method): its step
+# count, with the same quick refinement settings.
+NEWTON32_CANDIDATES = [
+    {"wg_per_cu": 0, "early_exit": 0, "iters": k, "quick_steps": qs, "quick_passes": qp}
+    for k in (4, 6, 8, 10, 12, 16) for (qs, qp) in ((2, 2), (3, 1))]
+
+
 def default_cache_path() -> str:
     base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
     return os.path.join(base, "fpt", "autotune.json")
 
 
-def _key(arch: str, order: int, n: int) -> str:
-    return f"v3/{arch}/order{order}/n2^{max(0, int(np.log2(max(n, 1))))}"
+def _key(arch: str, order: int, n: int, method: int, candidates) -> str:
+    tag = hashlib.sha1(json.dumps(candidates, sort_keys=True).encode()).hexdigest()[:8]
+    return (f"v4/{arch}/m{method}/c{tag}/order{order}/"
+            f"n2^{max(0, int(np.log2(max(n, 1))))}")
 
 
 def tune(solver, batch, opts, candidates=None, sample=1 << 18, repeats=3,
@@ -54,7 +65,7 @@ def tune(solver, batch, opts, candidates=None, sample=1 << 18, repeats=3,
     chosen = {}
     for n in sorted(set(int(v) for v in np.unique(batch.order))):
         idx = np.nonzero(batch.order == n)[0]
-        key = _key(arch, n, len(idx))
+        key = _key(arch, n, len(idx), int(getattr(opts, "method", 0)), candidates)
         if key in cache:
             chosen[n] = cache[key]["cfg"]
             continue

@@ -40,7 +40,7 @@ hipError_t launch_grad_invalid(const GradArgs& A, const int32_t* perm,
 struct fpt_handle {
   int device;
   int num_cu;
-  int occ[5][FPT_NMAX + 1];  // resident workgroups per CU, per phase/order
+  int occ[6][FPT_NMAX + 1];  // resident workgroups per CU, per phase/order
   // optional per-kernel timing
   static constexpr int kRing = 32;
   bool timing = false;
@@ -115,6 +115,7 @@ extern "C" void fpt_default_opts(fpt_opts* o) {
   o->quick_steps = 2;
   o->quick_passes = 2;
   o->concurrent_orders = 0;
+  o->method = FPT_METHOD_BFGS;
 }
 
 // Keeps the caller's current device and switches to the handle's for the
@@ -152,7 +153,7 @@ extern "C" fpt_status fpt_create(int device, fpt_handle** out) {
   fpt_handle* h = new fpt_handle();
   h->device = device;
   h->num_cu = prop.multiProcessorCount;
-  for (int ph = 0; ph < 5; ++ph)
+  for (int ph = 0; ph < 6; ++ph)
     for (int n = 1; n <= FPT_NMAX; ++n) {
       int occ = 0;
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -256,6 +257,8 @@ static fpt_status check_opts(const fpt_opts* o) {
     return fail(FPT_EINVAL, "fpt_solve: quick_steps outside 0..64");
   if (o->quick_passes < 1 || o->quick_passes > 2)
     return fail(FPT_EINVAL, "fpt_solve: quick_passes outside 1..2");
+  if (o->method != FPT_METHOD_BFGS && o->method != FPT_METHOD_NEWTON32)
+    return fail(FPT_EINVAL, "fpt_solve: unknown method");
   if (o->early_exit) {
     if (o->stage_iters[0] < 1)
       return fail(FPT_EINVAL, "fpt_solve: early exit needs stage_iters[0] >= 1");
@@ -508,6 +511,7 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
   A.n_iter = o->iters;
   A.fp_iters = o->fp_iters;
   A.early_exit = o->early_exit ? 1 : 0;
+  A.method = o->method;
   float ed = o->exit_rtol * o->scale;
   A.exit_d2 = ed * ed;
   A.scale = o->scale;
@@ -526,6 +530,8 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     return (int)(g < cap ? g : cap);
   };
   const bool any_ee = uses_early_exit(h, o, pa->n_max);
+  if (any_ee && o->method != FPT_METHOD_BFGS)
+    return fail(FPT_EINVAL, "fpt_solve: early exit is a BFGS schedule");
   const int n_lo = pa->order ? 1 : pa->n_max;  // all buckets, or only n_max
   // The orders are independent: with several orders (and no early-exit
   // states, which are shared) each runs on its own stream with its own path
@@ -571,8 +577,9 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
       if (!ee) {
         // one path per thread over the whole input, or persistent over the
         // bucket (its size is only known on the device)
-        int grid = perm ? persistent(0, n, c.wg_per_cu) : (int)cap;
-        e = fpt::launch_solve(0, n, An, perm, bucket, nullptr, grid, sn);
+        const int ph = An.method == FPT_METHOD_NEWTON32 ? 5 : 0;
+        int grid = perm ? persistent(ph, n, c.wg_per_cu) : (int)cap;
+        e = fpt::launch_solve(ph, n, An, perm, bucket, nullptr, grid, sn);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
       } else {
         int ns = 0;

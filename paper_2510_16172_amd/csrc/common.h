@@ -50,6 +50,26 @@ __device__ __forceinline__ double dot3d(const double* a, const double* b) {
   return fma(a[2], b[2], fma(a[1], b[1], a[0] * b[0]));
 }
 
+// The path algebra of path64.h in either precision: reciprocal (square
+// root) and dot product by type, the floor of a squared segment length, and
+// the relative slack of a length comparison (a few rounding errors of L).
+__device__ __forceinline__ float rsqr(float x) { return rsq32(x); }
+__device__ __forceinline__ double rsqr(double x) { return rsq64(x); }
+__device__ __forceinline__ float rcpr(float x) { return rcp32(x); }
+__device__ __forceinline__ double rcpr(double x) { return rcp64(x); }
+__device__ __forceinline__ float dot3r(const float* a, const float* b) { return dot3(a, b); }
+__device__ __forceinline__ double dot3r(const double* a, const double* b) { return dot3d(a, b); }
+template <class R>
+struct RealTraits;
+template <>
+struct RealTraits<float> {
+  static constexpr float tiny = 1e-30f, rel = 4e-7f;
+};
+template <>
+struct RealTraits<double> {
+  static constexpr double tiny = 1e-300, rel = 1e-15;
+};
+
 // Arguments shared by every launch of one fpt_solve call.
 struct SolveArgs {
   const float* obj;
@@ -67,7 +87,7 @@ struct SolveArgs {
   int64_t N;
   int32_t K, Q, n_max;
   // options
-  int32_t n_iter, fp_iters, early_exit;
+  int32_t n_iter, fp_iters, early_exit, method;
   float exit_d2;  // (exit_rtol * scale)^2
   float scale;
   int32_t n_levels;

@@ -1,5 +1,8 @@
-// FP64 algebra of one path (device side), shared by the refinement of the
-// solver and by the implicit-differentiation backward pass.
+// Algebra of one path (device side): points, smoothed segments, gradient and
+// the block-tridiagonal Newton solve. Written over the geometry's scalar type
+// (GEO::real): FP64 for the refinement of the solver and the
+// implicit-differentiation backward pass, FP32 for the exact-Hessian Newton
+// variant of the first phase.
 //
 // Parametrisation (Sec. III-B, Eq. 3): x_j = b_j + t_j0 a1_j + t_j1 a2_j,
 // with a2 = 0 for an edge (padding). Slot j = 0..n-1 is interaction j+1;
@@ -16,6 +19,7 @@ namespace fpt {
 template <int NO>
 struct Geo64 {
   static constexpr int kOrder = NO;
+  using real = double;
   double tx_[3], rx_[3];
   double b_[NO][3];
   double a_[NO][2][3];  // caller's basis vectors (a[j][1] = 0 for an edge)
@@ -38,6 +42,7 @@ __host__ __device__ constexpr int geo_lds_rows(int NO) { return 6 + 9 * NO; }
 template <int NO>
 struct GeoLds {
   static constexpr int kOrder = NO;
+  using real = double;
   const float* col;  // this lane's column: &lds[threadIdx.x]
   bool edge_[NO];
   __device__ __forceinline__ double tx(int c) const { return (double)col[c * kBlock]; }
@@ -91,9 +96,8 @@ __device__ __forceinline__ void load_geo64(const float* __restrict__ obj,
   }
 }
 
-template <class GEO>
-__device__ __forceinline__ void points64(const GEO& G, const double* t,
-                                         double (*x)[3]) {
+template <class GEO, class R = typename GEO::real>
+__device__ __forceinline__ void points64(const GEO& G, const R* t, R (*x)[3]) {
   constexpr int NO = GEO::kOrder;
 #pragma unroll
   for (int j = 0; j < NO; ++j)
@@ -105,47 +109,46 @@ __device__ __forceinline__ void points64(const GEO& G, const double* t,
 
 // Segments at t: v_i = r_i / l_i and il_i = 1 / l_i with
 // l_i = sqrt(|r_i|^2 + eps^2) (eps = 0: the exact length of Eq. 5).
-template <class GEO>
-__device__ __forceinline__ void segments64(const GEO& G,
-                                           const double* t, double eps2,
-                                           double (*v)[3], double* il) {
+template <class GEO, class R = typename GEO::real>
+__device__ __forceinline__ void segments64(const GEO& G, const R* t, R eps2, R (*v)[3],
+                                           R* il) {
   constexpr int NO = GEO::kOrder;
-  double x[NO][3];
+  R x[NO][3];
   points64(G, t, x);
 #pragma unroll
   for (int i = 0; i <= NO; ++i) {
-    double r[3];
+    R r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       r[c] = ((i == NO) ? G.rx(c) : x[i][c]) - ((i == 0) ? G.tx(c) : x[i - 1][c]);
-    double q = fmax(dot3d(r, r) + eps2, 1e-300);
-    il[i] = rsq64(q);
+    R q = fmax(dot3r(r, r) + eps2, RealTraits<R>::tiny);
+    il[i] = rsqr(q);
 #pragma unroll
     for (int c = 0; c < 3; ++c) v[i][c] = r[c] * il[i];
   }
 }
 
 // Segments of the (smoothed) length at t and the length itself.
-template <int NO>
+template <int NO, class R = double>
 struct Seg64 {
-  double v[NO + 1][3], il[NO + 1], L;
+  R v[NO + 1][3], il[NO + 1], L;
 };
 
-template <class GEO>
-__device__ __forceinline__ void eval64(const GEO& G, const double* t,
-                                       double eps2, Seg64<GEO::kOrder>& s) {
+template <class GEO, class R = typename GEO::real>
+__device__ __forceinline__ void eval64(const GEO& G, const R* t, R eps2,
+                                       Seg64<GEO::kOrder, R>& s) {
   constexpr int NO = GEO::kOrder;
-  double x[NO][3];
+  R x[NO][3];
   points64(G, t, x);
-  s.L = 0.0;
+  s.L = R(0);
 #pragma unroll
   for (int i = 0; i <= NO; ++i) {
-    double r[3];
+    R r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       r[c] = ((i == NO) ? G.rx(c) : x[i][c]) - ((i == 0) ? G.tx(c) : x[i - 1][c]);
-    double q = fmax(dot3d(r, r) + eps2, 1e-300);
-    s.il[i] = rsq64(q);
+    R q = fmax(dot3r(r, r) + eps2, RealTraits<R>::tiny);
+    s.il[i] = rsqr(q);
 #pragma unroll
     for (int c = 0; c < 3; ++c) s.v[i][c] = r[c] * s.il[i];
     s.L += q * s.il[i];
@@ -154,23 +157,22 @@ __device__ __forceinline__ void eval64(const GEO& G, const double* t,
 
 // Gradient of the (smoothed) length: g_j = A_j^T (v_j - v_{j+1}); the padded
 // parameter of an edge gets 0.
-template <class GEO>
-__device__ __forceinline__ void gradient64(const GEO& G,
-                                           const double (*v)[3], double* g) {
+template <class GEO, class R = typename GEO::real>
+__device__ __forceinline__ void gradient64(const GEO& G, const R (*v)[3], R* g) {
   constexpr int NO = GEO::kOrder;
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
-    double du[3];
+    R du[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) du[c] = v[j][c] - v[j + 1][c];
-    double a0[3], a1[3];
+    R a0[3], a1[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       a0[c] = G.a(j, 0, c);
       a1[c] = G.a(j, 1, c);
     }
-    g[2 * j] = G.fixed(j) ? 0.0 : dot3d(a0, du);
-    g[2 * j + 1] = G.edge(j) ? 0.0 : dot3d(a1, du);
+    g[2 * j] = G.fixed(j) ? R(0) : dot3r(a0, du);
+    g[2 * j + 1] = G.edge(j) ? R(0) : dot3r(a1, du);
   }
 }
 
@@ -185,81 +187,79 @@ __device__ __forceinline__ void gradient64(const GEO& G,
 // diagonal is set to 1 and its right-hand side to 0, so its d is 0. A fixed
 // slot has both parameters masked that way.
 // Returns false if a pivot block is not positive definite or d is not finite.
-template <class GEO>
-__device__ __forceinline__ bool hess_solve64(const GEO& G,
-                                             const double (*v)[3],
-                                             const double* il,
-                                             const double* rhs, double* d) {
+template <class GEO, class R = typename GEO::real>
+__device__ __forceinline__ bool hess_solve64(const GEO& G, const R (*v)[3], const R* il,
+                                             const R* rhs, R* d) {
   constexpr int NO = GEO::kOrder;
-  double Sinv[NO][3], E[NO][4], z[NO][2];
-  double pSinv[3] = {0, 0, 0}, pE[4] = {0, 0, 0, 0}, pz[2] = {0, 0};
+  R Sinv[NO][3], E[NO][4], z[NO][2];
+  R pSinv[3] = {0, 0, 0}, pE[4] = {0, 0, 0, 0}, pz[2] = {0, 0};
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
-    double a0[3], a1[3];
+    R a0[3], a1[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       a0[c] = G.a(j, 0, c);
       a1[c] = G.a(j, 1, c);
     }
-    double pin0 = dot3d(a0, v[j]), pin1 = dot3d(a1, v[j]);
-    double pout0 = dot3d(a0, v[j + 1]), pout1 = dot3d(a1, v[j + 1]);
-    double G00 = dot3d(a0, a0), G01 = dot3d(a0, a1), G11 = dot3d(a1, a1);
-    double D00 = (G00 - pin0 * pin0) * il[j] + (G00 - pout0 * pout0) * il[j + 1];
-    double D01 = (G01 - pin0 * pin1) * il[j] + (G01 - pout0 * pout1) * il[j + 1];
-    double D11 = (G11 - pin1 * pin1) * il[j] + (G11 - pout1 * pout1) * il[j + 1];
-    double rhs0 = rhs[2 * j], rhs1 = rhs[2 * j + 1];
+    R pin0 = dot3r(a0, v[j]), pin1 = dot3r(a1, v[j]);
+    R pout0 = dot3r(a0, v[j + 1]), pout1 = dot3r(a1, v[j + 1]);
+    R G00 = dot3r(a0, a0), G01 = dot3r(a0, a1), G11 = dot3r(a1, a1);
+    R D00 = (G00 - pin0 * pin0) * il[j] + (G00 - pout0 * pout0) * il[j + 1];
+    R D01 = (G01 - pin0 * pin1) * il[j] + (G01 - pout0 * pout1) * il[j + 1];
+    R D11 = (G11 - pin1 * pin1) * il[j] + (G11 - pout1 * pout1) * il[j + 1];
+    R rhs0 = rhs[2 * j], rhs1 = rhs[2 * j + 1];
     if (G.edge(j)) {
-      D01 = 0.0;
-      D11 = 1.0;
-      rhs1 = 0.0;
+      D01 = R(0);
+      D11 = R(1);
+      rhs1 = R(0);
     }
     if (G.fixed(j)) {
-      D00 = 1.0;
-      D01 = 0.0;
-      rhs0 = 0.0;
+      D00 = R(1);
+      D01 = R(0);
+      rhs0 = R(0);
     }
     if (j > 0) {
       // W = S_{j-1}^{-1} E_{j-1}; E rows: parameters of slot j-1
-      double W00 = pSinv[0] * pE[0] + pSinv[1] * pE[2];
-      double W01 = pSinv[0] * pE[1] + pSinv[1] * pE[3];
-      double W10 = pSinv[1] * pE[0] + pSinv[2] * pE[2];
-      double W11 = pSinv[1] * pE[1] + pSinv[2] * pE[3];
+      R W00 = pSinv[0] * pE[0] + pSinv[1] * pE[2];
+      R W01 = pSinv[0] * pE[1] + pSinv[1] * pE[3];
+      R W10 = pSinv[1] * pE[0] + pSinv[2] * pE[2];
+      R W11 = pSinv[1] * pE[1] + pSinv[2] * pE[3];
       D00 -= pE[0] * W00 + pE[2] * W10;
       D01 -= pE[0] * W01 + pE[2] * W11;
       D11 -= pE[1] * W01 + pE[3] * W11;
-      double w0 = pSinv[0] * pz[0] + pSinv[1] * pz[1];
-      double w1 = pSinv[1] * pz[0] + pSinv[2] * pz[1];
+      R w0 = pSinv[0] * pz[0] + pSinv[1] * pz[1];
+      R w1 = pSinv[1] * pz[0] + pSinv[2] * pz[1];
       rhs0 -= pE[0] * w0 + pE[2] * w1;
       rhs1 -= pE[1] * w0 + pE[3] * w1;
     }
-    double det = D00 * D11 - D01 * D01;
-    ok = ok && (det > 0.0) && (D00 > 0.0) && isfinite(det);
-    double idet = rcp64(det);
+    R det = D00 * D11 - D01 * D01;
+    ok = ok && (det > R(0)) && (D00 > R(0)) && isfinite(det);
+    R idet = rcpr(det);
     Sinv[j][0] = D11 * idet;
     Sinv[j][1] = -D01 * idet;
     Sinv[j][2] = D00 * idet;
     z[j][0] = rhs0;
     z[j][1] = rhs1;
     if (j + 1 < NO) {
-      double b0[3], b1[3];
+      R b0[3], b1[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         b0[c] = G.a(j + 1, 0, c);
         b1[c] = G.a(j + 1, 1, c);
       }
-      double qn0 = dot3d(b0, v[j + 1]), qn1 = dot3d(b1, v[j + 1]);
-      double il1 = il[j + 1];
-      E[j][0] = -(dot3d(a0, b0) - pout0 * qn0) * il1;
-      E[j][1] = -(dot3d(a0, b1) - pout0 * qn1) * il1;
-      E[j][2] = -(dot3d(a1, b0) - pout1 * qn0) * il1;
-      E[j][3] = -(dot3d(a1, b1) - pout1 * qn1) * il1;
-      if (G.edge(j)) E[j][2] = E[j][3] = 0.0;
-      if (G.edge(j + 1)) E[j][1] = E[j][3] = 0.0;
-      if (G.fixed(j)) E[j][0] = E[j][1] = 0.0;
-      if (G.fixed(j + 1)) E[j][0] = E[j][2] = 0.0;
+      R qn0 = dot3r(b0, v[j + 1]), qn1 = dot3r(b1, v[j + 1]);
+      R il1 = il[j + 1];
+      E[j][0] = -(dot3r(a0, b0) - pout0 * qn0) * il1;
+      E[j][1] = -(dot3r(a0, b1) - pout0 * qn1) * il1;
+      E[j][2] = -(dot3r(a1, b0) - pout1 * qn0) * il1;
+      E[j][3] = -(dot3r(a1, b1) - pout1 * qn1) * il1;
+      if (G.edge(j)) E[j][2] = E[j][3] = R(0);
+      if (G.edge(j + 1)) E[j][1] = E[j][3] = R(0);
+      if (G.fixed(j)) E[j][0] = E[j][1] = R(0);
+      if (G.fixed(j + 1)) E[j][0] = E[j][2] = R(0);
     } else {
-      E[j][0] = E[j][1] = E[j][2] = E[j][3] = 0.0;
+      E[j][0] = E[j][1] = E[j][2] = E[j][3] = R(0);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) pSinv[k] = Sinv[j][k];
@@ -268,15 +268,15 @@ __device__ __forceinline__ bool hess_solve64(const GEO& G,
     pz[0] = z[j][0];
     pz[1] = z[j][1];
   }
-  double n0 = 0.0, n1 = 0.0;
+  R n0 = R(0), n1 = R(0);
 #pragma unroll
   for (int j = NO - 1; j >= 0; --j) {
-    double c0 = z[j][0] - (E[j][0] * n0 + E[j][1] * n1);
-    double c1 = z[j][1] - (E[j][2] * n0 + E[j][3] * n1);
-    double d0 = Sinv[j][0] * c0 + Sinv[j][1] * c1;
-    double d1 = Sinv[j][1] * c0 + Sinv[j][2] * c1;
-    if (G.edge(j)) d1 = 0.0;
-    if (G.fixed(j)) d0 = 0.0;
+    R c0 = z[j][0] - (E[j][0] * n0 + E[j][1] * n1);
+    R c1 = z[j][1] - (E[j][2] * n0 + E[j][3] * n1);
+    R d0 = Sinv[j][0] * c0 + Sinv[j][1] * c1;
+    R d1 = Sinv[j][1] * c0 + Sinv[j][2] * c1;
+    if (G.edge(j)) d1 = R(0);
+    if (G.fixed(j)) d0 = R(0);
     d[2 * j] = d0;
     d[2 * j + 1] = d1;
     n0 = d0;

@@ -154,18 +154,17 @@ __device__ __forceinline__ void load_geo_lds(const SolveArgs& A, int64_t p,
   D.col = col;
 }
 
-template <class GEO>
-__device__ __forceinline__ double max_disp64(const GEO& G,
-                                             const double* d) {
+template <class GEO, class R = typename GEO::real>
+__device__ __forceinline__ R max_disp64(const GEO& G, const R* d) {
   constexpr int NO = GEO::kOrder;
-  double m = 0.0;
+  R m = R(0);
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
-    double w[3];
+    R w[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       w[c] = d[2 * j] * G.a(j, 0, c) + d[2 * j + 1] * G.a(j, 1, c);
-    m = fmax(m, dot3d(w, w));
+    m = fmax(m, dot3r(w, w));
   }
   return m;  // squared
 }
@@ -187,56 +186,54 @@ struct NewtonTrack {
   uint32_t n_eval, n_solve;
 };
 
-template <class GEO>
-__device__ __forceinline__ void newton_run64(const GEO& G, double* t,
-                                             double eps2, int nsteps,
-                                             double cert2, bool majorant,
-                                             NewtonTrack& k) {
+template <class GEO, class R = typename GEO::real>
+__device__ __forceinline__ void newton_run64(const GEO& G, R* t, R eps2, int nsteps,
+                                             R cert2, bool majorant, NewtonTrack& k) {
   constexpr int NO = GEO::kOrder;
-  Seg64<NO> cur;
+  Seg64<NO, R> cur;
   eval64(G, t, eps2, cur);
   ++k.n_eval;
   for (int st = 0; st < nsteps; ++st) {
     geo_fence();
-    double g[2 * NO], d[2 * NO];
+    R g[2 * NO], d[2 * NO];
     gradient64(G, cur.v, g);
 #pragma unroll
     for (int q = 0; q < 2 * NO; ++q) g[q] = -g[q];
-    const double bound = cur.L + 1e-15 * fabs(cur.L);
+    const R bound = cur.L + RealTraits<R>::rel * fabs(cur.L);
     const bool ok = hess_solve64(G, cur.v, cur.il, g, d);
     ++k.n_solve;
     k.prev_small = k.last_small;
     k.last_small = false;
     if (!ok) continue;
-    const double d2 = max_disp64(G, d);
+    const R d2 = max_disp64(G, d);
     // majorant step: a = -sum D_i.v_i / sum |D_i|^2 il_i (v_i = r_i il_i),
     // D_i = A_i d_i - A_{i-1} d_{i-1} the change of segment i along d
-    double num = 0.0, den = 0.0;
+    R num = R(0), den = R(0);
     {
-      double qp[3] = {0.0, 0.0, 0.0};
+      R qp[3] = {R(0), R(0), R(0)};
 #pragma unroll
       for (int i = 0; i <= NO; ++i) {
-        double qn[3], D[3];
+        R qn[3], D[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          qn[c] = (i == NO) ? 0.0 : fma(d[2 * i + 1], G.a(i, 1, c), d[2 * i] * G.a(i, 0, c));
+          qn[c] = (i == NO) ? R(0) : fma(d[2 * i + 1], G.a(i, 1, c), d[2 * i] * G.a(i, 0, c));
           D[c] = qn[c] - qp[c];
           qp[c] = qn[c];
         }
-        num += dot3d(D, cur.v[i]);
-        den = fma(dot3d(D, D), cur.il[i], den);
+        num += dot3r(D, cur.v[i]);
+        den = fma(dot3r(D, D), cur.il[i], den);
       }
     }
-    const double amm = (den > 0.0) ? -num * rcp64(den) : 0.0;
-    double s = 1.0;
+    const R amm = (den > R(0)) ? -num * rcpr(den) : R(0);
+    R s = R(1);
     bool acc = false;
     const int trials = majorant ? 2 : 7;
     for (int h = 0; h < trials; ++h) {
       geo_fence();
-      double tn[2 * NO];
+      R tn[2 * NO];
 #pragma unroll
       for (int q = 0; q < 2 * NO; ++q) tn[q] = fma(s, d[q], t[q]);
-      Seg64<NO> nx;
+      Seg64<NO, R> nx;
       eval64(G, tn, eps2, nx);
       ++k.n_eval;
       if (nx.L <= bound) {
@@ -249,10 +246,10 @@ __device__ __forceinline__ void newton_run64(const GEO& G, double* t,
       if (majorant) {
         // (the majorant step cannot lengthen the path in exact arithmetic,
         // whatever its size)
-        if (!(amm > 0.0) || !isfinite(amm) || amm == 1.0) break;
+        if (!(amm > R(0)) || !isfinite(amm) || amm == R(1)) break;
         s = amm;
       } else {
-        s *= 0.25;
+        s *= R(0.25);
       }
     }
     // (the segments at t are not kept across the trials: recomputed here in
@@ -261,7 +258,7 @@ __device__ __forceinline__ void newton_run64(const GEO& G, double* t,
       eval64(G, t, eps2, cur);
       ++k.n_eval;
     }
-    k.last_small = acc && (s == 1.0) && (d2 <= cert2);
+    k.last_small = acc && (s == R(1)) && (d2 <= cert2);
     k.refined = k.refined || acc;
   }
 }
@@ -1032,6 +1029,72 @@ __global__ __launch_bounds__(kBlock) void bfgs_kernel(
   }
 }
 
+// ---------------------------------------- exact-Hessian Newton, FP32 ----
+// A solver variant for the first phase: damped Newton in FP32 on the exact
+// Hessian of the smoothed length (the block-tridiagonal solve of path64.h
+// over the path's FP32 registers), from the same start as the BFGS
+// (unit-length basis, T = 0 or t_init). `n_iter` steps are split evenly over
+// four smoothing levels, the remainder going to the last; a step that would
+// lengthen the path is replaced by the majorant step along the Newton
+// direction. The FP64 refinement that follows is unchanged.
+template <int NO>
+struct Geo32View {
+  static constexpr int kOrder = NO;
+  using real = float;
+  const Geo32<NO>& g;
+  bool edge_[NO];
+  __device__ __forceinline__ float tx(int c) const { return g.tx[c]; }
+  __device__ __forceinline__ float rx(int c) const { return g.rx[c]; }
+  __device__ __forceinline__ float b(int j, int c) const { return g.b[j][c]; }
+  __device__ __forceinline__ float a(int j, int k, int c) const { return g.a[j][k][c]; }
+  __device__ __forceinline__ bool edge(int j) const { return edge_[j]; }
+  __device__ __forceinline__ bool fixed(int) const { return false; }
+};
+
+constexpr int kNewton32Levels = 4;
+__device__ __forceinline__ float newton32_eps(int lv) {
+  return lv == 0 ? 1e-2f : lv == 1 ? 1e-3f : lv == 2 ? 1e-4f : 1e-5f;
+}
+
+template <int NO>
+__global__ __launch_bounds__(kBlock) void newton32_kernel(
+    SolveArgs A, const int32_t* __restrict__ perm,
+    const int64_t* __restrict__ bucket) {
+  int64_t begin = 0, count = A.N;
+  if (bucket) {
+    begin = bucket[NO - 1];
+    count = bucket[NO] - begin;
+  }
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
+       idx += stride) {
+    const int64_t p = perm ? (int64_t)perm[begin + idx] : idx;
+    Geo32<NO> G;
+    float t0[NO][2];
+    const bool valid = load_path32<NO>(A, p, G, t0);
+    Geo32View<NO> V{G, {}};
+    float T[2 * NO];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      V.edge_[j] = G.a[j][1][0] == 0.f && G.a[j][1][1] == 0.f && G.a[j][1][2] == 0.f;
+      T[2 * j] = t0[j][0];
+      T[2 * j + 1] = V.edge_[j] ? 0.f : t0[j][1];
+    }
+    NewtonTrack k{false, false, false, 0, 0};
+    const int per = A.n_iter / kNewton32Levels;
+    for (int lv = 0; lv < kNewton32Levels; ++lv) {
+      const int steps = per + (lv == kNewton32Levels - 1 ? A.n_iter - kNewton32Levels * per : 0);
+      if (steps == 0) continue;
+      const float eps = newton32_eps(lv) * A.scale;
+      newton_run64(V, T, eps * eps, steps, 0.f, true, k);
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * NO; ++q) A.t[(int64_t)q * A.N + p] = isfinite(T[q]) ? T[q] : 0.f;
+    A.iters[p] = (uint16_t)(A.n_iter > 65535 ? 65535 : A.n_iter);
+    A.status[p] = valid ? 0 : FPT_ST_INVALID;
+  }
+}
+
 // Phase 1 with early exit, in stages. A stage runs every path of its input
 // for at most `iters` more iterations, all lanes of a wavefront in lockstep.
 // A path leaves once two consecutive steps moved no point by more than
@@ -1488,6 +1551,9 @@ static hipError_t launch_phase(int phase, const SolveArgs& A,
   else if (phase == 2)
     hipLaunchKernelGGL(bfgs_stage_kernel<NO>, dim3(grid), dim3(kBlock), 0,
                        st, A, perm, bucket, *stage);
+  else if (phase == 5)
+    hipLaunchKernelGGL(newton32_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A, perm,
+                       bucket);
   else
     hipLaunchKernelGGL(merge_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
                        *stage);
@@ -1495,7 +1561,8 @@ static hipError_t launch_phase(int phase, const SolveArgs& A,
 }
 
 // phase 0: bfgs_kernel<order>, 1: refine_kernel<order> (the quick variant
-// when stage->out_list is set),
+// when stage->out_list is set; phase 4 names that variant for occupancy
+// queries), 5: newton32_kernel<order> (the FP32 Newton variant of phase 0),
 // 2: bfgs_stage_kernel<order> (one early-exit stage, `stage` describes it),
 // 3: merge_kernel<order> (between the refinement passes)
 hipError_t launch_solve(int phase, int order, const SolveArgs& A,
@@ -1530,7 +1597,8 @@ static const void* phase_ptr(int phase) {
          : phase == 1 ? (const void*)refine_kernel<NO, false>
          : phase == 2 ? (const void*)bfgs_stage_kernel<NO>
          : phase == 3 ? (const void*)merge_kernel<NO>
-                      : (const void*)refine_kernel<NO, true>;
+         : phase == 4 ? (const void*)refine_kernel<NO, true>
+                      : (const void*)newton32_kernel<NO>;
 }
 
 const void* solve_kernel_ptr(int phase, int order) {

@@ -44,7 +44,7 @@ class _Opts(ctypes.Structure):
                 ("cert_rtol", ctypes.c_float),
                 ("stage_iters", ctypes.c_int32 * 4),
                 ("quick_steps", ctypes.c_int32), ("quick_passes", ctypes.c_int32),
-                ("concurrent_orders", ctypes.c_int32)]
+                ("concurrent_orders", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class _LaunchCfg(ctypes.Structure):
@@ -77,6 +77,7 @@ T_BUCKET, T_BFGS, T_REFINE, T_GRAD, T_REDUCE, T_MLP, T_VALIDATE, TIMERS = (
     0, 1, 7, 13, 14, 15, 16, 17)
 VALID_EXTENT, VALID_SPECULAR, VALID_VISIBLE = 1, 2, 4
 VALIDATE_ALL, VALIDATE_LAZY = 0, 1
+METHOD_BFGS, METHOD_NEWTON32 = 0, 1
 MLP_PARAMS = 172864  # padded parameter count: state[0:MLP_PARAMS] = weights
 
 _lib = None
@@ -173,6 +174,7 @@ class Opts:
     quick_steps: int = 2
     quick_passes: int = 2
     concurrent_orders: bool = False
+    method: int = 0  # METHOD_BFGS (the paper's) or METHOD_NEWTON32 (variant)
 
     def to_c(self) -> _Opts:
         o = _Opts()
@@ -198,6 +200,7 @@ class Opts:
         o.quick_steps = int(self.quick_steps)
         o.quick_passes = int(self.quick_passes)
         o.concurrent_orders = 1 if self.concurrent_orders else 0
+        o.method = int(self.method)
         return o
 
 
