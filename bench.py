@@ -70,6 +70,12 @@ def refine_eval_flops(n: int) -> int:
     return 12 * n + 24 * (n + 1)
 
 
+def refine_trial_flops(n: int) -> int:
+    """FP64 flops of one trial length of a Newton step (length_at): as
+    refine_eval_flops without the unit vectors, 21 per segment."""
+    return 12 * n + 21 * (n + 1)
+
+
 def refine_solve_flops(n: int) -> int:
     """FP64 flops of one Newton step of refine_kernel<n> besides the path
     evaluations: gradient 13n; block-tridiagonal Hessian assembly and
@@ -531,10 +537,12 @@ def main():
             + int(o2.sum()) * bfgs_init_flops(2))
     t_b = kt[fpt.T_BFGS + 1] * 1e-3
     kname_b = "bfgs_stage_kernel<2>" if ee2 else "bfgs_kernel<2>"
-    n_eval, n_solve, m_eval, m_solve = (v / args.steps for v in work[2])
+    n_eval, n_trial, n_solve, m_eval, m_trial, m_solve = (v / args.steps for v in work[2])
     # refinement passes at order 2, reduced paths of the collapse step at 1
-    fl_r = (n_eval * refine_eval_flops(2) + n_solve * refine_solve_flops(2)
-            + m_eval * refine_eval_flops(1) + m_solve * refine_solve_flops(1)
+    fl_r = (n_eval * refine_eval_flops(2) + n_trial * refine_trial_flops(2)
+            + n_solve * refine_solve_flops(2)
+            + m_eval * refine_eval_flops(1) + m_trial * refine_trial_flops(1)
+            + m_solve * refine_solve_flops(1)
             + int(o2.sum()) * refine_final_flops(2))
     t_r = kt[fpt.T_REFINE + 1] * 1e-3
     roof_b = {
@@ -551,8 +559,10 @@ def main():
         "unit": "TFLOP/s", "frac": fl_r / t_r / PEAK_FP64,
         "flops_per_launch": fl_r, "ms": t_r * 1e3,
         "evaluations_per_path": n_eval / int(o2.sum()),
+        "trial_lengths_per_path": n_trial / int(o2.sum()),
         "newton_solves_per_path": n_solve / int(o2.sum()),
         "collapse_step_evaluations_per_path": m_eval / int(o2.sum()),
+        "collapse_step_trial_lengths_per_path": m_trial / int(o2.sum()),
         "collapse_step_solves_per_path": m_solve / int(o2.sum()),
         "traffic": read_traffic("refine_kernel_2", workload),
     }

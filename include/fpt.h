@@ -326,14 +326,16 @@ fpt_status fpt_kernel_times(fpt_handle* h, float* ms);
 
 /* Work done by the FP64 refinement while timing is enabled, for the
  * algorithmic operation count of its kernels: for order n = 1..6,
- * counts[4(n-1)] = evaluations of the (smoothed) path (points, segment
- * lengths, unit vectors, total length) and counts[4(n-1)+1] = Newton solves
- * (gradient and block-tridiagonal Hessian solve) of the two refinement
- * passes; counts[4(n-1)+2], counts[4(n-1)+3] = the same for the reduced
- * paths of order n-1 solved by the collapse (merge) step. Summed over the
- * launches since the previous read; the counters are then cleared.
+ *   counts[6(n-1)]     evaluations of the (smoothed) path: points, segment
+ *                      lengths and unit vectors, total length;
+ *   counts[6(n-1)+1]   trial lengths of a Newton step (points, segment
+ *                      lengths, total length: no unit vectors);
+ *   counts[6(n-1)+2]   Newton solves (gradient, block-tridiagonal solve);
+ * of the refinement passes, and counts[6(n-1)+3 .. 6(n-1)+5] the same for
+ * the reduced paths of order n-1 solved by the collapse (merge) step. Summed
+ * over the launches since the previous read; the counters are then cleared.
  * Synchronises the device. All zero if timing was never enabled. */
-fpt_status fpt_work_counts(fpt_handle* h, uint64_t counts[4 * FPT_NMAX]);
+fpt_status fpt_work_counts(fpt_handle* h, uint64_t counts[6 * FPT_NMAX]);
 
 /* Learned initialiser (a better initial candidate, which Sec. V names as
  * future work): an MLP 66 -> 256 -> 256 -> 256 -> 8 with ReLU that maps the

@@ -393,7 +393,7 @@ extern "C" fpt_status fpt_set_timing(fpt_handle* h, int enable) {
         }
   }
   if (enable && !h->work) {
-    const size_t bytes = 4 * FPT_NMAX * fpt::kWorkSlots * sizeof(unsigned long long);
+    const size_t bytes = 6 * FPT_NMAX * fpt::kWorkSlots * sizeof(unsigned long long);
     hipError_t e = hipMalloc(&h->work, bytes);
     if (e != hipSuccess) return hip_fail(e, "fpt_set_timing: hipMalloc");
     e = hipMemset(h->work, 0, bytes);
@@ -407,16 +407,16 @@ extern "C" fpt_status fpt_set_timing(fpt_handle* h, int enable) {
 extern "C" fpt_status fpt_work_counts(fpt_handle* h, uint64_t* counts) {
   if (!h || !counts) return fail(FPT_EINVAL, "fpt_work_counts: NULL argument");
   DeviceGuard g(h->device);
-  for (int i = 0; i < 4 * FPT_NMAX; ++i) counts[i] = 0;
+  for (int i = 0; i < 6 * FPT_NMAX; ++i) counts[i] = 0;
   if (!h->work) return FPT_OK;
-  const int nw = 4 * FPT_NMAX * fpt::kWorkSlots;
+  const int nw = 6 * FPT_NMAX * fpt::kWorkSlots;
   std::vector<uint64_t> slots(nw);
   const size_t bytes = nw * sizeof(uint64_t);
   hipError_t e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(slots.data(), h->work, bytes, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemset(h->work, 0, bytes);
   if (e != hipSuccess) return hip_fail(e, "fpt_work_counts");
-  for (int i = 0; i < 4 * FPT_NMAX; ++i)
+  for (int i = 0; i < 6 * FPT_NMAX; ++i)
     for (int s = 0; s < fpt::kWorkSlots; ++s) counts[i] += slots[i * fpt::kWorkSlots + s];
   return FPT_OK;
 }
@@ -571,7 +571,7 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     if (c.use_override && c.iters > 0) An.n_iter = c.iters;
     if (c.use_override && c.quick_steps > 0 && A.quick_steps > 0) An.quick_steps = c.quick_steps;
     const int qpasses = (c.use_override && c.quick_passes > 0) ? c.quick_passes : o->quick_passes;
-    An.work = (h->timing && h->work) ? h->work + 4 * fpt::kWorkSlots * (n - 1) : nullptr;
+    An.work = (h->timing && h->work) ? h->work + 6 * fpt::kWorkSlots * (n - 1) : nullptr;
     {
       SlotTimer tm(h, FPT_T_BFGS + n - 1, sn);
       if (!ee) {

@@ -177,14 +177,37 @@ __device__ __forceinline__ R max_disp64(const GEO& G, const R* d) {
 // tried: one evaluation, where near a collapsed minimiser a backtracking
 // search from the (overshooting) Newton step takes many; with majorant =
 // false the step is backtracked by factors of 4 (up to 6 times), which
-// makes more progress per step on such paths. The segments of an accepted
-// trial are those of the next step. prev_small / last_small track whether
+// makes more progress per step on such paths. From two slots on a trial
+// evaluates the length only and the segments of the next step are evaluated
+// at the point reached; with one slot the accepted trial's segments are kept. prev_small / last_small track whether
 // the last two steps were taken in full and moved no point by more than
 // sqrt(cert2).
 struct NewtonTrack {
   bool prev_small, last_small, refined;
-  uint32_t n_eval, n_solve;
+  uint32_t n_eval, n_trial, n_solve;  // segment evaluations, trial lengths, solves
 };
+
+// The (smoothed) length alone at t: a trial of the step. Same arithmetic as
+// eval64's length, so an accepted trial and the segments evaluated after it
+// agree bit for bit; keeping only the length through the trials keeps one
+// set of segments live instead of two (fewer registers, more waves).
+template <class GEO, class R = typename GEO::real>
+__device__ __forceinline__ R length_at(const GEO& G, const R* t, R eps2) {
+  constexpr int NO = GEO::kOrder;
+  R x[NO][3];
+  points64(G, t, x);
+  R L = R(0);
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+    R r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      r[c] = ((i == NO) ? G.rx(c) : x[i][c]) - ((i == 0) ? G.tx(c) : x[i - 1][c]);
+    R q = fmax(dot3r(r, r) + eps2, RealTraits<R>::tiny);
+    L += q * rsqr(q);
+  }
+  return L;
+}
 
 template <class GEO, class R = typename GEO::real>
 __device__ __forceinline__ void newton_run64(const GEO& G, R* t, R eps2, int nsteps,
@@ -233,15 +256,27 @@ __device__ __forceinline__ void newton_run64(const GEO& G, R* t, R eps2, int nst
       R tn[2 * NO];
 #pragma unroll
       for (int q = 0; q < 2 * NO; ++q) tn[q] = fma(s, d[q], t[q]);
-      Seg64<NO, R> nx;
-      eval64(G, tn, eps2, nx);
-      ++k.n_eval;
-      if (nx.L <= bound) {
+      if constexpr (NO <= 1) {
+        // (one slot: registers to spare, the trial keeps its segments)
+        Seg64<NO, R> nx;
+        eval64(G, tn, eps2, nx);
+        ++k.n_eval;
+        if (nx.L <= bound) {
 #pragma unroll
-        for (int q = 0; q < 2 * NO; ++q) t[q] = tn[q];
-        cur = nx;
-        acc = true;
-        break;
+          for (int q = 0; q < 2 * NO; ++q) t[q] = tn[q];
+          cur = nx;
+          acc = true;
+          break;
+        }
+      } else {
+        const R Ln = length_at(G, tn, eps2);
+        ++k.n_trial;
+        if (Ln <= bound) {
+#pragma unroll
+          for (int q = 0; q < 2 * NO; ++q) t[q] = tn[q];
+          acc = true;
+          break;
+        }
       }
       if (majorant) {
         // (the majorant step cannot lengthen the path in exact arithmetic,
@@ -252,9 +287,8 @@ __device__ __forceinline__ void newton_run64(const GEO& G, R* t, R eps2, int nst
         s *= R(0.25);
       }
     }
-    // (the segments at t are not kept across the trials: recomputed here in
-    // the rare case that every trial failed)
-    if (!acc) {
+    if (NO > 1 || !acc) {
+      geo_fence();
       eval64(G, t, eps2, cur);
       ++k.n_eval;
     }
@@ -296,10 +330,10 @@ __device__ __forceinline__ bool nonsmooth_ok64(const GEO& G,
 template <class GEO>
 __device__ __forceinline__ RefineOut refine64(const GEO& G, double* t,
                                               const SolveArgs& A, bool quick,
-                                              uint32_t& n_eval, uint32_t& n_solve) {
+                                              uint32_t (&work)[3]) {
   constexpr int NO = GEO::kOrder;
   const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
-  NewtonTrack k{false, false, false, 0, 0};
+  NewtonTrack k{false, false, false, 0, 0, 0};
   const int lv0 = quick ? A.n_levels - 1 : 0;
   for (int lv = lv0; lv < A.n_levels; ++lv) {
     double eps = (double)A.level_eps[lv] * (double)A.scale;
@@ -308,8 +342,9 @@ __device__ __forceinline__ RefineOut refine64(const GEO& G, double* t,
     newton_run64(G, t, eps * eps, quick ? A.quick_steps : A.level_steps[lv],
                      cert2, quick, k);
   }
-  n_eval += k.n_eval;
-  n_solve += k.n_solve;
+  work[0] += k.n_eval;
+  work[1] += k.n_trial;
+  work[2] += k.n_solve;
   RefineOut o{false, k.refined, true};
   // One small full step is not enough: along a nearly flat valley of the
   // length a Newton step taken from well outside its quadratic region can be
@@ -568,8 +603,7 @@ __device__ __forceinline__ void pair64(const GEO& G, int a,
 
 template <class GEO>
 __device__ __forceinline__ bool merge64(const GEO& G, double* t,
-                                        const SolveArgs& A, uint32_t& n_eval,
-                                        uint32_t& n_solve) {
+                                        const SolveArgs& A, uint32_t (&work)[3]) {
   constexpr int NO = GEO::kOrder;
   if constexpr (NO < 2) {
     return false;
@@ -640,10 +674,11 @@ __device__ __forceinline__ bool merge64(const GEO& G, double* t,
     }
     const double eps = (double)A.level_eps[A.n_levels - 1] * S;
     const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
-    NewtonTrack k{false, false, false, 0, 0};
+    NewtonTrack k{false, false, false, 0, 0, 0};
     newton_run64(R, tr, eps * eps, 8, cert2, false, k);
-    n_eval += k.n_eval;
-    n_solve += k.n_solve;
+    work[0] += k.n_eval;
+    work[1] += k.n_trial;
+    work[2] += k.n_solve;
     if (!(k.prev_small && k.last_small)) return false;
     if (!nonsmooth_ok64(R, tr, eps, S)) return false;
     // subgradient of the collapsed segment: least-norm w with
@@ -655,7 +690,7 @@ __device__ __forceinline__ bool merge64(const GEO& G, double* t,
     {
       Seg64<NO - 1> sg;
       eval64(R, tr, 0.0, sg);
-      ++n_eval;
+      ++work[0];
       double xr[NO - 1][3];
       points64(R, tr, xr);
 #pragma unroll
@@ -1080,7 +1115,7 @@ __global__ __launch_bounds__(kBlock) void newton32_kernel(
       T[2 * j] = t0[j][0];
       T[2 * j + 1] = V.edge_[j] ? 0.f : t0[j][1];
     }
-    NewtonTrack k{false, false, false, 0, 0};
+    NewtonTrack k{false, false, false, 0, 0, 0};
     const int per = A.n_iter / kNewton32Levels;
     for (int lv = 0; lv < kNewton32Levels; ++lv) {
       const int steps = per + (lv == kNewton32Levels - 1 ? A.n_iter - kNewton32Levels * per : 0);
@@ -1212,6 +1247,23 @@ __global__ __launch_bounds__(kBlock) void bfgs_stage_kernel(
   }
 }
 
+// Work counters of a wave (segment evaluations, trial lengths, Newton
+// solves) into counters [3][kWorkSlots]: wave sums, one atomic per counter
+// per wave, spread over kWorkSlots slots by workgroup.
+__device__ __forceinline__ void add_work(unsigned long long* w, uint32_t (&work)[3],
+                                         int lane) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) work[q] += __shfl_xor(work[q], off);
+  if (lane == 0) {
+    const int slot = blockIdx.x % kWorkSlots;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      atomicAdd(w + q * kWorkSlots + slot, (unsigned long long)work[q]);
+  }
+}
+
 // Phase 2: FP64 refinement of the parameters left by bfgs_kernel in A.t
 // (unit-vector coordinates), certificate, and the final outputs.
 // With quick_steps > 0 the refinement runs in two passes: the first takes
@@ -1249,7 +1301,7 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  uint32_t n_eval = 0, n_solve = 0;
+  uint32_t work[3] = {0, 0, 0};
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
        idx += stride) {
     int64_t p;
@@ -1275,7 +1327,7 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
       td[2 * j] = (double)t0 * (double)inv[j][0];
       td[2 * j + 1] = D.edge(j) ? 0.0 : (double)t1 * (double)inv[j][1];
     }
-    RefineOut ro = refine64(D, td, A, quick, n_eval, n_solve);
+    RefineOut ro = refine64(D, td, A, quick, work);
     // first pass: defer the paths it does not certify
     const bool defer = quick && valid && !ro.certified;
     const unsigned long long more = __ballot(defer);
@@ -1303,19 +1355,7 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
     }
     write_path64(A, D, td, p, valid, ro.certified, ro.refined);
   }
-  if (A.work) {
-    // wave sums, one atomic per wave
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      n_eval += __shfl_xor(n_eval, off);
-      n_solve += __shfl_xor(n_solve, off);
-    }
-    if (lane == 0) {
-      const int slot = blockIdx.x % kWorkSlots;
-      atomicAdd(A.work + slot, (unsigned long long)n_eval);
-      atomicAdd(A.work + kWorkSlots + slot, (unsigned long long)n_solve);
-    }
-  }
+  if (A.work) add_work(A.work, work, lane);
 }
 
 // Between the two refinement passes: the paths the quick pass did not
@@ -1339,7 +1379,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  uint32_t n_eval = 0, n_solve = 0;
+  uint32_t work[3] = {0, 0, 0};
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
        idx += stride) {
     int lo = 0, hi = kRegions;
@@ -1359,10 +1399,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St
       td[2 * j] = (double)t0 * (double)inv[j][0];
       td[2 * j + 1] = D.edge(j) ? 0.0 : (double)t1 * (double)inv[j][1];
     }
-    uint32_t me = 0, ms = 0;
-    const bool ok = merge64(D, td, A, me, ms);
-    n_eval += me;
-    n_solve += ms;
+    const bool ok = merge64(D, td, A, work);
     const unsigned long long more = __ballot(!ok);
     if (more) {
       const int region = (int)((idx >> 6) % kRegions);
@@ -1377,18 +1414,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St
     }
     if (ok) write_path64(A, D, td, p, true, true, true, true);
   }
-  if (A.work) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      n_eval += __shfl_xor(n_eval, off);
-      n_solve += __shfl_xor(n_solve, off);
-    }
-    if (lane == 0) {
-      const int slot = blockIdx.x % kWorkSlots;
-      atomicAdd(A.work + 2 * kWorkSlots + slot, (unsigned long long)n_eval);
-      atomicAdd(A.work + 3 * kWorkSlots + slot, (unsigned long long)n_solve);
-    }
-  }
+  if (A.work) add_work(A.work + 3 * kWorkSlots, work, lane);
 }
 
 // ------------------------------------------------------ order bucketing ---

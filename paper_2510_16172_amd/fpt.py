@@ -355,12 +355,13 @@ class Solver:
         return out
 
     def work_counts(self):
-        """{order: (path evaluations, Newton solves, reduced-path evaluations,
-        reduced-path Newton solves)} of the FP64 refinement and collapse step
-        since the previous read (counted while timing is enabled)."""
-        c = (ctypes.c_uint64 * 24)()
+        """{order: (path evaluations, trial lengths, Newton solves, reduced-path
+        evaluations, reduced-path trial lengths, reduced-path Newton solves)}
+        of the FP64 refinement and collapse step since the previous read
+        (counted while timing is enabled)."""
+        c = (ctypes.c_uint64 * 36)()
         _check(load_library().fpt_work_counts(self._h, c), "fpt_work_counts")
-        return {n: tuple(int(c[4 * (n - 1) + k]) for k in range(4)) for n in range(1, 7)}
+        return {n: tuple(int(c[6 * (n - 1) + k]) for k in range(6)) for n in range(1, 7)}
 
     def set_launch(self, order: int, cfg: dict | None):
         """Per-order launch configuration (see fpt_launch_cfg); None resets."""

@@ -319,17 +319,26 @@ def test_refine_work_counts(solver):
     total_levels = sum(opts.level_steps)
     for n in (1, 2, 3):
         cnt = int((b.order == n).sum())
-        ev, so, mev, mso = wc[n]
+        ev, tr, so, mev, mtr, mso = wc[n]
         assert so >= opts.quick_steps * cnt
         assert so <= (opts.quick_passes * opts.quick_steps + total_levels) * cnt
-        assert ev >= cnt + so // 2
+        # one evaluation at the start of each Newton run (one run per quick
+        # pass and per level of the full schedule) plus one per solve that
+        # succeeds; one trial at least per such solve, at most 7
+        runs = opts.quick_passes + len(opts.level_eps)
         if n == 1:
-            assert (mev, mso) == (0, 0)
-        assert mso <= 5 * cnt and mev <= 5 * 9 * cnt
-    assert wc[4] == (0, 0, 0, 0)
+            # one slot: every trial is a full evaluation
+            assert tr == 0 and cnt + so // 2 <= ev <= 7 * so + runs * cnt
+        else:
+            assert cnt + so // 2 <= ev <= so + runs * cnt
+            assert so // 2 <= tr <= 7 * so
+        if n == 1:
+            assert (mev, mtr, mso) == (0, 0, 0)
+        assert mso <= 5 * cnt and mev <= 5 * 10 * cnt and mtr <= 7 * mso
+    assert wc[4] == (0,) * 6
     solver.solve(db, opts, out=out)
     torch.cuda.synchronize()
-    assert all(v == (0, 0, 0, 0) for v in solver.work_counts().values())
+    assert all(v == (0,) * 6 for v in solver.work_counts().values())
 
 
 @pytest.mark.parametrize("n", [2, 3])
