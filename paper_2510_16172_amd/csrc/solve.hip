@@ -1423,76 +1423,119 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St
 // (2) one workgroup turns the per-chunk counts into per-chunk output
 //     offsets (bucket of order n first for n = 1..n_max, invalid orders
 //     last), (3) each workgroup scatters its chunk in input order.
+// Thread t of a chunk owns its 32 consecutive paths (two 16-byte loads).
 // bucket[n-1] .. bucket[n] is the range of order n in perm;
 // bucket[n_max] .. bucket[n_max+1] holds the paths with an invalid order.
 
-__device__ __forceinline__ int order_bin(const uint8_t* order, int64_t i,
-                                         int64_t N, int n_max) {
-  if (i >= N) return -1;
-  int o = order[i];
-  return (o >= 1 && o <= n_max) ? o : 0;
+constexpr int kSortPer = kSortChunk / kBlock;  // paths per thread
+static_assert(kSortPer == 32, "two 16-byte loads per thread");
+
+// Bins of this thread's paths: 1..n_max, 0 for an invalid order, -1 past
+// the end of the chunk.
+__device__ __forceinline__ void sort_bins(const uint8_t* __restrict__ order, int64_t base,
+                                          int64_t c1, int n_max, int (&bins)[kSortPer]) {
+  uint8_t o[kSortPer];
+  if (base + kSortPer <= c1 && (((uintptr_t)(order + base)) & 15) == 0) {
+    const uint4 v0 = *reinterpret_cast<const uint4*>(order + base);
+    const uint4 v1 = *reinterpret_cast<const uint4*>(order + base + 16);
+    const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int q = 0; q < kSortPer; ++q) o[q] = (uint8_t)(w[q >> 2] >> (8 * (q & 3)));
+  } else {
+#pragma unroll
+    for (int q = 0; q < kSortPer; ++q) o[q] = (base + q < c1) ? order[base + q] : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int b = (o[q] >= 1 && o[q] <= n_max) ? (int)o[q] : 0;
+    bins[q] = (base + q < c1) ? b : -1;
+  }
+}
+
+__device__ __forceinline__ void bin_counts(const int (&bins)[kSortPer],
+                                           uint32_t (&cnt)[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) cnt[k] = 0;
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cnt[k] += (bins[q] == k) ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(kBlock) void bucket_count_kernel(
     const uint8_t* __restrict__ order, int64_t N, int n_max,
     uint32_t* __restrict__ ccount) {
-  __shared__ unsigned int loc[8];
-  if (threadIdx.x < 8) loc[threadIdx.x] = 0;
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
+  __shared__ uint32_t wsum[kBlock / 64][8];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
   const int64_t c1 = min(N, c0 + (int64_t)kSortChunk);
-  for (int64_t i0 = c0; i0 < c1; i0 += kBlock) {
-    int b = order_bin(order, i0 + threadIdx.x, c1, n_max);
-    for (int k = 0; k <= n_max; ++k) {
-      unsigned long long m = __ballot(b == k);
-      if (lane == 0 && m) atomicAdd(&loc[k], (unsigned int)__popcll(m));
-    }
-  }
+  int bins[kSortPer];
+  sort_bins(order, c0 + (int64_t)threadIdx.x * kSortPer, c1, n_max, bins);
+  uint32_t cnt[8];
+  bin_counts(bins, cnt);
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt[k] += __shfl_xor(cnt[k], off);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) wsum[w][k] = cnt[k];
   __syncthreads();
-  if (threadIdx.x < 8) ccount[(int64_t)blockIdx.x * 8 + threadIdx.x] = loc[threadIdx.x];
+  if (threadIdx.x < 8) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int v = 0; v < kBlock / 64; ++v) t += wsum[v][threadIdx.x];
+    ccount[(int64_t)blockIdx.x * 8 + threadIdx.x] = t;
+  }
 }
 
 // One workgroup: per-chunk offsets (in place over ccount) and bucket bounds.
+// Thread t sums a contiguous run of chunks; an exclusive scan over the
+// threads (per bin, in LDS, log2(kBlock) steps) gives each run's start.
 __global__ __launch_bounds__(kBlock) void bucket_scan_kernel(
     uint32_t* __restrict__ ccount, int64_t nchunks, int n_max,
     int64_t* __restrict__ bucket) {
-  __shared__ unsigned long long part[kBlock][8];
+  __shared__ unsigned long long part[2][kBlock][8];
   __shared__ unsigned long long start[8];
+  if (threadIdx.x < 8) start[threadIdx.x] = 0;
   const int64_t per = (nchunks + kBlock - 1) / kBlock;
   const int64_t c0 = (int64_t)threadIdx.x * per;
   const int64_t c1 = min(nchunks, c0 + per);
   unsigned long long sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t c = c0; c < c1; ++c)
-    for (int k = 0; k <= n_max; ++k) sum[k] += ccount[c * 8 + k];
-  for (int k = 0; k < 8; ++k) part[threadIdx.x][k] = sum[k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sum[k] += ccount[c * 8 + k];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) part[0][threadIdx.x][k] = sum[k];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // exclusive scan over threads, per bin; bin totals
-    unsigned long long tot[8];
-    for (int k = 0; k <= n_max; ++k) {
-      unsigned long long acc = 0;
-      for (int t = 0; t < kBlock; ++t) {
-        unsigned long long v = part[t][k];
-        part[t][k] = acc;
-        acc += v;
-      }
-      tot[k] = acc;
+  // inclusive Hillis-Steele scan over threads, ping-pong buffers
+  int cur = 0;
+  for (int d = 1; d < kBlock; d <<= 1) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      unsigned long long v = part[cur][threadIdx.x][k];
+      if ((int)threadIdx.x >= d) v += part[cur][threadIdx.x - d][k];
+      part[cur ^ 1][threadIdx.x][k] = v;
     }
+    cur ^= 1;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
     unsigned long long acc = 0;
     bucket[0] = 0;
     for (int n = 1; n <= n_max; ++n) {
       start[n] = acc;
-      acc += tot[n];
+      acc += part[cur][kBlock - 1][n];
       bucket[n] = (int64_t)acc;
     }
     start[0] = acc;
-    acc += tot[0];
+    acc += part[cur][kBlock - 1][0];
     bucket[n_max + 1] = (int64_t)acc;
   }
   __syncthreads();
   unsigned long long run[8];
-  for (int k = 0; k <= n_max; ++k) run[k] = start[k] + part[threadIdx.x][k];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) run[k] = start[k] + part[cur][threadIdx.x][k] - sum[k];
   for (int64_t c = c0; c < c1; ++c)
     for (int k = 0; k <= n_max; ++k) {
       uint32_t v = ccount[c * 8 + k];
@@ -1501,41 +1544,65 @@ __global__ __launch_bounds__(kBlock) void bucket_scan_kernel(
     }
 }
 
-// Scatter: within a chunk, slices of 256 paths in order; inside a slice,
-// wavefronts in order and lanes by rank (ballot + popcount): a stable sort.
+// Scatter: a stable sort of the chunk. Thread t's paths come after those of
+// threads < t in each bin: per-bin exclusive scan of the thread counts over
+// the wave (shuffles) and the waves (LDS). The sorted chunk is staged in LDS
+// (bins one after another, skewed by one slot per 32 against bank
+// conflicts) and copied out with consecutive threads on consecutive
+// addresses: each bin of the chunk is one contiguous run of perm.
+__device__ __forceinline__ int sort_skew(int i) { return i + (i >> 5); }
+
 __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
     const uint8_t* __restrict__ order, int64_t N, int n_max,
     const uint32_t* __restrict__ coff, int32_t* __restrict__ perm) {
-  __shared__ unsigned int run[8];
-  __shared__ unsigned int wcnt[kBlock / 64][8];
+  __shared__ uint32_t wtot[kBlock / 64][8];
+  __shared__ int32_t stage[kSortChunk + kSortChunk / 32];
+  __shared__ int32_t lstart[9];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  if (threadIdx.x < 8) run[threadIdx.x] = coff[(int64_t)blockIdx.x * 8 + threadIdx.x];
-  __syncthreads();
   const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
   const int64_t c1 = min(N, c0 + (int64_t)kSortChunk);
-  for (int64_t i0 = c0; i0 < c1; i0 += kBlock) {
-    const int64_t i = i0 + threadIdx.x;
-    const int b = order_bin(order, i, c1, n_max);
-    unsigned int my_rank = 0;
-    for (int k = 0; k <= n_max; ++k) {
-      unsigned long long m = __ballot(b == k);
-      if (lane == 0) wcnt[w][k] = (unsigned int)__popcll(m);
-      if (b == k) my_rank = (unsigned int)__popcll(m & below);
+  const int64_t base = c0 + (int64_t)threadIdx.x * kSortPer;
+  int bins[kSortPer];
+  sort_bins(order, base, c1, n_max, bins);
+  uint32_t cnt[8], incl[8];
+  bin_counts(bins, cnt);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    incl[k] = cnt[k];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(incl[k], d);
+      if (lane >= d) incl[k] += v;
     }
-    __syncthreads();
-    if (b >= 0) {
-      unsigned int off = run[b] + my_rank;
-      for (int v = 0; v < w; ++v) off += wcnt[v][b];
-      perm[off] = (int32_t)i;
+  }
+  if (lane == 63)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) wtot[w][k] = incl[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int k = 0; k < 8; ++k) {
+      lstart[k] = acc;
+      for (int v = 0; v < kBlock / 64; ++v) acc += (int)wtot[v][k];
     }
-    __syncthreads();
-    if (threadIdx.x <= n_max) {
-      unsigned int add = 0;
-      for (int v = 0; v < kBlock / 64; ++v) add += wcnt[v][threadIdx.x];
-      run[threadIdx.x] += add;
-    }
-    __syncthreads();
+    lstart[8] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    int off = lstart[k] + (int)(incl[k] - cnt[k]);
+    for (int v = 0; v < w; ++v) off += (int)wtot[v][k];
+#pragma unroll
+    for (int q = 0; q < kSortPer; ++q)
+      if (bins[q] == k) stage[sort_skew(off++)] = (int32_t)(base + q);
+  }
+  __syncthreads();
+  const int total = lstart[8];
+  for (int i = threadIdx.x; i < total; i += kBlock) {
+    int k = 0;
+#pragma unroll
+    for (int b = 1; b < 8; ++b) k += (i >= lstart[b]) ? 1 : 0;
+    perm[(int64_t)coff[(int64_t)blockIdx.x * 8 + k] + (i - lstart[k])] = stage[sort_skew(i)];
   }
 }
 

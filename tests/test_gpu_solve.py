@@ -385,3 +385,35 @@ def test_concurrent_orders_equal_sequential(solver):
             for k in want:
                 np.testing.assert_array_equal(rep[k], want[k], err_msg=k)
     g.close()
+
+
+def test_bucketing_ragged_unaligned_and_invalid_orders(solver):
+    """Order bucketing over a ragged size (three chunks of 8,192 paths and a
+    tail) with an order array that starts off 16-byte alignment (the
+    per-byte load path) and invalid orders: the same bits as with an aligned
+    order array, and the invalid paths flagged."""
+    import torch
+    from paper_2510_16172_amd import fpt
+    sc = scenes.canyon_scene()
+    N = 3 * 8192 + 77
+    b = scenes.canyon_sample_paths(sc, N, seed=4700, n=None, n_max=4)
+    order = b.order.copy()
+    order[::97] = 0
+    order[5::101] = 9
+    bad = (order < 1) | (order > 4)
+    db = fpt.DeviceBatch(b)
+    big = torch.zeros(N + 16, dtype=torch.uint8, device="cuda")
+    big[1:N + 1] = torch.from_numpy(order).cuda()
+    un = fpt.DeviceBatch.from_tensors(db.obj, db.pts, db.src, db.dst, db.ids,
+                                      big[1:N + 1], S=b.S)
+    al = fpt.DeviceBatch.from_tensors(db.obj, db.pts, db.src, db.dst, db.ids,
+                                      torch.from_numpy(order).cuda(), S=b.S)
+    assert un.order.data_ptr() % 16 == 1
+    opts = _opts(b.S, iters=16)
+    gu = {k: v.cpu().numpy() for k, v in solver.solve(un, opts).items()}
+    ga = {k: v.cpu().numpy() for k, v in solver.solve(al, opts).items()}
+    for k in ga:
+        np.testing.assert_array_equal(gu[k], ga[k], err_msg=k)
+    assert np.all((ga["status"][bad] & fpt.ST_INVALID) != 0)
+    assert np.all((ga["status"][~bad] & fpt.ST_INVALID) == 0)
+    assert ((ga["status"][~bad] & fpt.ST_CONVERGED) != 0).mean() > 0.85
