@@ -918,11 +918,14 @@ __device__ __forceinline__ void init_state(const Geo32<NO>& G,
 
 // One BFGS iteration (Sec. III-C): step size by the fixed-point iteration of
 // Eq. 6 (from the unit step, with the majorant step from 0 as fallback),
-// step, new gradient, inverse-Hessian update. Returns the squared largest
+// step, new gradient, inverse-Hessian update. On the first iteration the
+// identity is rescaled to (s^T y / y^T y) I before the update (the usual
+// choice of the initial inverse Hessian, Nocedal & Wright eq. 6.20): H = I
+// is off by the scale of the segment lengths. Returns the squared largest
 // point displacement of the step.
 template <int NO>
 __device__ __forceinline__ float bfgs_iter(const Geo32<NO>& G, State32<NO>& S,
-                                           int fp_iters) {
+                                           int fp_iters, bool first) {
   constexpr int M = State32<NO>::M, HP = State32<NO>::HP;
   // direction in point space: q_j = A_j p_j; segment change D_i
   float q[NO][3];
@@ -980,6 +983,21 @@ __device__ __forceinline__ float bfgs_iter(const Geo32<NO>& G, State32<NO>& S,
   // BFGS inverse update (Nocedal & Wright eq. 6.17), with
   // H y = H g' - H g = H g' + P
   float Hg[M], Hy[M], y[M];
+  if (first) {
+    // H = I still: scale it, and the direction P = -H g with it
+    float sy0 = 0.f, yy0 = 0.f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const float yk = gn[k] - S.g[k];
+      sy0 = fmaf(s[k], yk, sy0);
+      yy0 = fmaf(yk, yk, yy0);
+    }
+    const float gam = (sy0 > 1e-30f && yy0 > 1e-30f) ? sy0 * rcp32(yy0) : 1.f;
+#pragma unroll
+    for (int a = 0; a < M; ++a) S.H[pk(M, a, a)] *= gam;
+#pragma unroll
+    for (int k = 0; k < M; ++k) S.P[k] *= gam;
+  }
   symv<M>(S.H, gn, Hg);
   float sy = 0.f, yHy = 0.f, ss = 0.f, yy = 0.f;
 #pragma unroll
@@ -1059,7 +1077,7 @@ __global__ __launch_bounds__(kBlock) void bfgs_kernel(
     bool valid = load_path32<NO>(A, p, G, t0);
     State32<NO> S;
     init_state<NO>(G, t0, S);
-    for (int it = 0; it < A.n_iter; ++it) bfgs_iter<NO>(G, S, A.fp_iters);
+    for (int it = 0; it < A.n_iter; ++it) bfgs_iter<NO>(G, S, A.fp_iters, it == 0);
     store_phase1<NO>(A, p, S, A.n_iter, valid);
   }
 }
@@ -1210,7 +1228,7 @@ __global__ __launch_bounds__(kBlock) void bfgs_stage_kernel(
     for (int k = 0; k < St.iters; ++k) {
       if (__all(done)) break;
       if (!done) {
-        float d2 = bfgs_iter<NO>(G, S, A.fp_iters);
+        float d2 = bfgs_iter<NO>(G, S, A.fp_iters, it == 0);
         ++it;
         streak = (d2 <= A.exit_d2) ? streak + 1 : 0;
         done = streak >= 2 || it >= A.n_iter;

@@ -125,7 +125,7 @@ def evaluate(solver, mlp, db: fpt.DeviceBatch, opts, repeats: int = 3):
 
 
 def compare_fixed(solver, mlp, db: fpt.DeviceBatch, scale: float,
-                  iters=(8, 16, 24), repeats: int = 3):
+                  iters=(4, 8, 16, 24), repeats: int = 3):
     """Zero vs learned start at equal fixed iteration counts: certified
     fraction, solve time, and certified paths/s with and without the
     network's inference time (HIP events on the current stream)."""

@@ -3,8 +3,9 @@ iterations (the approach Sec. III-D replaces by implicit differentiation and
 Sec. IV-B times against it).
 
 The same FP32 BFGS as the HIP solver (unit-vector basis, identity initial
-inverse Hessian, the fixed-point step of Eq. 6 started at the unit step with
-the majorant step from zero as fallback) written with batched PyTorch ops,
+inverse Hessian rescaled by s^T y / y^T y at the first update, the
+fixed-point step of Eq. 6 started at the unit step with the majorant step
+from zero as fallback) written with batched PyTorch ops,
 so that autograd records every iteration. Used only to time the comparison;
 it is not part of the solver.
 """
@@ -53,7 +54,7 @@ def unrolled_bfgs(tx, rx, B, A1, A2, iters: int, fp_iters: int = 1):
     H = torch.eye(m, device=B.device, dtype=B.dtype).expand(N, m, m)
     g, r, l2, il = grad(T)
     P = -g
-    for _ in range(iters):
+    for it in range(iters):
         q = (A * P.view(N, n, 1, 2)).sum(-1)                       # N, n, 3
         z = torch.zeros_like(q[:, :1])
         D = torch.cat([q, z], 1) - torch.cat([z, q], 1)           # N, n+1, 3
@@ -78,6 +79,14 @@ def unrolled_bfgs(tx, rx, B, A1, A2, iters: int, fp_iters: int = 1):
         T = T + s
         gn, r, l2, il = grad(T)
         y = gn - g
+        if it == 0:
+            sy0 = (s * y).sum(-1)
+            yy0 = (y * y).sum(-1)
+            gam = torch.where((sy0 > 1e-30) & (yy0 > 1e-30),
+                              sy0 / torch.where(yy0 > 1e-30, yy0, torch.ones_like(yy0)),
+                              torch.ones_like(sy0))
+            H = H * gam[:, None, None]
+            P = P * gam[:, None]
         Hg = torch.bmm(H, gn[:, :, None])[..., 0]
         Hy = Hg + P
         sy = (s * y).sum(-1)
