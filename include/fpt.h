@@ -147,11 +147,16 @@ typedef struct {
                            majorant step when the full step lengthens the
                            path (no early exit). The FP64 refinement, the
                            certificate and the outputs are the same */
+  int32_t polish_steps; /* 0..8: FP32 Newton steps on the exact Hessian of the
+                           length (smoothed by 1e-7 scale) at the end of the
+                           BFGS phase, before the FP64 refinement; they start
+                           it within FP32 precision of the minimiser, so that
+                           fewer FP64 steps reach the certificate */
 } fpt_opts;
 
 enum { FPT_METHOD_BFGS = 0, FPT_METHOD_NEWTON32 = 1 };
 
-/* Defaults: 64 iterations, 1 fixed-point iteration, no early exit
+/* Defaults: 64 iterations, 1 fixed-point iteration, 1 polish step, no early exit
  * (exit_rtol = 1e-6, stages of 16, 16 and 32 iterations), refinement levels
  * eps/S = 1e-3, 1e-5, 1e-7 (2 steps each) and 1e-9 (3 steps) after a quick
  * pass of 2 steps at 1e-9 (twice: quick_passes = 2), cert_rtol = 1e-5, scale = 1. */

@@ -22,7 +22,7 @@ import numpy as np
 DEFAULT_CANDIDATES = (
     [{"wg_per_cu": 0, "early_exit": 0, "iters": k, "quick_steps": qs, "quick_passes": qp}
      for k in (8, 10, 12, 14, 16, 20, 24, 32, 48)
-     for (qs, qp) in ((2, 2), (3, 1))]
+     for (qs, qp) in ((2, 1), (2, 2), (3, 1))]
     + [{"wg_per_cu": 0, "early_exit": 1, "iters": 64, "stage_iters": s,
         "quick_steps": 2, "quick_passes": 2}
        for s in ([16, 16, 32], [12, 12, 16, 24])]
@@ -33,7 +33,7 @@ DEFAULT_CANDIDATES = (
 # count, with the same quick refinement settings.
 NEWTON32_CANDIDATES = [
     {"wg_per_cu": 0, "early_exit": 0, "iters": k, "quick_steps": qs, "quick_passes": qp}
-    for k in (4, 6, 8, 10, 12, 16) for (qs, qp) in ((2, 2), (3, 1))]
+    for k in (4, 6, 8, 10, 12, 16) for (qs, qp) in ((2, 1), (2, 2), (3, 1))]
 
 
 def default_cache_path() -> str:

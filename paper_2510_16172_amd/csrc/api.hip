@@ -116,6 +116,7 @@ extern "C" void fpt_default_opts(fpt_opts* o) {
   o->quick_passes = 2;
   o->concurrent_orders = 0;
   o->method = FPT_METHOD_BFGS;
+  o->polish_steps = 1;
 }
 
 // Keeps the caller's current device and switches to the handle's for the
@@ -259,6 +260,8 @@ static fpt_status check_opts(const fpt_opts* o) {
     return fail(FPT_EINVAL, "fpt_solve: quick_passes outside 1..2");
   if (o->method != FPT_METHOD_BFGS && o->method != FPT_METHOD_NEWTON32)
     return fail(FPT_EINVAL, "fpt_solve: unknown method");
+  if (o->polish_steps < 0 || o->polish_steps > 8)
+    return fail(FPT_EINVAL, "fpt_solve: polish_steps outside 0..8");
   if (o->early_exit) {
     if (o->stage_iters[0] < 1)
       return fail(FPT_EINVAL, "fpt_solve: early exit needs stage_iters[0] >= 1");
@@ -512,6 +515,7 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
   A.fp_iters = o->fp_iters;
   A.early_exit = o->early_exit ? 1 : 0;
   A.method = o->method;
+  A.polish_steps = o->polish_steps;
   float ed = o->exit_rtol * o->scale;
   A.exit_d2 = ed * ed;
   A.scale = o->scale;

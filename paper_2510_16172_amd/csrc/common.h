@@ -88,6 +88,7 @@ struct SolveArgs {
   int32_t K, Q, n_max;
   // options
   int32_t n_iter, fp_iters, early_exit, method;
+  int32_t polish_steps;  // FP32 Newton steps at the end of the BFGS phase
   float exit_d2;  // (exit_rtol * scale)^2
   float scale;
   int32_t n_levels;

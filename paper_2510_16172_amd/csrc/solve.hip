@@ -1045,6 +1045,49 @@ __device__ __forceinline__ float bfgs_iter(const Geo32<NO>& G, State32<NO>& S,
   return alpha * alpha * m2;
 }
 
+template <int NO>
+struct Geo32View {
+  static constexpr int kOrder = NO;
+  using real = float;
+  const Geo32<NO>& g;
+  bool edge_[NO];
+  __device__ __forceinline__ float tx(int c) const { return g.tx[c]; }
+  __device__ __forceinline__ float rx(int c) const { return g.rx[c]; }
+  __device__ __forceinline__ float b(int j, int c) const { return g.b[j][c]; }
+  __device__ __forceinline__ float a(int j, int k, int c) const { return g.a[j][k][c]; }
+  __device__ __forceinline__ bool edge(int j) const { return edge_[j]; }
+  __device__ __forceinline__ bool fixed(int) const { return false; }
+};
+
+// The end of the FP32 phase: `polish_steps` Newton steps in FP32 on the
+// exact block-tridiagonal Hessian of the length (smoothed by 1e-7 S, the
+// majorant step when the full one lengthens the path). The first FP64
+// refinement step then starts within FP32 precision of the minimiser, so
+// that fewer FP64 steps reach the certificate. A step that is not finite is
+// dropped.
+constexpr float kPolishEps = 1e-7f;
+
+template <int NO>
+__device__ __forceinline__ void polish32(const SolveArgs& A, const Geo32<NO>& G,
+                                         State32<NO>& S) {
+  if (A.polish_steps <= 0) return;
+  Geo32View<NO> V{G, {}};
+  float T[2 * NO];
+#pragma unroll
+  for (int j = 0; j < NO; ++j)
+    V.edge_[j] = G.a[j][1][0] == 0.f && G.a[j][1][1] == 0.f && G.a[j][1][2] == 0.f;
+#pragma unroll
+  for (int q = 0; q < 2 * NO; ++q) T[q] = S.T[q];
+  NewtonTrack k{false, false, false, 0, 0, 0};
+  const float eps = kPolishEps * A.scale;
+  newton_run64(V, T, eps * eps, A.polish_steps, 0.f, true, k);
+  bool fin = true;
+#pragma unroll
+  for (int q = 0; q < 2 * NO; ++q) fin = fin && isfinite(T[q]);
+#pragma unroll
+  for (int q = 0; q < 2 * NO; ++q) S.T[q] = fin ? T[q] : S.T[q];
+}
+
 // hands a path over to the refinement kernel: unit-vector parameters,
 // iteration count, validity
 template <int NO>
@@ -1078,6 +1121,7 @@ __global__ __launch_bounds__(kBlock) void bfgs_kernel(
     State32<NO> S;
     init_state<NO>(G, t0, S);
     for (int it = 0; it < A.n_iter; ++it) bfgs_iter<NO>(G, S, A.fp_iters, it == 0);
+    polish32<NO>(A, G, S);
     store_phase1<NO>(A, p, S, A.n_iter, valid);
   }
 }
@@ -1090,20 +1134,6 @@ __global__ __launch_bounds__(kBlock) void bfgs_kernel(
 // four smoothing levels, the remainder going to the last; a step that would
 // lengthen the path is replaced by the majorant step along the Newton
 // direction. The FP64 refinement that follows is unchanged.
-template <int NO>
-struct Geo32View {
-  static constexpr int kOrder = NO;
-  using real = float;
-  const Geo32<NO>& g;
-  bool edge_[NO];
-  __device__ __forceinline__ float tx(int c) const { return g.tx[c]; }
-  __device__ __forceinline__ float rx(int c) const { return g.rx[c]; }
-  __device__ __forceinline__ float b(int j, int c) const { return g.b[j][c]; }
-  __device__ __forceinline__ float a(int j, int k, int c) const { return g.a[j][k][c]; }
-  __device__ __forceinline__ bool edge(int j) const { return edge_[j]; }
-  __device__ __forceinline__ bool fixed(int) const { return false; }
-};
-
 constexpr int kNewton32Levels = 4;
 __device__ __forceinline__ float newton32_eps(int lv) {
   return lv == 0 ? 1e-2f : lv == 1 ? 1e-3f : lv == 2 ? 1e-4f : 1e-5f;
@@ -1235,7 +1265,10 @@ __global__ __launch_bounds__(kBlock) void bfgs_stage_kernel(
       }
     }
     const bool fin = done || !St.out_list || !valid;
-    if (fin) store_phase1<NO>(A, p, S, it, valid);
+    if (fin) {
+      polish32<NO>(A, G, S);
+      store_phase1<NO>(A, p, S, it, valid);
+    }
     const unsigned long long more = __ballot(!fin);
     if (more) {
       // region of this 64-path chunk of the input: chunks are spread over

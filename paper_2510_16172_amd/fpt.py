@@ -44,7 +44,8 @@ class _Opts(ctypes.Structure):
                 ("cert_rtol", ctypes.c_float),
                 ("stage_iters", ctypes.c_int32 * 4),
                 ("quick_steps", ctypes.c_int32), ("quick_passes", ctypes.c_int32),
-                ("concurrent_orders", ctypes.c_int32), ("method", ctypes.c_int32)]
+                ("concurrent_orders", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("polish_steps", ctypes.c_int32)]
 
 
 class _LaunchCfg(ctypes.Structure):
@@ -175,6 +176,7 @@ class Opts:
     quick_passes: int = 2
     concurrent_orders: bool = False
     method: int = 0  # METHOD_BFGS (the paper's) or METHOD_NEWTON32 (variant)
+    polish_steps: int = 1
 
     def to_c(self) -> _Opts:
         o = _Opts()
@@ -201,6 +203,7 @@ class Opts:
         o.quick_passes = int(self.quick_passes)
         o.concurrent_orders = 1 if self.concurrent_orders else 0
         o.method = int(self.method)
+        o.polish_steps = int(self.polish_steps)
         return o
 
 
