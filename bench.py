@@ -61,6 +61,22 @@ def bfgs_init_flops(n: int) -> int:
     return 25 * n + 12 * (n + 1) + 18 * n
 
 
+def polish_flops(n: int, steps: int) -> int:
+    """FP32 flops of the polish Newton steps at the end of bfgs_kernel<n>
+    (newton_run64 on the path's FP32 registers): an evaluation at the start
+    and one per step (points 12n; per segment difference 3, squared length 5,
+    + eps^2 1, hardware rsq 1, unit vector 3, length sum 2), one trial length
+    per step (no unit vectors: 12 per segment), and the Newton solve of
+    refine_solve_flops with hardware reciprocals (1 flop instead of 7 for
+    each of the n pivots and the majorant step)."""
+    if steps <= 0:
+        return 0
+    ev = 12 * n + 15 * (n + 1)
+    tr = 12 * n + 12 * (n + 1)
+    so = refine_solve_flops(n) - 6 * (n + 1)
+    return ev + steps * (ev + tr + so)
+
+
 def refine_eval_flops(n: int) -> int:
     """FP64 flops of one evaluation of the smoothed path in refine_kernel<n>
     (eval64): points 4 per coordinate (12n), and per segment difference 3,
@@ -534,7 +550,7 @@ def main():
     ee2 = bool(chosen.get(2, {}).get("early_exit", int(args.early_exit)))
     it2 = out_np["iters"][o2].astype(np.int64)
     fl_b = (int(it2.sum()) * bfgs_flops_per_iter(2, args.fp_iters, ee2)
-            + int(o2.sum()) * bfgs_init_flops(2))
+            + int(o2.sum()) * (bfgs_init_flops(2) + polish_flops(2, opts.polish_steps)))
     t_b = kt[fpt.T_BFGS + 1] * 1e-3
     kname_b = "bfgs_stage_kernel<2>" if ee2 else "bfgs_kernel<2>"
     n_eval, n_trial, n_solve, m_eval, m_trial, m_solve = (v / args.steps for v in work[2])
