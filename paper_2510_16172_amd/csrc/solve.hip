@@ -179,12 +179,16 @@ __device__ __forceinline__ R max_disp64(const GEO& G, const R* d) {
 // false the step is backtracked by factors of 4 (up to 6 times), which
 // makes more progress per step on such paths. From two slots on a trial
 // evaluates the length only and the segments of the next step are evaluated
-// at the point reached; with one slot the accepted trial's segments are kept. prev_small / last_small track whether
-// the last two steps were taken in full and moved no point by more than
-// sqrt(cert2).
+// at the point reached; with one slot the accepted trial's segments are
+// kept. prev_small / last_small track whether the last two steps were taken
+// in full and moved no point by more than sqrt(cert2); contracting whether
+// the last step was at most a tenth of the one before (the quadratic
+// contraction of Newton's method near its solution; small steps that do
+// not contract are a slow walk along a flat valley), or below 1e-4 sqrt(cert2).
 struct NewtonTrack {
-  bool prev_small, last_small, refined;
-  uint32_t n_eval, n_trial, n_solve;  // segment evaluations, trial lengths, solves
+  bool prev_small = false, last_small = false, refined = false, contracting = false;
+  uint32_t n_eval = 0, n_trial = 0, n_solve = 0;  // evaluations, trial lengths, solves
+  double last_d2 = INFINITY;  // squared largest displacement of the last step
 };
 
 // The (smoothed) length alone at t: a trial of the step. Same arithmetic as
@@ -227,7 +231,11 @@ __device__ __forceinline__ void newton_run64(const GEO& G, R* t, R eps2, int nst
     ++k.n_solve;
     k.prev_small = k.last_small;
     k.last_small = false;
-    if (!ok) continue;
+    k.contracting = false;
+    if (!ok) {
+      k.last_d2 = 0.0;
+      continue;
+    }
     const R d2 = max_disp64(G, d);
     // majorant step: a = -sum D_i.v_i / sum |D_i|^2 il_i (v_i = r_i il_i),
     // D_i = A_i d_i - A_{i-1} d_{i-1} the change of segment i along d
@@ -293,68 +301,11 @@ __device__ __forceinline__ void newton_run64(const GEO& G, R* t, R eps2, int nst
       ++k.n_eval;
     }
     k.last_small = acc && (s == R(1)) && (d2 <= cert2);
+    k.contracting = acc && (s == R(1)) &&
+                    ((double)d2 <= 1e-2 * k.last_d2 || (double)d2 <= 1e-8 * (double)cert2);
+    k.last_d2 = acc ? (double)(d2 * s * s) : 0.0;
     k.refined = k.refined || acc;
   }
-}
-
-// Nonsmooth check. At the smoothed optimum v_i = r_i / l_i plays the role of
-// the subgradient of |r_i|: a genuine collapse (r_i -> 0) has |v_i| bounded
-// away from 1, while a short segment (< 1e-3 S) with |v_i| close to 1 is a
-// degenerate configuration in which the length is nearly flat along the
-// segment and the smoothing can pull the points together. Such a path is not
-// certified.
-template <class GEO>
-__device__ __forceinline__ bool nonsmooth_ok64(const GEO& G,
-                                               const double* t, double eps,
-                                               double scale) {
-  constexpr int NO = GEO::kOrder;
-  const double short2 = 1e-6 * scale * scale;
-  double x[NO][3];
-  points64(G, t, x);
-  bool ok = true;
-#pragma unroll
-  for (int i = 0; i <= NO; ++i) {
-    double r[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      r[c] = ((i == NO) ? G.rx(c) : x[i][c]) - ((i == 0) ? G.tx(c) : x[i - 1][c]);
-    // |v_i|^2 = q / (q + eps^2) > 0.98^2
-    double q = dot3d(r, r);
-    if (q < short2 && q > (0.98 * 0.98) * (q + eps * eps)) ok = false;
-  }
-  return ok;
-}
-
-// Damped Newton refinement, level by level (quick: only the last level, with
-// quick_steps steps). t is in the caller's parametrisation.
-template <class GEO>
-__device__ __forceinline__ RefineOut refine64(const GEO& G, double* t,
-                                              const SolveArgs& A, bool quick,
-                                              uint32_t (&work)[3]) {
-  constexpr int NO = GEO::kOrder;
-  const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
-  NewtonTrack k{false, false, false, 0, 0, 0};
-  const int lv0 = quick ? A.n_levels - 1 : 0;
-  for (int lv = lv0; lv < A.n_levels; ++lv) {
-    double eps = (double)A.level_eps[lv] * (double)A.scale;
-    // (the quick pass, which every path takes, uses the one-evaluation
-    // majorant fallback; the paths left for the full schedule backtrack)
-    newton_run64(G, t, eps * eps, quick ? A.quick_steps : A.level_steps[lv],
-                     cert2, quick, k);
-  }
-  work[0] += k.n_eval;
-  work[1] += k.n_trial;
-  work[2] += k.n_solve;
-  RefineOut o{false, k.refined, true};
-  // One small full step is not enough: along a nearly flat valley of the
-  // length a Newton step taken from well outside its quadratic region can be
-  // short and still leave the point far from the minimiser (the next step
-  // then jumps). Two consecutive small full steps are required.
-  o.certified = A.n_levels > 0 && k.prev_small && k.last_small;
-  if (o.certified)
-    o.certified = nonsmooth_ok64(
-        G, t, (double)A.level_eps[A.n_levels - 1] * (double)A.scale, (double)A.scale);
-  return o;
 }
 
 // ------------------------------------------------ collapsed minimisers ---
@@ -601,6 +552,179 @@ __device__ __forceinline__ void pair64(const GEO& G, int a,
   }
 }
 
+// The subgradient test of a collapse between slots a and a + 1 (the two
+// points coincide): u_in and u_out are the unit vectors of the segments into
+// slot a and out of slot a + 1, nul an orthonormal basis of the directions
+// orthogonal to both objects (zero rows beyond their number). The least-norm
+// w with P_U w = P_U u_in and P_V w = P_V u_out (P = projector onto an
+// object's directions) is w = (P_U + P_V + P_null)^-1 (P_U u_in + P_V u_out);
+// it must satisfy both (residual, so that the path is stationary along the
+// intersection too) and |w|^2 <= 1 - 1e-6. Then 0 is a subgradient of the
+// length there: the point is the global minimiser (L is convex).
+template <class GEO>
+__device__ __forceinline__ bool subgradient_ok64(const GEO& G, int a, const double* uin,
+                                                 const double* uout,
+                                                 const double (*nul)[3]) {
+  double aa[2][3] = {}, ab[2][3] = {}, ba[3] = {}, bb[3] = {};
+  bool ea = false, eb = false;
+  pair64(G, a, aa, ba, ea, ab, bb, eb);
+  {
+    const Basis64 U = basis64(aa, ea), V = basis64(ab, eb);
+    double M[3][3], rhs[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      rhs[r] = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        M[r][c] = nul[0][r] * nul[0][c] + nul[1][r] * nul[1][c];
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < 2; ++k2) {
+      const double* qu = U.q[k2];
+      const double* qv = V.q[k2];
+      double pu = dot3d(qu, uin), pv = dot3d(qv, uout);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        rhs[r] += qu[r] * pu + qv[r] * pv;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) M[r][c] += qu[r] * qu[c] + qv[r] * qv[c];
+      }
+    }
+    double C0[3], C1[3], C2[3];
+    cross3d(M[1], M[2], C0);
+    cross3d(M[2], M[0], C1);
+    cross3d(M[0], M[1], C2);
+    double idet = rcp64(dot3d(M[0], C0));
+    double w[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      w[c] = (C0[c] * rhs[0] + C1[c] * rhs[1] + C2[c] * rhs[2]) * idet;
+    // consistency (the reduced stationarity) and |w| < 1
+    double res = 0.0;
+#pragma unroll
+    for (int k2 = 0; k2 < 2; ++k2) {
+      double dd[3], ee[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        dd[c] = uin[c] - w[c];
+        ee[c] = w[c] - uout[c];
+      }
+      double ru = dot3d(U.q[k2], dd), rv = dot3d(V.q[k2], ee);
+      res += ru * ru + rv * rv;
+    }
+    if (!(res <= 1e-10) || !(dot3d(w, w) <= 1.0 - 1e-6)) return false;
+  }
+  return true;
+}
+
+// Nonsmooth check. At the smoothed optimum v_i = r_i / l_i plays the role of
+// the subgradient of |r_i|: a genuine collapse (r_i -> 0) has |v_i| bounded
+// away from 1, while a short segment (< 1e-3 S) with |v_i| close to 1 is a
+// degenerate configuration in which the length is nearly flat along the
+// segment and the smoothing can pull the points together. Such a path is not
+// certified. An interior collapse (|v_i| <= 0.98) must also pass the exact
+// subgradient test of its two objects: next to a collapse the smoothed
+// length is curved like 1 / eps, so Newton steps are tiny there whether or
+// not the point is stationary, and small steps alone prove nothing.
+template <class GEO>
+__device__ __forceinline__ bool nonsmooth_ok64(const GEO& G,
+                                               const double* t, double eps,
+                                               double scale) {
+  constexpr int NO = GEO::kOrder;
+  const double short2 = 1e-6 * scale * scale;
+  double x[NO][3];
+  points64(G, t, x);
+  bool ok = true;
+  int ncol = 0, a = 0;
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      r[c] = ((i == NO) ? G.rx(c) : x[i][c]) - ((i == 0) ? G.tx(c) : x[i - 1][c]);
+    // |v_i|^2 = q / (q + eps^2) > 0.98^2
+    double q = dot3d(r, r);
+    const bool flat = q > (0.98 * 0.98) * (q + eps * eps);
+    if (q < short2 && flat) ok = false;
+    if (q < short2 && !flat && i > 0 && i < NO) {
+      ++ncol;
+      a = i - 1;
+    }
+  }
+  if (!ok || ncol == 0) return ok;
+  if (ncol > 1) return false;
+  if constexpr (NO < 2) {
+    return false;
+  } else {
+    // the segments into slot a and out of slot a + 1, the collapse point
+    double rin[3] = {0.0, 0.0, 0.0}, rout[3] = {0.0, 0.0, 0.0}, ymid[3] = {0.0, 0.0, 0.0};
+    bool fixed = false;
+#pragma unroll
+    for (int k = 0; k + 1 < NO; ++k) {
+      const bool sel = (k == a);
+      fixed = fixed || (sel && (G.fixed(k) || G.fixed(k + 1)));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double p0 = (k == 0) ? G.tx(c) : x[k > 0 ? k - 1 : 0][c];
+        const double p3 = (k + 2 == NO) ? G.rx(c) : x[k + 2 < NO ? k + 2 : 0][c];
+        rin[c] = sel ? x[k][c] - p0 : rin[c];
+        rout[c] = sel ? p3 - x[k + 1][c] : rout[c];
+        ymid[c] = sel ? 0.5 * (x[k][c] + x[k + 1][c]) : ymid[c];
+      }
+    }
+    const double li = dot3d(rin, rin), lo = dot3d(rout, rout);
+    if (fixed || !(li > 0.0) || !(lo > 0.0)) return false;
+    double uin[3], uout[3];
+    const double ii = rsq64(li), io = rsq64(lo);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      uin[c] = rin[c] * ii;
+      uout[c] = rout[c] * io;
+    }
+    double aa[2][3] = {}, ab[2][3] = {}, ba[3] = {}, bb[3] = {};
+    bool ea = false, eb = false;
+    pair64(G, a, aa, ba, ea, ab, bb, eb);
+    const Basis64 U = basis64(aa, ea), V = basis64(ab, eb);
+    Virt64 X;
+    if (!intersect64(U, ba, V, bb, ymid, 1e-6 * scale, 1.44e-2 * scale * scale, X))
+      return false;
+    return subgradient_ok64(G, a, uin, uout, X.nul);
+  }
+}
+
+// Damped Newton refinement, level by level (quick: only the last level, with
+// quick_steps steps). t is in the caller's parametrisation.
+template <class GEO>
+__device__ __forceinline__ RefineOut refine64(const GEO& G, double* t,
+                                              const SolveArgs& A, bool quick,
+                                              uint32_t (&work)[3]) {
+  constexpr int NO = GEO::kOrder;
+  const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
+  NewtonTrack k;
+  const int lv0 = quick ? A.n_levels - 1 : 0;
+  for (int lv = lv0; lv < A.n_levels; ++lv) {
+    double eps = (double)A.level_eps[lv] * (double)A.scale;
+    // (the quick pass, which every path takes, uses the one-evaluation
+    // majorant fallback; the paths left for the full schedule backtrack)
+    newton_run64(G, t, eps * eps, quick ? A.quick_steps : A.level_steps[lv],
+                     cert2, quick, k);
+  }
+  work[0] += k.n_eval;
+  work[1] += k.n_trial;
+  work[2] += k.n_solve;
+  RefineOut o{false, k.refined, true};
+  // One small full step is not enough: along a nearly flat valley of the
+  // length a Newton step taken from well outside its quadratic region can be
+  // short and still leave the point far from the minimiser (the next step
+  // then jumps, or the steps stay alike). Two consecutive small full steps
+  // are required, the second contracting.
+  o.certified = A.n_levels > 0 && k.prev_small && k.last_small && k.contracting;
+  if (o.certified)
+    o.certified = nonsmooth_ok64(
+        G, t, (double)A.level_eps[A.n_levels - 1] * (double)A.scale, (double)A.scale);
+  return o;
+}
+
 template <class GEO>
 __device__ __forceinline__ bool merge64(const GEO& G, double* t,
                                         const SolveArgs& A, uint32_t (&work)[3]) {
@@ -674,12 +798,12 @@ __device__ __forceinline__ bool merge64(const GEO& G, double* t,
     }
     const double eps = (double)A.level_eps[A.n_levels - 1] * S;
     const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
-    NewtonTrack k{false, false, false, 0, 0, 0};
+    NewtonTrack k;
     newton_run64(R, tr, eps * eps, 8, cert2, false, k);
     work[0] += k.n_eval;
     work[1] += k.n_trial;
     work[2] += k.n_solve;
-    if (!(k.prev_small && k.last_small)) return false;
+    if (!(k.prev_small && k.last_small && k.contracting)) return false;
     if (!nonsmooth_ok64(R, tr, eps, S)) return false;
     // subgradient of the collapsed segment: least-norm w with
     // P_U w = P_U u_in and P_V w = P_V u_out (P = projector onto the
@@ -704,55 +828,10 @@ __device__ __forceinline__ bool merge64(const GEO& G, double* t,
         }
       }
     }
+    if (!subgradient_ok64(G, a, uin, uout, nul)) return false;
     double aa[2][3] = {}, ab[2][3] = {}, ba[3] = {}, bb[3] = {};
     bool ea = false, eb = false;
     pair64(G, a, aa, ba, ea, ab, bb, eb);
-    {
-      const Basis64 U = basis64(aa, ea), V = basis64(ab, eb);
-      double M[3][3], rhs[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        rhs[r] = 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          M[r][c] = nul[0][r] * nul[0][c] + nul[1][r] * nul[1][c];
-      }
-#pragma unroll
-      for (int k2 = 0; k2 < 2; ++k2) {
-        const double* qu = U.q[k2];
-        const double* qv = V.q[k2];
-        double pu = dot3d(qu, uin), pv = dot3d(qv, uout);
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          rhs[r] += qu[r] * pu + qv[r] * pv;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) M[r][c] += qu[r] * qu[c] + qv[r] * qv[c];
-        }
-      }
-      double C0[3], C1[3], C2[3];
-      cross3d(M[1], M[2], C0);
-      cross3d(M[2], M[0], C1);
-      cross3d(M[0], M[1], C2);
-      double idet = rcp64(dot3d(M[0], C0));
-      double w[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        w[c] = (C0[c] * rhs[0] + C1[c] * rhs[1] + C2[c] * rhs[2]) * idet;
-      // consistency (the reduced stationarity) and |w| < 1
-      double res = 0.0;
-#pragma unroll
-      for (int k2 = 0; k2 < 2; ++k2) {
-        double dd[3], ee[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          dd[c] = uin[c] - w[c];
-          ee[c] = w[c] - uout[c];
-        }
-        double ru = dot3d(U.q[k2], dd), rv = dot3d(V.q[k2], ee);
-        res += ru * ru + rv * rv;
-      }
-      if (!(res <= 1e-10) || !(dot3d(w, w) <= 1.0 - 1e-6)) return false;
-    }
     // back to the caller's parameters of the full path
     double ta[2], tb[2];
     coords64(aa, ba, ea, y, ta);
@@ -1078,7 +1157,7 @@ __device__ __forceinline__ void polish32(const SolveArgs& A, const Geo32<NO>& G,
     V.edge_[j] = G.a[j][1][0] == 0.f && G.a[j][1][1] == 0.f && G.a[j][1][2] == 0.f;
 #pragma unroll
   for (int q = 0; q < 2 * NO; ++q) T[q] = S.T[q];
-  NewtonTrack k{false, false, false, 0, 0, 0};
+  NewtonTrack k;
   const float eps = kPolishEps * A.scale;
   newton_run64(V, T, eps * eps, A.polish_steps, 0.f, true, k);
   bool fin = true;
@@ -1163,7 +1242,7 @@ __global__ __launch_bounds__(kBlock) void newton32_kernel(
       T[2 * j] = t0[j][0];
       T[2 * j + 1] = V.edge_[j] ? 0.f : t0[j][1];
     }
-    NewtonTrack k{false, false, false, 0, 0, 0};
+    NewtonTrack k;
     const int per = A.n_iter / kNewton32Levels;
     for (int lv = 0; lv < kNewton32Levels; ++lv) {
       const int steps = per + (lv == kNewton32Levels - 1 ? A.n_iter - kNewton32Levels * per : 0);
