@@ -417,3 +417,30 @@ def test_bucketing_ragged_unaligned_and_invalid_orders(solver):
     assert np.all((ga["status"][bad] & fpt.ST_INVALID) != 0)
     assert np.all((ga["status"][~bad] & fpt.ST_INVALID) == 0)
     assert ((ga["status"][~bad] & fpt.ST_CONVERGED) != 0).mean() > 0.85
+
+
+def test_no_certificate_at_nonstationary_collapse(solver, oracle_mod):
+    """Three order-2 canyon paths whose iterates end on the intersection line
+    of their two walls, which is not where the minimum is (the oracle's path
+    is 6.6e-6 m to 8 cm shorter). The smoothed length is curved like 1 / eps
+    there, so the Newton steps are tiny; the certificate must not accept them
+    (the exact subgradient test rejects them: |w| > 1). Under the schedules
+    that led them there (BFGS with 16 iterations and 3 quick steps; the FP32
+    Newton variant with 8 steps and 2 quick steps), no certified path may be
+    more than 1e-4 S from the oracle."""
+    from paper_2510_16172_amd import fpt
+    sc = scenes.canyon_scene()
+    full = scenes.canyon_all_paths(sc, n_max=2)
+    idx = np.array([1508927, 3696120, 5793027])
+    rng = np.random.default_rng(4800)
+    idx = np.sort(np.concatenate([idx, rng.choice(np.nonzero(full.order == 2)[0], 509, replace=False)]))
+    b = full.subset(idx)
+    b = type(b)(b.obj, b.pts, b.src, b.dst, b.order, np.ascontiguousarray(b.ids[:2]), b.S, b.meta)
+    ref = oracle_mod.solve(b, threads=8)
+    for method, iters, qs in ((fpt.METHOD_BFGS, 16, 3), (fpt.METHOD_NEWTON32, 8, 2)):
+        g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=iters, quick_steps=qs, quick_passes=1,
+                                              method=method), with_order=False)
+        s = gpu_util.summary(b, g, ref)
+        print(f"method {method}: cert {s['frac_cert']:.4f} ok {s['frac_ok']:.4f}", flush=True)
+        assert s["false_pos"] == 0
+        assert s["frac_cert"] > 0.9
