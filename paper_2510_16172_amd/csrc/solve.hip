@@ -295,7 +295,10 @@ __device__ __forceinline__ void newton_run64(const GEO& G, R* t, R eps2, int nst
         s *= R(0.25);
       }
     }
-    if (NO > 1 || !acc) {
+    // (the segments at t are current unless a length-only trial moved t;
+    // after the last step they are not needed: whatever follows evaluates
+    // its own)
+    if (NO > 1 && acc && st + 1 < nsteps) {
       geo_fence();
       eval64(G, t, eps2, cur);
       ++k.n_eval;

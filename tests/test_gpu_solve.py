@@ -324,13 +324,14 @@ def test_refine_work_counts(solver):
         assert so <= (opts.quick_passes * opts.quick_steps + total_levels) * cnt
         # one evaluation at the start of each Newton run (one run per quick
         # pass and per level of the full schedule) plus one per solve that
-        # succeeds; one trial at least per such solve, at most 7
+        # succeeds but the run's last; one trial at least per such solve, at
+        # most 7
         runs = opts.quick_passes + len(opts.level_eps)
         if n == 1:
             # one slot: every trial is a full evaluation
-            assert tr == 0 and cnt + so // 2 <= ev <= 7 * so + runs * cnt
+            assert tr == 0 and cnt <= ev <= 7 * so + runs * cnt
         else:
-            assert cnt + so // 2 <= ev <= so + runs * cnt
+            assert cnt <= ev <= so + runs * cnt
             assert so // 2 <= tr <= 7 * so
         if n == 1:
             assert (mev, mtr, mso) == (0, 0, 0)
