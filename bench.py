@@ -385,6 +385,9 @@ def main():
     ap.add_argument("--schedule", type=str, default=None,
                     help="JSON {order: launch config} applied with fpt_set_launch "
                          "instead of autotuning (e.g. a previous run's config.schedule)")
+    ap.add_argument("--split", type=int, default=0,
+                    help="parts per order on their own streams (0: automatic, "
+                         "2 from 2^21 paths on); the instrumented pass uses 1")
     ap.add_argument("--no-variant", action="store_true",
                     help="skip the FP32 Newton solver-variant leg")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -415,7 +418,7 @@ def main():
     solver = fpt.Solver(0)
     db = fpt.DeviceBatch(batch, device="cuda:0")
     opts = fpt.Opts(scale=batch.S, iters=args.iters, fp_iters=args.fp_iters,
-                    early_exit=args.early_exit)
+                    early_exit=args.early_exit, split=args.split)
     out = solver.alloc_out(db)
     stream = torch.cuda.current_stream()
     chosen = {}
@@ -451,11 +454,15 @@ def main():
     ms_step = ev[0].elapsed_time(ev[-1]) / args.steps
     per_step = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
     # the same steps again with the per-kernel HIP-event timers and the
-    # refinement work counters on, for the kernel breakdown and rooflines
+    # refinement work counters on, for the kernel breakdown and rooflines; in
+    # one part per order (split = 1), so that each timer brackets one launch
+    # of the order's whole bucket (the parts overlap in the timed steps)
+    import dataclasses
+    opts_one = dataclasses.replace(opts, split=1)
     solver.set_timing(True)
     solver.work_counts()  # clear
     for k in range(args.steps):
-        solver.solve(db, opts, out=out, stream=stream)
+        solver.solve(db, opts_one, out=out, stream=stream)
     kt = solver.kernel_times()
     work = solver.work_counts()
     solver.set_timing(False)
@@ -614,6 +621,8 @@ def main():
             "refine_levels": list(zip(opts.level_eps, opts.level_steps)),
             "quick_steps": opts.quick_steps,
             "quick_passes": opts.quick_passes,
+            "polish_steps": opts.polish_steps,
+            "split": opts.split if opts.split > 0 else (2 if N >= (1 << 21) else 1),
         },
         "certified_fraction": certified / N,
         "paths_per_s_all": N / (ms_step / 1e3),

@@ -152,6 +152,12 @@ typedef struct {
                            BFGS phase, before the FP64 refinement; they start
                            it within FP32 precision of the minimiser, so that
                            fewer FP64 steps reach the certificate */
+  int32_t split;        /* 0..4: each order's paths are solved in `split`
+                           equal parts, each on its own stream (forked from
+                           and joined back into hip_stream), so that one
+                           part's latency-bound passes overlap another's;
+                           the results are the same. 0: 2 parts from 2^21
+                           paths on, else 1. Early exit uses 1 */
 } fpt_opts;
 
 enum { FPT_METHOD_BFGS = 0, FPT_METHOD_NEWTON32 = 1 };

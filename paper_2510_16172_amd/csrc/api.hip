@@ -37,6 +37,12 @@ hipError_t launch_grad_invalid(const GradArgs& A, const int32_t* perm,
 #include "mlp_host.h"
 
 
+// Units of work that can run on their own stream: an order, or one of up to
+// kMaxSplit parts of an order's paths (unit_of).
+static const int kMaxSplit = 4;
+static const int kUnits = FPT_NMAX * kMaxSplit;
+static int unit_of(int n, int part) { return (n - 1) * kMaxSplit + part + 1; }
+
 struct fpt_handle {
   int device;
   int num_cu;
@@ -61,15 +67,16 @@ struct fpt_handle {
   // their own streams, else set 0) two ping-pong index lists and four
   // counter blocks (kRegions counters kCounterStride apart, one block per
   // stage, all cleared by one launch); the early-exit BFGS states (set 0)
-  unsigned long long* scount = nullptr;  // [FPT_NMAX + 1][4][kRegions * kCounterStride]
-  int32_t* slist[FPT_NMAX + 1][2] = {};
+  unsigned long long* scount = nullptr;  // [kUnits + 1][4][kRegions * kCounterStride]
+  int32_t* slist[kUnits + 1][2] = {};
   float* sstate[2] = {nullptr, nullptr};
-  int64_t list_cap[FPT_NMAX + 1] = {};  // rcap the lists of a set were sized for
+  int64_t list_cap[kUnits + 1] = {};  // rcap the lists of a set were sized for
   int64_t stage_state_cap = 0, state_rcap = 0;
-  // one stream per order (default priority) with fork / join events
-  hipStream_t ostream[FPT_NMAX + 1] = {};
+  // one stream per unit (an order, or a part of one; default priority) with
+  // fork / join events
+  hipStream_t ostream[kUnits + 1] = {};
   hipEvent_t ev_fork = nullptr;
-  hipEvent_t ev_join[FPT_NMAX + 1] = {};
+  hipEvent_t ev_join[kUnits + 1] = {};
   // per-order launch configuration (autotuner)
   fpt_launch_cfg cfg[FPT_NMAX + 1] = {};
   // learned-initialiser activations (grown on demand)
@@ -117,6 +124,7 @@ extern "C" void fpt_default_opts(fpt_opts* o) {
   o->concurrent_orders = 0;
   o->method = FPT_METHOD_BFGS;
   o->polish_steps = 1;
+  o->split = 0;
 }
 
 // Keeps the caller's current device and switches to the handle's for the
@@ -171,7 +179,7 @@ extern "C" fpt_status fpt_create(int device, fpt_handle** out) {
   h->counts = (unsigned long long*)p;
   h->cursor = h->counts + 8;
   h->bucket = (int64_t*)(h->counts + 16);
-  e = hipMalloc(&p, (size_t)(FPT_NMAX + 1) * 4 * fpt::kRegions * fpt::kCounterStride *
+  e = hipMalloc(&p, (size_t)(kUnits + 1) * 4 * fpt::kRegions * fpt::kCounterStride *
                        sizeof(unsigned long long));
   if (e != hipSuccess) {
     (void)hipFree(h->counts);
@@ -196,10 +204,10 @@ extern "C" fpt_status fpt_destroy(fpt_handle* h) {
   if (h->mlp_mem) (void)hipFree(h->mlp_mem);
   for (int k = 0; k < 2; ++k)
     if (h->sstate[k]) (void)hipFree(h->sstate[k]);
-  for (int w = 0; w <= FPT_NMAX; ++w)
+  for (int w = 0; w <= kUnits; ++w)
     for (int k = 0; k < 2; ++k)
       if (h->slist[w][k]) (void)hipFree(h->slist[w][k]);
-  for (int w = 0; w <= FPT_NMAX; ++w) {
+  for (int w = 0; w <= kUnits; ++w) {
     if (h->ostream[w]) (void)hipStreamDestroy(h->ostream[w]);
     if (h->ev_join[w]) (void)hipEventDestroy(h->ev_join[w]);
   }
@@ -262,6 +270,8 @@ static fpt_status check_opts(const fpt_opts* o) {
     return fail(FPT_EINVAL, "fpt_solve: unknown method");
   if (o->polish_steps < 0 || o->polish_steps > 8)
     return fail(FPT_EINVAL, "fpt_solve: polish_steps outside 0..8");
+  if (o->split < 0 || o->split > kMaxSplit)
+    return fail(FPT_EINVAL, "fpt_solve: split outside 0..4");
   if (o->early_exit) {
     if (o->stage_iters[0] < 1)
       return fail(FPT_EINVAL, "fpt_solve: early exit needs stage_iters[0] >= 1");
@@ -340,16 +350,40 @@ static fpt_status ensure_states(fpt_handle* h, int64_t N, int n_state) {
   return FPT_OK;
 }
 
-static fpt_status ensure_streams(fpt_handle* h) {
-  if (h->ev_fork) return FPT_OK;
-  for (int w = 1; w <= FPT_NMAX; ++w) {
-    if (hipStreamCreateWithFlags(&h->ostream[w], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_join[w], hipEventDisableTiming) != hipSuccess)
-      return fail(FPT_EHIP, "fpt_solve: stream creation failed");
-  }
-  if (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess)
+// The stream and join event of unit w (and the fork event), created once.
+static fpt_status ensure_stream(fpt_handle* h, int w) {
+  if (!h->ev_fork &&
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess)
     return fail(FPT_EHIP, "fpt_solve: event creation failed");
+  if (h->ostream[w]) return FPT_OK;
+  if (hipStreamCreateWithFlags(&h->ostream[w], hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join[w], hipEventDisableTiming) != hipSuccess)
+    return fail(FPT_EHIP, "fpt_solve: stream creation failed");
   return FPT_OK;
+}
+
+// How a call is scheduled: units on their own streams (several orders with
+// concurrent_orders, or parts of orders) or everything on the caller's
+// stream; and the number of parts per order (split; 0 = 2 parts from 2^21
+// paths on). Early exit keeps one part on the caller's stream (its BFGS
+// states are shared).
+struct SolvePlan {
+  bool multi;  // units on their own streams
+  bool conc;   // one unit per order and part (else per part: the orders of a
+               // part run one after another on its stream)
+  int split;
+  int n_lo;
+  int unit(int n, int part) const { return conc ? unit_of(n, part) : part + 1; }
+};
+
+static SolvePlan solve_plan(const fpt_paths* pa, const fpt_opts* o, bool any_ee) {
+  SolvePlan P;
+  P.n_lo = pa->order ? 1 : pa->n_max;
+  P.split = o->split > 0 ? o->split : (pa->N >= ((int64_t)1 << 21) ? 2 : 1);
+  if (any_ee) P.split = 1;
+  P.conc = !any_ee && o->concurrent_orders && P.n_lo < pa->n_max;
+  P.multi = !any_ee && (P.conc || P.split > 1);
+  return P;
 }
 
 // Does any order of this call run the early-exit stages?
@@ -452,21 +486,30 @@ extern "C" fpt_status fpt_kernel_times(fpt_handle* h, float* ms) {
 // graph capture): order buckets, path lists per list set, early-exit
 // states, and the per-order streams.
 static fpt_status prepare_solve(fpt_handle* h, const fpt_paths* pa, const fpt_opts* o,
-                                bool any_ee, bool concurrent) {
+                                bool any_ee, const SolvePlan& P) {
   fpt_status s;
   if (pa->order) {
     s = ensure_perm(h, pa->N);
     if (s != FPT_OK) return s;
   }
   const bool lists = any_ee || (o->n_levels > 0 && o->quick_steps > 0);
-  if (!lists) return FPT_OK;
-  if (concurrent) {
-    s = ensure_streams(h);
-    if (s != FPT_OK) return s;
-    for (int n = 1; n <= pa->n_max; ++n) {
-      s = ensure_lists(h, pa->N, n);
-      if (s != FPT_OK) return s;
-    }
+  if (!lists) {
+    if (P.multi)
+      for (int n = P.n_lo; n <= pa->n_max; ++n)
+        for (int c = 0; c < P.split; ++c) {
+          s = ensure_stream(h, P.unit(n, c));
+          if (s != FPT_OK) return s;
+        }
+    return FPT_OK;
+  }
+  if (P.multi) {
+    for (int n = P.n_lo; n <= pa->n_max; ++n)
+      for (int c = 0; c < P.split; ++c) {
+        s = ensure_stream(h, P.unit(n, c));
+        if (s != FPT_OK) return s;
+        s = ensure_lists(h, pa->N, P.unit(n, c));
+        if (s != FPT_OK) return s;
+      }
   } else {
     s = ensure_lists(h, pa->N, 0);
     if (s != FPT_OK) return s;
@@ -536,13 +579,13 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
   const bool any_ee = uses_early_exit(h, o, pa->n_max);
   if (any_ee && o->method != FPT_METHOD_BFGS)
     return fail(FPT_EINVAL, "fpt_solve: early exit is a BFGS schedule");
-  const int n_lo = pa->order ? 1 : pa->n_max;  // all buckets, or only n_max
-  // The orders are independent: with several orders (and no early-exit
-  // states, which are shared) each runs on its own stream with its own path
-  // lists, so that the small orders and the latency-bound tails of each
-  // order's passes overlap.
-  const bool concurrent = o->concurrent_orders && n_lo < pa->n_max && !any_ee;
-  s = prepare_solve(h, pa, o, any_ee, concurrent);
+  // The orders, and parts of one order's paths, are independent: each unit
+  // can run on its own stream with its own path lists, so that the small
+  // orders and the latency-bound tails of each unit's passes (collapse step,
+  // full schedule) overlap other units' work.
+  const SolvePlan P = solve_plan(pa, o, any_ee);
+  const int n_lo = P.n_lo;
+  s = prepare_solve(h, pa, o, any_ee, P);
   if (s != FPT_OK) return s;
   const int32_t* perm = nullptr;
   const int64_t* bucket = nullptr;
@@ -554,16 +597,17 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     perm = h->perm;
     bucket = h->bucket;
   }
-  if (concurrent) {
+  if (P.multi) {
     e = hipEventRecord(h->ev_fork, st);
     if (e != hipSuccess) return hip_fail(e, "fpt_solve: event record");
   }
   const int nc = fpt::kRegions * fpt::kCounterStride;
   const int64_t rcap = stage_rcap(pa->N);
-  for (int n = n_lo; n <= pa->n_max; ++n) {
-    const int w = concurrent ? n : 0;               // list set
-    hipStream_t sn = concurrent ? h->ostream[n] : st;
-    if (concurrent) {
+  for (int n = n_lo; n <= pa->n_max; ++n)
+  for (int part = 0; part < P.split; ++part) {
+    const int w = P.multi ? P.unit(n, part) : 0;  // list set and stream
+    hipStream_t sn = P.multi ? h->ostream[w] : st;
+    if (P.multi) {
       e = hipStreamWaitEvent(sn, h->ev_fork, 0);
       if (e != hipSuccess) return hip_fail(e, "fpt_solve: stream wait");
     }
@@ -572,6 +616,8 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     const bool ee = c.use_override ? c.early_exit != 0 : A.early_exit != 0;
     const int32_t* stages = (c.use_override && ee) ? c.stage_iters : o->stage_iters;
     fpt::SolveArgs An = A;
+    An.sub = part;
+    An.nsub = P.split;
     if (c.use_override && c.iters > 0) An.n_iter = c.iters;
     if (c.use_override && c.quick_steps > 0 && A.quick_steps > 0) An.quick_steps = c.quick_steps;
     const int qpasses = (c.use_override && c.quick_passes > 0) ? c.quick_passes : o->quick_passes;
@@ -667,10 +713,10 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
       }
       if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
     }
-    if (concurrent) {
-      e = hipEventRecord(h->ev_join[n], sn);
+    if (P.multi) {
+      e = hipEventRecord(h->ev_join[w], sn);
       if (e != hipSuccess) return hip_fail(e, "fpt_solve: event record");
-      e = hipStreamWaitEvent(st, h->ev_join[n], 0);
+      e = hipStreamWaitEvent(st, h->ev_join[w], 0);
       if (e != hipSuccess) return hip_fail(e, "fpt_solve: stream wait");
     }
   }
@@ -1098,8 +1144,7 @@ extern "C" fpt_status fpt_graph_capture(fpt_handle* h, const fpt_scene* sc,
   // no allocation inside the capture
   {
     const bool any_ee = uses_early_exit(h, o, pa->n_max);
-    const bool concurrent = o->concurrent_orders && pa->order && pa->n_max > 1 && !any_ee;
-    s = prepare_solve(h, pa, o, any_ee, concurrent);
+    s = prepare_solve(h, pa, o, any_ee, solve_plan(pa, o, any_ee));
     if (s != FPT_OK) return s;
   }
   hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);

@@ -89,6 +89,7 @@ struct SolveArgs {
   // options
   int32_t n_iter, fp_iters, early_exit, method;
   int32_t polish_steps;  // FP32 Newton steps at the end of the BFGS phase
+  int32_t sub, nsub;     // this launch is part sub of nsub of its range (sub_range)
   float exit_d2;  // (exit_rtol * scale)^2
   float scale;
   int32_t n_levels;

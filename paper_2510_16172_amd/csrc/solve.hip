@@ -96,6 +96,18 @@ struct RefineOut {
   bool certified, refined, finite;
 };
 
+// Part A.sub of A.nsub equal parts of a launch's range of paths (the parts
+// of one order run on separate streams, so that one part's latency-bound
+// passes overlap the next part's BFGS).
+__device__ __forceinline__ void sub_range(const SolveArgs& A, int64_t& begin,
+                                          int64_t& count) {
+  if (A.nsub > 1) {
+    const int64_t lo = count * A.sub / A.nsub, hi = count * (A.sub + 1) / A.nsub;
+    begin += lo;
+    count = hi - lo;
+  }
+}
+
 // ---------------------------------------------------------------- FP64 ----
 
 // Reads path p's geometry in FP64 and the FP32 1/|a| factors that map the
@@ -1193,10 +1205,11 @@ __global__ __launch_bounds__(kBlock) void bfgs_kernel(
     begin = bucket[NO - 1];
     count = bucket[NO] - begin;
   }
+  sub_range(A, begin, count);
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
        idx += stride) {
-    const int64_t p = perm ? (int64_t)perm[begin + idx] : idx;
+    const int64_t p = perm ? (int64_t)perm[begin + idx] : begin + idx;
     Geo32<NO> G;
     float t0[NO][2];
     bool valid = load_path32<NO>(A, p, G, t0);
@@ -1230,10 +1243,11 @@ __global__ __launch_bounds__(kBlock) void newton32_kernel(
     begin = bucket[NO - 1];
     count = bucket[NO] - begin;
   }
+  sub_range(A, begin, count);
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
        idx += stride) {
-    const int64_t p = perm ? (int64_t)perm[begin + idx] : idx;
+    const int64_t p = perm ? (int64_t)perm[begin + idx] : begin + idx;
     Geo32<NO> G;
     float t0[NO][2];
     const bool valid = load_path32<NO>(A, p, G, t0);
@@ -1296,9 +1310,12 @@ __global__ __launch_bounds__(kBlock) void bfgs_stage_kernel(
     }
     __syncthreads();
     count = pre[kRegions];
-  } else if (bucket) {
-    begin = bucket[NO - 1];
-    count = bucket[NO] - begin;
+  } else {
+    if (bucket) {
+      begin = bucket[NO - 1];
+      count = bucket[NO] - begin;
+    }
+    sub_range(A, begin, count);
   }
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -1315,7 +1332,7 @@ __global__ __launch_bounds__(kBlock) void bfgs_stage_kernel(
       slot_in = (int64_t)lo * St.rcap + (idx - pre[lo]);
     }
     const int64_t p = St.in_list ? (int64_t)St.in_list[slot_in]
-                                 : (perm ? (int64_t)perm[begin + idx] : idx);
+                                 : (perm ? (int64_t)perm[begin + idx] : begin + idx);
     Geo32<NO> G;
     float t0[NO][2];
     const bool valid = load_path32<NO>(A, p, G, t0);
@@ -1425,9 +1442,12 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
     }
     __syncthreads();
     count = pre[kRegions];
-  } else if (bucket) {
-    begin = bucket[NO - 1];
-    count = bucket[NO] - begin;
+  } else {
+    if (bucket) {
+      begin = bucket[NO - 1];
+      count = bucket[NO] - begin;
+    }
+    sub_range(A, begin, count);
   }
   constexpr bool quick = QUICK;
   __shared__ float geo[geo_lds_rows(NO) * kBlock];
@@ -1446,7 +1466,7 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
       }
       p = St.in_list[(int64_t)lo * St.rcap + (idx - pre[lo])];
     } else {
-      p = perm ? (int64_t)perm[begin + idx] : idx;
+      p = perm ? (int64_t)perm[begin + idx] : begin + idx;
     }
     const bool valid = (A.status[p] & FPT_ST_INVALID) == 0;
     GeoLds<NO> D;

@@ -45,7 +45,7 @@ class _Opts(ctypes.Structure):
                 ("stage_iters", ctypes.c_int32 * 4),
                 ("quick_steps", ctypes.c_int32), ("quick_passes", ctypes.c_int32),
                 ("concurrent_orders", ctypes.c_int32), ("method", ctypes.c_int32),
-                ("polish_steps", ctypes.c_int32)]
+                ("polish_steps", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 class _LaunchCfg(ctypes.Structure):
@@ -177,6 +177,7 @@ class Opts:
     concurrent_orders: bool = False
     method: int = 0  # METHOD_BFGS (the paper's) or METHOD_NEWTON32 (variant)
     polish_steps: int = 1
+    split: int = 0  # parts per order on their own streams (0: automatic)
 
     def to_c(self) -> _Opts:
         o = _Opts()
@@ -204,6 +205,7 @@ class Opts:
         o.concurrent_orders = 1 if self.concurrent_orders else 0
         o.method = int(self.method)
         o.polish_steps = int(self.polish_steps)
+        o.split = int(self.split)
         return o
 
 

@@ -445,3 +445,47 @@ def test_no_certificate_at_nonstationary_collapse(solver, oracle_mod):
         print(f"method {method}: cert {s['frac_cert']:.4f} ok {s['frac_ok']:.4f}", flush=True)
         assert s["false_pos"] == 0
         assert s["frac_cert"] > 0.9
+
+
+@pytest.mark.parametrize("with_order", [True, False])
+def test_split_parts_equal_one_part(solver, with_order):
+    """Solving each order in 2, 3 or 4 parts on their own streams gives the
+    same bits as one part (ragged sizes: the parts differ by one path)."""
+    from paper_2510_16172_amd import fpt
+    sc = scenes.canyon_scene()
+    if with_order:
+        b = scenes.canyon_sample_paths(sc, 50001, seed=4900, n=None, n_max=4)
+    else:
+        b = scenes.canyon_sample_paths(sc, 30001, seed=4901, n=3)
+    ref = gpu_util.run_gpu(solver, b, _opts(b.S, iters=10, split=1), with_order=with_order)
+    for k in (2, 3, 4):
+        g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=10, split=k), with_order=with_order)
+        for key in ref:
+            np.testing.assert_array_equal(g[key], ref[key], err_msg=f"split {k} {key}")
+
+
+def test_split_graph_replays_match_eager(solver):
+    """A captured solve in 2 parts per order (streams forked and joined
+    inside the graph) replays to the same bits as the eager solve."""
+    import torch
+    from paper_2510_16172_amd import fpt
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 40000, seed=4902, n=None, n_max=3)
+    opts = _opts(b.S, iters=10, split=2)
+    db = fpt.DeviceBatch(b)
+    eager = {k: v.cpu().numpy() for k, v in solver.solve(db, opts).items()}
+    out = solver.alloc_out(db)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        g = solver.capture(db, opts, out, st)
+    try:
+        for _ in range(3):
+            for v in out.values():
+                v.zero_()
+            torch.cuda.synchronize()
+            g.launch(st)
+            st.synchronize()
+            for k in eager:
+                np.testing.assert_array_equal(out[k].cpu().numpy(), eager[k], err_msg=k)
+    finally:
+        g.close()
