@@ -162,10 +162,12 @@ typedef struct {
 
 enum { FPT_METHOD_BFGS = 0, FPT_METHOD_NEWTON32 = 1 };
 
-/* Defaults: 64 iterations, 1 fixed-point iteration, 1 polish step, no early exit
- * (exit_rtol = 1e-6, stages of 16, 16 and 32 iterations), refinement levels
- * eps/S = 1e-3, 1e-5, 1e-7 (2 steps each) and 1e-9 (3 steps) after a quick
- * pass of 2 steps at 1e-9 (twice: quick_passes = 2), cert_rtol = 1e-5, scale = 1. */
+/* Defaults: the BFGS method, 64 iterations, 1 fixed-point iteration, 1
+ * polish step, no early exit (exit_rtol = 1e-6, stages of 16, 16 and 32
+ * iterations), refinement levels eps/S = 1e-3, 1e-5, 1e-7 (2 steps each) and
+ * 1e-9 (3 steps) after a quick pass of 2 steps at 1e-9 (twice: quick_passes
+ * = 2), cert_rtol = 1e-5, scale = 1, orders one after another, split 0
+ * (automatic). */
 void fpt_default_opts(fpt_opts* opts);
 
 typedef struct {

@@ -489,3 +489,32 @@ def test_split_graph_replays_match_eager(solver):
                 np.testing.assert_array_equal(out[k].cpu().numpy(), eager[k], err_msg=k)
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("polish", [0, 2])
+def test_polish_steps_keep_parity(solver, oracle_mod, polish):
+    """No FP32 polish step, or two: the certificate and the parity bar hold
+    (the polish step only moves where the FP64 refinement starts)."""
+    b = scenes.random_paths(2000, 3, seed=5000 + polish)
+    ref = oracle_mod.solve(b, threads=8)
+    g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=24, polish_steps=polish), with_order=False)
+    _check_common(b, g, ref, min_ok=0.95)
+
+
+@pytest.mark.parametrize("variant", ["one_pass", "no_refinement", "concurrent"])
+def test_split_variants_equal_one_part(solver, variant):
+    """Parts on their own streams with the refinement as one full pass (no
+    lists), with no refinement at all, and together with one stream per
+    order: the same bits as one part on the caller's stream."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 30001, seed=5100, n=None, n_max=5)
+    kw = {"iters": 12}
+    if variant == "one_pass":
+        kw["quick_steps"] = 0
+    elif variant == "no_refinement":
+        kw["level_eps"], kw["level_steps"] = [], []
+    ref = gpu_util.run_gpu(solver, b, _opts(b.S, split=1, **kw))
+    g = gpu_util.run_gpu(solver, b, _opts(b.S, split=2,
+                                          concurrent_orders=(variant == "concurrent"), **kw))
+    for key in ref:
+        np.testing.assert_array_equal(g[key], ref[key], err_msg=f"{variant} {key}")
