@@ -36,7 +36,9 @@ struct Geo64 {
 // Geometry of one lane in LDS: the FP32 scene values (exact in FP64, widened
 // on use) in one column of a [geo_lds_rows(NO)][kBlock] float array, so that
 // the FP64 kernels keep fewer live registers. Rows: TX, RX, then b, a1, a2
-// per slot.
+// per slot. (FP64 values in LDS would save the widening on each use, but
+// double the array, which then limits how many workgroups of the other
+// kernels share the CU.)
 __host__ __device__ constexpr int geo_lds_rows(int NO) { return 6 + 9 * NO; }
 
 template <int NO>
@@ -155,27 +157,6 @@ __device__ __forceinline__ void eval64(const GEO& G, const R* t, R eps2,
   }
 }
 
-// Gradient of the (smoothed) length: g_j = A_j^T (v_j - v_{j+1}); the padded
-// parameter of an edge gets 0.
-template <class GEO, class R = typename GEO::real>
-__device__ __forceinline__ void gradient64(const GEO& G, const R (*v)[3], R* g) {
-  constexpr int NO = GEO::kOrder;
-#pragma unroll
-  for (int j = 0; j < NO; ++j) {
-    R du[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) du[c] = v[j][c] - v[j + 1][c];
-    R a0[3], a1[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      a0[c] = G.a(j, 0, c);
-      a1[c] = G.a(j, 1, c);
-    }
-    g[2 * j] = G.fixed(j) ? R(0) : dot3r(a0, du);
-    g[2 * j + 1] = G.edge(j) ? R(0) : dot3r(a1, du);
-  }
-}
-
 // Solves H d = rhs for the Hessian of the (smoothed) length, given the
 // segments (v, il) at the current point. H is block tridiagonal with 2x2
 // blocks (slot j couples only to j-1 and j+1):
@@ -186,8 +167,12 @@ __device__ __forceinline__ void gradient64(const GEO& G, const R (*v)[3], R* g) 
 // The padded parameter of an edge has a zero row and column in H; its
 // diagonal is set to 1 and its right-hand side to 0, so its d is 0. A fixed
 // slot has both parameters masked that way.
+// With kNewton the right-hand side is minus the gradient of the length at
+// the same segments (rhs is not read): g_j = A_j^T (v_j - v_{j+1}) is the
+// difference of the projections of v_j and v_{j+1} on the object's directions,
+// which the diagonal blocks need anyway.
 // Returns false if a pivot block is not positive definite or d is not finite.
-template <class GEO, class R = typename GEO::real>
+template <bool kNewton = false, class GEO, class R = typename GEO::real>
 __device__ __forceinline__ bool hess_solve64(const GEO& G, const R (*v)[3], const R* il,
                                              const R* rhs, R* d) {
   constexpr int NO = GEO::kOrder;
@@ -208,7 +193,14 @@ __device__ __forceinline__ bool hess_solve64(const GEO& G, const R (*v)[3], cons
     R D00 = (G00 - pin0 * pin0) * il[j] + (G00 - pout0 * pout0) * il[j + 1];
     R D01 = (G01 - pin0 * pin1) * il[j] + (G01 - pout0 * pout1) * il[j + 1];
     R D11 = (G11 - pin1 * pin1) * il[j] + (G11 - pout1 * pout1) * il[j + 1];
-    R rhs0 = rhs[2 * j], rhs1 = rhs[2 * j + 1];
+    R rhs0, rhs1;
+    if constexpr (kNewton) {
+      rhs0 = pout0 - pin0;
+      rhs1 = pout1 - pin1;
+    } else {
+      rhs0 = rhs[2 * j];
+      rhs1 = rhs[2 * j + 1];
+    }
     if (G.edge(j)) {
       D01 = R(0);
       D11 = R(1);

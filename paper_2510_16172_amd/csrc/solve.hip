@@ -197,6 +197,10 @@ __device__ __forceinline__ R max_disp64(const GEO& G, const R* d) {
 // the last step was at most a tenth of the one before (the quadratic
 // contraction of Newton's method near its solution; small steps that do
 // not contract are a slow walk along a flat valley), or below 1e-4 sqrt(cert2).
+// With stop = true the run ends at the first step (its second or later, so
+// that both steps are taken at this smoothing) after which these three hold:
+// the step conditions of the certificate, as they would stand had nsteps
+// been that step count.
 struct NewtonTrack {
   bool prev_small = false, last_small = false, refined = false, contracting = false;
   uint32_t n_eval = 0, n_trial = 0, n_solve = 0;  // evaluations, trial lengths, solves
@@ -227,19 +231,17 @@ __device__ __forceinline__ R length_at(const GEO& G, const R* t, R eps2) {
 
 template <class GEO, class R = typename GEO::real>
 __device__ __forceinline__ void newton_run64(const GEO& G, R* t, R eps2, int nsteps,
-                                             R cert2, bool majorant, NewtonTrack& k) {
+                                             R cert2, bool majorant, NewtonTrack& k,
+                                             bool stop = false) {
   constexpr int NO = GEO::kOrder;
   Seg64<NO, R> cur;
   eval64(G, t, eps2, cur);
   ++k.n_eval;
   for (int st = 0; st < nsteps; ++st) {
     geo_fence();
-    R g[2 * NO], d[2 * NO];
-    gradient64(G, cur.v, g);
-#pragma unroll
-    for (int q = 0; q < 2 * NO; ++q) g[q] = -g[q];
+    R d[2 * NO];
     const R bound = cur.L + RealTraits<R>::rel * fabs(cur.L);
-    const bool ok = hess_solve64(G, cur.v, cur.il, g, d);
+    const bool ok = hess_solve64<true>(G, cur.v, cur.il, (const R*)nullptr, d);
     ++k.n_solve;
     k.prev_small = k.last_small;
     k.last_small = false;
@@ -307,6 +309,12 @@ __device__ __forceinline__ void newton_run64(const GEO& G, R* t, R eps2, int nst
         s *= R(0.25);
       }
     }
+    k.last_small = acc && (s == R(1)) && (d2 <= cert2);
+    k.contracting = acc && (s == R(1)) &&
+                    ((double)d2 <= 1e-2 * k.last_d2 || (double)d2 <= 1e-8 * (double)cert2);
+    k.last_d2 = acc ? (double)(d2 * s * s) : 0.0;
+    k.refined = k.refined || acc;
+    if (stop && st >= 1 && k.prev_small && k.last_small && k.contracting) break;
     // (the segments at t are current unless a length-only trial moved t;
     // after the last step they are not needed: whatever follows evaluates
     // its own)
@@ -315,11 +323,6 @@ __device__ __forceinline__ void newton_run64(const GEO& G, R* t, R eps2, int nst
       eval64(G, t, eps2, cur);
       ++k.n_eval;
     }
-    k.last_small = acc && (s == R(1)) && (d2 <= cert2);
-    k.contracting = acc && (s == R(1)) &&
-                    ((double)d2 <= 1e-2 * k.last_d2 || (double)d2 <= 1e-8 * (double)cert2);
-    k.last_d2 = acc ? (double)(d2 * s * s) : 0.0;
-    k.refined = k.refined || acc;
   }
 }
 
@@ -722,7 +725,7 @@ __device__ __forceinline__ RefineOut refine64(const GEO& G, double* t,
     // (the quick pass, which every path takes, uses the one-evaluation
     // majorant fallback; the paths left for the full schedule backtrack)
     newton_run64(G, t, eps * eps, quick ? A.quick_steps : A.level_steps[lv],
-                     cert2, quick, k);
+                 cert2, quick, k, lv == A.n_levels - 1);
   }
   work[0] += k.n_eval;
   work[1] += k.n_trial;
@@ -814,7 +817,7 @@ __device__ __forceinline__ bool merge64(const GEO& G, double* t,
     const double eps = (double)A.level_eps[A.n_levels - 1] * S;
     const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
     NewtonTrack k;
-    newton_run64(R, tr, eps * eps, 8, cert2, false, k);
+    newton_run64(R, tr, eps * eps, 8, cert2, false, k, true);
     work[0] += k.n_eval;
     work[1] += k.n_trial;
     work[2] += k.n_solve;
@@ -1605,14 +1608,22 @@ __device__ __forceinline__ void sort_bins(const uint8_t* __restrict__ order, int
   }
 }
 
+// A thread's count per bin as eight 6-bit fields of one 64-bit word (at most
+// kSortPer = 32 paths per bin): one shift and one add per path.
+__device__ __forceinline__ uint64_t bin_unit(int b) {
+  return (b >= 0) ? (1ull << (6 * b)) : 0ull;
+}
+__device__ __forceinline__ uint32_t bin_field(uint64_t packed, int b) {
+  return (uint32_t)(packed >> (6 * b)) & 63u;
+}
+
 __device__ __forceinline__ void bin_counts(const int (&bins)[kSortPer],
                                            uint32_t (&cnt)[8]) {
+  uint64_t packed = 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) cnt[k] = 0;
+  for (int q = 0; q < kSortPer; ++q) packed += bin_unit(bins[q]);
 #pragma unroll
-  for (int q = 0; q < kSortPer; ++q)
-#pragma unroll
-    for (int k = 0; k < 8; ++k) cnt[k] += (bins[q] == k) ? 1u : 0u;
+  for (int k = 0; k < 8; ++k) cnt[k] = bin_field(packed, k);
 }
 
 __global__ __launch_bounds__(kBlock) void bucket_count_kernel(
@@ -1655,9 +1666,21 @@ __global__ __launch_bounds__(kBlock) void bucket_scan_kernel(
   const int64_t c0 = (int64_t)threadIdx.x * per;
   const int64_t c1 = min(nchunks, c0 + per);
   unsigned long long sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t c = c0; c < c1; ++c)
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sum[k] += ccount[c * 8 + k];
+  // (a chunk's 8 counts are 32 aligned bytes: two 16-byte loads, several
+  // chunks in flight)
+#pragma unroll 4
+  for (int64_t c = c0; c < c1; ++c) {
+    const uint4 lo = *reinterpret_cast<const uint4*>(ccount + c * 8);
+    const uint4 hi = *reinterpret_cast<const uint4*>(ccount + c * 8 + 4);
+    sum[0] += lo.x;
+    sum[1] += lo.y;
+    sum[2] += lo.z;
+    sum[3] += lo.w;
+    sum[4] += hi.x;
+    sum[5] += hi.y;
+    sum[6] += hi.z;
+    sum[7] += hi.w;
+  }
 #pragma unroll
   for (int k = 0; k < 8; ++k) part[0][threadIdx.x][k] = sum[k];
   __syncthreads();
@@ -1689,20 +1712,31 @@ __global__ __launch_bounds__(kBlock) void bucket_scan_kernel(
   unsigned long long run[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) run[k] = start[k] + part[cur][threadIdx.x][k] - sum[k];
-  for (int64_t c = c0; c < c1; ++c)
-    for (int k = 0; k <= n_max; ++k) {
-      uint32_t v = ccount[c * 8 + k];
-      ccount[c * 8 + k] = (uint32_t)run[k];
-      run[k] += v;
+#pragma unroll 4
+  for (int64_t c = c0; c < c1; ++c) {
+    const uint4 lo = *reinterpret_cast<const uint4*>(ccount + c * 8);
+    const uint4 hi = *reinterpret_cast<const uint4*>(ccount + c * 8 + 4);
+    const uint32_t v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    uint32_t o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      o[k] = (uint32_t)run[k];
+      run[k] += v[k];
     }
+    *reinterpret_cast<uint4*>(ccount + c * 8) = make_uint4(o[0], o[1], o[2], o[3]);
+    *reinterpret_cast<uint4*>(ccount + c * 8 + 4) = make_uint4(o[4], o[5], o[6], o[7]);
+  }
 }
 
 // Scatter: a stable sort of the chunk. Thread t's paths come after those of
 // threads < t in each bin: per-bin exclusive scan of the thread counts over
-// the wave (shuffles) and the waves (LDS). The sorted chunk is staged in LDS
-// (bins one after another, skewed by one slot per 32 against bank
-// conflicts) and copied out with consecutive threads on consecutive
-// addresses: each bin of the chunk is one contiguous run of perm.
+// the wave (shuffles) and the waves (LDS). Each path's place is its thread's
+// start in its bin (kept in LDS, one column per thread) plus the running
+// count of that bin over the thread's earlier paths (packed as in
+// bin_counts). The sorted chunk is staged in LDS (bins one after another,
+// skewed by one slot per 32 against bank conflicts) and copied out with
+// consecutive threads on consecutive addresses: each bin of the chunk is one
+// contiguous run of perm.
 __device__ __forceinline__ int sort_skew(int i) { return i + (i >> 5); }
 
 __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
@@ -1710,7 +1744,9 @@ __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
     const uint32_t* __restrict__ coff, int32_t* __restrict__ perm) {
   __shared__ uint32_t wtot[kBlock / 64][8];
   __shared__ int32_t stage[kSortChunk + kSortChunk / 32];
+  __shared__ int32_t toff[8][kBlock];
   __shared__ int32_t lstart[9];
+  __shared__ uint32_t gstart[8];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
   const int64_t c1 = min(N, c0 + (int64_t)kSortChunk);
@@ -1731,6 +1767,7 @@ __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
   if (lane == 63)
 #pragma unroll
     for (int k = 0; k < 8; ++k) wtot[w][k] = incl[k];
+  if (threadIdx.x < 8) gstart[threadIdx.x] = coff[(int64_t)blockIdx.x * 8 + threadIdx.x];
   __syncthreads();
   if (threadIdx.x == 0) {
     int acc = 0;
@@ -1745,9 +1782,17 @@ __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
   for (int k = 0; k < 8; ++k) {
     int off = lstart[k] + (int)(incl[k] - cnt[k]);
     for (int v = 0; v < w; ++v) off += (int)wtot[v][k];
+    toff[k][threadIdx.x] = off;
+  }
+  // (each thread reads back only its own column: no barrier)
+  uint64_t run = 0;
 #pragma unroll
-    for (int q = 0; q < kSortPer; ++q)
-      if (bins[q] == k) stage[sort_skew(off++)] = (int32_t)(base + q);
+  for (int q = 0; q < kSortPer; ++q) {
+    const int b = bins[q];
+    if (b >= 0) {
+      stage[sort_skew(toff[b][threadIdx.x] + (int)bin_field(run, b))] = (int32_t)(base + q);
+      run += bin_unit(b);
+    }
   }
   __syncthreads();
   const int total = lstart[8];
@@ -1755,7 +1800,7 @@ __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
     int k = 0;
 #pragma unroll
     for (int b = 1; b < 8; ++b) k += (i >= lstart[b]) ? 1 : 0;
-    perm[(int64_t)coff[(int64_t)blockIdx.x * 8 + k] + (i - lstart[k])] = stage[sort_skew(i)];
+    perm[(int64_t)gstart[k] + (i - lstart[k])] = stage[sort_skew(i)];
   }
 }
 
