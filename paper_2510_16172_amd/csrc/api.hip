@@ -603,8 +603,12 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
   }
   const int nc = fpt::kRegions * fpt::kCounterStride;
   const int64_t rcap = stage_rcap(pa->N);
-  for (int n = n_lo; n <= pa->n_max; ++n)
+  // (with parts on streams of their own, odd parts take the orders from the
+  // top down: the short, latency-bound launches of a small order then run
+  // beside another part's large order instead of beside each other)
+  for (int i = 0; i <= pa->n_max - n_lo; ++i)
   for (int part = 0; part < P.split; ++part) {
+    const int n = (P.multi && !P.conc && (part & 1)) ? pa->n_max - i : n_lo + i;
     const int w = P.multi ? P.unit(n, part) : 0;  // list set and stream
     hipStream_t sn = P.multi ? h->ostream[w] : st;
     if (P.multi) {
