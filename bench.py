@@ -94,14 +94,15 @@ def refine_trial_flops(n: int) -> int:
 
 def refine_solve_flops(n: int) -> int:
     """FP64 flops of one Newton step of refine_kernel<n> besides the path
-    evaluations: gradient 13n; block-tridiagonal Hessian assembly and
-    block-Thomas solve 83 per slot + 80 per coupling (slot pairs): Gram
-    and projection dot products 35, diagonal blocks 21, determinant 3,
-    reciprocal 7, inverse 3, back substitution 14 per slot; off-diagonal
-    block 42 and Schur complement 38 per coupling; largest displacement 14n;
-    bound 2; trial point 4n; majorant step along d: point changes 9n,
+    evaluations: gradient 2n (differences of the projections the diagonal
+    blocks use); block-tridiagonal Hessian assembly and block-Thomas solve
+    83 per slot + 74 per coupling (slot pairs): Gram and projection dot
+    products 35, diagonal blocks 21, determinant 3, reciprocal 7, inverse 3,
+    y = S^-1 z 6 and back substitution 8 per slot; off-diagonal block 42,
+    W = S^-1 E 12 and Schur complement 20 per coupling; largest displacement
+    14n; bound 2; trial point 4n; majorant step along d: point changes 9n,
     segment changes 3(n+1), two sums 12(n+1), reciprocal and product 8."""
-    return (13 * n + 83 * n + 80 * (n - 1) + 14 * n + 2 + 4 * n
+    return (2 * n + 83 * n + 74 * (n - 1) + 14 * n + 2 + 4 * n
             + 9 * n + 15 * (n + 1) + 8)
 
 

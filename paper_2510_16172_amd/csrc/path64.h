@@ -176,8 +176,10 @@ template <bool kNewton = false, class GEO, class R = typename GEO::real>
 __device__ __forceinline__ bool hess_solve64(const GEO& G, const R (*v)[3], const R* il,
                                              const R* rhs, R* d) {
   constexpr int NO = GEO::kOrder;
-  R Sinv[NO][3], E[NO][4], z[NO][2];
-  R pSinv[3] = {0, 0, 0}, pE[4] = {0, 0, 0, 0}, pz[2] = {0, 0};
+  // kept for the back substitution d_j = y_j - W_j d_{j+1}:
+  // W_j = S_j^{-1} E_j (rows: slot j's parameters) and y_j = S_j^{-1} z_j
+  R W[NO][4], y[NO][2];
+  R pW[4] = {0, 0, 0, 0}, pE[4] = {0, 0, 0, 0}, py[2] = {0, 0};
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
@@ -212,27 +214,20 @@ __device__ __forceinline__ bool hess_solve64(const GEO& G, const R (*v)[3], cons
       rhs0 = R(0);
     }
     if (j > 0) {
-      // W = S_{j-1}^{-1} E_{j-1}; E rows: parameters of slot j-1
-      R W00 = pSinv[0] * pE[0] + pSinv[1] * pE[2];
-      R W01 = pSinv[0] * pE[1] + pSinv[1] * pE[3];
-      R W10 = pSinv[1] * pE[0] + pSinv[2] * pE[2];
-      R W11 = pSinv[1] * pE[1] + pSinv[2] * pE[3];
-      D00 -= pE[0] * W00 + pE[2] * W10;
-      D01 -= pE[0] * W01 + pE[2] * W11;
-      D11 -= pE[1] * W01 + pE[3] * W11;
-      R w0 = pSinv[0] * pz[0] + pSinv[1] * pz[1];
-      R w1 = pSinv[1] * pz[0] + pSinv[2] * pz[1];
-      rhs0 -= pE[0] * w0 + pE[2] * w1;
-      rhs1 -= pE[1] * w0 + pE[3] * w1;
+      // S_j = D_j - E_{j-1}^T W_{j-1},  z_j = rhs_j - E_{j-1}^T y_{j-1}
+      D00 -= pE[0] * pW[0] + pE[2] * pW[2];
+      D01 -= pE[0] * pW[1] + pE[2] * pW[3];
+      D11 -= pE[1] * pW[1] + pE[3] * pW[3];
+      rhs0 -= pE[0] * py[0] + pE[2] * py[1];
+      rhs1 -= pE[1] * py[0] + pE[3] * py[1];
     }
     R det = D00 * D11 - D01 * D01;
     ok = ok && (det > R(0)) && (D00 > R(0)) && isfinite(det);
     R idet = rcpr(det);
-    Sinv[j][0] = D11 * idet;
-    Sinv[j][1] = -D01 * idet;
-    Sinv[j][2] = D00 * idet;
-    z[j][0] = rhs0;
-    z[j][1] = rhs1;
+    const R S0 = D11 * idet, S1 = -D01 * idet, S2 = D00 * idet;  // S_j^{-1}
+    y[j][0] = S0 * rhs0 + S1 * rhs1;
+    y[j][1] = S1 * rhs0 + S2 * rhs1;
+    R E[4] = {R(0), R(0), R(0), R(0)};
     if (j + 1 < NO) {
       R b0[3], b1[3];
 #pragma unroll
@@ -242,31 +237,32 @@ __device__ __forceinline__ bool hess_solve64(const GEO& G, const R (*v)[3], cons
       }
       R qn0 = dot3r(b0, v[j + 1]), qn1 = dot3r(b1, v[j + 1]);
       R il1 = il[j + 1];
-      E[j][0] = -(dot3r(a0, b0) - pout0 * qn0) * il1;
-      E[j][1] = -(dot3r(a0, b1) - pout0 * qn1) * il1;
-      E[j][2] = -(dot3r(a1, b0) - pout1 * qn0) * il1;
-      E[j][3] = -(dot3r(a1, b1) - pout1 * qn1) * il1;
-      if (G.edge(j)) E[j][2] = E[j][3] = R(0);
-      if (G.edge(j + 1)) E[j][1] = E[j][3] = R(0);
-      if (G.fixed(j)) E[j][0] = E[j][1] = R(0);
-      if (G.fixed(j + 1)) E[j][0] = E[j][2] = R(0);
-    } else {
-      E[j][0] = E[j][1] = E[j][2] = E[j][3] = R(0);
+      E[0] = -(dot3r(a0, b0) - pout0 * qn0) * il1;
+      E[1] = -(dot3r(a0, b1) - pout0 * qn1) * il1;
+      E[2] = -(dot3r(a1, b0) - pout1 * qn0) * il1;
+      E[3] = -(dot3r(a1, b1) - pout1 * qn1) * il1;
+      if (G.edge(j)) E[2] = E[3] = R(0);
+      if (G.edge(j + 1)) E[1] = E[3] = R(0);
+      if (G.fixed(j)) E[0] = E[1] = R(0);
+      if (G.fixed(j + 1)) E[0] = E[2] = R(0);
     }
+    W[j][0] = S0 * E[0] + S1 * E[2];
+    W[j][1] = S0 * E[1] + S1 * E[3];
+    W[j][2] = S1 * E[0] + S2 * E[2];
+    W[j][3] = S1 * E[1] + S2 * E[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) pSinv[k] = Sinv[j][k];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) pE[k] = E[j][k];
-    pz[0] = z[j][0];
-    pz[1] = z[j][1];
+    for (int k = 0; k < 4; ++k) {
+      pW[k] = W[j][k];
+      pE[k] = E[k];
+    }
+    py[0] = y[j][0];
+    py[1] = y[j][1];
   }
   R n0 = R(0), n1 = R(0);
 #pragma unroll
   for (int j = NO - 1; j >= 0; --j) {
-    R c0 = z[j][0] - (E[j][0] * n0 + E[j][1] * n1);
-    R c1 = z[j][1] - (E[j][2] * n0 + E[j][3] * n1);
-    R d0 = Sinv[j][0] * c0 + Sinv[j][1] * c1;
-    R d1 = Sinv[j][1] * c0 + Sinv[j][2] * c1;
+    R d0 = y[j][0] - (W[j][0] * n0 + W[j][1] * n1);
+    R d1 = y[j][1] - (W[j][2] * n0 + W[j][3] * n1);
     if (G.edge(j)) d1 = R(0);
     if (G.fixed(j)) d0 = R(0);
     d[2 * j] = d0;
