@@ -631,9 +631,15 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
       if (!ee) {
         // one path per thread over the whole input, or persistent over the
         // bucket (its size is only known on the device)
+        // (it also clears the counter blocks of the refinement's lists)
         const int ph = An.method == FPT_METHOD_NEWTON32 ? 5 : 0;
         int grid = perm ? persistent(ph, n, c.wg_per_cu) : (int)cap;
-        e = fpt::launch_solve(ph, n, An, perm, bucket, nullptr, grid, sn);
+        fpt::SolveArgs Ab = An;
+        if (An.quick_steps > 0) {
+          Ab.clear = cnt;
+          Ab.clear_n = 4 * nc;
+        }
+        e = fpt::launch_solve(ph, n, Ab, perm, bucket, nullptr, grid, sn);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
       } else {
         int ns = 0;
@@ -669,9 +675,12 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
       int grid = perm ? persistent(1, n, 0) : (int)cap;
       if (An.quick_steps > 0) {
         // stage k lists its uncertified paths in list k & 1 with counter
-        // block k; the blocks are cleared together first
-        e = fpt::launch_zero_u64(cnt, 4 * nc, sn);
-        if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+        // block k; the blocks are cleared together first (by the first
+        // phase's launch unless it ran in early-exit stages, which use them)
+        if (ee) {
+          e = fpt::launch_zero_u64(cnt, 4 * nc, sn);
+          if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+        }
         R.rcap = rcap;
         R.cap = rcap * fpt::kRegions;
         // pass 1: quick steps for all, list the uncertified paths

@@ -102,7 +102,17 @@ struct SolveArgs {
   // refine_kernel, then of merge_kernel's reduced paths; a wave adds to
   // slot blockIdx.x % kWorkSlots so that the atomics do not contend
   unsigned long long* work;
+  // null, or clear_n counters that workgroup 0 of a first-phase launch
+  // zeroes for the refinement passes that follow it on the same stream (in
+  // place of a launch of its own)
+  unsigned long long* clear;
+  int32_t clear_n;
 };
+
+__device__ __forceinline__ void clear_counters(const SolveArgs& A) {
+  if (A.clear && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < A.clear_n; i += kBlock) A.clear[i] = 0ull;
+}
 
 // One early-exit stage of the FP32 solver (see bfgs_stage_kernel).
 struct StageArgs {

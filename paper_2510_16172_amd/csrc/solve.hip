@@ -1203,6 +1203,7 @@ template <int NO>
 __global__ __launch_bounds__(kBlock) void bfgs_kernel(
     SolveArgs A, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ bucket) {
+  clear_counters(A);
   int64_t begin = 0, count = A.N;
   if (bucket) {
     begin = bucket[NO - 1];
@@ -1241,6 +1242,7 @@ template <int NO>
 __global__ __launch_bounds__(kBlock) void newton32_kernel(
     SolveArgs A, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ bucket) {
+  clear_counters(A);
   int64_t begin = 0, count = A.N;
   if (bucket) {
     begin = bucket[NO - 1];
