@@ -405,9 +405,9 @@ def main():
                          "calibrating the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is "
-              "not supported (paths are independent: the design for several "
-              "GPUs shards the path list, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not "
+              "supported (paths are independent: several GPUs would each "
+              "solve a shard of the path list)", file=sys.stderr)
         sys.exit(2)
 
     import torch

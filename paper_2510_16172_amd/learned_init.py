@@ -4,7 +4,8 @@ The network (fpt_mlp_*) maps the geometry of an order-4 path to starting
 parameters; the solver refines them to the same accuracy bar, and paths the
 solver does not certify from the learned start are solved again from T = 0
 (fallback). The plain solver is therefore both the teacher (its certified
-solutions are the training targets) and the judge of the prediction.
+solutions are the training targets) and what decides whether a prediction
+was good enough.
 """
 from __future__ import annotations
 
