@@ -99,3 +99,16 @@ def test_newton32_rejects_early_exit(solver):
     b = scenes.random_paths(64, 2, seed=8500)
     with pytest.raises(fpt.FptError):
         gpu_util.run_gpu(solver, b, _opts(b.S, iters=8, early_exit=True), with_order=False)
+
+
+def test_newton32_two_parts_equal_one(solver):
+    """The FP32 Newton first phase with each order's paths in two parts on
+    their own streams (the first phase then clears the refinement's list
+    counters, and the second part takes the orders from the top down) gives
+    the same bits as one part."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 30001, seed=8600, n=None, n_max=4)
+    one = gpu_util.run_gpu(solver, b, _opts(b.S, iters=8, split=1))
+    two = gpu_util.run_gpu(solver, b, _opts(b.S, iters=8, split=2))
+    for key in one:
+        np.testing.assert_array_equal(two[key], one[key], err_msg=key)

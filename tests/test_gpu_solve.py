@@ -518,3 +518,15 @@ def test_split_variants_equal_one_part(solver, variant):
                                           concurrent_orders=(variant == "concurrent"), **kw))
     for key in ref:
         np.testing.assert_array_equal(g[key], ref[key], err_msg=f"{variant} {key}")
+
+
+def test_three_quick_steps_keep_parity(solver, oracle_mod):
+    """Three quick steps per path (the run may stop after the second once the
+    certificate's step conditions hold): no certified path is wrong and the
+    parity bar holds, on the canyon paths with their collapsed minimisers."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 4000, seed=5200, n=2)
+    ref = oracle_mod.solve(b, threads=8)
+    g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=12, quick_steps=3, quick_passes=1),
+                         with_order=False)
+    _check_common(b, g, ref, min_ok=0.95)
