@@ -36,8 +36,11 @@ __device__ __forceinline__ void acc_add(float* lds_base, float* glob, int64_t id
     unsafeAtomicAdd(glob + idx, v);
 }
 
+// (three slots: the compiler's register choice lands two VGPRs above what
+// three waves per SIMD allow; asked for three it fits them without spilling)
 template <int NO>
-__global__ __launch_bounds__(kBlock) void grad_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NO == 3 ? 3 : 1)))
+void grad_kernel(
     GradArgs A, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ bucket) {
   extern __shared__ float sh[];  // [9K] object gradient, then [3Q] points
