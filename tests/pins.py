@@ -191,3 +191,88 @@ def batch_from_paths(paths, S):
     obj = np.array(cols, np.float32).T.copy()
     pts = np.array(P, np.float32).T.copy()
     return Batch(obj, pts, src, dst, order, ids, float(S))
+
+
+def _span_basis(a1, a2):
+    """Orthonormal basis (3 x d) of an object's directions (d = 1 for an
+    edge, whose second vector is zero padding)."""
+    if not np.any(a2 != 0):
+        return (a1 / np.linalg.norm(a1))[:, None]
+    q, _ = np.linalg.qr(np.stack([a1, a2], 1))
+    return q
+
+
+def collapse_runs(xs, S, tol=1e-6):
+    """Runs of coinciding interaction points of a path xs = [x_0..x_{n+1}]:
+    lists of slot indices j (point x_{j+1}) joined by segments shorter than
+    tol * S. Endpoint segments never join (x_0, x_{n+1} are not slots)."""
+    n = len(xs) - 2
+    ell = np.linalg.norm(np.diff(xs, axis=0), axis=1)
+    runs, j = [], 0
+    while j < n:
+        run = [j]
+        while j + 1 < n and ell[j + 1] < tol * S:
+            j += 1
+            run.append(j)
+        runs.append(run)
+        j += 1
+    return runs, ell
+
+
+def run_subgradient(objs_run, u_in, u_out):
+    """Optimality of a run of coinciding points x_a = ... = x_b (Sec. III-B:
+    L is a sum of norms, convex in T, so T is a minimiser iff 0 lies in the
+    subdifferential of L). The zero-length segment between slots s and s+1
+    contributes any w_s with |w_s| <= 1; with u_in (u_out) the unit vector of
+    the segment into x_a (out of x_b), stationarity of every point of the run
+    along its object reads
+        P_a (u_in - w_a) = 0,  P_s (w_{s-1} - w_s) = 0,  P_b (w_{b-1} - u_out) = 0
+    (P_s = orthogonal projector onto object s's directions). Returns the
+    least-norm solution w (numpy least squares on the stacked constraints),
+    the constraint residual and max_s |w_s|. For one zero-length segment the
+    least-norm w is also the one of least |w|, so max |w| <= 1 decides
+    optimality exactly; for longer runs it is a sufficient test."""
+    Qs = [_span_basis(a1, a2) for (_, a1, a2) in objs_run]
+    r = len(Qs)
+    m = 3 * (r - 1)
+    rows, rhs = [], []
+    for s, Q in enumerate(Qs):
+        for k in range(Q.shape[1]):
+            q = Q[:, k]
+            row = np.zeros(m)
+            if s < r - 1:
+                row[3 * s:3 * s + 3] -= q       # -w_s
+            if s > 0:
+                row[3 * (s - 1):3 * s] += q     # +w_{s-1}
+            rows.append(row)
+            rhs.append(-(q @ u_in) if s == 0 else 0.0)
+            if s == r - 1:
+                rhs[-1] += q @ u_out
+    C = np.array(rows)
+    b = np.array(rhs)
+    w = np.linalg.lstsq(C, b, rcond=1e-12)[0]
+    res = float(np.abs(C @ w - b).max())
+    wn = np.linalg.norm(w.reshape(r - 1, 3), axis=1)
+    return w.reshape(r - 1, 3), res, float(wn.max())
+
+
+def subgradient_optimality(tx, rx, objs, xs, S, tol=1e-6):
+    """0 in the subdifferential of L at the points xs = [x_0..x_{n+1}]:
+    (max stationarity residual over smooth slots and runs, max |w| over the
+    zero-length segments, or 0 when there is none)."""
+    runs, ell = collapse_runs(xs, S, tol)
+    r = np.diff(xs, axis=0)
+    u = r / np.where(ell > 0, ell, 1.0)[:, None]
+    res, wmax = 0.0, 0.0
+    for run in runs:
+        a, b = run[0], run[-1]
+        if ell[a] < tol * S or ell[b + 1] < tol * S:
+            raise ValueError("a point coincides with TX or RX")
+        if len(run) == 1:
+            Q = _span_basis(*objs[a][1:])
+            res = max(res, float(np.abs(Q.T @ (u[a] - u[a + 1])).max()))
+        else:
+            _, rr, wm = run_subgradient([objs[k] for k in run], u[a], u[b + 1])
+            res = max(res, rr)
+            wmax = max(wmax, wm)
+    return res, wmax

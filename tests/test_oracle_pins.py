@@ -30,15 +30,21 @@ def test_golden_hand_worked(oracle_mod):
              for c in cases]
     b = pins.batch_from_paths(paths, S=10.0)
     r = _solve(oracle_mod, b)
+    want = {"collapsed pass-through at a corner line",
+            "straight through the corner of three planes",
+            "ground reflection then a corner line"}
     for i, c in enumerate(cases):
         n = len(c["objects"])
-        np.testing.assert_allclose(r["x"][i, :n], np.array(c["x"]), atol=1e-9,
+        # smooth minimisers: the smoothing (eps = 1e-15 S at the last level)
+        # moves a point by O(eps); where points coincide by O(eps^(2/3)),
+        # about 1e-10 S
+        atol = 1e-9 * b.S if c["name"] in want else 1e-9
+        np.testing.assert_allclose(r["x"][i, :n], np.array(c["x"]), atol=atol,
                                    err_msg=c["name"])
         assert abs(r["len"][i] - c["L"]) < 1e-12, c["name"]
     names = [c["name"] for c in cases]
     collapsed = r["flags"] & oracle_mod.COLLAPSED != 0
-    assert collapsed[names.index("collapsed pass-through at a corner line")]
-    assert collapsed.sum() == 1
+    assert {names[i] for i in np.nonzero(collapsed)[0]} == want
 
 
 def test_single_reflection_image_method(oracle_mod):
@@ -115,8 +121,10 @@ def test_brute_force_tiny(oracle_mod):
 
 
 def _check_optimality(oracle_mod, b, r, rng):
-    """Stationarity, reflection / Keller-cone laws, bounds."""
+    """Stationarity, reflection / Keller-cone laws, subgradients at
+    collapsed minimisers, bounds. Returns the number of collapsed paths."""
     probes = 0
+    collapsed = 0
     for i in range(b.N):
         tx, rx, objs = pins.path_geometry(b, i)
         n = len(objs)
@@ -130,6 +138,13 @@ def _check_optimality(oracle_mod, b, r, rng):
             np.testing.assert_allclose(bb + tt[0] * a1 + tt[1] * a2, x,
                                        atol=1e-12 * b.S)
         if r["flags"][i] & oracle_mod.COLLAPSED:
+            # nonsmooth minimiser: 0 must lie in the subdifferential of the
+            # convex L (Sec. III-B, Eq. 5), i.e. every zero-length segment has
+            # a subgradient w, |w| <= 1, that makes all points stationary
+            res, wmax = pins.subgradient_optimality(tx, rx, objs, xs, b.S)
+            assert res < 1e-9, (i, res)
+            assert 0.0 < wmax <= 1.0 + 1e-9, (i, wmax)
+            collapsed += 1
             continue
         for j, (bb, a1, a2) in enumerate(objs):
             du = u[j] - u[j + 1]
@@ -155,24 +170,26 @@ def _check_optimality(oracle_mod, b, r, rng):
         ok = b.order > 0
         assert np.all(r["len"][ok] <= L[ok] + 1e-12 * b.S)
         probes += ok.sum()
-    return probes
+    return collapsed
 
 
 def test_optimality_random(oracle_mod):
     rng = np.random.default_rng(5)
-    for n in (1, 2, 3, 5):
+    for n in (1, 2, 3, 5, 6):
         b = scenes.random_paths(300, n, seed=50 + n)
         r = _solve(oracle_mod, b)
-        _check_optimality(oracle_mod, b, r, rng)
+        ncol = _check_optimality(oracle_mod, b, r, rng)
+        assert n == 1 or ncol >= 30
 
 
 def test_optimality_canyon(oracle_mod):
     rng = np.random.default_rng(6)
     sc = scenes.canyon_scene()
-    for n in (1, 2, 3, 6):
+    for n in (1, 2, 3, 5, 6):
         b = scenes.canyon_sample_paths(sc, 400, seed=60 + n, n=n)
         r = _solve(oracle_mod, b)
-        _check_optimality(oracle_mod, b, r, rng)
+        ncol = _check_optimality(oracle_mod, b, r, rng)
+        assert n == 1 or ncol >= 30
 
 
 def test_reversal_symmetry(oracle_mod):
@@ -437,3 +454,40 @@ def test_validity_crossing_vs_linear_solve(oracle_mod):
     keep = np.array(keep)
     assert keep.sum() > 390 and 0.2 < np.mean(want) < 0.9
     np.testing.assert_array_equal(got[keep], np.array(want)[keep])
+
+
+def test_subgradient_pin_catches_displaced_collapse(oracle_mod):
+    """The subgradient check above is sharp: moving a run of coinciding
+    points together along a direction they share (a collapse that is no
+    longer stationary) or opening the zero-length segment fails it."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 400, seed=63, n=3)
+    r = _solve(oracle_mod, b)
+    moved = opened = 0
+    for i in np.nonzero(r["flags"] & oracle_mod.COLLAPSED)[0]:
+        tx, rx, objs = pins.path_geometry(b, i)
+        xs = np.vstack([tx, r["x"][i, :3], rx])
+        runs, _ = pins.collapse_runs(xs, b.S)
+        run = next((q for q in runs if len(q) == 2), None)
+        if run is None:
+            continue
+        Qa = pins._span_basis(*objs[run[0]][1:])
+        Qb = pins._span_basis(*objs[run[1]][1:])
+        # a direction in both objects (their meeting line), if any
+        M = Qa @ Qa.T + Qb @ Qb.T
+        ev, V = np.linalg.eigh(M)
+        if ev[-1] > 2.0 - 1e-9:
+            e = V[:, -1]
+            ys = xs.copy()
+            for k in run:
+                ys[k + 1] += 1e-3 * b.S * e
+            res, _ = pins.subgradient_optimality(tx, rx, objs, ys, b.S)
+            assert res > 1e-5
+            moved += 1
+        # open the collapse: the first point moves within its own object
+        ys = xs.copy()
+        ys[run[0] + 1] += 1e-3 * b.S * Qa[:, 0]
+        res, _ = pins.subgradient_optimality(tx, rx, objs, ys, b.S)
+        assert res > 1e-5
+        opened += 1
+    assert moved >= 10 and opened >= 30
