@@ -182,7 +182,9 @@ typedef struct {
  * *h receives the handle, or NULL on error. */
 fpt_status fpt_create(int device, fpt_handle** h);
 
-/* Frees the handle and its workspace (synchronises the device first). */
+/* Frees the handle and its workspace (synchronises the device first).
+ * FPT_EINVAL (and nothing freed) while a graph captured on the handle
+ * (fpt_graph_capture) has not been destroyed. */
 fpt_status fpt_destroy(fpt_handle* h);
 
 /* Solves every path (Sec. III-B Eq. 4 by the BFGS / fixed-point method of
@@ -300,7 +302,11 @@ fpt_status fpt_set_launch(fpt_handle* h, int order, const fpt_launch_cfg* cfg);
  * the given pointers and options: replays read and write the same buffers.
  * The handle's workspace is sized before the capture; counters are cleared
  * by kernels inside the graph (no memset nodes), so a replay can follow any
- * other work. fpt_graph_launch replays it on `hip_stream`. */
+ * other work. fpt_graph_launch replays it on `hip_stream`.
+ * The graph also records the handle's workspace. Until it is destroyed, a
+ * call on the handle that would grow (and so free) a workspace buffer the
+ * graph uses returns FPT_EINVAL and launches nothing, and fpt_destroy is
+ * refused; capture the largest problem first, or use one handle per size. */
 typedef struct fpt_graph fpt_graph;
 fpt_status fpt_graph_capture(fpt_handle* h, const fpt_scene* scene,
                              const fpt_paths* paths, const fpt_opts* opts,

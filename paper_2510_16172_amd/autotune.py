@@ -7,9 +7,9 @@ the one with the most certified-converged paths per second of that order's
 kernels (BFGS + refinement, timed with the library's HIP-event timers). The
 iteration count trades FP32 BFGS time against FP64 refinement time: paths
 the BFGS leaves further from the minimiser need more Newton steps. Results are
-cached in a JSON file keyed by GPU architecture, first-phase method,
-candidate set, order, and a power-of-two bucket of the sample size, and
-applied with fpt_set_launch.
+cached in a JSON file keyed by GPU architecture, a digest of the built
+library, a digest of every solver option, the candidate set, the order, and
+a power-of-two bucket of the sample size, and applied with fpt_set_launch.
 """
 from __future__ import annotations
 
@@ -41,9 +41,31 @@ def default_cache_path() -> str:
     return os.path.join(base, "fpt", "autotune.json")
 
 
-def _key(arch: str, order: int, n: int, method: int, candidates) -> str:
+_LIB_DIGEST = None
+
+
+def _lib_digest() -> str:
+    """Digest of the built library: a rebuild (changed kernels, certificate
+    or defaults) invalidates every cached choice."""
+    global _LIB_DIGEST
+    if _LIB_DIGEST is None:
+        from . import fpt
+        with open(fpt.LIB_PATH, "rb") as fh:
+            _LIB_DIGEST = hashlib.sha1(fh.read()).hexdigest()[:12]
+    return _LIB_DIGEST
+
+
+def _opts_digest(opts) -> str:
+    """Digest of every solver option (the C struct's bytes): iteration and
+    fixed-point counts, polish steps, refinement levels, tolerances, split."""
+    import ctypes
+    c = opts.to_c()
+    return hashlib.sha1(ctypes.string_at(ctypes.addressof(c), ctypes.sizeof(c))).hexdigest()[:12]
+
+
+def _key(arch: str, order: int, n: int, opts, candidates) -> str:
     tag = hashlib.sha1(json.dumps(candidates, sort_keys=True).encode()).hexdigest()[:8]
-    return (f"v4/{arch}/m{method}/c{tag}/order{order}/"
+    return (f"v5/{arch}/lib{_lib_digest()}/o{_opts_digest(opts)}/c{tag}/order{order}/"
             f"n2^{max(0, int(np.log2(max(n, 1))))}")
 
 
@@ -65,7 +87,7 @@ def tune(solver, batch, opts, candidates=None, sample=1 << 18, repeats=3,
     chosen = {}
     for n in sorted(set(int(v) for v in np.unique(batch.order))):
         idx = np.nonzero(batch.order == n)[0]
-        key = _key(arch, n, len(idx), int(getattr(opts, "method", 0)), candidates)
+        key = _key(arch, n, len(idx), opts, candidates)
         if key in cache:
             chosen[n] = cache[key]["cfg"]
             continue

@@ -82,6 +82,9 @@ struct fpt_handle {
   // learned-initialiser activations (grown on demand)
   fpt::MlpWork mlp = {};
   void* mlp_mem = nullptr;
+  // captured graphs that record this handle's solve workspace: while any
+  // exists, the workspace is neither grown nor freed
+  int live_graphs = 0;
 };
 
 static thread_local std::string g_err;
@@ -96,6 +99,7 @@ static fpt_status hip_fail(hipError_t e, const char* what) {
 }
 
 extern "C" const char* fpt_last_error(void) { return g_err.c_str(); }
+
 
 extern "C" void fpt_default_opts(fpt_opts* o) {
   if (!o) return;
@@ -193,6 +197,8 @@ extern "C" fpt_status fpt_create(int device, fpt_handle** out) {
 
 extern "C" fpt_status fpt_destroy(fpt_handle* h) {
   if (!h) return FPT_OK;
+  if (h->live_graphs > 0)
+    return fail(FPT_EINVAL, "fpt_destroy: captured graphs still use this handle");
   DeviceGuard g(h->device);
   (void)hipDeviceSynchronize();
   if (h->perm) (void)hipFree(h->perm);
@@ -282,8 +288,17 @@ static fpt_status check_opts(const fpt_opts* o) {
   return FPT_OK;
 }
 
+// A captured graph holds the addresses of the solve workspace: growing it
+// (which frees the old buffers) would leave the graph writing freed memory.
+static fpt_status refuse_growth(const fpt_handle*) {
+  return fail(FPT_EINVAL,
+              "the handle's workspace must grow, but a captured graph records it: "
+              "destroy the graphs first (or capture with the largest size first)");
+}
+
 static fpt_status ensure_perm(fpt_handle* h, int64_t N) {
   if (h->perm_cap >= N) return FPT_OK;
+  if (h->perm && h->live_graphs > 0) return refuse_growth(h);
   if (h->perm) (void)hipFree(h->perm);
   if (h->ccount) (void)hipFree(h->ccount);
   h->perm = nullptr;
@@ -315,6 +330,7 @@ static int64_t stage_rcap(int64_t N) {
 static fpt_status ensure_lists(fpt_handle* h, int64_t N, int w) {
   const int64_t rcap = stage_rcap(N);
   if (h->list_cap[w] >= rcap) return FPT_OK;
+  if (h->slist[w][0] && h->live_graphs > 0) return refuse_growth(h);
   for (int k = 0; k < 2; ++k) {
     if (h->slist[w][k]) (void)hipFree(h->slist[w][k]);
     h->slist[w][k] = nullptr;
@@ -334,6 +350,7 @@ static fpt_status ensure_states(fpt_handle* h, int64_t N, int n_state) {
   const int64_t rcap = stage_rcap(N);
   const int64_t need = n_state > 0 ? (int64_t)fpt::stage_fields_for(n_state) * rcap * fpt::kRegions : 0;
   if (h->stage_state_cap >= need && h->state_rcap >= rcap) return FPT_OK;
+  if (h->sstate[0] && h->live_graphs > 0) return refuse_growth(h);
   for (int k = 0; k < 2; ++k) {
     if (h->sstate[k]) (void)hipFree(h->sstate[k]);
     h->sstate[k] = nullptr;
@@ -517,25 +534,61 @@ static fpt_status prepare_solve(fpt_handle* h, const fpt_paths* pa, const fpt_op
   return ensure_states(h, pa->N, any_ee ? pa->n_max : 0);
 }
 
-extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
-                                const fpt_paths* pa, const fpt_opts* o,
-                                const fpt_out* out, void* stream) {
-  if (!h) return fail(FPT_EINVAL, "fpt_solve: handle is NULL");
-  fpt_status s = check_common(sc, pa, "fpt_solve");
+// Checks of an fpt_solve call.
+static fpt_status check_solve(const fpt_handle* h, const fpt_scene* sc,
+                              const fpt_paths* pa, const fpt_opts* o,
+                              const fpt_out* out, const char* fn) {
+  const std::string f(fn);
+  if (!h) return fail(FPT_EINVAL, f + ": handle is NULL");
+  fpt_status s = check_common(sc, pa, fn);
   if (s != FPT_OK) return s;
   s = check_opts(o);
   if (s != FPT_OK) return s;
-  if (!out) return fail(FPT_EINVAL, "fpt_solve: out is NULL");
+  if (!out) return fail(FPT_EINVAL, f + ": out is NULL");
   if (pa->N == 0) return FPT_OK;
   if (!out->x || !out->len || !out->t || !out->status || !out->iters)
-    return fail(FPT_EINVAL, "fpt_solve: an output pointer is NULL");
+    return fail(FPT_EINVAL, f + ": an output pointer is NULL");
   if (!aligned(out->x, 4) || !aligned(out->len, 4) || !aligned(out->t, 4) ||
       !aligned(out->iters, 2))
-    return fail(FPT_EINVAL, "fpt_solve: misaligned output pointer");
-  DeviceGuard g(h->device);
-  if (!g.ok) return fail(FPT_EHIP, "fpt_solve: hipSetDevice failed");
-  hipStream_t st = (hipStream_t)stream;
+    return fail(FPT_EINVAL, f + ": misaligned output pointer");
+  if (uses_early_exit(h, o, pa->n_max) && o->method != FPT_METHOD_BFGS)
+    return fail(FPT_EINVAL, f + ": early exit is a BFGS schedule");
+  return FPT_OK;
+}
 
+// Device buffers one solve works in: the order sort (perm, per-chunk counts,
+// bucket bounds), the path-list counters (four blocks of kRegions counters,
+// kCounterStride apart, per list set), the two ping-pong path lists of each
+// list set, and the early-exit BFGS states.
+struct SolveWs {
+  int32_t* perm;
+  uint32_t* ccount;
+  int64_t* bucket;
+  unsigned long long* scount;
+  int32_t* slist[kUnits + 1][2];
+  float* sstate[2];
+};
+
+static SolveWs handle_ws(const fpt_handle* h) {
+  SolveWs W;
+  memset(&W, 0, sizeof(W));
+  W.perm = h->perm;
+  W.ccount = h->ccount;
+  W.bucket = h->bucket;
+  W.scount = h->scount;
+  for (int w = 0; w <= kUnits; ++w)
+    for (int k = 0; k < 2; ++k) W.slist[w][k] = h->slist[w][k];
+  W.sstate[0] = h->sstate[0];
+  W.sstate[1] = h->sstate[1];
+  return W;
+}
+
+// The launches of one solve on stream st, with the plan P (which units run
+// on streams of their own; their streams exist) in the workspace W (sized
+// for pa->N).
+static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths* pa,
+                            const fpt_opts* o, const fpt_out* out, hipStream_t st,
+                            const SolvePlan& P, const SolveWs& W) {
   fpt::SolveArgs A;
   memset(&A, 0, sizeof(A));
   A.obj = sc->obj;
@@ -576,26 +629,16 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     int64_t g = (int64_t)h->num_cu * (wg_per_cu > 0 ? wg_per_cu : h->occ[ph][n]);
     return (int)(g < cap ? g : cap);
   };
-  const bool any_ee = uses_early_exit(h, o, pa->n_max);
-  if (any_ee && o->method != FPT_METHOD_BFGS)
-    return fail(FPT_EINVAL, "fpt_solve: early exit is a BFGS schedule");
-  // The orders, and parts of one order's paths, are independent: each unit
-  // can run on its own stream with its own path lists, so that the small
-  // orders and the latency-bound tails of each unit's passes (collapse step,
-  // full schedule) overlap other units' work.
-  const SolvePlan P = solve_plan(pa, o, any_ee);
   const int n_lo = P.n_lo;
-  s = prepare_solve(h, pa, o, any_ee, P);
-  if (s != FPT_OK) return s;
   const int32_t* perm = nullptr;
   const int64_t* bucket = nullptr;
   if (pa->order) {
     SlotTimer tm(h, FPT_T_BUCKET, st);
-    e = fpt::launch_bucketing(pa->order, pa->N, pa->n_max, h->ccount,
-                              h->bucket, h->perm, st);
+    e = fpt::launch_bucketing(pa->order, pa->N, pa->n_max, W.ccount,
+                              W.bucket, W.perm, st);
     if (e != hipSuccess) return hip_fail(e, "fpt_solve: bucketing launch");
-    perm = h->perm;
-    bucket = h->bucket;
+    perm = W.perm;
+    bucket = W.bucket;
   }
   if (P.multi) {
     e = hipEventRecord(h->ev_fork, st);
@@ -615,7 +658,7 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
       e = hipStreamWaitEvent(sn, h->ev_fork, 0);
       if (e != hipSuccess) return hip_fail(e, "fpt_solve: stream wait");
     }
-    unsigned long long* cnt = h->scount + (size_t)w * 4 * nc;  // 4 stage blocks
+    unsigned long long* cnt = W.scount + (size_t)w * 4 * nc;  // 4 stage blocks
     const fpt_launch_cfg& c = h->cfg[n];
     const bool ee = c.use_override ? c.early_exit != 0 : A.early_exit != 0;
     const int32_t* stages = (c.use_override && ee) ? c.stage_iters : o->stage_iters;
@@ -651,14 +694,14 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
           S.cap = rcap * fpt::kRegions;
           S.iters = stages[k];
           if (k > 0) {
-            S.in_list = h->slist[w][(k - 1) & 1];
+            S.in_list = W.slist[w][(k - 1) & 1];
             S.in_count = cnt + ((k - 1) & 1) * nc;
-            S.state_in = h->sstate[(k - 1) & 1];
+            S.state_in = W.sstate[(k - 1) & 1];
           }
           if (k + 1 < ns) {
-            S.out_list = h->slist[w][k & 1];
+            S.out_list = W.slist[w][k & 1];
             S.out_count = cnt + (k & 1) * nc;
-            S.state_out = h->sstate[k & 1];
+            S.state_out = W.sstate[k & 1];
             e = fpt::launch_zero_u64(S.out_count, nc, sn);
             if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
           }
@@ -684,7 +727,7 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
         R.rcap = rcap;
         R.cap = rcap * fpt::kRegions;
         // pass 1: quick steps for all, list the uncertified paths
-        R.out_list = h->slist[w][0];
+        R.out_list = W.slist[w][0];
         R.out_count = cnt;
         e = fpt::launch_solve(1, n, An, perm, bucket, &R, perm ? persistent(4, n, 0) : (int)cap,
                               sn);
@@ -695,9 +738,9 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
           memset(&Q, 0, sizeof(Q));
           Q.rcap = R.rcap;
           Q.cap = R.cap;
-          Q.in_list = h->slist[w][k & 1];
+          Q.in_list = W.slist[w][k & 1];
           Q.in_count = cnt + k * nc;
-          Q.out_list = h->slist[w][(k + 1) & 1];
+          Q.out_list = W.slist[w][(k + 1) & 1];
           Q.out_count = cnt + (k + 1) * nc;
           ++k;
           return fpt::launch_solve(phase, n, An, nullptr, nullptr, &Q, grid_x, sn);
@@ -717,7 +760,7 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
         memset(&R2, 0, sizeof(R2));
         R2.rcap = R.rcap;
         R2.cap = R.cap;
-        R2.in_list = h->slist[w][k & 1];
+        R2.in_list = W.slist[w][k & 1];
         R2.in_count = cnt + k * nc;
         // pass 2: the full schedule on the list
         e = fpt::launch_solve(1, n, An, perm, bucket, &R2, persistent(1, n, 0), sn);
@@ -734,10 +777,29 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
     }
   }
   if (pa->order) {
-    e = fpt::launch_invalid(A, h->perm, h->bucket, h->num_cu * 4, st);
+    e = fpt::launch_invalid(A, W.perm, W.bucket, h->num_cu * 4, st);
     if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
   }
   return FPT_OK;
+}
+
+
+extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
+                                const fpt_paths* pa, const fpt_opts* o,
+                                const fpt_out* out, void* stream) {
+  fpt_status s = check_solve(h, sc, pa, o, out, "fpt_solve");
+  if (s != FPT_OK || pa->N == 0) return s;
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(FPT_EHIP, "fpt_solve: hipSetDevice failed");
+  const bool any_ee = uses_early_exit(h, o, pa->n_max);
+  // The orders, and parts of one order's paths, are independent: each unit
+  // can run on its own stream with its own path lists, so that the small
+  // orders and the latency-bound tails of each unit's passes (collapse step,
+  // full schedule) overlap other units' work.
+  const SolvePlan P = solve_plan(pa, o, any_ee);
+  s = prepare_solve(h, pa, o, any_ee, P);
+  if (s != FPT_OK) return s;
+  return solve_run(h, sc, pa, o, out, (hipStream_t)stream, P, handle_ws(h));
 }
 
 // LDS budget of the per-workgroup accumulation of the scene gradient
@@ -1136,6 +1198,7 @@ extern "C" fpt_status fpt_set_launch(fpt_handle* h, int order,
 
 struct fpt_graph {
   int device;
+  fpt_handle* h = nullptr;  // whose workspace the graph records
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -1178,6 +1241,8 @@ extern "C" fpt_status fpt_graph_capture(fpt_handle* h, const fpt_scene* sc,
   }
   fpt_graph* G = new fpt_graph();
   G->device = h->device;
+  G->h = h;
+  h->live_graphs += 1;
   G->graph = graph;
   G->exec = exec;
   *g = G;
@@ -1197,6 +1262,7 @@ extern "C" fpt_status fpt_graph_destroy(fpt_graph* g) {
   DeviceGuard dg(g->device);
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->h) g->h->live_graphs -= 1;
   delete g;
   return FPT_OK;
 }

@@ -716,7 +716,6 @@ template <class GEO>
 __device__ __forceinline__ RefineOut refine64(const GEO& G, double* t,
                                               const SolveArgs& A, bool quick,
                                               uint32_t (&work)[3]) {
-  constexpr int NO = GEO::kOrder;
   const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
   NewtonTrack k;
   const int lv0 = quick ? A.n_levels - 1 : 0;

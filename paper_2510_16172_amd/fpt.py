@@ -297,7 +297,7 @@ class Solver:
 
     def close(self):
         if getattr(self, "_h", None):
-            load_library().fpt_destroy(self._h)
+            _check(load_library().fpt_destroy(self._h), "fpt_destroy")
             self._h = None
 
     def __del__(self):
@@ -396,7 +396,7 @@ class Solver:
             self._h, ctypes.byref(sc), ctypes.byref(pa), ctypes.byref(oc),
             ctypes.byref(ou), _stream_ptr(stream), ctypes.byref(g)),
             "fpt_graph_capture")
-        return Graph(g, keep=(db, opts, out))
+        return Graph(g, keep=(self, db, opts, out))
 
     def alloc_out(self, db: DeviceBatch):
         import torch
@@ -493,7 +493,9 @@ class Graph:
 
     def __init__(self, handle, keep):
         self._g = handle
-        self._keep = keep  # buffers the graph reads and writes
+        # the solver whose workspace the graph records (destroyed after the
+        # graph), and the buffers the graph reads and writes
+        self._keep = keep
 
     def launch(self, stream=None):
         _check(load_library().fpt_graph_launch(self._g, _stream_ptr(stream)),

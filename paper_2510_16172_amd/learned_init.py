@@ -65,7 +65,9 @@ def train(solver, mlp, db: fpt.DeviceBatch, target, scale: float, epochs: int,
 
 def evaluate(solver, mlp, db: fpt.DeviceBatch, opts, repeats: int = 3):
     """Zero start vs learned start (+ fallback) on db. Returns statistics and
-    timings (HIP events on the current stream)."""
+    timings (HIP events on the current stream), the zero-start outputs, and
+    the learned-start outputs in which every path the learned start left
+    uncertified carries the result of the fallback solve from T = 0."""
     import torch
     st = torch.cuda.current_stream()
 
@@ -108,6 +110,11 @@ def evaluate(solver, mlp, db: fpt.DeviceBatch, opts, repeats: int = 3):
     c1 = int(cert1.sum().item())
     it0 = out0["iters"].cpu().numpy().astype(np.int64)
     it1 = out1["iters"].cpu().numpy().astype(np.int64)
+    if fb.numel() > 0:
+        # the fallback's results replace the learned start's at its paths
+        # (path index last in every output array)
+        for k in out1:
+            out1[k][..., fb] = outf[k]
     N = db.N
     res = {
         "paths": N,

@@ -530,3 +530,40 @@ def test_three_quick_steps_keep_parity(solver, oracle_mod):
     g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=12, quick_steps=3, quick_passes=1),
                          with_order=False)
     _check_common(b, g, ref, min_ok=0.95)
+
+
+def test_graph_keeps_its_workspace():
+    """While a captured graph records a handle's workspace, a call that
+    would grow (and so free) it is refused, and so is destroying the handle;
+    after the graph is destroyed both work, and the replay before that still
+    gives the eager result."""
+    import torch
+    from paper_2510_16172_amd import fpt
+    s = fpt.Solver(0)
+    sc = scenes.canyon_scene()
+    small = scenes.canyon_sample_paths(sc, 5000, seed=4310, n=None, n_max=4)
+    big = scenes.canyon_sample_paths(sc, 50000, seed=4311, n=None, n_max=4)
+    opts = _opts(small.S, iters=16)
+    dbs, dbb = fpt.DeviceBatch(small), fpt.DeviceBatch(big)
+    eager = s.solve(dbs, opts)
+    torch.cuda.synchronize()
+    eager = {k: v.cpu().numpy() for k, v in eager.items()}
+    st = torch.cuda.Stream()
+    out = s.alloc_out(dbs)
+    with torch.cuda.stream(st):
+        graph = s.capture(dbs, opts, out, st)
+    with pytest.raises(fpt.FptError, match="captured graph"):
+        s.solve(dbb, opts)
+    with pytest.raises(fpt.FptError, match="captured graphs"):
+        s.close()
+    # a solve that fits the recorded workspace is fine
+    s.solve(fpt.DeviceBatch(small.subset(np.arange(1000))), opts)
+    torch.cuda.synchronize()
+    graph.launch(st)
+    st.synchronize()
+    for k in eager:
+        np.testing.assert_array_equal(out[k].cpu().numpy(), eager[k], err_msg=k)
+    graph.close()
+    s.solve(dbb, opts)
+    torch.cuda.synchronize()
+    s.close()
