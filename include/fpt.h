@@ -197,6 +197,26 @@ fpt_status fpt_solve(fpt_handle* h, const fpt_scene* scene,
                      const fpt_paths* paths, const fpt_opts* opts,
                      const fpt_out* out, void* hip_stream);
 
+/* Allocation-free variant of fpt_solve, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). Same arguments, outputs and
+ * per-path results as fpt_solve (bit for bit), but it never calls hipMalloc
+ * or hipFree: its workspace (the order sort and the refinement's path lists)
+ * is a fixed array of device memory that the library holds on each GPU from
+ * the first fpt_create on that device until the process ends, sized for
+ * fpt_noalloc_max_paths() paths (2^20; about 12.7 MB). Limits: N above that
+ * maximum, or early exit in opts or in a launch configuration of the handle,
+ * return FPT_EINVAL and launch nothing. Every unit runs on hip_stream (the
+ * split and concurrent_orders options do not apply). Every call on one GPU
+ * shares that array, and it keeps the last call's contents: calls that
+ * overlap on one GPU (on different streams, or from different handles or
+ * threads) race and must be ordered by the caller. The kernels clear what
+ * must start at zero. */
+fpt_status fpt_solve_noalloc(fpt_handle* h, const fpt_scene* scene,
+                             const fpt_paths* paths, const fpt_opts* opts,
+                             const fpt_out* out, void* hip_stream);
+int64_t fpt_noalloc_max_paths(void);
+
 /* Implicit-differentiation backward pass (Sec. III-D, Eqs. 8-13) at the
  * solution `fwd` of fpt_solve, for the loss
  *     sum_i g_len[i] * len[i] + sum_{i,j} g_x[j][:][i] . x[j][:][i].

@@ -3,6 +3,7 @@
 // kernels on the caller's stream.
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -85,6 +86,8 @@ struct fpt_handle {
   // captured graphs that record this handle's solve workspace: while any
   // exists, the workspace is neither grown nor freed
   int live_graphs = 0;
+  // this device's copy of the allocation-free solve's scratch array
+  unsigned char* scratch = nullptr;
 };
 
 static thread_local std::string g_err;
@@ -100,6 +103,7 @@ static fpt_status hip_fail(hipError_t e, const char* what) {
 
 extern "C" const char* fpt_last_error(void) { return g_err.c_str(); }
 
+static fpt_status scratch_address(int device, unsigned char** out);
 
 extern "C" void fpt_default_opts(fpt_opts* o) {
   if (!o) return;
@@ -191,6 +195,15 @@ extern "C" fpt_status fpt_create(int device, fpt_handle** out) {
     return fail(FPT_ENOMEM, "fpt_create: workspace allocation failed");
   }
   h->scount = (unsigned long long*)p;
+  {
+    fpt_status ss = scratch_address(device, &h->scratch);
+    if (ss != FPT_OK) {
+      (void)hipFree(h->counts);
+      (void)hipFree(h->scount);
+      delete h;
+      return ss;
+    }
+  }
   *out = h;
   return FPT_OK;
 }
@@ -534,7 +547,7 @@ static fpt_status prepare_solve(fpt_handle* h, const fpt_paths* pa, const fpt_op
   return ensure_states(h, pa->N, any_ee ? pa->n_max : 0);
 }
 
-// Checks of an fpt_solve call.
+// Checks shared by fpt_solve and fpt_solve_noalloc.
 static fpt_status check_solve(const fpt_handle* h, const fpt_scene* sc,
                               const fpt_paths* pa, const fpt_opts* o,
                               const fpt_out* out, const char* fn) {
@@ -800,6 +813,83 @@ extern "C" fpt_status fpt_solve(fpt_handle* h, const fpt_scene* sc,
   s = prepare_solve(h, pa, o, any_ee, P);
   if (s != FPT_OK) return s;
   return solve_run(h, sc, pa, o, out, (hipStream_t)stream, P, handle_ws(h));
+}
+
+// ------------------------------------------------ allocation-free solve ----
+// fpt_solve_noalloc works in a fixed array of device memory, `scratch`, in
+// place of the handle's growing workspace: the order sort, one list set's
+// counters and its two path lists, sized for kNoAllocPaths paths. Each GPU
+// holds its own copy for the life of the process. In host code the array's
+// name is not a device address: fpt_create looks up this device's copy once
+// (hipGetSymbolAddress) and every use goes through that address.
+static const int64_t kNoAllocPaths = (int64_t)1 << 20;
+static const size_t kNaPermOff = 0;
+static const size_t kNaCcountOff = kNaPermOff + (size_t)kNoAllocPaths * sizeof(int32_t);
+static const size_t kNaBucketOff =
+    kNaCcountOff + (size_t)(kNoAllocPaths / fpt::kSortChunk) * 8 * sizeof(uint32_t);
+static const size_t kNaCountOff = kNaBucketOff + 256;
+static const size_t kNaCountBytes =
+    (size_t)4 * fpt::kRegions * fpt::kCounterStride * sizeof(unsigned long long);
+static const size_t kNaListOff = kNaCountOff + kNaCountBytes;
+static const size_t kNaListBytes =
+    (size_t)64 * (kNoAllocPaths / (64 * fpt::kRegions) + 1) * fpt::kRegions * sizeof(int32_t);
+static const size_t kNoAllocBytes = kNaListOff + 2 * kNaListBytes;
+static_assert(kNoAllocPaths % fpt::kSortChunk == 0, "whole sort chunks");
+static_assert(kNaListBytes % 256 == 0 && kNaCountBytes % 256 == 0, "aligned parts");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// This device's address of `scratch`, looked up once per device (the
+// caller's device is current).
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_dev[64] = {};
+
+static fpt_status scratch_address(int device, unsigned char** out) {
+  *out = nullptr;
+  if (device < 0 || device >= 64)
+    return fail(FPT_EUNSUPPORTED, "fpt_create: device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "fpt_create: hipGetSymbolAddress(scratch)");
+    if (!p) return fail(FPT_EHIP, "fpt_create: no device address for scratch");
+    g_scratch_dev[device] = (unsigned char*)p;
+  }
+  *out = g_scratch_dev[device];
+  return FPT_OK;
+}
+
+extern "C" int64_t fpt_noalloc_max_paths(void) { return kNoAllocPaths; }
+
+extern "C" fpt_status fpt_solve_noalloc(fpt_handle* h, const fpt_scene* sc,
+                                        const fpt_paths* pa, const fpt_opts* o,
+                                        const fpt_out* out, void* stream) {
+  fpt_status s = check_solve(h, sc, pa, o, out, "fpt_solve_noalloc");
+  if (s != FPT_OK || pa->N == 0) return s;
+  if (pa->N > kNoAllocPaths)
+    return fail(FPT_EINVAL, "fpt_solve_noalloc: N above fpt_noalloc_max_paths() (2^20)");
+  if (uses_early_exit(h, o, pa->n_max))
+    return fail(FPT_EINVAL, "fpt_solve_noalloc: early exit needs the handle's workspace");
+  if (!h->scratch) return fail(FPT_EHIP, "fpt_solve_noalloc: scratch address unknown");
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(FPT_EHIP, "fpt_solve_noalloc: hipSetDevice failed");
+  // every unit on the caller's stream, one list set (the results do not
+  // depend on the split or on concurrent orders)
+  SolvePlan P = solve_plan(pa, o, false);
+  P.multi = false;
+  P.conc = false;
+  P.split = 1;
+  SolveWs W;
+  memset(&W, 0, sizeof(W));
+  unsigned char* base = h->scratch;
+  W.perm = (int32_t*)(base + kNaPermOff);
+  W.ccount = (uint32_t*)(base + kNaCcountOff);
+  W.bucket = (int64_t*)(base + kNaBucketOff);
+  W.scount = (unsigned long long*)(base + kNaCountOff);
+  W.slist[0][0] = (int32_t*)(base + kNaListOff);
+  W.slist[0][1] = (int32_t*)(base + kNaListOff + kNaListBytes);
+  return solve_run(h, sc, pa, o, out, (hipStream_t)stream, P, W);
 }
 
 // LDS budget of the per-workgroup accumulation of the scene gradient

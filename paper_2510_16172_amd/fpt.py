@@ -71,7 +71,8 @@ EXPORTED = ["fpt_default_opts", "fpt_create", "fpt_destroy", "fpt_solve",
             "fpt_mlp_state_floats", "fpt_mlp_init", "fpt_mlp_train_step",
             "fpt_mlp_infer", "fpt_set_launch", "fpt_graph_capture",
             "fpt_graph_launch", "fpt_graph_destroy", "fpt_validate",
-            "fpt_work_counts", "fpt_enum_count", "fpt_enumerate"]
+            "fpt_work_counts", "fpt_enum_count", "fpt_enumerate",
+            "fpt_solve_noalloc", "fpt_noalloc_max_paths"]
 
 # timer slots of fpt_kernel_times
 T_BUCKET, T_BFGS, T_REFINE, T_GRAD, T_REDUCE, T_MLP, T_VALIDATE, TIMERS = (
@@ -104,6 +105,10 @@ def load_library(path: str = LIB_PATH):
                               ctypes.POINTER(_Paths), ctypes.POINTER(_Opts),
                               ctypes.POINTER(_Out), _P]
     lib.fpt_solve.restype = ctypes.c_int
+    lib.fpt_solve_noalloc.argtypes = lib.fpt_solve.argtypes
+    lib.fpt_solve_noalloc.restype = ctypes.c_int
+    lib.fpt_noalloc_max_paths.argtypes = []
+    lib.fpt_noalloc_max_paths.restype = ctypes.c_int64
     lib.fpt_grad.argtypes = [_P, ctypes.POINTER(_Scene),
                              ctypes.POINTER(_Paths), ctypes.POINTER(_Out),
                              _P, _P, _P, _P, _P, _P, _P]
@@ -428,6 +433,27 @@ class Solver:
                                         ctypes.byref(ou), _stream_ptr(stream)),
                "fpt_solve")
         return out
+
+    def solve_noalloc(self, db: DeviceBatch, opts: Opts | None = None, out=None,
+                      stream=None):
+        """fpt_solve_noalloc: fpt_solve in the library's fixed per-GPU
+        scratch memory (no device allocation by the library; at most
+        noalloc_max_paths() paths, no early exit, every unit on `stream`).
+        `out` is allocated here by torch if it is not given."""
+        if opts is None:
+            opts = Opts(scale=db.S)
+        if out is None:
+            out = self.alloc_out(db)
+        sc, pa, oc, ou = db.c_scene(), db.c_paths(), opts.to_c(), self.c_out(out)
+        _check(load_library().fpt_solve_noalloc(self._h, ctypes.byref(sc),
+                                                ctypes.byref(pa), ctypes.byref(oc),
+                                                ctypes.byref(ou), _stream_ptr(stream)),
+               "fpt_solve_noalloc")
+        return out
+
+    @staticmethod
+    def noalloc_max_paths() -> int:
+        return int(load_library().fpt_noalloc_max_paths())
 
     def grad(self, db: DeviceBatch, fwd, g_len=None, g_x=None, g_pts=None,
              g_obj=None, g_slot=None, g_end=None, stream=None):
