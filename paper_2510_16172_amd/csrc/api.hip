@@ -742,41 +742,47 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
         // pass 1: quick steps for all, list the uncertified paths
         R.out_list = W.slist[w][0];
         R.out_count = cnt;
-        e = fpt::launch_solve(1, n, An, perm, bucket, &R, perm ? persistent(4, n, 0) : (int)cap,
+        e = fpt::launch_solve(4, n, An, perm, bucket, &R, perm ? persistent(4, n, 0) : (int)cap,
                               sn);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         int k = 0;  // the stage whose list is current
-        auto next_stage = [&](int phase, int grid_x) -> hipError_t {
+        // stage k reads list k & 1 with counter block k, and (unless it is
+        // the last) lists what it leaves in list (k + 1) & 1 with block k + 1;
+        // at most four blocks: quick pass, second quick pass, collapse step,
+        // full schedule
+        auto next_stage = [&](int phase, int grid_x, bool last, int mode) -> hipError_t {
           fpt::StageArgs Q;
           memset(&Q, 0, sizeof(Q));
           Q.rcap = R.rcap;
           Q.cap = R.cap;
           Q.in_list = W.slist[w][k & 1];
           Q.in_count = cnt + k * nc;
-          Q.out_list = W.slist[w][(k + 1) & 1];
-          Q.out_count = cnt + (k + 1) * nc;
+          if (!last) {
+            Q.out_list = W.slist[w][(k + 1) & 1];
+            Q.out_count = cnt + (k + 1) * nc;
+          }
+          Q.mode = mode;
           ++k;
           return fpt::launch_solve(phase, n, An, nullptr, nullptr, &Q, grid_x, sn);
         };
         if (qpasses > 1) {
           // second quick pass on the paths the first did not certify
-          e = next_stage(1, persistent(4, n, 0));
+          e = next_stage(4, persistent(4, n, 0), false, 0);
           if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         }
         if (n >= 2) {
-          // collapsed minimisers: merge attempt on the list, the rest listed
-          // again for pass 2
-          e = next_stage(3, persistent(3, n, 0));
+          // collapsed minimisers from the quick pass's point: merge attempt on
+          // the list, the rest listed again for the full schedule
+          e = next_stage(3, persistent(3, n, 0), false, 0);
           if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         }
-        fpt::StageArgs R2;
-        memset(&R2, 0, sizeof(R2));
-        R2.rcap = R.rcap;
-        R2.cap = R.cap;
-        R2.in_list = W.slist[w][k & 1];
-        R2.in_count = cnt + k * nc;
-        // pass 2: the full schedule on the list
-        e = fpt::launch_solve(1, n, An, perm, bucket, &R2, persistent(1, n, 0), sn);
+        // the full schedule on the list; with n >= 2 it lists the paths it
+        // leaves uncertified for a last collapse step from its own output,
+        // where a collapse has come close enough to be told from a short
+        // segment
+        e = next_stage(1, persistent(1, n, 0), n < 2, 0);
+        if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+        if (n >= 2) e = next_stage(3, persistent(3, n, 0), true, 1);
       } else {
         e = fpt::launch_solve(1, n, An, perm, bucket, &R, grid, sn);
       }

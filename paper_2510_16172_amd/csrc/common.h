@@ -125,6 +125,8 @@ struct StageArgs {
   int64_t cap;                          // kRegions * rcap: state field stride
   int64_t rcap;                         // slots per region
   int32_t iters;
+  int32_t mode;                         // collapse step: 0 after the quick
+                                        // pass, 1 after the full schedule
 };
 
 // Arguments of one fpt_grad call.

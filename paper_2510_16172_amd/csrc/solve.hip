@@ -330,13 +330,13 @@ __device__ __forceinline__ void newton_run64(const GEO& G, R* t, R eps2, int nst
 // At many minimisers two consecutive interaction points coincide (e.g. a
 // reflection on a face at the edge that bounds it). The length is not
 // differentiable there and the smoothed Newton iteration approaches such a
-// point slowly, so refine64 does not certify it. merge64 handles a single
-// such collapse: if exactly one interior segment is short, its two points a,
-// b = a + 1 become one point on the intersection of their objects (a line, a
-// point, or a plane for two coplanar planes), the reduced path of order
-// NO - 1 is solved by the same Newton iteration and certificate, and the
-// collapse is certified optimal if some w with |w| < 1 (|w|^2 <= 1 - 1e-6)
-// satisfies the stationarity of both original points,
+// point slowly, so refine64 does not certify it. The collapse step
+// (merge_runs64 below) makes the two points a, b = a + 1 of a short interior
+// segment one point on the intersection of their objects (a line, a point,
+// or a plane for two coplanar planes), solves the reduced path by the same
+// Newton iteration and certificate, and certifies the collapse as optimal if
+// some w with |w| < 1 (|w|^2 <= 1 - 1e-6) satisfies the stationarity of both
+// original points,
 //   A_a^T (u_in - w) = 0,   A_b^T (w - u_out) = 0,
 // where u_in, u_out are the unit vectors of the segments entering a and
 // leaving b. Such a w is a subgradient of the zero-length segment's length,
@@ -644,10 +644,14 @@ __device__ __forceinline__ bool subgradient_ok64(const GEO& G, int a, const doub
 // subgradient test of its two objects: next to a collapse the smoothed
 // length is curved like 1 / eps, so Newton steps are tiny there whether or
 // not the point is stationary, and small steps alone prove nothing.
+// nlast < NO: only segments 0..nlast are checked and nlast is the last one
+// (a reduced path whose slots past nlast - 1 are fixed at RX); with
+// allow_collapse false any collapse fails the check.
 template <class GEO>
 __device__ __forceinline__ bool nonsmooth_ok64(const GEO& G,
                                                const double* t, double eps,
-                                               double scale) {
+                                               double scale, int nlast = GEO::kOrder,
+                                               bool allow_collapse = true) {
   constexpr int NO = GEO::kOrder;
   const double short2 = 1e-6 * scale * scale;
   double x[NO][3];
@@ -656,6 +660,7 @@ __device__ __forceinline__ bool nonsmooth_ok64(const GEO& G,
   int ncol = 0, a = 0;
 #pragma unroll
   for (int i = 0; i <= NO; ++i) {
+    if (i > nlast) continue;
     double r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -664,13 +669,14 @@ __device__ __forceinline__ bool nonsmooth_ok64(const GEO& G,
     double q = dot3d(r, r);
     const bool flat = q > (0.98 * 0.98) * (q + eps * eps);
     if (q < short2 && flat) ok = false;
-    if (q < short2 && !flat && i > 0 && i < NO) {
+    if (q < short2 && !flat && (i == 0 || i == nlast)) ok = false;
+    if (q < short2 && !flat && i > 0 && i < nlast) {
       ++ncol;
       a = i - 1;
     }
   }
   if (!ok || ncol == 0) return ok;
-  if (ncol > 1) return false;
+  if (ncol > 1 || !allow_collapse) return false;
   if constexpr (NO < 2) {
     return false;
   } else {
@@ -742,126 +748,519 @@ __device__ __forceinline__ RefineOut refine64(const GEO& G, double* t,
   return o;
 }
 
+// ------------------------------------------- several collapsed segments ---
+// merge_runs64 takes any number of collapses. Every
+// interior segment shorter than short_rel * S is taken as collapsed, and
+// each run of consecutive collapsed segments (at most two: three coinciding
+// points) becomes one point on the intersection of the run's objects, found
+// object by object (a plane, a line or a point; the run fails if they do not
+// meet). The reduced path has NO minus the number of collapsed segments
+// slots. It is held in a Geo64<NO - 1> whose unused trailing slots are
+// points fixed at RX: the segments between them have zero length and no free
+// parameter (the smoothed length gains a constant), so the Newton iteration,
+// its certificate and the smoothness check run on it unchanged. Then every
+// run must pass the subgradient test of run_subgradient64.
+
+// An affine flat: origin o and orthonormal directions q (rows beyond dim are
+// zero); dim 0 is a point, 1 a line, 2 a plane.
+struct Flat64 {
+  double o[3], q[2][3];
+  int dim;
+};
+
+// The flat of slot j's object (j may be a run-time index: the geometry is
+// read through the accessors, from LDS for a GeoLds). An edge has a zero
+// second vector.
 template <class GEO>
-__device__ __forceinline__ bool merge64(const GEO& G, double* t,
-                                        const SolveArgs& A, uint32_t (&work)[3]) {
+__device__ __forceinline__ Flat64 flat_of64(const GEO& G, int j) {
+  double a[2][3];
+  Flat64 F;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    a[0][c] = G.a(j, 0, c);
+    a[1][c] = G.a(j, 1, c);
+    F.o[c] = G.b(j, c);
+  }
+  const bool edge = a[1][0] == 0.0 && a[1][1] == 0.0 && a[1][2] == 0.0;
+  const Basis64 B = basis64(a, edge);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    F.q[0][c] = B.q[0][c];
+    F.q[1][c] = B.q[1][c];
+  }
+  F.dim = B.line ? 1 : 2;
+  return F;
+}
+
+__device__ __forceinline__ Basis64 basis_of_flat(const Flat64& F) {
+  Basis64 B;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    B.q[0][c] = F.q[0][c];
+    B.q[1][c] = F.q[1][c];
+  }
+  cross3d(F.q[0], F.q[1], B.n);
+  B.line = F.dim == 1;
+  return B;
+}
+
+// The intersection X of two flats near ymid (see intersect64): false if they
+// do not meet within tol, or meet further than sqrt(far2) from ymid. A point
+// meets a flat if it lies on it within tol.
+__device__ __forceinline__ bool meet64(const Flat64& U, const Flat64& V,
+                                       const double* ymid, double tol, double far2,
+                                       Flat64& X) {
+  if (U.dim == 0 || V.dim == 0) {
+    const bool up = U.dim == 0;
+    double m[3], po[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      po[c] = up ? U.o[c] : V.o[c];
+      m[c] = po[c] - (up ? V.o[c] : U.o[c]);
+    }
+    double d2 = dot3d(m, m);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      double qk[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) qk[c] = up ? V.q[k][c] : U.q[k][c];
+      const double pk = dot3d(m, qk);
+      d2 -= pk * pk;
+    }
+    if (!(d2 < tol * tol)) return false;
+    double g[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      X.o[c] = po[c];
+      X.q[0][c] = X.q[1][c] = 0.0;
+      g[c] = ymid[c] - po[c];
+    }
+    X.dim = 0;
+    return dot3d(g, g) < far2;
+  }
+  Virt64 W;
+  if (!intersect64(basis_of_flat(U), U.o, basis_of_flat(V), V.o, ymid, tol, far2, W))
+    return false;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    X.o[c] = W.y0[c];
+    X.q[0][c] = W.e[0][c];
+    X.q[1][c] = W.e[1][c];
+  }
+  X.dim = W.dim;
+  return true;
+}
+
+// The subgradient test of a run of m = 2 or 3 coinciding points whose
+// objects have the orthonormal bases Q_i (rows of F[i].q; an edge has one):
+// the segments between them have zero length, u_in enters the first point
+// and u_out leaves the last. Point i is stationary along its object if
+//   Q_i^T (w_i - w_{i+1}) = 0,   w_0 = u_in,  w_m = u_out,
+// for subgradients w_1 .. w_{m-1} of the zero-length segments. The least-norm
+// solution is w_j = Q_j mu_j - Q_{j-1} mu_{j-1} with M mu = h, where
+// M = C C^T of the constraint matrix C is block tridiagonal (I at the two
+// ends of the diagonal, 2 I inside, -Q_i^T Q_{i+1} beside it),
+// h_0 = -Q_0^T u_in and h_{m-1} = Q_{m-1}^T u_out. M is singular along
+// nu_e = (Q_i^T e)_i for every direction e common to all the objects (E, the
+// run's flat); adding nu_e nu_e^T for each leaves w unchanged and makes M
+// positive definite. The run passes (0 is returned) if the w satisfy every
+// equation (the reduced path is stationary along E) and each has
+// |w_j|^2 <= 1 - 1e-6: then 0 is a subgradient of L at the point (L is convex
+// in T), in the same way as subgradient_ok64 for a single collapse.
+// Otherwise bit j - 1 is set for each w_j above that bound (the segment
+// would open: moving the points apart shortens the path), and bit 2 if the
+// equations are not met.
+__device__ __forceinline__ unsigned run_subgradient64(const Flat64 (&F)[3], int m,
+                                                      const double* uin, const double* uout,
+                                                      const Flat64& E) {
+  constexpr int NB = 6;
+  double M[NB][NB], h[NB];
+  bool act[3][2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) act[i][k] = i < m && k < F[i].dim;
+#pragma unroll
+  for (int r = 0; r < NB; ++r) {
+    h[r] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) M[r][c] = 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double ci = (i == 0 || i == m - 1) ? 1.0 : 2.0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      M[2 * i + k][2 * i + k] = act[i][k] ? ci : 1.0;
+      const double pin = dot3d(F[i].q[k], uin), pout = dot3d(F[i].q[k], uout);
+      h[2 * i + k] = !act[i][k] ? 0.0 : (i == 0 ? -pin : (i == m - 1 ? pout : 0.0));
+    }
+    if (i + 1 < 3) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+          const double v = (act[i][k] && act[i + 1][l]) ? -dot3d(F[i].q[k], F[i + 1].q[l]) : 0.0;
+          M[2 * i + k][2 * (i + 1) + l] = v;
+          M[2 * (i + 1) + l][2 * i + k] = v;
+        }
+    }
+  }
+  // deflation along the common directions
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    if (e >= E.dim) continue;
+    double nu[NB];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) nu[2 * i + k] = act[i][k] ? dot3d(F[i].q[k], E.q[e]) : 0.0;
+#pragma unroll
+    for (int r = 0; r < NB; ++r)
+#pragma unroll
+      for (int c = 0; c < NB; ++c) M[r][c] = fma(nu[r], nu[c], M[r][c]);
+  }
+  // Cholesky M = L L^T in place (lower triangle), then the two solves
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    double d = M[j][j];
+#pragma unroll
+    for (int p = 0; p < j; ++p) d -= M[j][p] * M[j][p];
+    if (!(d > 1e-12)) return 4u;
+    const double il = rsq64(d);
+    M[j][j] = d * il;
+#pragma unroll
+    for (int r = j + 1; r < NB; ++r) {
+      double v = M[r][j];
+#pragma unroll
+      for (int p = 0; p < j; ++p) v -= M[r][p] * M[j][p];
+      M[r][j] = v * il;
+    }
+  }
+  double mu[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) {
+    double v = h[r];
+#pragma unroll
+    for (int p = 0; p < r; ++p) v -= M[r][p] * mu[p];
+    mu[r] = v * rcp64(M[r][r]);
+  }
+#pragma unroll
+  for (int r = NB - 1; r >= 0; --r) {
+    double v = mu[r];
+#pragma unroll
+    for (int p = r + 1; p < NB; ++p) v -= M[p][r] * mu[p];
+    mu[r] = v * rcp64(M[r][r]);
+  }
+  // w_j (j = 1, 2; w_0 = u_in, w_m = u_out), Q mu of each point
+  double qm[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      qm[i][c] = (act[i][0] ? mu[2 * i] * F[i].q[0][c] : 0.0) +
+                 (act[i][1] ? mu[2 * i + 1] * F[i].q[1][c] : 0.0);
+  double w[4][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    w[0][c] = uin[c];
+    w[1][c] = qm[1][c] - qm[0][c];
+    w[2][c] = (m == 2) ? uout[c] : qm[2][c] - qm[1][c];
+    w[3][c] = uout[c];
+  }
+  unsigned open = 0u;
+  double res = 0.0;
+#pragma unroll
+  for (int j = 1; j <= 2; ++j)
+    if (j < m && !(dot3d(w[j], w[j]) <= 1.0 - 1e-6)) open |= 1u << (j - 1);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (i >= m) continue;
+    double dlt[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dlt[c] = w[i][c] - w[i + 1][c];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const double rk = act[i][k] ? dot3d(F[i].q[k], dlt) : 0.0;
+      res = fma(rk, rk, res);
+    }
+  }
+  return open | (res <= 1e-10 ? 0u : 4u);
+}
+
+// Collapsed segments are taken as those shorter than kMergeShortQuick * S
+// from the quick pass's point, and kMergeShortFull * S from the full
+// schedule's output or a reduced solution.
+constexpr double kMergeShortQuick = 6e-2, kMergeShortFull = 1e-3;
+
+// Interior segments of the path at t shorter than sqrt(short2): bit i for
+// segment i (slots i - 1 and i); *endshort if the first or last one is.
+template <class GEO>
+__device__ __forceinline__ unsigned short_segments64(const GEO& G, const double* t,
+                                                     double short2, bool* endshort) {
   constexpr int NO = GEO::kOrder;
+  double x[NO][3];
+  points64(G, t, x);
+  unsigned z = 0u;
+  bool es = false;
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      r[c] = ((i == NO) ? G.rx(c) : x[i][c]) - ((i == 0) ? G.tx(c) : x[i - 1][c]);
+    const bool sh = dot3d(r, r) < short2;
+    if (i == 0 || i == NO)
+      es = es || sh;
+    else
+      z |= sh ? (1u << i) : 0u;
+  }
+  *endshort = es;
+  return z;
+}
+
+// Collapsed minimisers with one or more collapses (see above). t (caller's
+// parametrisation) is the start point; on success it holds the certified
+// minimiser. The collapsed set is found in rounds, as in an active-set
+// method: the first merges the segments shorter than short_rel * S and
+// solves the reduced path at the last smoothing level. If that is not
+// certified, the next round changes the set and solves again after two
+// smoothing levels (1e-4 S, 1e-6 S) from the reduced solution mapped back to
+// the full path: a segment whose subgradient exceeds norm 1 is taken out (a
+// short segment that is not collapsed: it is never merged again), and the
+// segments now shorter than kMergeShortFull * S are added (a collapse the
+// start point had not yet come near). At most `rounds` rounds. The geometry is read from LDS with run-time slot
+// indices inside the loops over reduced slots, so that the intersection and
+// the subgradient test are written once.
+template <int NO>
+__device__ __forceinline__ bool merge_runs64(const GeoLds<NO>& G, double* t,
+                                             const SolveArgs& A, double short_rel,
+                                             int rounds, uint32_t (&work)[3]) {
   if constexpr (NO < 2) {
     return false;
   } else {
+    constexpr int NR = NO - 1;
     const double S = (double)A.scale;
-    // candidates: exactly one segment shorter than 6e-2 S, and it is
-    // interior (segment a + 1 joins slots a and a + 1); the start point may
-    // be far from converged on such paths, the certificate decides
-    const double short2 = 3.6e-3 * S * S;
-    int nshort = 0, a = 0;
-    double ymid[3] = {0.0, 0.0, 0.0};
-    {
+    const double eps = (double)A.level_eps[A.n_levels - 1] * S;
+    const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
+    bool endshort = false;
+    unsigned z = short_segments64(G, t, short_rel * short_rel * S * S, &endshort);
+    if (z == 0u || endshort) return false;
+    unsigned opened = 0u;  // segments taken out of the set: never merged again
+#pragma unroll 1
+    for (int round = 0; round < rounds; ++round) {
+      // at most three coinciding points in a run
+      if (z == 0u || (z & (z >> 1) & (z >> 2)) != 0u) return false;
+      const int nr = NO - __popc(z);
       double x[NO][3];
       points64(G, t, x);
+      // reduced slot of every slot; first slot and size of every reduced slot
+      int rs[NO], first[NR], cnt[NR];
 #pragma unroll
-      for (int i = 0; i <= NO; ++i) {
-        double r[3];
+      for (int q = 0; q < NR; ++q) first[q] = cnt[q] = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          r[c] = ((i == NO) ? G.rx(c) : x[i][c]) - ((i == 0) ? G.tx(c) : x[i - 1][c]);
-        bool sh = dot3d(r, r) < short2;
-        nshort += sh ? ((i == 0 || i == NO) ? 2 : 1) : 0;
-        a = sh ? i - 1 : a;
-        if (i >= 1 && i < NO) {
+      for (int j = 0; j < NO; ++j) {
+        rs[j] = j - __popc(z & ((2u << j) - 2u));
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
-            ymid[c] = sh ? 0.5 * (x[i - 1][c] + x[i][c]) : ymid[c];
+        for (int q = 0; q < NR; ++q) {
+          first[q] = (q == rs[j] && cnt[q] == 0) ? j : first[q];
+          cnt[q] += (q == rs[j]) ? 1 : 0;
         }
       }
-    }
-    if (nshort != 1) return false;
-    // intersection of the two objects; the reduced path: slot a is the
-    // intersection, slots after a + 1 shift down
-    Geo64<NO - 1> R;
-    double tr[2 * (NO - 1)];
-    double nul[2][3];
-    {
-      double aa[2][3] = {}, ab[2][3] = {}, ba[3] = {}, bb[3] = {};
-      bool ea = false, eb = false;
-      pair64(G, a, aa, ba, ea, ab, bb, eb);
-      const Basis64 U = basis64(aa, ea), V = basis64(ab, eb);
-      Virt64 X;
-      if (!intersect64(U, ba, V, bb, ymid, 1e-6 * S, 1.44e-2 * S * S, X)) return false;
+      // the reduced path: unused slots fixed at RX
+      Geo64<NR> R;
+      double tr[2 * NR];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         R.tx_[c] = G.tx(c);
         R.rx_[c] = G.rx(c);
-        nul[0][c] = X.nul[0][c];
-        nul[1][c] = X.nul[1][c];
       }
 #pragma unroll
-      for (int j = 0; j < NO - 1; ++j) {
-        const bool lo = j < a, vi = j == a;
+      for (int q = 0; q < NR; ++q) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          R.b_[j][c] = vi ? X.y0[c] : (lo ? G.b(j, c) : G.b(j + 1, c));
-          R.a_[j][0][c] = vi ? X.e[0][c] : (lo ? G.a(j, 0, c) : G.a(j + 1, 0, c));
-          R.a_[j][1][c] = vi ? X.e[1][c] : (lo ? G.a(j, 1, c) : G.a(j + 1, 1, c));
+          R.b_[q][c] = G.rx(c);
+          R.a_[q][0][c] = R.a_[q][1][c] = 0.0;
         }
-        R.edge_[j] = vi ? (X.dim < 2) : (lo ? G.edge(j) : G.edge(j + 1));
-        R.fixed_[j] = vi && X.dim == 0;
-        double m[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) m[c] = ymid[c] - X.y0[c];
-        tr[2 * j] = vi ? dot3d(m, X.e[0]) : (lo ? t[2 * j] : t[2 * j + 2]);
-        tr[2 * j + 1] = vi ? dot3d(m, X.e[1]) : (lo ? t[2 * j + 1] : t[2 * j + 3]);
+        R.edge_[q] = R.fixed_[q] = true;
+        tr[2 * q] = tr[2 * q + 1] = 0.0;
       }
-    }
-    const double eps = (double)A.level_eps[A.n_levels - 1] * S;
-    const double cert2 = (double)A.cert_abs * (double)A.cert_abs;
-    NewtonTrack k;
-    newton_run64(R, tr, eps * eps, 8, cert2, false, k, true);
-    work[0] += k.n_eval;
-    work[1] += k.n_trial;
-    work[2] += k.n_solve;
-    if (!(k.prev_small && k.last_small && k.contracting)) return false;
-    if (!nonsmooth_ok64(R, tr, eps, S)) return false;
-    // subgradient of the collapsed segment: least-norm w with
-    // P_U w = P_U u_in and P_V w = P_V u_out (P = projector onto the
-    // object's directions), w = (P_U + P_V)^+ (P_U u_in + P_V u_out); the
-    // pseudo-inverse by adding the projector onto the common normals (the
-    // null space of P_U + P_V, which the right-hand side does not reach)
-    double uin[3] = {}, uout[3] = {}, y[3] = {};
-    {
-      Seg64<NO - 1> sg;
-      eval64(R, tr, 0.0, sg);
-      ++work[0];
-      double xr[NO - 1][3];
+#pragma unroll 1
+      for (int rr = 0; rr < nr; ++rr) {
+        int js = 0, m = 0;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          js = (q == rr) ? first[q] : js;
+          m = (q == rr) ? cnt[q] : m;
+        }
+        double ym[3] = {0.0, 0.0, 0.0}, t0 = 0.0, t1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+          const bool in = rs[j] == rr;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) ym[c] += in ? x[j][c] : 0.0;
+          t0 = (j == js) ? t[2 * j] : t0;
+          t1 = (j == js) ? t[2 * j + 1] : t1;
+        }
+        const double im = (m == 3) ? (1.0 / 3.0) : (m == 2 ? 0.5 : 1.0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ym[c] *= im;
+        double nb[3], na[2][3], n0 = t0, n1 = t1;
+        bool ne, nf = false;
+        if (m == 1) {
+          // the object itself, in the caller's basis
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            nb[c] = G.b(js, c);
+            na[0][c] = G.a(js, 0, c);
+            na[1][c] = G.a(js, 1, c);
+          }
+          ne = na[1][0] == 0.0 && na[1][1] == 0.0 && na[1][2] == 0.0;
+        } else {
+          Flat64 X;
+          if (!meet64(flat_of64(G, js), flat_of64(G, js + 1), ym, 1e-6 * S, 1.44e-2 * S * S, X))
+            return false;
+          if (m == 3) {
+            Flat64 X3;
+            if (!meet64(X, flat_of64(G, js + 2), ym, 1e-6 * S, 1.44e-2 * S * S, X3))
+              return false;
+            X = X3;
+          }
+          double dm[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            nb[c] = X.o[c];
+            na[0][c] = X.q[0][c];
+            na[1][c] = X.q[1][c];
+            dm[c] = ym[c] - X.o[c];
+          }
+          ne = X.dim < 2;
+          nf = X.dim == 0;
+          n0 = nf ? 0.0 : dot3d(dm, X.q[0]);
+          n1 = ne ? 0.0 : dot3d(dm, X.q[1]);
+        }
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          const bool s = q == rr;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            R.b_[q][c] = s ? nb[c] : R.b_[q][c];
+            R.a_[q][0][c] = s ? na[0][c] : R.a_[q][0][c];
+            R.a_[q][1][c] = s ? (ne ? 0.0 : na[1][c]) : R.a_[q][1][c];
+          }
+          R.edge_[q] = s ? ne : R.edge_[q];
+          R.fixed_[q] = s ? nf : R.fixed_[q];
+          tr[2 * q] = s ? n0 : tr[2 * q];
+          tr[2 * q + 1] = s ? n1 : tr[2 * q + 1];
+        }
+      }
+      // solve the reduced path (after two smoothing levels in later rounds):
+      // the smooth certificate, no collapse left
+      if (round > 0) {
+        NewtonTrack k0;
+        newton_run64(R, tr, 1e-8 * S * S, 3, cert2, false, k0);
+        newton_run64(R, tr, 1e-12 * S * S, 3, cert2, false, k0);
+        work[0] += k0.n_eval;
+        work[1] += k0.n_trial;
+        work[2] += k0.n_solve;
+      }
+      NewtonTrack k;
+      newton_run64(R, tr, eps * eps, 8, cert2, false, k, true);
+      work[0] += k.n_eval;
+      work[1] += k.n_trial;
+      work[2] += k.n_solve;
+      bool good = k.prev_small && k.last_small && k.contracting &&
+                  nonsmooth_ok64(R, tr, eps, S, nr, false);
+      unsigned open = 0u;  // collapsed segments whose subgradient is too long
+      double xr[NR][3];
       points64(R, tr, xr);
+      if (good) {
+        // every run: the subgradient test against its own objects
+        Seg64<NR> sg;
+        eval64(R, tr, 0.0, sg);
+        ++work[0];
+#pragma unroll 1
+        for (int rr = 0; rr < nr; ++rr) {
+          int js = 0, m = 0;
 #pragma unroll
-      for (int j = 0; j < NO - 1; ++j) {
-        const bool s = (j == a);
+          for (int q = 0; q < NR; ++q) {
+            js = (q == rr) ? first[q] : js;
+            m = (q == rr) ? cnt[q] : m;
+          }
+          if (m < 2) continue;
+          double uin[3], uout[3];
+          Flat64 E;
+          E.dim = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          uin[c] = s ? sg.v[j][c] : uin[c];
-          uout[c] = s ? sg.v[j + 1][c] : uout[c];
-          y[c] = s ? xr[j][c] : y[c];
+          for (int c = 0; c < 3; ++c) uin[c] = uout[c] = E.o[c] = E.q[0][c] = E.q[1][c] = 0.0;
+#pragma unroll
+          for (int q = 0; q < NR; ++q) {
+            const bool s = q == rr;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              uin[c] = s ? sg.v[q][c] : uin[c];
+              uout[c] = s ? sg.v[q + 1][c] : uout[c];
+              E.q[0][c] = s ? R.a_[q][0][c] : E.q[0][c];
+              E.q[1][c] = s ? R.a_[q][1][c] : E.q[1][c];
+            }
+            E.dim = s ? (R.fixed_[q] ? 0 : (R.edge_[q] ? 1 : 2)) : E.dim;
+          }
+          Flat64 F[3];
+          F[0] = flat_of64(G, js);
+          F[1] = flat_of64(G, js + 1);
+          if (m == 3) {
+            F[2] = flat_of64(G, js + 2);
+          } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) F[2].o[c] = F[2].q[0][c] = F[2].q[1][c] = 0.0;
+            F[2].dim = 0;
+          }
+          const unsigned r = run_subgradient64(F, m, uin, uout, E);
+          good = good && r == 0u;
+          // (w_1, w_2 of the run belong to segments js + 1, js + 2)
+          open |= (r & 3u) << (js + 1);
         }
       }
-    }
-    if (!subgradient_ok64(G, a, uin, uout, nul)) return false;
-    double aa[2][3] = {}, ab[2][3] = {}, ba[3] = {}, bb[3] = {};
-    bool ea = false, eb = false;
-    pair64(G, a, aa, ba, ea, ab, bb, eb);
-    // back to the caller's parameters of the full path
-    double ta[2], tb[2];
-    coords64(aa, ba, ea, y, ta);
-    coords64(ab, bb, eb, y, tb);
+      // back to the caller's parameters of the full path
 #pragma unroll
-    for (int j = 0; j < NO; ++j) {
-      const bool lo = j < a, isa = j == a, isb = j == a + 1;
-      const int jr = (j >= 1) ? j - 1 : 0;  // reduced slot of j > a + 1
-      const int jl = (j < NO - 1) ? j : 0;  // reduced slot of j < a
-      t[2 * j] = isa ? ta[0] : (isb ? tb[0] : (lo ? tr[2 * jl] : tr[2 * jr]));
-      t[2 * j + 1] = isa ? ta[1] : (isb ? tb[1] : (lo ? tr[2 * jl + 1] : tr[2 * jr + 1]));
+      for (int j = 0; j < NO; ++j) {
+        int m = 0;
+        double y[3] = {0.0, 0.0, 0.0}, p0 = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          const bool s = q == rs[j];
+          m = s ? cnt[q] : m;
+          p0 = s ? tr[2 * q] : p0;
+          p1 = s ? tr[2 * q + 1] : p1;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) y[c] = s ? xr[q][c] : y[c];
+        }
+        if (m >= 2) {
+          double aj[2][3], bj[3], tj[2];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            aj[0][c] = G.a(j, 0, c);
+            aj[1][c] = G.a(j, 1, c);
+            bj[c] = G.b(j, c);
+          }
+          coords64(aj, bj, G.edge(j), y, tj);
+          p0 = tj[0];
+          p1 = tj[1];
+        }
+        t[2 * j] = p0;
+        t[2 * j + 1] = p1;
+      }
+      if (good) return true;
+      // segments that open leave the set; a collapse the start point had not
+      // come near shows in the reduced solution as a short segment
+      opened |= open;
+      const unsigned z2 =
+          (z | short_segments64(G, t, kMergeShortFull * kMergeShortFull * S * S, &endshort)) &
+          ~opened;
+      if (endshort || (z2 == z && round > 0)) return false;
+      z = z2;
     }
-    return true;
+    return false;
   }
 }
 
@@ -1485,9 +1884,11 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
       td[2 * j + 1] = D.edge(j) ? 0.0 : (double)t1 * (double)inv[j][1];
     }
     RefineOut ro = refine64(D, td, A, quick, work);
-    // first pass: defer the paths it does not certify
-    const bool defer = quick && valid && !ro.certified;
-    const unsigned long long more = __ballot(defer);
+    // list the paths this pass does not certify: the quick pass defers
+    // them (to the collapse step and the full schedule), the full schedule
+    // writes them and hands them to the last collapse step
+    const bool listed = St.out_list != nullptr && valid && !ro.certified;
+    const unsigned long long more = __ballot(listed);
     if (more) {
       const int region = (int)((idx >> 6) % kRegions);
       unsigned long long base = 0;
@@ -1495,11 +1896,11 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
         base = atomicAdd(St.out_count + region * kCounterStride,
                          (unsigned long long)__popcll(more));
       base = __shfl(base, 0);
-      if (defer)
+      if (listed)
         St.out_list[(int64_t)region * St.rcap +
                     (int64_t)(base + (unsigned long long)__popcll(more & below))] = (int32_t)p;
     }
-    if (defer) {
+    if (quick && listed) {
       // hand the quick pass's point to the collapse step and the second pass
       // (unit-vector coordinates, as the FP32 phase left them)
 #pragma unroll
@@ -1515,10 +1916,17 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
   if (A.work) add_work(A.work, work, lane);
 }
 
-// Between the two refinement passes: the paths the quick pass did not
-// certify (St.in_list) get one attempt of merge64 from the FP32 result;
-// those it certifies are written, the others are listed (St.out_list) for
-// the second pass.
+// The collapse step (merge_runs64) on the listed paths (St.in_list). Mode
+// 0, between the quick pass and the full schedule: from the quick pass's
+// point (unit-vector coordinates), with collapsed segments taken as those
+// shorter than kMergeShortQuick; the paths it certifies are written, the
+// others listed (St.out_list) for the full schedule. Mode 1, after the full
+// schedule: from its written output (caller's parametrisation), where a
+// collapse has come much closer, with kMergeShortFull; it overwrites the
+// paths it certifies and leaves the others as written. Mode 0 takes one
+// round of merge_runs64 (most of its paths have one collapse, and the full
+// schedule follows for the others), mode 1 up to four.
+
 template <int NO>
 __global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St) {
   __shared__ int64_t pre[kRegions + 1];
@@ -1549,15 +1957,17 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St
     float inv[NO][2];
     load_geo_lds<NO>(A, p, geo + threadIdx.x, D, inv);
     double td[2 * NO];
+    const bool unit = St.mode == 0;
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
       float t0 = A.t[(int64_t)(2 * j) * A.N + p];
       float t1 = A.t[(int64_t)(2 * j + 1) * A.N + p];
-      td[2 * j] = (double)t0 * (double)inv[j][0];
-      td[2 * j + 1] = D.edge(j) ? 0.0 : (double)t1 * (double)inv[j][1];
+      td[2 * j] = (double)t0 * (unit ? (double)inv[j][0] : 1.0);
+      td[2 * j + 1] = D.edge(j) ? 0.0 : (double)t1 * (unit ? (double)inv[j][1] : 1.0);
     }
-    const bool ok = merge64(D, td, A, work);
-    const unsigned long long more = __ballot(!ok);
+    const bool ok =
+        merge_runs64<NO>(D, td, A, unit ? kMergeShortQuick : kMergeShortFull, unit ? 1 : 4, work);
+    const unsigned long long more = __ballot(!ok && St.out_list != nullptr);
     if (more) {
       const int region = (int)((idx >> 6) % kRegions);
       unsigned long long base = 0;
@@ -1834,7 +2244,7 @@ static hipError_t launch_phase(int phase, const SolveArgs& A,
   if (phase == 0)
     hipLaunchKernelGGL(bfgs_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
                        perm, bucket);
-  else if (phase == 1 && stage && stage->out_list)
+  else if (phase == 4)
     hipLaunchKernelGGL((refine_kernel<NO, true>), dim3(grid), dim3(kBlock), 0, st, A,
                        perm, bucket, *stage);
   else if (phase == 1)
@@ -1852,11 +2262,11 @@ static hipError_t launch_phase(int phase, const SolveArgs& A,
   return hipGetLastError();
 }
 
-// phase 0: bfgs_kernel<order>, 1: refine_kernel<order> (the quick variant
-// when stage->out_list is set; phase 4 names that variant for occupancy
-// queries), 5: newton32_kernel<order> (the FP32 Newton variant of phase 0),
-// 2: bfgs_stage_kernel<order> (one early-exit stage, `stage` describes it),
-// 3: merge_kernel<order> (between the refinement passes)
+// phase 0: bfgs_kernel<order>, 1: refine_kernel<order> with the full
+// schedule (listing the paths it does not certify when stage->out_list is
+// set), 4: its quick pass, 5: newton32_kernel<order> (the FP32 Newton variant
+// of phase 0), 2: bfgs_stage_kernel<order> (one early-exit stage, `stage`
+// describes it), 3: merge_kernel<order> (the collapse step, stage->mode)
 hipError_t launch_solve(int phase, int order, const SolveArgs& A,
                         const int32_t* perm, const int64_t* bucket,
                         const StageArgs* stage, int grid, hipStream_t st) {

@@ -27,13 +27,43 @@ def point_error(batch, gpu, ref):
     return diff.max(axis=1) / batch.S
 
 
-def summary(batch, gpu, ref, rtol=1e-4):
+def summary(batch, gpu, ref, rtol=1e-4, ltol=1e-5):
+    """Per-path comparison with the oracle. The gate of a path: its points
+    within rtol * S of the oracle's where the oracle's minimiser is neither
+    COLLAPSED nor ILL (unique and smooth), else its length within ltol * S of
+    the minimum (at a collapse the points converge much more slowly than the
+    length)."""
     from paper_2510_16172_amd import fpt
     e = point_error(batch, gpu, ref)
     ok = e <= rtol
     cert = (gpu["status"] & fpt.ST_CONVERGED) != 0
     ill = (ref["flags"] & 2) != 0
     col = (ref["flags"] & 1) != 0
-    return dict(err=e, ok=ok, cert=cert, ill=ill, col=col,
+    dL = np.abs(gpu["len"].astype(np.float64) - ref["len"]) / batch.S
+    dL = np.where(np.isfinite(dL), dL, np.inf)
+    gate = np.where(col | ill, dL <= ltol, ok)
+    return dict(err=e, ok=ok, cert=cert, ill=ill, col=col, gate=gate,
                 frac_ok=float(ok.mean()), frac_cert=float(cert.mean()),
+                frac_gate=float(gate.mean()),
                 false_pos=int((cert & ~ok & ~ill).sum()))
+
+
+def zero_runs(batch, ref, tol=1e-6):
+    """Per path, from the oracle's solution: the number of runs of
+    consecutive zero-length segments (shorter than tol * S) and the longest
+    run (1: two coinciding points)."""
+    tx = batch.pts[:, batch.src].T.astype(np.float64)
+    rx = batch.pts[:, batch.dst].T.astype(np.float64)
+    runs = np.zeros(batch.N, np.int64)
+    longest = np.zeros(batch.N, np.int64)
+    for i in range(batch.N):
+        n = int(batch.order[i])
+        P = np.concatenate([tx[i][None], ref["x"][i, :n], rx[i][None]], 0)
+        seg = np.linalg.norm(np.diff(P, axis=0), axis=-1) / batch.S
+        cur = 0
+        for z in seg < tol:
+            cur = cur + 1 if z else 0
+            if cur == 1:
+                runs[i] += 1
+            longest[i] = max(longest[i], cur)
+    return runs, longest

@@ -29,37 +29,53 @@ def _opts(S, **kw):
     return fpt.Opts(scale=S, method=fpt.METHOD_NEWTON32, **kw)
 
 
-def _check(b, g, ref, min_ok, min_cert):
+def _check(b, g, ref, min_cert, min_gate=0.99):
+    """No certified path wrong, no path shorter than the minimum, and the
+    per-path gate of the BFGS tests (points for smooth unique minimisers,
+    length for collapsed ones) on min_gate of the paths."""
     from paper_2510_16172_amd import fpt
     s = gpu_util.summary(b, g, ref)
-    print(f"N={b.N} ok={s['frac_ok']:.4f} cert={s['frac_cert']:.4f} "
-          f"falsepos={s['false_pos']}", flush=True)
+    print(f"N={b.N} gate={s['frac_gate']:.4f} ok={s['frac_ok']:.4f} "
+          f"cert={s['frac_cert']:.4f} falsepos={s['false_pos']}", flush=True)
     assert s["false_pos"] == 0
     assert np.all(g["len"].astype(np.float64) >= ref["len"] - 1e-6 * b.S)
-    assert s["frac_ok"] >= min_ok and s["frac_cert"] >= min_cert
+    assert s["frac_gate"] >= min_gate and s["frac_cert"] >= min_cert
     assert np.all((g["status"] & (fpt.ST_INVALID | fpt.ST_NONFINITE)) == 0)
     return s
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4])
+# The variant reaches the parity bar of the BFGS with 32 FP32 Newton steps
+# (8 per smoothing level); with 8 steps, where its certified paths/s is
+# highest, up to 5 % of the order-6 paths end neither certified nor within
+# the gate (the FP64 refinement does not recover a start point left at a
+# spurious near-collapse).
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
 def test_newton32_random_each_order(solver, oracle_mod, n):
     # 2,000 paths: several workgroups and a ragged tail
     b = scenes.random_paths(2000, n, seed=8100 + n)
     ref = oracle_mod.solve(b, threads=8)
-    g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=12), with_order=False)
-    _check(b, g, ref, min_ok={1: 0.99, 2: 0.95, 3: 0.9, 4: 0.85}[n],
-           min_cert={1: 0.9, 2: 0.85, 3: 0.8, 4: 0.7}[n])
-    assert np.all(g["iters"] == 12)
+    g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=32), with_order=False)
+    _check(b, g, ref, min_cert=0.95)
+    assert np.all(g["iters"] == 32)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
 def test_newton32_canyon_each_order(solver, oracle_mod, n):
     sc = scenes.canyon_scene()
     b = scenes.canyon_sample_paths(sc, 5000, seed=8200 + n, n=n)
     ref = oracle_mod.solve(b, threads=8)
+    g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=32), with_order=False)
+    _check(b, g, ref, min_cert=0.95)
+
+
+def test_newton32_eight_steps_no_certified_path_wrong(solver, oracle_mod):
+    """At its fastest setting (8 steps) the variant certifies fewer paths,
+    but none of them wrongly, and no path is shorter than the minimum."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 5000, seed=8206, n=6)
+    ref = oracle_mod.solve(b, threads=8)
     g = gpu_util.run_gpu(solver, b, _opts(b.S, iters=8), with_order=False)
-    _check(b, g, ref, min_ok={1: 0.99, 2: 0.95, 3: 0.9}[n],
-           min_cert={1: 0.95, 2: 0.9, 3: 0.85}[n])
+    _check(b, g, ref, min_cert=0.9, min_gate=0.9)
 
 
 def test_newton32_and_bfgs_agree_where_both_certify(solver):
