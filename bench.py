@@ -1,22 +1,31 @@
 #!/usr/bin/env python3
 """Throughput of the Fermat path solver on one MI355X.
 
-Workload: the street canyon (24 boxes, 121 faces + 192 edges, 64 TX/RX
-pairs), every interaction sequence of order 1 and 2 with no immediate repeat:
-6,270,016 paths, solved in FP32 (BFGS with the fixed-point step of Eq. 6)
-plus FP64 refinement. One step = one fpt_solve over all paths, inputs
-resident in HBM. The per-order schedule (number of BFGS iterations, or
-early exit in stages) is chosen by the autotuner on a sample before timing
-(--no-autotune: --iters / --early-exit for every order). Metric: converged
-paths per second, where converged means certified by the kernel's FP64
-Newton check; the cpu_baseline leg checks every GPU output against the
-oracle and reports how many certified paths are outside 1e-4 S.
+Headline workload (default): the street canyon (24 boxes, 121 faces + 192
+edges, 64 TX/RX pairs), 8,388,608 sampled interaction sequences of orders
+1..6 with P(n) proportional to 2^-n, mixed in one call: order bucketing,
+per-order persistent launches (orders on streams of their own) and the FP64
+refinement, captured as one HIP graph and replayed. The per-order schedule
+(BFGS iteration count, quick refinement passes) is chosen by the autotuner on
+a sample before timing, or fixed with --schedule. One step = one graph
+replay over all paths, inputs resident in HBM. Metric: converged paths per
+second, where converged means certified by the kernel's FP64 check (smooth
+Newton certificate, or the subgradient test of a collapsed minimiser); the
+cpu_baseline leg times the FP64 oracle on the host and checks the GPU
+outputs against it.
 
-Prints ONE JSON line (see the keys at the end of main()).
+Legs that follow (each can be switched off): all 6,270,016 order <= 2
+sequences (c2) with validity, enumeration and the FP32 Newton variant on
+them; solve + implicit gradient on 2^20 order-3 paths with unrolled autodiff
+for comparison (fwd_grad); the learned initialiser trained on 2^22 order-4
+paths and evaluated on 2^20 others (learned_init).
+
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -33,8 +42,36 @@ PEAK_FP32 = 157.3e12      # published FP32 vector peak (counts packed FP32)
 PEAK_FP32_UNPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop x 2.4 GHz
 PEAK_FP64 = 78.6e12        # published FP64 vector peak
 PEAK_HBM = 8.0e12
+PEAK_BF16 = 2.5e15         # dense BF16 MFMA
 
 
+# ------------------------------------------------- algorithmic counts -----
+# The method's own work, independent of how the kernels are written:
+#   one BFGS iteration of an order-n path with m parameters: gradient
+#   (points, segments, reciprocal square roots, projections), direction
+#   P = -H g (2 m^2), the fixed-point step of Eq. 6, the update T += a P and
+#   the inverse-Hessian update (5 m^2):  7 m^2 + 85 n + 28 FP32 FLOP
+#   (FMA = 2), which is 28 n^2 + 85 n + 28 on the padded layout m = 2 n:
+#   141, 310, 535, 816, 1153, 1546 for n = 1..6;
+#   one FP64 Newton step of the refinement: about 150 n FLOP;
+#   bytes: 9 + 4 n read per path (indices) and 20 n + 7 written.
+
+def f_iter(n: int, m: int | None = None) -> int:
+    m = 2 * n if m is None else m
+    return 7 * m * m + 85 * n + 28
+
+
+def newton_step_flops(n: int) -> int:
+    return 150 * n
+
+
+def io_bytes(n: int) -> int:
+    return (9 + 4 * n) + (20 * n + 7)
+
+
+# The builder's own term-by-term FLOP model of each kernel, reported beside
+# the algorithmic count (it counts the padded layout, the polish step and the
+# refinement's evaluations and trial lengths as the kernels execute them).
 def bfgs_flops_per_iter(n: int, fp_iters: int, early_exit: bool) -> int:
     """FP32 flops of one iteration of bfgs_kernel<n> (FMA = 2, every other
     arithmetic op and each rsq / rcp = 1; comparisons and selects = 0).
@@ -111,94 +148,6 @@ def refine_final_flops(n: int) -> int:
     return 12 * n + 20 * (n + 1)
 
 
-def source_digest() -> str:
-    h = hashlib.sha256()
-    for f in ("solve.hip", "path64.h", "common.h", "api.hip"):
-        with open(os.path.join(ROOT, "paper_2510_16172_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def read_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if there is none for the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}__{workload}.counters.json")
-    if not os.path.exists(path):
-        return None
-    try:
-        d = json.load(open(path))
-    except Exception:
-        return None
-    if d.get("source_digest") != source_digest():
-        return None
-    return d.get("hbm_bytes_per_launch")
-
-
-def cpu_baseline(batch, out_np, seconds: float, threads: int, seed: int = 7,
-                 others=None):
-    """The FP64 oracle timed on host cores on a seeded random sample of the
-    workload (chunks of 2^14 paths until `seconds` have elapsed), and the GPU
-    result checked against it on that sample (also each of `others`, a
-    {name: output} dict of other GPU results on the same workload)."""
-    import oracle
-    rng = np.random.default_rng(seed)
-    perm = rng.permutation(batch.N)
-    chunk = 1 << 14
-    done, t_used = 0, 0.0
-    outs = {"": out_np, **(others or {})}
-    tally = {k: [0, 0, 0] for k in outs}  # within 1e-4, certified, certified but wrong
-    while t_used < seconds and done < batch.N:
-        idx = np.sort(perm[done:done + chunk])
-        sub = batch.subset(idx)
-        t0 = time.perf_counter()
-        ref = oracle.solve(sub, threads=threads)
-        t_used += time.perf_counter() - t0
-        done += len(idx)
-        j = np.arange(sub.n_max)[None, :]
-        ill = (ref["flags"] & 2) != 0
-        for k, o in outs.items():
-            x = np.transpose(o["x"][:, :, idx], (2, 0, 1)).astype(np.float64)
-            d = np.linalg.norm(x - ref["x"], axis=-1)
-            d = np.where(j < sub.order[:, None].astype(np.int64), d, 0.0)
-            err = np.where(np.isfinite(d), d, np.inf).max(axis=1) / sub.S
-            ok = err <= 1e-4
-            cert = (o["status"][idx] & 1) != 0
-            tally[k][0] += int(ok.sum())
-            tally[k][1] += int(cert.sum())
-            tally[k][2] += int((cert & ~ok & ~ill).sum())
-    n_ok, n_cert, n_fp = tally[""]
-    # one thread, on the first chunk of the same sample
-    sub = batch.subset(np.sort(perm[:min(chunk, batch.N)]))
-    t0 = time.perf_counter()
-    oracle.solve(sub, threads=1)
-    t1 = time.perf_counter() - t0
-    what = (f"all {done} paths of the workload" if done == batch.N else
-            f"{done} seeded random paths of the workload")
-    return {"value": done / t_used, "unit": "paths/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{what} ({t_used:.1f} s on {threads} threads)",
-            "value_1thread": sub.N / t1,
-            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
-            "gpu_within_1e-4_on_sample": n_ok / done,
-            "gpu_within_1e-4_paths": n_ok,
-            "gpu_certified_on_sample": n_cert / done,
-            "gpu_certified_but_wrong_on_sample": n_fp,
-            "others": {k: {"gpu_within_1e-4_on_sample": v[0] / done,
-                           "gpu_within_1e-4_paths": v[0],
-                           "gpu_certified_on_sample": v[1] / done,
-                           "gpu_certified_but_wrong_on_sample": v[2]}
-                       for k, v in tally.items() if k}}
-
-
-def _cpu_model() -> str:
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return "unknown"
-
 
 def grad_bytes_per_path(n: int) -> int:
     """Algorithmic HBM bytes of grad_kernel<n> per path: reads T* (8n),
@@ -217,8 +166,7 @@ def run_fwd_grad(args, fpt, scenes, torch):
     g_len, g_x = scenes.upstream_grads(b.N, b.n_max, seed=1104)
     solver = fpt.Solver(0)
     db = fpt.DeviceBatch(b, with_order=False)
-    opts = fpt.Opts(scale=b.S, iters=args.iters, fp_iters=args.fp_iters,
-                    early_exit=args.early_exit)
+    opts = fpt.Opts(scale=b.S, iters=args.iters, fp_iters=args.fp_iters)
     chosen = {}
     if not args.no_autotune:
         from paper_2510_16172_amd import autotune
@@ -257,8 +205,7 @@ def run_fwd_grad(args, fpt, scenes, torch):
     res = {
         "workload": "street canyon: 1,048,576 sampled order-3 paths, "
                     "upstream gradients N(0,1)",
-        "schedule": chosen.get(3) or {"iters": args.iters,
-                                      "early_exit": int(args.early_exit)},
+        "schedule": chosen.get(3) or {"iters": args.iters},
         "ms_fwd": t_f, "ms_grad": t_g, "grad_kernel_ms": tg_kernel,
         "certified_fraction": cert / b.N,
         "converged_paths_per_s_fwd_grad": cert / ((t_f + t_g) * 1e-3),
@@ -321,158 +268,361 @@ def run_fwd_grad(args, fpt, scenes, torch):
     return res
 
 
-def run_uneven(args, fpt, scenes, torch):
-    """8,388,608 canyon paths, orders 1..6 with P(n) ~ 2^-n, one captured
-    HIP graph per step, per-order launch configuration from the autotuner."""
-    from paper_2510_16172_amd import autotune
-    sc = scenes.canyon_scene()
-    b = scenes.canyon_sample_paths(sc, 1 << 23, seed=1003, n=None, n_max=6)
-    solver = fpt.Solver(0)
-    # the orders run on streams of their own (their passes overlap)
-    opts = fpt.Opts(scale=b.S, iters=64, concurrent_orders=True)
-    chosen = autotune.tune(solver, b, opts, sample=1 << 18, repeats=2)
-    db = fpt.DeviceBatch(b)
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("solve.hip", "path64.h", "common.h", "api.hip", "grad.hip", "mlp.hip"):
+        with open(os.path.join(ROOT, "paper_2510_16172_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_counters(kernel: str, workload: str):
+    """The committed rocprofv3 counter summary of a kernel (group) on a
+    workload, or None if there is none for the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}__{workload}.counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_digest") != source_digest():
+        return None
+    return d
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _compare(sub, ref, o, idx):
+    """Per-path comparison of GPU outputs `o` (full arrays, paths idx) with
+    the oracle on the sub-batch: within 1e-4 S (points), the gate (points for
+    a smooth unique minimiser, length within 1e-5 S for a collapsed or
+    non-unique one), certified, certified but outside 1e-4 S."""
+    j = np.arange(sub.n_max)[None, :]
+    ill = (ref["flags"] & 2) != 0
+    col = (ref["flags"] & 1) != 0
+    x = np.transpose(o["x"][:, :, idx], (2, 0, 1)).astype(np.float64)
+    d = np.linalg.norm(x - ref["x"], axis=-1)
+    d = np.where(j < sub.order[:, None].astype(np.int64), d, 0.0)
+    err = np.where(np.isfinite(d), d, np.inf).max(axis=1) / sub.S
+    ok = err <= 1e-4
+    dL = np.abs(o["len"][idx].astype(np.float64) - ref["len"]) / sub.S
+    gate = np.where(col | ill, np.where(np.isfinite(dL), dL, np.inf) <= 1e-5, ok)
+    cert = (o["status"][idx] & 1) != 0
+    return ok, gate, cert, cert & ~ok & ~ill
+
+
+def cpu_baseline(batch, outs, seconds: float, threads: int, seed: int = 7):
+    """The FP64 oracle timed on host cores on a seeded random sample of the
+    workload (chunks of 2^15 paths until `seconds` have elapsed, or every
+    path), and the GPU results `outs` ({name: output}, "" the headline)
+    checked against it on that sample, per order."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(batch.N)
+    chunk = 1 << 15
+    done, t_used = 0, 0.0
+    nmax = batch.n_max
+    tally = {k: np.zeros((nmax + 1, 5), np.int64) for k in outs}  # paths, ok, gate, cert, wrong
+    while t_used < seconds and done < batch.N:
+        idx = np.sort(perm[done:done + chunk])
+        sub = batch.subset(idx)
+        t0 = time.perf_counter()
+        ref = oracle.solve(sub, threads=threads)
+        t_used += time.perf_counter() - t0
+        done += len(idx)
+        for k, o in outs.items():
+            ok, gate, cert, wrong = _compare(sub, ref, o, idx)
+            for n in range(1, nmax + 1):
+                m = sub.order == n
+                tally[k][n] += [m.sum(), ok[m].sum(), gate[m].sum(), cert[m].sum(), wrong[m].sum()]
+    # one thread, on the first chunk of the same sample
+    sub = batch.subset(np.sort(perm[:min(chunk, batch.N)]))
+    t0 = time.perf_counter()
+    oracle.solve(sub, threads=1)
+    t1 = time.perf_counter() - t0
+    what = (f"all {done} paths of the workload" if done == batch.N else
+            f"{done} seeded random paths of the workload")
+
+    def summ(t):
+        tot = t[1:].sum(0)
+        return {"within_1e-4": tot[1] / tot[0], "gate": tot[2] / tot[0],
+                "certified": tot[3] / tot[0], "certified_but_wrong": int(tot[4]),
+                "paths_within_1e-4": int(tot[1]),
+                "per_order": {str(n): {"paths": int(t[n, 0]),
+                                       "within_1e-4": float(t[n, 1] / max(t[n, 0], 1)),
+                                       "gate": float(t[n, 2] / max(t[n, 0], 1)),
+                                       "certified": float(t[n, 3] / max(t[n, 0], 1)),
+                                       "certified_but_wrong": int(t[n, 4])}
+                              for n in range(1, nmax + 1) if t[n, 0] > 0}}
+    res = {"value": done / t_used, "unit": "paths/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{what} ({t_used:.1f} s on {threads} threads)",
+           "all_paths": done == batch.N,
+           "value_1thread": sub.N / t1,
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+           "gpu_vs_oracle": summ(tally[""])}
+    others = {k: summ(v) for k, v in tally.items() if k}
+    if others:
+        res["others_vs_oracle"] = others
+    return res
+
+
+def host_threads() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+
+
+# ------------------------------------------------------- solve timing -----
+
+def timed_solve(args, solver, db, opts, torch):
+    """One fpt_solve captured as a HIP graph on a side stream: W warm-up
+    replays, then K timed replays bracketed by HIP events on that stream.
+    Returns (ms per step, per-step ms, outputs on the host)."""
     out = solver.alloc_out(db)
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
         solver.solve(db, opts, out=out, stream=st)
         st.synchronize()
         graph = solver.capture(db, opts, out, st)
-        for _ in range(2):
+        for _ in range(args.warmup):
             graph.launch(st)
         st.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        steps = max(3, args.steps // 2)
-        e0.record(st)
-        for _ in range(steps):
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        ev[0].record(st)
+        for k in range(args.steps):
             graph.launch(st)
-        e1.record(st)
+            ev[k + 1].record(st)
         st.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    cert = int(((out["status"] & fpt.ST_CONVERGED) != 0).sum().item())
+        torch.cuda.synchronize()
     graph.close()
-    solver.close()
-    return {"workload": "street canyon: 8,388,608 paths, orders 1..6 with "
-                        "P(n) proportional to 2^-n, one HIP graph per step, "
-                        "one stream per order inside it",
-            "ms_per_step": ms, "certified_fraction": cert / b.N,
-            "converged_paths_per_s": cert / (ms * 1e-3),
-            "autotuned": {str(k): v for k, v in chosen.items()},
-            "order_counts": {str(n): int((b.order == n).sum()) for n in range(1, 7)}}
+    ms = ev[0].elapsed_time(ev[-1]) / args.steps
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    return ms, per, {k: v.cpu().numpy() for k, v in out.items()}
 
 
-def run_learned(args, fpt, torch):
-    from paper_2510_16172_amd import learned_init
+def breakdown(args, solver, db, opts, torch):
+    """The same solve with the library's per-kernel HIP-event timers and the
+    refinement's work counters on: orders one after another, one part each,
+    so that every timer brackets one order's launches alone on the stream
+    they run on. Returns (timer ms, work counts per solve)."""
+    opts_seq = dataclasses.replace(opts, concurrent_orders=False, split=1)
+    out = solver.alloc_out(db)
+    solver.solve(db, opts_seq, out=out)
+    torch.cuda.synchronize()
+    solver.set_timing(True)
+    solver.work_counts()  # clear
+    for _ in range(args.steps):
+        solver.solve(db, opts_seq, out=out)
+    kt = solver.kernel_times()
+    work = solver.work_counts()
+    solver.set_timing(False)
+    work = {n: tuple(v / args.steps for v in w) for n, w in work.items()}
+    return kt, work
+
+
+def order_rooflines(fpt, batch, out_np, kt, work, opts, workload):
+    """Roofline of each order's FP32 phase and FP64 refinement group: the
+    algorithmic FLOP count per launch (above) over the launch's measured
+    time, against the FP32 / FP64 vector peaks; the builder's model and the
+    committed counters beside it."""
+    rows = []
+    edge = np.all(batch.obj[6:9] == 0, axis=0)
+    for n in range(1, batch.n_max + 1):
+        sel = batch.order == n
+        cnt = int(sel.sum())
+        if cnt == 0:
+            continue
+        it = out_np["iters"][sel].astype(np.int64)
+        # active parameters per path: 2 per face, 1 per edge
+        m_act = (2 * n - edge[batch.ids[:n][:, sel]].sum(0)).astype(np.int64)
+        fl_pad = int(it.sum()) * f_iter(n)
+        fl_act = int((it * (7 * m_act * m_act + 85 * n + 28)).sum())
+        fl_mod = (int(it.sum()) * bfgs_flops_per_iter(n, opts.fp_iters, False)
+                  + cnt * (bfgs_init_flops(n) + polish_flops(n, opts.polish_steps)))
+        t_b = kt[fpt.T_BFGS + n - 1] * 1e-3
+        name_b = "newton32_kernel" if opts.method == fpt.METHOD_NEWTON32 else "bfgs_kernel"
+        cb = read_counters(f"{name_b}_{n}", workload)
+        rows.append({
+            "kernel": f"{name_b}<{n}>", "order": n, "paths": cnt, "bound": "alu",
+            "achieved": fl_pad / t_b / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+            "frac": fl_pad / t_b / PEAK_FP32,
+            "frac_of_unpacked_fp32": fl_pad / t_b / PEAK_FP32_UNPACKED,
+            "ms": t_b * 1e3, "flops_per_launch": fl_pad,
+            "flops_active_dims": fl_act, "flops_builder_model": fl_mod,
+            "iterations_per_path": float(it.mean()),
+            "traffic": cb["hbm_bytes_per_launch"] if cb else None,
+            "counter_fp32_flop_per_launch": cb.get("counter_fp32_flop_per_launch") if cb else None,
+        })
+        ev, tr, so, mev, mtr, mso = work[n]
+        fl_r = so * newton_step_flops(n) + mso * newton_step_flops(max(n - 1, 1))
+        fl_rm = (ev * refine_eval_flops(n) + tr * refine_trial_flops(n)
+                 + so * refine_solve_flops(n)
+                 + mev * refine_eval_flops(max(n - 1, 1)) + mtr * refine_trial_flops(max(n - 1, 1))
+                 + mso * refine_solve_flops(max(n - 1, 1)) + cnt * refine_final_flops(n))
+        t_r = kt[fpt.T_REFINE + n - 1] * 1e-3
+        cr = read_counters(f"refine_group_{n}", workload)
+        rows.append({
+            "kernel": f"refinement group of order {n}: refine_kernel<{n}, true> (quick pass), "
+                      f"merge_kernel<{n}> (collapse steps), refine_kernel<{n}, false> (full schedule)",
+            "order": n, "paths": cnt, "bound": "alu",
+            "achieved": fl_r / t_r / 1e12 if t_r > 0 else 0.0, "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s", "frac": fl_r / t_r / PEAK_FP64 if t_r > 0 else 0.0,
+            "ms": t_r * 1e3, "flops_per_launch": fl_r, "flops_builder_model": fl_rm,
+            "achieved_builder_model": fl_rm / t_r / 1e12 if t_r > 0 else 0.0,
+            "newton_solves_per_path": so / cnt, "collapse_step_solves_per_path": mso / cnt,
+            "evaluations_per_path": ev / cnt, "trial_lengths_per_path": tr / cnt,
+            "traffic": cr["hbm_bytes_per_launch"] if cr else None,
+            "counter_fp64_flop_per_launch": cr.get("counter_fp64_flop_per_launch") if cr else None,
+        })
+    return rows
+
+
+def solve_workload(args, fpt, torch, solver, batch, opts, chosen, workload, outs_extra=None):
+    db = fpt.DeviceBatch(batch, device="cuda:0")
+    ms, per, out_np = timed_solve(args, solver, db, opts, torch)
+    kt, work = breakdown(args, solver, db, opts, torch)
+    rows = order_rooflines(fpt, batch, out_np, kt, work, opts, workload)
+    st = out_np["status"]
+    cert = (st & fpt.ST_CONVERGED) != 0
+    per_order = {str(n): {"paths": int((batch.order == n).sum()),
+                          "certified": float(cert[batch.order == n].mean())}
+                 for n in range(1, batch.n_max + 1) if (batch.order == n).any()}
+    kernel_ms = {"bucketing": kt[fpt.T_BUCKET]}
+    for n in range(1, batch.n_max + 1):
+        if (batch.order == n).any():
+            kernel_ms[f"first_phase_order{n}"] = kt[fpt.T_BFGS + n - 1]
+            kernel_ms[f"refine_order{n}"] = kt[fpt.T_REFINE + n - 1]
+    dominant = max(rows, key=lambda r: r["ms"])
+    other = [r for r in rows if r["peak"] != dominant["peak"]]
+    other = max(other, key=lambda r: r["ms"]) if other else None
+    del db
+    return {
+        "ms_per_step": ms, "ms_per_step_median": float(np.median(per)),
+        "ms_per_step_min": float(np.min(per)),
+        "certified": int(cert.sum()), "certified_fraction": float(cert.mean()),
+        "certified_paths_per_s": float(cert.sum() / (ms * 1e-3)),
+        "paths_per_s_all": batch.N / (ms * 1e-3),
+        "certified_per_order": per_order,
+        "schedule": {str(k): v for k, v in chosen.items()},
+        "kernel_ms_orders_one_after_another": kernel_ms,
+        "kernel_ms_sum": float(sum(v for v in kernel_ms.values() if v > 0)),
+        "roofline": dominant, "roofline_other": other, "rooflines": rows,
+    }, out_np
+
+
+def tune_or_fix(args, solver, batch, opts, sample, repeats, schedule=None, candidates=None):
+    if schedule:
+        chosen = {int(k): v for k, v in json.loads(schedule).items()}
+        for n, cfg in chosen.items():
+            solver.set_launch(n, cfg)
+        return chosen, False
+    if args.no_autotune:
+        return {}, False
+    from paper_2510_16172_amd import autotune
+    return autotune.tune(solver, batch, opts, sample=sample, repeats=repeats,
+                         candidates=candidates), True
+
+
+# ------------------------------------------------------------ workloads ----
+
+C3_WORKLOAD = ("street canyon: 8,388,608 sampled paths, orders 1..6 with P(n) "
+               "proportional to 2^-n (313 objects, 64 TX/RX pairs), one HIP graph per "
+               "step, the orders on streams of their own")
+C2_WORKLOAD = ("street canyon: all 6,270,016 interaction sequences of order <= 2 "
+               "(313 objects, 64 TX/RX pairs), one HIP graph per step")
+
+
+def run_c3(args, fpt, scenes, torch):
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 1 << 23, seed=1003, n=None, n_max=6)
     solver = fpt.Solver(0)
-    res, _ = learned_init.run(solver, n_train=1 << 22, n_test=1 << 20,
-                              epochs=args.mlp_epochs,
-                              log=lambda m: print(m, file=sys.stderr, flush=True))
+    opts = fpt.Opts(scale=b.S, iters=args.iters, fp_iters=args.fp_iters,
+                    concurrent_orders=True, split=args.split)
+    chosen, tuned = tune_or_fix(args, solver, b, opts, 1 << 18, 2, args.schedule)
+    res, out_np = solve_workload(args, fpt, torch, solver, b, opts, chosen, "canyon_c3")
+    res["config"] = {
+        "workload": C3_WORKLOAD, "paths": b.N,
+        "order_counts": {str(n): int((b.order == n).sum()) for n in range(1, 7)},
+        "autotuned": tuned, "fp_iters": opts.fp_iters,
+        "refine_levels": list(zip(opts.level_eps, opts.level_steps)),
+        "quick_steps": opts.quick_steps, "quick_passes": opts.quick_passes,
+        "polish_steps": opts.polish_steps, "concurrent_orders": True,
+        "split": opts.split if opts.split > 0 else 2,
+    }
     solver.close()
-    return res
+    return res, b, out_np
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--iters", type=int, default=64,
-                    help="BFGS iterations when the schedule is not autotuned")
-    ap.add_argument("--fp-iters", type=int, default=1)
-    ap.add_argument("--early-exit", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="use --iters / --early-exit for every order instead "
-                         "of the autotuned per-order schedule")
-    ap.add_argument("--schedule", type=str, default=None,
-                    help="JSON {order: launch config} applied with fpt_set_launch "
-                         "instead of autotuning (e.g. a previous run's config.schedule)")
-    ap.add_argument("--split", type=int, default=0,
-                    help="parts per order on their own streams (0: automatic, "
-                         "2 from 2^21 paths on); the instrumented pass uses 1")
-    ap.add_argument("--no-variant", action="store_true",
-                    help="skip the FP32 Newton solver-variant leg")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-grad", action="store_true",
-                    help="skip the forward+gradient leg")
-    ap.add_argument("--uneven", action="store_true",
-                    help="also run the mixed-order (1..6) graph workload")
-    ap.add_argument("--learned", action="store_true",
-                    help="also train and evaluate the learned initialiser")
-    ap.add_argument("--mlp-epochs", type=int, default=40)
-    ap.add_argument("--copy-calib", action="store_true",
-                    help="also run a plain device copy of known size (for "
-                         "calibrating the HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not "
-              "supported (paths are independent: several GPUs would each "
-              "solve a shard of the path list)", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2510_16172_amd import fpt, scenes
-
+def run_c2(args, fpt, scenes, torch, post=True, variant=True, check_seconds=0.0):
+    """All order <= 2 sequences; then (not in the metric) validity of the
+    solved paths, candidate enumeration and the chain enumerate -> solve ->
+    validity, and the FP32 Newton variant of the first phase."""
     scene = scenes.canyon_scene()
     batch = scenes.canyon_all_paths(scene, n_max=2)
     N = batch.N
     solver = fpt.Solver(0)
-    db = fpt.DeviceBatch(batch, device="cuda:0")
-    opts = fpt.Opts(scale=batch.S, iters=args.iters, fp_iters=args.fp_iters,
-                    early_exit=args.early_exit, split=args.split)
-    out = solver.alloc_out(db)
+    opts = fpt.Opts(scale=batch.S, iters=args.iters, fp_iters=args.fp_iters, split=args.split)
+    chosen, tuned = tune_or_fix(args, solver, batch, opts, 1 << 20, 3, args.schedule_c2)
+    res, out_np = solve_workload(args, fpt, torch, solver, batch, opts, chosen, "canyon_c2")
+    res["config"] = {"workload": C2_WORKLOAD, "paths": N, "autotuned": tuned,
+                     "split": opts.split if opts.split > 0 else 2}
+    outs = {"": out_np}
     stream = torch.cuda.current_stream()
-    chosen = {}
-    if args.schedule:
-        chosen = {int(k): v for k, v in json.loads(args.schedule).items()}
-        for n, cfg in chosen.items():
-            solver.set_launch(n, cfg)
-    elif not args.no_autotune:
+    db = fpt.DeviceBatch(batch, device="cuda:0")
+    out = solver.alloc_out(db)
+    solver.solve(db, opts, out=out)
+    torch.cuda.synchronize()
+    if variant:
+        opts_n = fpt.Opts(scale=batch.S, method=fpt.METHOD_NEWTON32)
         from paper_2510_16172_amd import autotune
-        chosen = autotune.tune(solver, batch, opts, sample=1 << 20, repeats=3)
-    orders = sorted(int(v) for v in np.unique(batch.order))
-
-    if args.copy_calib:
-        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")  # 256 MiB
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
+        chosen_n, _ = tune_or_fix(args, solver, batch, opts_n, 1 << 20, 3, None,
+                                  candidates=autotune.NEWTON32_CANDIDATES)
+        outv = solver.alloc_out(db)
+        for _ in range(args.warmup):
+            solver.solve(db, opts_n, out=outv, stream=stream)
         torch.cuda.synchronize()
-        print(f"copy calibration: {a.numel() * 4} bytes read and written per copy",
-              file=sys.stderr, flush=True)
+        v0, v1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        v0.record(stream)
+        for _ in range(args.steps):
+            solver.solve(db, opts_n, out=outv, stream=stream)
+        v1.record(stream)
+        torch.cuda.synchronize()
+        ms_n = v0.elapsed_time(v1) / args.steps
+        outs["newton32"] = {k: v.cpu().numpy() for k, v in outv.items()}
+        cert_n = int(((outs["newton32"]["status"] & fpt.ST_CONVERGED) != 0).sum())
+        res["variant_newton32"] = {
+            "method": "FP32 exact-Hessian Newton first phase (fpt_opts.method = 1)",
+            "schedule": {str(k): v for k, v in chosen_n.items()},
+            "ms_per_step": ms_n, "certified_fraction": cert_n / N,
+            "certified_paths_per_s": cert_n / (ms_n * 1e-3)}
+        for n in (1, 2):
+            solver.set_launch(n, chosen.get(n))
+        solver.solve(db, opts, out=out)
+        torch.cuda.synchronize()
+    if post:
+        res.update(post_legs(fpt, torch, solver, scene, batch, db, out, opts, stream))
+    if check_seconds > 0:
+        res["oracle_check"] = cpu_baseline(batch, outs, check_seconds, host_threads(), seed=8)
+        res["oracle_check"].pop("value_1thread", None)
+    solver.close()
+    return res
 
-    for _ in range(args.warmup):
-        solver.solve(db, opts, out=out, stream=stream)
-    torch.cuda.synchronize()
-    # the timed steps (no library instrumentation)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    ev[0].record(stream)
-    for k in range(args.steps):
-        solver.solve(db, opts, out=out, stream=stream)
-        ev[k + 1].record(stream)
-    torch.cuda.synchronize()
-    ms_step = ev[0].elapsed_time(ev[-1]) / args.steps
-    per_step = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
-    # the same steps again with the per-kernel HIP-event timers and the
-    # refinement work counters on, for the kernel breakdown and rooflines; in
-    # one part per order (split = 1), so that each timer brackets one launch
-    # of the order's whole bucket (the parts overlap in the timed steps)
-    import dataclasses
-    opts_one = dataclasses.replace(opts, split=1)
-    solver.set_timing(True)
-    solver.work_counts()  # clear
-    for k in range(args.steps):
-        solver.solve(db, opts_one, out=out, stream=stream)
-    kt = solver.kernel_times()
-    work = solver.work_counts()
-    solver.set_timing(False)
 
-    # post-processing (not part of the metric): validity of the solved paths
-    # on the scene's finite objects
+def post_legs(fpt, torch, solver, scene, batch, db, out, opts, stream):
+    N = batch.N
+    v0, v1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     vflags = solver.validate(db, out, stream=stream)
     torch.cuda.synchronize()
-    v0, v1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     v0.record(stream)
     for _ in range(3):
         solver.validate(db, out, flags=vflags, stream=stream)
@@ -480,7 +630,6 @@ def main():
     torch.cuda.synchronize()
     ms_val = v0.elapsed_time(v1) / 3
     vf = vflags.cpu().numpy()
-    # lazy mode: occlusion only for paths that pass the extent and side tests
     lflags = solver.validate(db, out, lazy=True, stream=stream)
     torch.cuda.synchronize()
     v0.record(stream)
@@ -490,14 +639,7 @@ def main():
     torch.cuda.synchronize()
     ms_val_lazy = v0.elapsed_time(v1) / 3
     lazy_same_valid = bool(np.array_equal(lflags.cpu().numpy() == 7, vf == 7))
-
-    out_np = {k: v.cpu().numpy() for k, v in out.items()}
-    st = out_np["status"]
-    certified = int(((st & fpt.ST_CONVERGED) != 0).sum())
-    value = certified / (ms_step / 1e3)
-
-    # candidate enumeration on the device (the step before the solve), and
-    # the chain candidates -> solve -> validity (lazy) on one stream
+    st = out["status"].cpu().numpy()
     n_pairs = scene.meta["n_pairs"]
     tps = torch.arange(0, 2 * n_pairs, 2, dtype=torch.int32, device="cuda:0")
     tpd = tps + 1
@@ -511,125 +653,22 @@ def main():
     v1.record(stream)
     torch.cuda.synchronize()
     ms_enum = v0.elapsed_time(v1) / 5
-    enum_bytes = 4 + 4 + 1 + 4 * batch.n_max  # src, dst, order, ids written per candidate
+    enum_bytes = 4 + 4 + 1 + 4 * batch.n_max
     dbe = fpt.DeviceBatch.from_tensors(db.obj, db.pts, eo["src"], eo["dst"], eo["ids"],
                                        eo["order"], S=batch.S)
+    outc = solver.alloc_out(dbe)
     cflags = solver.validate(dbe, out, lazy=True, stream=stream)
+    solver.solve(dbe, opts, out=outc, stream=stream)
     torch.cuda.synchronize()
     v0.record(stream)
     for _ in range(3):
         solver.enumerate(tps, tpd, scene.K, 1, 2, out=eo, stream=stream)
-        solver.solve(dbe, opts, out=out, stream=stream)
-        solver.validate(dbe, out, flags=cflags, lazy=True, stream=stream)
+        solver.solve(dbe, opts, out=outc, stream=stream)
+        solver.validate(dbe, outc, flags=cflags, lazy=True, stream=stream)
     v1.record(stream)
     torch.cuda.synchronize()
     ms_chain = v0.elapsed_time(v1) / 3
-    chain_valid = int((cflags == 7).sum().item())
-
-    # solver variant (not the paper's method, not in `value`): the FP32
-    # exact-Hessian Newton first phase, autotuned the same way, same steps
-    variant, others = None, {}
-    if not args.no_variant:
-        from paper_2510_16172_amd import autotune
-        opts_n = fpt.Opts(scale=batch.S, method=fpt.METHOD_NEWTON32)
-        chosen_n = autotune.tune(solver, batch, opts_n,
-                                 candidates=autotune.NEWTON32_CANDIDATES,
-                                 sample=1 << 20, repeats=3)
-        for _ in range(args.warmup):
-            solver.solve(db, opts_n, out=out, stream=stream)
-        torch.cuda.synchronize()
-        v0.record(stream)
-        for _ in range(args.steps):
-            solver.solve(db, opts_n, out=out, stream=stream)
-        v1.record(stream)
-        torch.cuda.synchronize()
-        ms_n = v0.elapsed_time(v1) / args.steps
-        others["newton32"] = {k: v.cpu().numpy() for k, v in out.items()}
-        cert_n = int(((others["newton32"]["status"] & fpt.ST_CONVERGED) != 0).sum())
-        variant = {"method": "FP32 exact-Hessian Newton first phase (fpt_opts.method = 1)",
-                   "schedule": {str(k): v for k, v in chosen_n.items()},
-                   "ms_per_step": ms_n, "certified_fraction": cert_n / N,
-                   "certified_paths_per_s": cert_n / (ms_n * 1e-3)}
-
-    # rooflines of the two kernels of the order-2 bucket (99.7 % of the
-    # paths): FP32 BFGS and FP64 refinement; the dominant one is `roofline`
-    workload = "canyon_order2_all"
-    o2 = batch.order == 2
-    ee2 = bool(chosen.get(2, {}).get("early_exit", int(args.early_exit)))
-    it2 = out_np["iters"][o2].astype(np.int64)
-    fl_b = (int(it2.sum()) * bfgs_flops_per_iter(2, args.fp_iters, ee2)
-            + int(o2.sum()) * (bfgs_init_flops(2) + polish_flops(2, opts.polish_steps)))
-    t_b = kt[fpt.T_BFGS + 1] * 1e-3
-    kname_b = "bfgs_stage_kernel<2>" if ee2 else "bfgs_kernel<2>"
-    n_eval, n_trial, n_solve, m_eval, m_trial, m_solve = (v / args.steps for v in work[2])
-    # refinement passes at order 2, reduced paths of the collapse step at 1
-    fl_r = (n_eval * refine_eval_flops(2) + n_trial * refine_trial_flops(2)
-            + n_solve * refine_solve_flops(2)
-            + m_eval * refine_eval_flops(1) + m_trial * refine_trial_flops(1)
-            + m_solve * refine_solve_flops(1)
-            + int(o2.sum()) * refine_final_flops(2))
-    t_r = kt[fpt.T_REFINE + 1] * 1e-3
-    roof_b = {
-        "kernel": kname_b + (" (every stage launch)" if ee2 else ""),
-        "bound": "alu", "achieved": fl_b / t_b / 1e12, "peak": PEAK_FP32 / 1e12,
-        "unit": "TFLOP/s", "frac": fl_b / t_b / PEAK_FP32,
-        "frac_of_unpacked_fp32": fl_b / t_b / PEAK_FP32_UNPACKED,
-        "flops_per_launch": fl_b, "ms": t_b * 1e3,
-        "traffic": read_traffic(kname_b.split("<")[0] + "_2", workload),
-    }
-    roof_r = {
-        "kernel": "refine_kernel<2> (both passes) + merge_kernel<2>",
-        "bound": "alu", "achieved": fl_r / t_r / 1e12, "peak": PEAK_FP64 / 1e12,
-        "unit": "TFLOP/s", "frac": fl_r / t_r / PEAK_FP64,
-        "flops_per_launch": fl_r, "ms": t_r * 1e3,
-        "evaluations_per_path": n_eval / int(o2.sum()),
-        "trial_lengths_per_path": n_trial / int(o2.sum()),
-        "newton_solves_per_path": n_solve / int(o2.sum()),
-        "collapse_step_evaluations_per_path": m_eval / int(o2.sum()),
-        "collapse_step_trial_lengths_per_path": m_trial / int(o2.sum()),
-        "collapse_step_solves_per_path": m_solve / int(o2.sum()),
-        "traffic": read_traffic("refine_kernel_2", workload),
-    }
-    dominant, other = (roof_b, roof_r) if t_b >= t_r else (roof_r, roof_b)
-    kernels_ms = {"bucketing": kt[fpt.T_BUCKET]}
-    for n in orders:
-        kernels_ms[f"bfgs_order{n}"] = kt[fpt.T_BFGS + n - 1]
-        kernels_ms[f"refine_order{n}"] = kt[fpt.T_REFINE + n - 1]
-    schedule = {str(n): (chosen.get(n) or {"iters": args.iters,
-                                           "early_exit": int(args.early_exit)})
-                for n in orders}
-    res = {
-        "metric": "converged paths/s (fwd, fwd+grad) at <=1e-4 rel error",
-        "value": value,
-        "unit": "paths/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "ms_per_step_median": float(np.median(per_step)),
-        "ms_per_step_min": float(np.min(per_step)),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {
-            "workload": "street canyon: all 6,270,016 interaction sequences "
-                        "of order <= 2 (313 objects, 64 TX/RX pairs)",
-            "paths": N, "fp_iters": args.fp_iters,
-            "schedule": schedule,
-            "autotuned": not args.no_autotune and not args.schedule,
-            "refine_levels": list(zip(opts.level_eps, opts.level_steps)),
-            "quick_steps": opts.quick_steps,
-            "quick_passes": opts.quick_passes,
-            "polish_steps": opts.polish_steps,
-            "split": opts.split if opts.split > 0 else (2 if N >= (1 << 21) else 1),
-        },
-        "certified_fraction": certified / N,
-        "paths_per_s_all": N / (ms_step / 1e3),
-        "kernel_ms": kernels_ms,
-        "roofline": dominant,
-        "roofline_other": other,
+    return {
         "validate": {
             "ms": ms_val, "paths_per_s": N / (ms_val * 1e-3),
             "ms_lazy": ms_val_lazy, "lazy_same_valid_set": lazy_same_valid,
@@ -647,33 +686,130 @@ def main():
                          "frac": N * enum_bytes / (ms_enum * 1e-3) / 1e9 / 8000.0},
             "same_as_host_generator": enum_same,
         },
-        "variant_newton32": variant,
         "chain": {
             "steps": "enumerate + solve + lazy validity, one stream",
             "ms": ms_chain, "candidates_per_s": N / (ms_chain * 1e-3),
-            "valid_paths": chain_valid,
+            "valid_paths": int((cflags == 7).sum().item()),
         },
     }
-    if not args.no_cpu_baseline:
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-        res["cpu_baseline"] = cpu_baseline(batch, out_np, args.cpu_seconds, threads,
-                                           others=others)
-        if res["cpu_baseline"]["sample"].startswith("all "):
-            # every output checked against the oracle: paths within 1e-4 S per
-            # second, certified or not (the certificate is conservative)
-            res["paths_within_1e-4_per_s_oracle_checked"] = (
-                res["cpu_baseline"]["gpu_within_1e-4_paths"] / (ms_step / 1e3))
+
+
+def run_learned(args, fpt, torch):
+    from paper_2510_16172_amd import learned_init
+    solver = fpt.Solver(0)
+    res, _ = learned_init.run(solver, n_train=1 << 22, n_test=1 << 20,
+                              epochs=args.mlp_epochs,
+                              log=lambda m: print(m, file=sys.stderr, flush=True))
     solver.close()
-    del db, out
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=("c3", "c2"), default="c3",
+                    help="headline: c3 (orders 1..6, 2^23 paths) or c2 (all order <= 2)")
+    ap.add_argument("--iters", type=int, default=64,
+                    help="BFGS iterations when the schedule is not autotuned")
+    ap.add_argument("--fp-iters", type=int, default=1)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use --iters for every order instead of the autotuned schedule")
+    ap.add_argument("--schedule", type=str, default=None,
+                    help="JSON {order: launch config} for the headline workload instead of "
+                         "autotuning (e.g. a previous run's config.schedule)")
+    ap.add_argument("--schedule-c2", type=str, default=None,
+                    help="the same for the c2 leg")
+    ap.add_argument("--split", type=int, default=0,
+                    help="parts per order on their own streams (0: automatic)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c2", action="store_true", help="skip the order <= 2 leg")
+    ap.add_argument("--no-post", action="store_true",
+                    help="skip validity / enumeration / chain on the c2 leg")
+    ap.add_argument("--no-variant", action="store_true",
+                    help="skip the FP32 Newton variant on the c2 leg")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the solve + implicit gradient leg")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training and evaluating the learned initialiser")
+    ap.add_argument("--mlp-epochs", type=int, default=40)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="copy a 256 MiB buffer three times first (for calibrating the "
+                         "HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not "
+              "supported (paths are independent: several GPUs would each "
+              "solve a shard of the path list)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_16172_amd import fpt, scenes
+
+    if args.copy_calib:
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")  # 256 MiB
+        bb = torch.empty_like(a)
+        for _ in range(3):
+            bb.copy_(a)
+        torch.cuda.synchronize()
+        del a, bb
+        print("copy calibration: 268435456 bytes read and written per copy",
+              file=sys.stderr, flush=True)
+
+    legs = {}
+    if args.workload == "c3":
+        head, batch, out_np = run_c3(args, fpt, scenes, torch)
+    else:
+        args.schedule_c2 = args.schedule_c2 or args.schedule
+        head = run_c2(args, fpt, scenes, torch, post=not args.no_post,
+                      variant=not args.no_variant)
+        batch, out_np = None, None
     torch.cuda.empty_cache()
+    res = {
+        "metric": "converged paths/s (fwd, fwd+grad) at <=1e-4 rel error; % FP32 VALU peak",
+        "value": head["certified_paths_per_s"],
+        "unit": "paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "ms_per_step_median": head["ms_per_step_median"],
+        "ms_per_step_min": head["ms_per_step_min"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {**head["config"], "schedule": head["schedule"]},
+        "certified_fraction": head["certified_fraction"],
+        "certified_per_order": head["certified_per_order"],
+        "paths_per_s_all": head["paths_per_s_all"],
+        "roofline": head["roofline"],
+        "roofline_other": head["roofline_other"],
+        "rooflines": head["rooflines"],
+        "kernel_ms_orders_one_after_another": head["kernel_ms_orders_one_after_another"],
+    }
+    for k in ("validate", "enumerate", "chain", "variant_newton32"):
+        if k in head:
+            res[k] = head[k]
+    if not args.no_cpu_baseline and batch is not None:
+        res["cpu_baseline"] = cpu_baseline(batch, {"": out_np}, args.cpu_seconds,
+                                           host_threads())
+    del out_np
+    if args.workload == "c3" and not args.no_c2:
+        legs["c2"] = run_c2(args, fpt, scenes, torch, post=not args.no_post,
+                            variant=not args.no_variant,
+                            check_seconds=0.0 if args.no_cpu_baseline else 6.0)
+        torch.cuda.empty_cache()
     if not args.no_grad:
-        res["fwd_grad"] = run_fwd_grad(args, fpt, scenes, torch)
+        legs["fwd_grad"] = run_fwd_grad(args, fpt, scenes, torch)
         torch.cuda.empty_cache()
-    if args.uneven:
-        res["uneven_orders"] = run_uneven(args, fpt, scenes, torch)
+    if not args.no_learned:
+        legs["learned_init"] = run_learned(args, fpt, torch)
         torch.cuda.empty_cache()
-    if args.learned:
-        res["learned_init"] = run_learned(args, fpt, torch)
+    res.update(legs)
     print(json.dumps(res), flush=True)
 
 
