@@ -497,7 +497,7 @@ def solve_workload(args, fpt, torch, solver, batch, opts, chosen, workload, outs
     per_order = {str(n): {"paths": int((batch.order == n).sum()),
                           "certified": float(cert[batch.order == n].mean())}
                  for n in range(1, batch.n_max + 1) if (batch.order == n).any()}
-    kernel_ms = {"bucketing": kt[fpt.T_BUCKET]}
+    kernel_ms = {"bucketing_and_gather": kt[fpt.T_BUCKET], "unsort": kt[fpt.T_UNSORT]}
     for n in range(1, batch.n_max + 1):
         if (batch.order == n).any():
             kernel_ms[f"first_phase_order{n}"] = kt[fpt.T_BFGS + n - 1]

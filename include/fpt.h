@@ -342,13 +342,16 @@ fpt_status fpt_graph_destroy(fpt_graph* g);
  * and writes, per timer slot, the mean duration in milliseconds over the
  * launches recorded since the previous read (at most the last 32), or -1 if
  * there were none, to ms[FPT_TIMERS]; it then clears the counts. Slots:
- *   FPT_T_BUCKET           order bucketing (count, scan, scatter)
+ *   FPT_T_BUCKET           order bucketing (count, scan, scatter) and the
+ *                          copy of the paths' indices into bucket order
  *   FPT_T_BFGS + n - 1     FP32 BFGS kernel of order n (n = 1..6)
  *   FPT_T_REFINE + n - 1   FP64 refinement kernel of order n
  *   FPT_T_GRAD             implicit-differentiation kernel
  *   FPT_T_REDUCE           per-object gradient reduction
  *   FPT_T_MLP              learned-initialiser inference
  *   FPT_T_VALIDATE         path validity (fpt_validate)
+ *   FPT_T_UNSORT           the copy of the outputs from bucket order to the
+ *                          caller's order (solves with an order array)
  * Enabling allocates the events (returns FPT_EHIP if that fails). */
 enum {
   FPT_T_BUCKET = 0,
@@ -358,7 +361,8 @@ enum {
   FPT_T_REDUCE = 14,
   FPT_T_MLP = 15,
   FPT_T_VALIDATE = 16,
-  FPT_TIMERS = 17
+  FPT_T_UNSORT = 17,
+  FPT_TIMERS = 18
 };
 fpt_status fpt_set_timing(fpt_handle* h, int enable);
 fpt_status fpt_kernel_times(fpt_handle* h, float* ms);

@@ -17,9 +17,11 @@ int stage_fields_for(int order);
 const void* solve_kernel_ptr(int phase, int order);
 hipError_t launch_bucketing(const uint8_t* order, int64_t N, int n_max,
                             uint32_t* ccount, int64_t* bucket, int32_t* perm,
-                            hipStream_t st);
+                            hipStream_t st, int32_t* inv = nullptr);
 hipError_t launch_invalid(const SolveArgs& A, const int32_t* perm,
                           const int64_t* bucket, int grid, hipStream_t st);
+hipError_t launch_unsort(const SolveArgs& S, const SolveArgs& A, const int32_t* inv,
+                         const int64_t* bucket, int grid, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 hipError_t launch_grad(int order, const GradArgs& A, const int32_t* perm,
                        const int64_t* bucket, int grid, size_t shmem,
@@ -83,6 +85,11 @@ struct fpt_handle {
   // learned-initialiser activations (grown on demand)
   fpt::MlpWork mlp = {};
   void* mlp_mem = nullptr;
+  // the solve in bucket order (an order array given): the paths' indices
+  // and start points in bucket order, the inverse permutation, and the
+  // outputs in bucket order (one allocation, see sorted_layout)
+  void* sorted_mem = nullptr;
+  size_t sorted_bytes = 0;
   // captured graphs that record this handle's solve workspace: while any
   // exists, the workspace is neither grown nor freed
   int live_graphs = 0;
@@ -221,6 +228,7 @@ extern "C" fpt_status fpt_destroy(fpt_handle* h) {
   if (h->faces) (void)hipFree(h->faces);
   if (h->scount) (void)hipFree(h->scount);
   if (h->mlp_mem) (void)hipFree(h->mlp_mem);
+  if (h->sorted_mem) (void)hipFree(h->sorted_mem);
   for (int k = 0; k < 2; ++k)
     if (h->sstate[k]) (void)hipFree(h->sstate[k]);
   for (int w = 0; w <= kUnits; ++w)
@@ -380,6 +388,51 @@ static fpt_status ensure_states(fpt_handle* h, int64_t N, int n_state) {
   return FPT_OK;
 }
 
+// Buffers of the solve in bucket order for N paths of at most n_max
+// interactions, each 256-byte aligned: outputs x [n_max][3][N],
+// t [n_max][2][N], len [N], iters [N], status [N]; the copied indices
+// src, dst [N], ids [n_max][N]; the inverse permutation inv [N].
+struct SortedLayout {
+  size_t x, t, len, iters, status, src, dst, ids, inv, total;
+};
+
+static SortedLayout sorted_layout(int64_t N, int n_max) {
+  SortedLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t n = (size_t)N;
+  L.x = take(n * 3 * n_max * sizeof(float));
+  L.t = take(n * 2 * n_max * sizeof(float));
+  L.len = take(n * sizeof(float));
+  L.iters = take(n * sizeof(uint16_t));
+  L.status = take(n);
+  L.src = take(n * sizeof(int32_t));
+  L.dst = take(n * sizeof(int32_t));
+  L.ids = take(n * n_max * sizeof(int32_t));
+  L.inv = take(n * sizeof(int32_t));
+  L.total = off;
+  return L;
+}
+
+static fpt_status ensure_sorted(fpt_handle* h, int64_t N, int n_max) {
+  const size_t need = sorted_layout(N, n_max).total;
+  if (h->sorted_bytes >= need) return FPT_OK;
+  if (h->sorted_mem && h->live_graphs > 0) return refuse_growth(h);
+  if (h->sorted_mem) (void)hipFree(h->sorted_mem);
+  h->sorted_mem = nullptr;
+  h->sorted_bytes = 0;
+  if (hipMalloc(&h->sorted_mem, need) != hipSuccess) {
+    h->sorted_mem = nullptr;
+    return fail(FPT_ENOMEM, "bucket-order workspace allocation failed");
+  }
+  h->sorted_bytes = need;
+  return FPT_OK;
+}
+
 // The stream and join event of unit w (and the fork event), created once.
 static fpt_status ensure_stream(fpt_handle* h, int w) {
   if (!h->ev_fork &&
@@ -521,6 +574,8 @@ static fpt_status prepare_solve(fpt_handle* h, const fpt_paths* pa, const fpt_op
   if (pa->order) {
     s = ensure_perm(h, pa->N);
     if (s != FPT_OK) return s;
+    s = ensure_sorted(h, pa->N, pa->n_max);
+    if (s != FPT_OK) return s;
   }
   const bool lists = any_ee || (o->n_levels > 0 && o->quick_steps > 0);
   if (!lists) {
@@ -580,11 +635,13 @@ struct SolveWs {
   unsigned long long* scount;
   int32_t* slist[kUnits + 1][2];
   float* sstate[2];
+  unsigned char* sorted;  // bucket-order buffers (sorted_layout), or null
 };
 
 static SolveWs handle_ws(const fpt_handle* h) {
   SolveWs W;
   memset(&W, 0, sizeof(W));
+  W.sorted = (unsigned char*)h->sorted_mem;
   W.perm = h->perm;
   W.ccount = h->ccount;
   W.bucket = h->bucket;
@@ -635,6 +692,7 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
   }
   A.cert_abs = o->cert_rtol * o->scale;
   A.quick_steps = o->n_levels > 0 ? o->quick_steps : 0;
+  A.pad_outputs = 1;
 
   hipError_t e;
   int64_t cap = (pa->N + fpt::kBlock - 1) / fpt::kBlock;
@@ -645,13 +703,43 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
   const int n_lo = P.n_lo;
   const int32_t* perm = nullptr;
   const int64_t* bucket = nullptr;
+  // with a bucket-order workspace the per-order kernels see the paths in
+  // bucket order (As, perm null); the caller's arrays are written at the end
+  fpt::SolveArgs As = A, Af = A;
+  const bool sorted = pa->order && W.sorted;
+  const SortedLayout SL = sorted_layout(pa->N, pa->n_max);
   if (pa->order) {
     SlotTimer tm(h, FPT_T_BUCKET, st);
-    e = fpt::launch_bucketing(pa->order, pa->N, pa->n_max, W.ccount,
-                              W.bucket, W.perm, st);
+    e = fpt::launch_bucketing(pa->order, pa->N, pa->n_max, W.ccount, W.bucket, W.perm, st,
+                              sorted ? (int32_t*)(W.sorted + SL.inv) : nullptr);
     if (e != hipSuccess) return hip_fail(e, "fpt_solve: bucketing launch");
     perm = W.perm;
     bucket = W.bucket;
+    if (sorted) {
+      unsigned char* b = W.sorted;
+      As.x = (float*)(b + SL.x);
+      As.len = (float*)(b + SL.len);
+      As.t = (float*)(b + SL.t);
+      As.iters = (uint16_t*)(b + SL.iters);
+      As.status = b + SL.status;
+      As.src = (const int32_t*)(b + SL.src);
+      As.dst = (const int32_t*)(b + SL.dst);
+      As.ids = (const int32_t*)(b + SL.ids);
+      As.t_init = nullptr;
+      As.order = nullptr;
+      As.pad_outputs = 0;
+      // the first phase gathers the inputs through the permutation
+      Af = As;
+      Af.perm_in = W.perm;
+      Af.src_in = pa->src;
+      Af.dst_in = pa->dst;
+      Af.ids_in = pa->ids;
+      Af.tinit_in = pa->t_init;
+      Af.src_cp = (int32_t*)(b + SL.src);
+      Af.dst_cp = (int32_t*)(b + SL.dst);
+      Af.ids_cp = (int32_t*)(b + SL.ids);
+      perm = nullptr;
+    }
   }
   if (P.multi) {
     e = hipEventRecord(h->ev_fork, st);
@@ -675,13 +763,23 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
     const fpt_launch_cfg& c = h->cfg[n];
     const bool ee = c.use_override ? c.early_exit != 0 : A.early_exit != 0;
     const int32_t* stages = (c.use_override && ee) ? c.stage_iters : o->stage_iters;
-    fpt::SolveArgs An = A;
+    fpt::SolveArgs An = As;
     An.sub = part;
     An.nsub = P.split;
     if (c.use_override && c.iters > 0) An.n_iter = c.iters;
     if (c.use_override && c.quick_steps > 0 && A.quick_steps > 0) An.quick_steps = c.quick_steps;
     const int qpasses = (c.use_override && c.quick_passes > 0) ? c.quick_passes : o->quick_passes;
     An.work = (h->timing && h->work) ? h->work + 6 * fpt::kWorkSlots * (n - 1) : nullptr;
+    // the first phase (its first stage with early exit) gathers the inputs
+    fpt::SolveArgs Anf = An;
+    Anf.perm_in = Af.perm_in;
+    Anf.src_in = Af.src_in;
+    Anf.dst_in = Af.dst_in;
+    Anf.ids_in = Af.ids_in;
+    Anf.tinit_in = Af.tinit_in;
+    Anf.src_cp = Af.src_cp;
+    Anf.dst_cp = Af.dst_cp;
+    Anf.ids_cp = Af.ids_cp;
     {
       SlotTimer tm(h, FPT_T_BFGS + n - 1, sn);
       if (!ee) {
@@ -689,8 +787,8 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
         // bucket (its size is only known on the device)
         // (it also clears the counter blocks of the refinement's lists)
         const int ph = An.method == FPT_METHOD_NEWTON32 ? 5 : 0;
-        int grid = perm ? persistent(ph, n, c.wg_per_cu) : (int)cap;
-        fpt::SolveArgs Ab = An;
+        int grid = bucket ? persistent(ph, n, c.wg_per_cu) : (int)cap;
+        fpt::SolveArgs Ab = Anf;
         if (An.quick_steps > 0) {
           Ab.clear = cnt;
           Ab.clear_n = 4 * nc;
@@ -718,8 +816,8 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
             e = fpt::launch_zero_u64(S.out_count, nc, sn);
             if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
           }
-          int grid = (k == 0 && !perm) ? (int)cap : persistent(2, n, c.wg_per_cu);
-          e = fpt::launch_solve(2, n, An, perm, bucket, &S, grid, sn);
+          int grid = (k == 0 && !bucket) ? (int)cap : persistent(2, n, c.wg_per_cu);
+          e = fpt::launch_solve(2, n, k == 0 ? Anf : An, perm, bucket, &S, grid, sn);
           if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         }
       }
@@ -728,7 +826,7 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
       SlotTimer tm(h, FPT_T_REFINE + n - 1, sn);
       fpt::StageArgs R;
       memset(&R, 0, sizeof(R));
-      int grid = perm ? persistent(1, n, 0) : (int)cap;
+      int grid = bucket ? persistent(1, n, 0) : (int)cap;
       if (An.quick_steps > 0) {
         // stage k lists its uncertified paths in list k & 1 with counter
         // block k; the blocks are cleared together first (by the first
@@ -742,7 +840,7 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
         // pass 1: quick steps for all, list the uncertified paths
         R.out_list = W.slist[w][0];
         R.out_count = cnt;
-        e = fpt::launch_solve(4, n, An, perm, bucket, &R, perm ? persistent(4, n, 0) : (int)cap,
+        e = fpt::launch_solve(4, n, An, perm, bucket, &R, bucket ? persistent(4, n, 0) : (int)cap,
                               sn);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         int k = 0;  // the stage whose list is current
@@ -796,8 +894,14 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
     }
   }
   if (pa->order) {
-    e = fpt::launch_invalid(A, W.perm, W.bucket, h->num_cu * 4, st);
+    e = fpt::launch_invalid(As, perm, W.bucket, h->num_cu * 4, st);
     if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+    if (sorted) {
+      SlotTimer tm(h, FPT_T_UNSORT, st);
+      e = fpt::launch_unsort(As, A, (const int32_t*)(W.sorted + SL.inv), W.bucket,
+                             h->num_cu * 8, st);
+      if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
+    }
   }
   return FPT_OK;
 }

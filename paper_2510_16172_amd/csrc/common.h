@@ -97,6 +97,20 @@ struct SolveArgs {
   int32_t level_steps[FPT_MAX_LEVELS];
   float cert_abs;  // cert_rtol * scale
   int32_t quick_steps;  // > 0: two-pass refinement (see refine_kernel)
+  int32_t pad_outputs;  // 1: write NaN to the entries beyond a path's order
+                        // (0 in bucket order: the final copy writes them)
+  // The first phase of a solve in bucket order (perm_in non-null): path
+  // slot p's inputs are read from the caller's arrays at perm_in[p], and its
+  // indices are copied to the bucket-order rows src_cp, dst_cp, ids_cp, which
+  // the passes that follow read as src, dst, ids.
+  const int32_t* perm_in;
+  const int32_t* src_in;
+  const int32_t* dst_in;
+  const int32_t* ids_in;
+  const float* tinit_in;
+  int32_t* src_cp;
+  int32_t* dst_cp;
+  int32_t* ids_cp;
   // null, or the work counters of the launch's order (accounting while
   // timing): [4][kWorkSlots] FP64 path evaluations and Newton solves of
   // refine_kernel, then of merge_kernel's reduced paths; a wave adds to

@@ -1309,7 +1309,7 @@ __device__ __forceinline__ void write_path64(const SolveArgs& A,
     A.t[(int64_t)(2 * j) * A.N + p] = valid ? (float)td[2 * j] : qnan;
     A.t[(int64_t)(2 * j + 1) * A.N + p] = valid ? (float)td[2 * j + 1] : qnan;
   }
-  for (int j = NO; j < A.n_max; ++j) {
+  for (int j = NO; j < (A.pad_outputs ? A.n_max : 0); ++j) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) A.x[(int64_t)(3 * j + c) * A.N + p] = qnan;
     A.t[(int64_t)(2 * j) * A.N + p] = qnan;
@@ -1337,7 +1337,19 @@ template <int NO>
 __device__ __forceinline__ bool load_path32(const SolveArgs& A, int64_t p,
                                             Geo32<NO>& G, float (*t0)[2]) {
   bool valid = true;
-  int32_t s = A.src[p], e = A.dst[p];
+  // (in bucket order, the first phase reads the caller's arrays through the
+  // permutation and leaves copies of the indices at slot p)
+  const bool gather = A.perm_in != nullptr;
+  const int64_t q = gather ? (int64_t)A.perm_in[p] : p;
+  const int32_t* __restrict__ srcv = gather ? A.src_in : A.src;
+  const int32_t* __restrict__ dstv = gather ? A.dst_in : A.dst;
+  const int32_t* __restrict__ idsv = gather ? A.ids_in : A.ids;
+  const float* __restrict__ tin = gather ? A.tinit_in : A.t_init;
+  int32_t s = srcv[q], e = dstv[q];
+  if (gather) {
+    A.src_cp[p] = s;
+    A.dst_cp[p] = e;
+  }
   valid = valid && s >= 0 && s < A.Q && e >= 0 && e < A.Q;
   s = valid ? s : 0;
   e = valid ? e : 0;
@@ -1349,7 +1361,8 @@ __device__ __forceinline__ bool load_path32(const SolveArgs& A, int64_t p,
   }
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
-    int32_t k = A.ids[(int64_t)j * A.N + p];
+    int32_t k = idsv[(int64_t)j * A.N + q];
+    if (gather) A.ids_cp[(int64_t)j * A.N + p] = k;
     bool kok = k >= 0 && k < A.K;
     valid = valid && kok;
     k = kok ? k : 0;
@@ -1372,10 +1385,10 @@ __device__ __forceinline__ bool load_path32(const SolveArgs& A, int64_t p,
       G.a[j][1][c] = a2[c] * i2;
     }
     float u0 = 0.f, u1 = 0.f;
-    if (A.t_init) {
+    if (tin) {
       // to unit-vector coordinates: that = t * |a|
-      u0 = A.t_init[(int64_t)(2 * j) * A.N + p] * rcp32(i1);
-      u1 = edge ? 0.f : A.t_init[(int64_t)(2 * j + 1) * A.N + p] * rcp32(i2);
+      u0 = tin[(int64_t)(2 * j) * A.N + q] * rcp32(i1);
+      u1 = edge ? 0.f : tin[(int64_t)(2 * j + 1) * A.N + q] * rcp32(i2);
       if (!isfinite(u0)) u0 = 0.f;
       if (!isfinite(u1)) u1 = 0.f;
     }
@@ -2152,7 +2165,8 @@ __device__ __forceinline__ int sort_skew(int i) { return i + (i >> 5); }
 
 __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
     const uint8_t* __restrict__ order, int64_t N, int n_max,
-    const uint32_t* __restrict__ coff, int32_t* __restrict__ perm) {
+    const uint32_t* __restrict__ coff, int32_t* __restrict__ perm,
+    int32_t* __restrict__ inv) {
   __shared__ uint32_t wtot[kBlock / 64][8];
   __shared__ int32_t stage[kSortChunk + kSortChunk / 32];
   __shared__ int32_t toff[8][kBlock];
@@ -2197,11 +2211,14 @@ __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
   }
   // (each thread reads back only its own column: no barrier)
   uint64_t run = 0;
+  int lp[kSortPer];  // each path's place in the sorted chunk
 #pragma unroll
   for (int q = 0; q < kSortPer; ++q) {
     const int b = bins[q];
+    lp[q] = -1;
     if (b >= 0) {
-      stage[sort_skew(toff[b][threadIdx.x] + (int)bin_field(run, b))] = (int32_t)(base + q);
+      lp[q] = toff[b][threadIdx.x] + (int)bin_field(run, b);
+      stage[sort_skew(lp[q])] = (int32_t)(base + q);
       run += bin_unit(b);
     }
   }
@@ -2213,16 +2230,25 @@ __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
     for (int b = 1; b < 8; ++b) k += (i >= lstart[b]) ? 1 : 0;
     perm[(int64_t)gstart[k] + (i - lstart[k])] = stage[sort_skew(i)];
   }
+  if (!inv) return;
+  // the inverse permutation (inv[p] = slot of path p), if asked for: each
+  // thread writes its 32 consecutive paths
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int b = bins[q];
+    if (b >= 0) inv[base + q] = (int32_t)(gstart[b] + (uint32_t)(lp[q] - lstart[b]));
+  }
 }
 
-// Paths with an order outside 1..n_max: NaN outputs, INVALID status.
+// Paths with an order outside 1..n_max: NaN outputs, INVALID status (perm
+// null: the outputs are in bucket order).
 __global__ __launch_bounds__(kBlock) void invalid_kernel(
     SolveArgs A, const int32_t* __restrict__ perm, const int64_t* __restrict__ bucket) {
   int64_t begin = bucket[A.n_max], count = bucket[A.n_max + 1] - begin;
   const float qnan = __builtin_nanf("");
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count; idx += stride) {
-    int64_t p = perm[begin + idx];
+    int64_t p = perm ? (int64_t)perm[begin + idx] : begin + idx;
     for (int j = 0; j < A.n_max; ++j) {
       for (int c = 0; c < 3; ++c) A.x[(int64_t)(3 * j + c) * A.N + p] = qnan;
       A.t[(int64_t)(2 * j) * A.N + p] = qnan;
@@ -2231,6 +2257,69 @@ __global__ __launch_bounds__(kBlock) void invalid_kernel(
     A.len[p] = qnan;
     A.status[p] = FPT_ST_INVALID;
     A.iters[p] = 0;
+  }
+}
+
+// ------------------------------------------------------ bucket order -----
+// With an order array, the paths of one order are scattered over the
+// caller's arrays, and every per-order kernel would read and write them
+// through the permutation: a wave's 64 paths then touch many cache lines per
+// access (for an order that holds 1/k of the paths, about k times as many as
+// contiguous paths). So the solve works in bucket order: the first phase
+// reads each path's inputs through the permutation and leaves copies of its
+// indices at its bucket slot s (SolveArgs.perm_in), the passes that follow
+// read and write slot s contiguously, and unsort_kernel writes the caller's
+// arrays in the caller's order at the end, with consecutive threads on
+// consecutive paths (the NaN entries beyond a path's order included), from
+// the inverse permutation that the bucketing scatter writes.
+
+// Order of bucket slot s: 1..n_max, or n_max + 1 (the invalid orders).
+__device__ __forceinline__ int bucket_order(const int64_t* bnd, int n_max, int64_t s) {
+  int n = 1;
+  while (n <= n_max && s >= bnd[n]) ++n;
+  return n;
+}
+
+// Outputs in the caller's order from the bucket-order ones (S): path p from
+// slot inv[p], entries beyond its order NaN.
+template <int NMAX>
+__global__ __launch_bounds__(kBlock) void unsort_kernel(
+    SolveArgs S, float* __restrict__ x, float* __restrict__ len, float* __restrict__ t,
+    uint8_t* __restrict__ status, uint16_t* __restrict__ iters,
+    const int32_t* __restrict__ inv, const int64_t* __restrict__ bucket) {
+  __shared__ int64_t bnd[FPT_NMAX + 2];
+  if (threadIdx.x <= (unsigned)NMAX + 1) bnd[threadIdx.x] = bucket[threadIdx.x];
+  __syncthreads();
+  const float qnan = __builtin_nanf("");
+  const int64_t N = S.N;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+    const int64_t s = inv[p];
+    const int n = bucket_order(bnd, NMAX, s);
+    float v[5 * NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+      const bool in = j < n && n <= NMAX;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[5 * j + c] = in ? S.x[(int64_t)(3 * j + c) * N + s] : qnan;
+      v[5 * j + 3] = in ? S.t[(int64_t)(2 * j) * N + s] : qnan;
+      v[5 * j + 4] = in ? S.t[(int64_t)(2 * j + 1) * N + s] : qnan;
+    }
+    const float l = S.len[s];
+    const uint8_t st = S.status[s];
+    const uint16_t it = S.iters[s];
+    // (streaming stores: nothing here is read again by this solve)
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        __builtin_nontemporal_store(v[5 * j + c], x + (int64_t)(3 * j + c) * N + p);
+      __builtin_nontemporal_store(v[5 * j + 3], t + (int64_t)(2 * j) * N + p);
+      __builtin_nontemporal_store(v[5 * j + 4], t + (int64_t)(2 * j + 1) * N + p);
+    }
+    __builtin_nontemporal_store(l, len + p);
+    __builtin_nontemporal_store(st, status + p);
+    __builtin_nontemporal_store(it, iters + p);
   }
 }
 
@@ -2317,14 +2406,35 @@ const void* solve_kernel_ptr(int phase, int order) {
 
 hipError_t launch_bucketing(const uint8_t* order, int64_t N, int n_max,
                             uint32_t* ccount, int64_t* bucket, int32_t* perm,
-                            hipStream_t st) {
+                            hipStream_t st, int32_t* inv) {
   const int64_t nchunks = (N + kSortChunk - 1) / kSortChunk;
   hipLaunchKernelGGL(bucket_count_kernel, dim3((unsigned)nchunks), dim3(kBlock), 0, st,
                      order, N, n_max, ccount);
   hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(kBlock), 0, st, ccount,
                      nchunks, n_max, bucket);
   hipLaunchKernelGGL(bucket_scatter_kernel, dim3((unsigned)nchunks), dim3(kBlock), 0, st,
-                     order, N, n_max, ccount, perm);
+                     order, N, n_max, ccount, perm, inv);
+  return hipGetLastError();
+}
+
+template <int NMAX>
+static void unsort_launch(const SolveArgs& S, const SolveArgs& A, const int32_t* inv,
+                          const int64_t* bucket, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(unsort_kernel<NMAX>, dim3(grid), dim3(kBlock), 0, st, S, A.x, A.len,
+                     A.t, A.status, A.iters, inv, bucket);
+}
+
+hipError_t launch_unsort(const SolveArgs& S, const SolveArgs& A, const int32_t* inv,
+                         const int64_t* bucket, int grid, hipStream_t st) {
+  switch (S.n_max) {
+    case 1: unsort_launch<1>(S, A, inv, bucket, grid, st); break;
+    case 2: unsort_launch<2>(S, A, inv, bucket, grid, st); break;
+    case 3: unsort_launch<3>(S, A, inv, bucket, grid, st); break;
+    case 4: unsort_launch<4>(S, A, inv, bucket, grid, st); break;
+    case 5: unsort_launch<5>(S, A, inv, bucket, grid, st); break;
+    case 6: unsort_launch<6>(S, A, inv, bucket, grid, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -75,8 +75,8 @@ EXPORTED = ["fpt_default_opts", "fpt_create", "fpt_destroy", "fpt_solve",
             "fpt_solve_noalloc", "fpt_noalloc_max_paths"]
 
 # timer slots of fpt_kernel_times
-T_BUCKET, T_BFGS, T_REFINE, T_GRAD, T_REDUCE, T_MLP, T_VALIDATE, TIMERS = (
-    0, 1, 7, 13, 14, 15, 16, 17)
+T_BUCKET, T_BFGS, T_REFINE, T_GRAD, T_REDUCE, T_MLP, T_VALIDATE, T_UNSORT, TIMERS = (
+    0, 1, 7, 13, 14, 15, 16, 17, 18)
 VALID_EXTENT, VALID_SPECULAR, VALID_VISIBLE = 1, 2, 4
 VALIDATE_ALL, VALIDATE_LAZY = 0, 1
 METHOD_BFGS, METHOD_NEWTON32 = 0, 1
