@@ -201,6 +201,11 @@ def run_fwd_grad(args, fpt, scenes, torch):
     t_f /= steps
     t_g /= steps
     cert = int(((out["status"] & fpt.ST_CONVERGED) != 0).sum().item())
+    # certified paths that get a gradient (no FPT_ST_NOGRAD: collapsed
+    # minimisers get none)
+    cert_grad = int((((out["status"] & fpt.ST_CONVERGED) != 0)
+                     & ((out["status"] & fpt.ST_NOGRAD) == 0)).sum().item())
+    nograd = float(((out["status"] & fpt.ST_NOGRAD) != 0).float().mean().item())
     tg_kernel = kt[fpt.T_GRAD]
     res = {
         "workload": "street canyon: 1,048,576 sampled order-3 paths, "
@@ -208,7 +213,10 @@ def run_fwd_grad(args, fpt, scenes, torch):
         "schedule": chosen.get(3) or {"iters": args.iters},
         "ms_fwd": t_f, "ms_grad": t_g, "grad_kernel_ms": tg_kernel,
         "certified_fraction": cert / b.N,
-        "converged_paths_per_s_fwd_grad": cert / ((t_f + t_g) * 1e-3),
+        "no_gradient_fraction": nograd,
+        "certified_with_gradient_fraction": cert_grad / b.N,
+        "converged_paths_per_s_fwd_grad": cert_grad / ((t_f + t_g) * 1e-3),
+        "certified_paths_per_s_fwd_grad_incl_no_gradient": cert / ((t_f + t_g) * 1e-3),
         "grad_roofline": {
             "kernel": "grad_kernel<3>", "bound": "hbm",
             "achieved": grad_bytes_per_path(3) * b.N / (tg_kernel * 1e-3) / 1e9,

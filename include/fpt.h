@@ -82,7 +82,11 @@ enum {
   FPT_ST_REFINED = 2,   /* at least one FP64 refinement step was accepted */
   FPT_ST_COLLAPSED = 4, /* two consecutive points closer than 1e-6 * scale */
   FPT_ST_NONFINITE = 8, /* the solve produced a non-finite value */
-  FPT_ST_INVALID = 16   /* bad order / id / point index, or non-finite input */
+  FPT_ST_INVALID = 16,  /* bad order / id / point index, or non-finite input */
+  FPT_ST_NOGRAD = 32    /* fpt_grad gives this path no gradient (zero): set
+                           with FPT_ST_COLLAPSED, FPT_ST_NONFINITE or
+                           FPT_ST_INVALID, where the Hessian of Sec. III-D is
+                           singular or undefined */
 };
 
 typedef struct fpt_handle fpt_handle;

@@ -1301,6 +1301,7 @@ __device__ __forceinline__ void write_path64(const SolveArgs& A,
     if (minl2 < cs * cs || collapsed) st |= FPT_ST_COLLAPSED;
     if (!finite) st |= FPT_ST_NONFINITE;
   }
+  if (st & (FPT_ST_COLLAPSED | FPT_ST_NONFINITE | FPT_ST_INVALID)) st |= FPT_ST_NOGRAD;
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
 #pragma unroll
@@ -2255,7 +2256,7 @@ __global__ __launch_bounds__(kBlock) void invalid_kernel(
       A.t[(int64_t)(2 * j + 1) * A.N + p] = qnan;
     }
     A.len[p] = qnan;
-    A.status[p] = FPT_ST_INVALID;
+    A.status[p] = FPT_ST_INVALID | FPT_ST_NOGRAD;
     A.iters[p] = 0;
   }
 }

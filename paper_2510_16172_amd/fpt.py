@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libfpt.so")
 FPT_NMAX = 6
 FPT_MAX_LEVELS = 8
 
-ST_CONVERGED, ST_REFINED, ST_COLLAPSED, ST_NONFINITE, ST_INVALID = 1, 2, 4, 8, 16
+ST_CONVERGED, ST_REFINED, ST_COLLAPSED, ST_NONFINITE, ST_INVALID, ST_NOGRAD = (
+    1, 2, 4, 8, 16, 32)
 
 _P = ctypes.c_void_p
 

@@ -89,3 +89,35 @@ def targets(b, t, status, S):
         M[:, 2 * j] = cert & np.isfinite(T[:, 2 * j])
         M[:, 2 * j + 1] = cert & (n2 > 0) & np.isfinite(T[:, 2 * j + 1])
     return np.nan_to_num(T) * M, M
+
+
+def bf16(a):
+    """Round to bfloat16 (nearest even), as the kernels store operands."""
+    a = np.asarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def loss_and_grad_bf16(W, X, T, M):
+    """loss_and_grad with the training kernels' storage precision: weights,
+    inputs, the hidden activations H1..H3, the output error dY and the
+    back-propagated dH3..dH1 rounded to bfloat16 where the kernels store
+    them (products and sums exact here, FP32 accumulation there). W holds
+    the bf16-rounded weights; X the bf16-rounded features."""
+    B = X.shape[0]
+    H1 = bf16(np.maximum(X @ W["W1"].T + W["b1"], 0))
+    H2 = bf16(np.maximum(H1 @ W["W2"].T + W["b2"], 0))
+    H3 = bf16(np.maximum(H2 @ W["W3"].T + W["b3"], 0))
+    Y = H3 @ W["W4"].T + W["b4"]
+    E = (Y - T) * M
+    L = float((E * E).sum() / (OUT * B))
+    dY = bf16(2.0 * E / (OUT * B))
+    g = {"W4": dY.T @ H3, "b4": dY.sum(0)}
+    d3 = bf16((dY @ W["W4"]) * (H3 > 0))
+    g["W3"], g["b3"] = d3.T @ H2, d3.sum(0)
+    d2 = bf16((d3 @ W["W3"]) * (H2 > 0))
+    g["W2"], g["b2"] = d2.T @ H1, d2.sum(0)
+    d1 = bf16((d2 @ W["W2"]) * (H1 > 0))
+    g["W1"], g["b1"] = d1.T @ X, d1.sum(0)
+    return L, g

@@ -3,6 +3,7 @@
 import numpy as np
 import pytest
 
+import gpu_util
 import mlp_ref
 from paper_2510_16172_amd import scenes
 
@@ -84,6 +85,19 @@ def test_train_step_gradient_matches_reference(solver):
         rel = np.linalg.norm(a - w) / (np.linalg.norm(w) + 1e-30)
         print(f"{k}: cos {cos:.5f} rel {rel:.3e}", flush=True)
         assert cos > 0.995 and rel < 0.1, k
+    # element by element against the reference that stores the activations
+    # and back-propagated errors in bfloat16 where the kernels do: what is
+    # left is FP32 accumulation order and the rare value that rounds to the
+    # other bfloat16 neighbour. Bound per element: 2^-9 of (|g| + the
+    # tensor's RMS), half the bfloat16 unit roundoff (2^-8).
+    Lb, gb = mlp_ref.loss_and_grad_bf16(Wb, X, T, M)
+    assert abs(loss.item() - Lb) <= 1e-3 * Lb
+    for k in gb:
+        a, w = g_gpu[k].ravel(), gb[k].ravel()
+        rms = np.sqrt(np.mean(w * w)) + 1e-30
+        err = np.abs(a - w) / (np.abs(w) + rms)
+        print(f"{k}: max elementwise error {err.max():.2e} (x (|g| + rms))", flush=True)
+        assert err.max() <= 2.0 ** -9, k
 
 
 def test_training_reduces_loss(solver):
@@ -142,3 +156,42 @@ def test_learned_init_gains_over_zero_start(solver):
     iz, il = ze["iters"].astype(np.float64).mean(), le["iters"].astype(np.float64).mean()
     print(f"mean iterations under early exit: zero {iz:.2f} learned {il:.2f}", flush=True)
     assert il < iz
+
+
+def test_learned_start_fallback(solver, oracle_mod):
+    """learned_init.evaluate: the paths the learned start leaves uncertified
+    are solved again from T = 0 and their results replace the learned
+    start's. With the fallback, at least as many paths are certified as from
+    T = 0 alone, and no certified path of the merged output is wrong against
+    the oracle (sampled)."""
+    import torch
+    from paper_2510_16172_amd import fpt, learned_init
+    sc = scenes.canyon_scene()
+    test = scenes.canyon_sample_paths(sc, 1 << 15, seed=6400, n=4)
+    train = learned_init.dedup_against(
+        scenes.canyon_sample_paths(sc, 1 << 17, seed=6401, n=4), test)
+    dbt = fpt.DeviceBatch(train, with_order=False)
+    target = solver.solve(dbt, fpt.Opts(scale=sc.S, iters=96))
+    mlp = fpt.Mlp(solver, seed=2)
+    learned_init.train(solver, mlp, dbt, target, sc.S, epochs=4, lr=2e-3, batch=8192)
+    dbe = fpt.DeviceBatch(test, with_order=False)
+    # few iterations, so that the learned start leaves paths to the fallback
+    res, out0, out1 = learned_init.evaluate(solver, mlp, dbe, fpt.Opts(scale=sc.S, iters=4),
+                                            repeats=1)
+    torch.cuda.synchronize()
+    li = res["learned_init"]
+    print(res["zero_init"]["certified"], li["certified"], li["certified_with_fallback"],
+          li["fallback_paths"], flush=True)
+    assert li["fallback_paths"] > 0
+    assert li["certified_with_fallback"] >= res["zero_init"]["certified"]
+    st1 = out1["status"].cpu().numpy()
+    cert1 = (st1 & fpt.ST_CONVERGED) != 0
+    assert abs(cert1.mean() - li["certified_with_fallback"]) < 1e-9
+    idx = np.sort(np.random.default_rng(6402).choice(test.N, 4096, replace=False))
+    sub = test.subset(idx)
+    ref = oracle_mod.solve(sub, threads=8)
+    g = {k: (v.cpu().numpy()[..., idx] if v.dim() > 1 else v.cpu().numpy()[idx])
+         for k, v in out1.items()}
+    s = gpu_util.summary(sub, g, ref)
+    assert s["false_pos"] == 0
+    assert s["frac_gate"] >= 0.97
