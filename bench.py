@@ -555,7 +555,8 @@ def run_c3(args, fpt, scenes, torch):
     b = scenes.canyon_sample_paths(sc, 1 << 23, seed=1003, n=None, n_max=6)
     solver = fpt.Solver(0)
     opts = fpt.Opts(scale=b.S, iters=args.iters, fp_iters=args.fp_iters,
-                    concurrent_orders=True, split=args.split)
+                    concurrent_orders=not args.sequential,
+                    split=1 if args.sequential else args.split)
     chosen, tuned = tune_or_fix(args, solver, b, opts, 1 << 18, 2, args.schedule)
     res, out_np = solve_workload(args, fpt, torch, solver, b, opts, chosen, "canyon_c3")
     res["config"] = {
@@ -564,7 +565,7 @@ def run_c3(args, fpt, scenes, torch):
         "autotuned": tuned, "fp_iters": opts.fp_iters,
         "refine_levels": list(zip(opts.level_eps, opts.level_steps)),
         "quick_steps": opts.quick_steps, "quick_passes": opts.quick_passes,
-        "polish_steps": opts.polish_steps, "concurrent_orders": True,
+        "polish_steps": opts.polish_steps, "concurrent_orders": opts.concurrent_orders,
         "split": opts.split if opts.split > 0 else 2,
     }
     solver.close()
@@ -743,6 +744,11 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training and evaluating the learned initialiser")
     ap.add_argument("--mlp-epochs", type=int, default=40)
+    ap.add_argument("--sequential", action="store_true",
+                    help="profiling: the timed steps of the headline run the orders one "
+                         "after another in one part (as the kernel breakdown does)")
+    ap.add_argument("--legs-only", action="store_true",
+                    help="profiling: skip the headline workload, run only the legs")
     ap.add_argument("--copy-calib", action="store_true",
                     help="copy a 256 MiB buffer three times first (for calibrating the "
                          "HBM byte counters)")
@@ -767,6 +773,13 @@ def main():
               file=sys.stderr, flush=True)
 
     legs = {}
+    if args.legs_only:
+        if not args.no_grad:
+            legs["fwd_grad"] = run_fwd_grad(args, fpt, scenes, torch)
+        if not args.no_learned:
+            legs["learned_init"] = run_learned(args, fpt, torch)
+        print(json.dumps({"legs_only": True, **legs}), flush=True)
+        return
     if args.workload == "c3":
         head, batch, out_np = run_c3(args, fpt, scenes, torch)
     else:
