@@ -33,6 +33,8 @@
  *   status uint8  [N]             FPT_ST_* bits
  *   iters  uint16 [N]             BFGS iterations run
  * Entries beyond a path's order are written as NaN (x, t).
+ * t_init may be the same memory as the output t (a warm start from an
+ * earlier solve's result); no other input may overlap an output.
  *
  * Errors: a whole-call error (null or misaligned pointer, n_max outside
  * 1..FPT_NMAX, N < 0, K/Q out of range, bad options) returns a negative
@@ -266,9 +268,12 @@ fpt_status fpt_validate(fpt_handle* h, const fpt_scene* scene,
                         const fpt_paths* paths, const fpt_out* fwd,
                         uint8_t* flags, int32_t mode, void* hip_stream);
 
-/* Launch configuration of the FP32 solver kernel of one order (what the
- * autotuner chooses). wg_per_cu: resident workgroups per compute unit for
- * the persistent launches (0 = as many as the kernel's register use allows);
+/* Launch configuration of the kernels of one order (what the autotuner
+ * chooses). wg_per_cu: workgroups per compute unit of the persistent
+ * first-phase launches (0 = as many as the kernel's register use lets
+ * reside at once; more than that oversubscribes the CUs, which then take a
+ * new workgroup as one ends); refine_wg_per_cu: the same for the FP64
+ * refinement launches (quick passes, collapse steps, full schedule);
  * early_exit / stage_iters / iters / quick_steps / quick_passes (each if
  * > 0) override the corresponding fpt_opts fields for paths of that order
  * when use_override is 1. */
@@ -315,6 +320,7 @@ typedef struct {
   int32_t iters;        /* 0..65535; 0 = fpt_opts.iters */
   int32_t quick_steps;  /* 0..64; 0 = fpt_opts.quick_steps */
   int32_t quick_passes; /* 0..2; 0 = fpt_opts.quick_passes */
+  int32_t refine_wg_per_cu; /* 0..32 */
 } fpt_launch_cfg;
 
 /* Sets (cfg != NULL) or resets to defaults (cfg == NULL) the configuration

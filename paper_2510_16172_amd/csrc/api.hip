@@ -457,6 +457,19 @@ struct SolvePlan {
   int split;
   int n_lo;
   int unit(int n, int part) const { return conc ? unit_of(n, part) : part + 1; }
+  // The order issued i-th for a part. With one stream per unit, the orders
+  // go from the top down: a high order has few paths, and its passes are
+  // latency-bound chains that then run beside the large low orders'
+  // ALU-bound work instead of after it. The runtime gives streams to its
+  // hardware queues in turn as they are created, and a queue runs its
+  // launches in order, so the streams are created in this order too (the
+  // first multi-stream call on a handle decides). With parts only, odd
+  // parts go from the top down: the short, latency-bound launches of a
+  // small order then run beside another part's large order.
+  int nth(int i, int part, int n_max) const {
+    const bool down = multi && (conc || (part & 1));
+    return down ? n_max - i : n_lo + i;
+  }
 };
 
 static SolvePlan solve_plan(const fpt_paths* pa, const fpt_opts* o, bool any_ee) {
@@ -580,16 +593,17 @@ static fpt_status prepare_solve(fpt_handle* h, const fpt_paths* pa, const fpt_op
   const bool lists = any_ee || (o->n_levels > 0 && o->quick_steps > 0);
   if (!lists) {
     if (P.multi)
-      for (int n = P.n_lo; n <= pa->n_max; ++n)
+      for (int i = 0; i <= pa->n_max - P.n_lo; ++i)
         for (int c = 0; c < P.split; ++c) {
-          s = ensure_stream(h, P.unit(n, c));
+          s = ensure_stream(h, P.unit(P.nth(i, c, pa->n_max), c));
           if (s != FPT_OK) return s;
         }
     return FPT_OK;
   }
   if (P.multi) {
-    for (int n = P.n_lo; n <= pa->n_max; ++n)
+    for (int i = 0; i <= pa->n_max - P.n_lo; ++i)
       for (int c = 0; c < P.split; ++c) {
+        const int n = P.nth(i, c, pa->n_max);
         s = ensure_stream(h, P.unit(n, c));
         if (s != FPT_OK) return s;
         s = ensure_lists(h, pa->N, P.unit(n, c));
@@ -747,12 +761,9 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
   }
   const int nc = fpt::kRegions * fpt::kCounterStride;
   const int64_t rcap = stage_rcap(pa->N);
-  // (with parts on streams of their own, odd parts take the orders from the
-  // top down: the short, latency-bound launches of a small order then run
-  // beside another part's large order instead of beside each other)
   for (int i = 0; i <= pa->n_max - n_lo; ++i)
   for (int part = 0; part < P.split; ++part) {
-    const int n = (P.multi && !P.conc && (part & 1)) ? pa->n_max - i : n_lo + i;
+    const int n = P.nth(i, part, pa->n_max);
     const int w = P.multi ? P.unit(n, part) : 0;  // list set and stream
     hipStream_t sn = P.multi ? h->ostream[w] : st;
     if (P.multi) {
@@ -826,7 +837,8 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
       SlotTimer tm(h, FPT_T_REFINE + n - 1, sn);
       fpt::StageArgs R;
       memset(&R, 0, sizeof(R));
-      int grid = bucket ? persistent(1, n, 0) : (int)cap;
+      const int rw = c.refine_wg_per_cu;
+      int grid = bucket ? persistent(1, n, rw) : (int)cap;
       if (An.quick_steps > 0) {
         // stage k lists its uncertified paths in list k & 1 with counter
         // block k; the blocks are cleared together first (by the first
@@ -840,7 +852,7 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
         // pass 1: quick steps for all, list the uncertified paths
         R.out_list = W.slist[w][0];
         R.out_count = cnt;
-        e = fpt::launch_solve(4, n, An, perm, bucket, &R, bucket ? persistent(4, n, 0) : (int)cap,
+        e = fpt::launch_solve(4, n, An, perm, bucket, &R, bucket ? persistent(4, n, rw) : (int)cap,
                               sn);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         int k = 0;  // the stage whose list is current
@@ -865,22 +877,22 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
         };
         if (qpasses > 1) {
           // second quick pass on the paths the first did not certify
-          e = next_stage(4, persistent(4, n, 0), false, 0);
+          e = next_stage(4, persistent(4, n, rw), false, 0);
           if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         }
         if (n >= 2) {
           // collapsed minimisers from the quick pass's point: merge attempt on
           // the list, the rest listed again for the full schedule
-          e = next_stage(3, persistent(3, n, 0), false, 0);
+          e = next_stage(3, persistent(3, n, rw), false, 0);
           if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
         }
         // the full schedule on the list; with n >= 2 it lists the paths it
         // leaves uncertified for a last collapse step from its own output,
         // where a collapse has come close enough to be told from a short
         // segment
-        e = next_stage(1, persistent(1, n, 0), n < 2, 0);
+        e = next_stage(1, persistent(1, n, rw), n < 2, 0);
         if (e != hipSuccess) return hip_fail(e, "fpt_solve: launch");
-        if (n >= 2) e = next_stage(3, persistent(3, n, 0), true, 1);
+        if (n >= 2) e = next_stage(3, persistent(3, n, rw), true, 1);
       } else {
         e = fpt::launch_solve(1, n, An, perm, bucket, &R, grid, sn);
       }
@@ -1376,8 +1388,9 @@ extern "C" fpt_status fpt_set_launch(fpt_handle* h, int order,
     h->cfg[order] = fpt_launch_cfg{};
     return FPT_OK;
   }
-  if (cfg->wg_per_cu < 0 || cfg->wg_per_cu > 32)
-    return fail(FPT_EINVAL, "fpt_set_launch: wg_per_cu outside 0..32");
+  if (cfg->wg_per_cu < 0 || cfg->wg_per_cu > 32 || cfg->refine_wg_per_cu < 0 ||
+      cfg->refine_wg_per_cu > 32)
+    return fail(FPT_EINVAL, "fpt_set_launch: wg_per_cu / refine_wg_per_cu outside 0..32");
   if (cfg->use_override && (cfg->iters < 0 || cfg->iters > 65535))
     return fail(FPT_EINVAL, "fpt_set_launch: iters outside 0..65535");
   if (cfg->use_override && (cfg->quick_steps < 0 || cfg->quick_steps > 64 ||

@@ -53,7 +53,7 @@ class _LaunchCfg(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("use_override", ctypes.c_int32),
                 ("early_exit", ctypes.c_int32), ("stage_iters", ctypes.c_int32 * 4),
                 ("iters", ctypes.c_int32), ("quick_steps", ctypes.c_int32),
-                ("quick_passes", ctypes.c_int32)]
+                ("quick_passes", ctypes.c_int32), ("refine_wg_per_cu", ctypes.c_int32)]
 
 
 class _EnumSpec(ctypes.Structure):
@@ -382,6 +382,7 @@ class Solver:
             return
         c = _LaunchCfg()
         c.wg_per_cu = int(cfg.get("wg_per_cu", 0))
+        c.refine_wg_per_cu = int(cfg.get("refine_wg_per_cu", 0))
         c.use_override = 1 if any(k in cfg for k in (
             "early_exit", "iters", "quick_steps", "quick_passes")) else 0
         c.early_exit = int(cfg.get("early_exit", 0))

@@ -399,6 +399,32 @@ def test_concurrent_orders_equal_sequential(solver):
     g.close()
 
 
+def test_warm_start_in_place(solver):
+    """t_init may be the output t itself (a warm start from the previous
+    solve's result, overwritten in place): the same bits as the same start
+    from a separate buffer, one order after another and with concurrent
+    orders, and NaN in t beyond each path's order."""
+    import torch
+    from paper_2510_16172_amd import fpt
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 20000, seed=4900, n=None, n_max=5)
+    for conc in (False, True):
+        opts = _opts(b.S, iters=8, concurrent_orders=conc)
+        db = fpt.DeviceBatch(b)
+        out = solver.solve(db, opts)
+        db.t_init = out["t"].clone()
+        want = {k: v.cpu().numpy() for k, v in solver.solve(db, opts).items()}
+        db.t_init = out["t"]
+        solver.solve(db, opts, out=out)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        for k in want:
+            np.testing.assert_array_equal(got[k], want[k], err_msg=k)
+        for n in range(1, 5):
+            assert np.all(np.isnan(got["t"][n:, :, b.order == n]))
+            assert np.all(np.isnan(want["x"][n:, :, b.order == n]))
+
+
 def test_bucketing_ragged_unaligned_and_invalid_orders(solver):
     """Order bucketing over a ragged size (three chunks of 8,192 paths and a
     tail) with an order array that starts off 16-byte alignment (the
