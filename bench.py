@@ -278,8 +278,10 @@ def run_fwd_grad(args, fpt, scenes, torch):
 
 
 def source_digest() -> str:
+    """Digest of the kernels' sources (the host code that launches them,
+    api.hip, changes no kernel's bytes or arithmetic and is left out)."""
     h = hashlib.sha256()
-    for f in ("solve.hip", "path64.h", "common.h", "api.hip", "grad.hip", "mlp.hip"):
+    for f in ("solve.hip", "path64.h", "common.h", "grad.hip", "mlp.hip"):
         with open(os.path.join(ROOT, "paper_2510_16172_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -438,11 +440,24 @@ def breakdown(args, solver, db, opts, torch):
     return kt, work
 
 
-def order_rooflines(fpt, batch, out_np, kt, work, opts, workload):
+def _same_schedule(counters, schedule, n, keys):
+    """Whether the committed counters of order n were taken with the
+    schedule `schedule` gives that order (the FLOP counts depend on it; the
+    HBM bytes do not: a kernel reads its paths and writes its results once
+    whatever its step counts)."""
+    if not counters or schedule is None:
+        return False
+    a = (counters.get("schedule") or {}).get(str(n)) or {}
+    b = schedule.get(n) or schedule.get(str(n)) or {}
+    return all(a.get(k) == b.get(k) for k in keys)
+
+
+def order_rooflines(fpt, batch, out_np, kt, work, opts, workload, schedule=None):
     """Roofline of each order's FP32 phase and FP64 refinement group: the
     algorithmic FLOP count per launch (above) over the launch's measured
     time, against the FP32 / FP64 vector peaks; the builder's model and the
-    committed counters beside it."""
+    committed counters beside it (their FLOP counts only where this run's
+    schedule for the order is the profiled one)."""
     rows = []
     edge = np.all(batch.obj[6:9] == 0, axis=0)
     for n in range(1, batch.n_max + 1):
@@ -469,7 +484,8 @@ def order_rooflines(fpt, batch, out_np, kt, work, opts, workload):
             "flops_active_dims": fl_act, "flops_builder_model": fl_mod,
             "iterations_per_path": float(it.mean()),
             "traffic": cb["hbm_bytes_per_launch"] if cb else None,
-            "counter_fp32_flop_per_launch": cb.get("counter_fp32_flop_per_launch") if cb else None,
+            "counter_fp32_flop_per_launch": cb.get("counter_fp32_flop_per_launch")
+            if _same_schedule(cb, schedule, n, ("iters", "early_exit")) else None,
         })
         ev, tr, so, mev, mtr, mso = work[n]
         fl_r = so * newton_step_flops(n) + mso * newton_step_flops(max(n - 1, 1))
@@ -490,7 +506,9 @@ def order_rooflines(fpt, batch, out_np, kt, work, opts, workload):
             "newton_solves_per_path": so / cnt, "collapse_step_solves_per_path": mso / cnt,
             "evaluations_per_path": ev / cnt, "trial_lengths_per_path": tr / cnt,
             "traffic": cr["hbm_bytes_per_launch"] if cr else None,
-            "counter_fp64_flop_per_launch": cr.get("counter_fp64_flop_per_launch") if cr else None,
+            "counter_fp64_flop_per_launch": cr.get("counter_fp64_flop_per_launch")
+            if _same_schedule(cr, schedule, n, ("iters", "early_exit", "quick_steps",
+                                                "quick_passes")) else None,
         })
     return rows
 
@@ -499,7 +517,7 @@ def solve_workload(args, fpt, torch, solver, batch, opts, chosen, workload, outs
     db = fpt.DeviceBatch(batch, device="cuda:0")
     ms, per, out_np = timed_solve(args, solver, db, opts, torch)
     kt, work = breakdown(args, solver, db, opts, torch)
-    rows = order_rooflines(fpt, batch, out_np, kt, work, opts, workload)
+    rows = order_rooflines(fpt, batch, out_np, kt, work, opts, workload, chosen)
     st = out_np["status"]
     cert = (st & fpt.ST_CONVERGED) != 0
     per_order = {str(n): {"paths": int((batch.order == n).sum()),
