@@ -69,6 +69,14 @@ def io_bytes(n: int) -> int:
     return (9 + 4 * n) + (20 * n + 7)
 
 
+def store_bytes(n: int, n_max: int) -> int:
+    """Bytes the store step moves per path of order n when the outputs come
+    back from bucket order to the caller's (the unsort kernel): its results
+    read at its bucket slot (20n + 7) and its slot index (4), the caller's
+    padded rows written (20 n_max + 7: x and t beyond the order are NaN)."""
+    return (20 * n + 7) + 4 + (20 * n_max + 7)
+
+
 # The builder's own term-by-term FLOP model of each kernel, reported beside
 # the algorithmic count (it counts the padded layout, the polish step and the
 # refinement's evaluations and trial lengths as the kernels execute them).
@@ -513,6 +521,25 @@ def order_rooflines(fpt, batch, out_np, kt, work, opts, workload, schedule=None)
     return rows
 
 
+def phase_rooflines(rows):
+    """The FP32 first phase and the FP64 refinement of every order together:
+    algorithmic FLOPs over the summed launch times (orders one after
+    another)."""
+    out = {}
+    for key, pick, peak in (("fp32_first_phase", lambda r: not r["kernel"].startswith("refinement"),
+                             PEAK_FP32),
+                            ("fp64_refinement", lambda r: r["kernel"].startswith("refinement"),
+                             PEAK_FP64)):
+        sel = [r for r in rows if r.get("unit") == "TFLOP/s" and pick(r)]
+        if not sel:
+            continue
+        fl = sum(r["flops_per_launch"] for r in sel)
+        ms = sum(r["ms"] for r in sel)
+        out[key] = {"flops": fl, "ms": ms, "achieved": fl / (ms * 1e-3) / 1e12,
+                    "peak": peak / 1e12, "unit": "TFLOP/s", "frac": fl / (ms * 1e-3) / peak}
+    return out
+
+
 def solve_workload(args, fpt, torch, solver, batch, opts, chosen, workload, outs_extra=None):
     db = fpt.DeviceBatch(batch, device="cuda:0")
     ms, per, out_np = timed_solve(args, solver, db, opts, torch)
@@ -528,9 +555,26 @@ def solve_workload(args, fpt, torch, solver, batch, opts, chosen, workload, outs
         if (batch.order == n).any():
             kernel_ms[f"first_phase_order{n}"] = kt[fpt.T_BFGS + n - 1]
             kernel_ms[f"refine_order{n}"] = kt[fpt.T_REFINE + n - 1]
-    dominant = max(rows, key=lambda r: r["ms"])
-    other = [r for r in rows if r["peak"] != dominant["peak"]]
-    other = max(other, key=lambda r: r["ms"]) if other else None
+    phases = phase_rooflines(rows)
+    if kt[fpt.T_UNSORT] > 0:
+        # the store step in the caller's layout: one launch per solve
+        t_u = kt[fpt.T_UNSORT] * 1e-3
+        by = sum(int((batch.order == n).sum()) * store_bytes(n, batch.n_max)
+                 for n in range(1, batch.n_max + 1))
+        cu = read_counters("unsort_kernel", workload)
+        rows.append({
+            "kernel": f"unsort{'4' if batch.N % 4 == 0 else ''}_kernel<{batch.n_max}>",
+            "order": None, "paths": batch.N,
+            "bound": "hbm", "achieved": by / t_u / 1e9, "peak": PEAK_HBM / 1e9,
+            "unit": "GB/s", "frac": by / t_u / PEAK_HBM, "ms": t_u * 1e3,
+            "bytes_per_launch": by,
+            "traffic": cu["hbm_bytes_per_launch"] if cu else None})
+    # the dominant kernel: the longest single launch (a refinement group is
+    # three to five launches: its rows stand beside it)
+    single = [r for r in rows if not r["kernel"].startswith("refinement group")]
+    dominant = max(single, key=lambda r: r["ms"])
+    groups = [r for r in rows if r["kernel"].startswith("refinement group")]
+    other = max(groups, key=lambda r: r["ms"]) if groups else None
     del db
     return {
         "ms_per_step": ms, "ms_per_step_median": float(np.median(per)),
@@ -543,6 +587,7 @@ def solve_workload(args, fpt, torch, solver, batch, opts, chosen, workload, outs
         "kernel_ms_orders_one_after_another": kernel_ms,
         "kernel_ms_sum": float(sum(v for v in kernel_ms.values() if v > 0)),
         "roofline": dominant, "roofline_other": other, "rooflines": rows,
+        "phase_rooflines": phases,
     }, out_np
 
 
@@ -828,6 +873,7 @@ def main():
         "roofline": head["roofline"],
         "roofline_other": head["roofline_other"],
         "rooflines": head["rooflines"],
+        "phase_rooflines": head["phase_rooflines"],
         "kernel_ms_orders_one_after_another": head["kernel_ms_orders_one_after_another"],
     }
     for k in ("validate", "enumerate", "chain", "variant_newton32"):

@@ -2324,6 +2324,64 @@ __global__ __launch_bounds__(kBlock) void unsort_kernel(
   }
 }
 
+// The same with four consecutive paths per thread, so that every row goes
+// out as one 16-byte store (status and iters packed into 4 and 8 bytes):
+// for N a multiple of 4 and the caller's arrays aligned to match (the
+// one-path kernel above takes every other case).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <int NMAX>
+__global__ __launch_bounds__(kBlock) void unsort4_kernel(
+    SolveArgs S, float* __restrict__ x, float* __restrict__ len, float* __restrict__ t,
+    uint8_t* __restrict__ status, uint16_t* __restrict__ iters,
+    const int32_t* __restrict__ inv, const int64_t* __restrict__ bucket) {
+  __shared__ int64_t bnd[FPT_NMAX + 2];
+  if (threadIdx.x <= (unsigned)NMAX + 1) bnd[threadIdx.x] = bucket[threadIdx.x];
+  __syncthreads();
+  const float qnan = __builtin_nanf("");
+  const int64_t N = S.N, N4 = N / 4;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < N4; q += stride) {
+    const int4 iv = reinterpret_cast<const int4*>(inv)[q];
+    const int64_t s[4] = {iv.x, iv.y, iv.z, iv.w};
+    int n[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      n[k] = bucket_order(bnd, NMAX, s[k]);
+      n[k] = n[k] <= NMAX ? n[k] : 0;  // invalid orders: every row NaN
+    }
+    // (streaming stores: nothing here is read again by this solve)
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+#pragma unroll
+      for (int r = 0; r < 5; ++r) {
+        const float* src = r < 3 ? S.x + (int64_t)(3 * j + r) * N : S.t + (int64_t)(2 * j + r - 3) * N;
+        float* dst = r < 3 ? x + (int64_t)(3 * j + r) * N : t + (int64_t)(2 * j + r - 3) * N;
+        f32x4 v;
+        v.x = j < n[0] ? src[s[0]] : qnan;
+        v.y = j < n[1] ? src[s[1]] : qnan;
+        v.z = j < n[2] ? src[s[2]] : qnan;
+        v.w = j < n[3] ? src[s[3]] : qnan;
+        __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(dst) + q);
+      }
+    }
+    f32x4 l;
+    l.x = S.len[s[0]];
+    l.y = S.len[s[1]];
+    l.z = S.len[s[2]];
+    l.w = S.len[s[3]];
+    __builtin_nontemporal_store(l, reinterpret_cast<f32x4*>(len) + q);
+    uint32_t st = 0u;
+    uint64_t it = 0ull;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      st |= (uint32_t)S.status[s[k]] << (8 * k);
+      it |= (uint64_t)S.iters[s[k]] << (16 * k);
+    }
+    __builtin_nontemporal_store(st, reinterpret_cast<uint32_t*>(status) + q);
+    __builtin_nontemporal_store(it, reinterpret_cast<uint64_t*>(iters) + q);
+  }
+}
+
 // ------------------------------------------------------------- launch -----
 
 template <int NO>
@@ -2421,8 +2479,14 @@ hipError_t launch_bucketing(const uint8_t* order, int64_t N, int n_max,
 template <int NMAX>
 static void unsort_launch(const SolveArgs& S, const SolveArgs& A, const int32_t* inv,
                           const int64_t* bucket, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(unsort_kernel<NMAX>, dim3(grid), dim3(kBlock), 0, st, S, A.x, A.len,
-                     A.t, A.status, A.iters, inv, bucket);
+  const auto al = [](const void* p, uintptr_t a) { return (uintptr_t)p % a == 0; };
+  if (S.N % 4 == 0 && al(A.x, 16) && al(A.t, 16) && al(A.len, 16) && al(A.status, 4) &&
+      al(A.iters, 8) && al(inv, 16))
+    hipLaunchKernelGGL(unsort4_kernel<NMAX>, dim3(grid), dim3(kBlock), 0, st, S, A.x, A.len,
+                       A.t, A.status, A.iters, inv, bucket);
+  else
+    hipLaunchKernelGGL(unsort_kernel<NMAX>, dim3(grid), dim3(kBlock), 0, st, S, A.x, A.len,
+                       A.t, A.status, A.iters, inv, bucket);
 }
 
 hipError_t launch_unsort(const SolveArgs& S, const SolveArgs& A, const int32_t* inv,
