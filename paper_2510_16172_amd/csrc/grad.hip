@@ -27,31 +27,39 @@ namespace fpt {
 
 constexpr uint8_t kSkip = FPT_ST_COLLAPSED | FPT_ST_INVALID | FPT_ST_NONFINITE;
 
-__device__ __forceinline__ void acc_add(float* lds_base, float* glob, int64_t idx,
-                                        float v, bool lds) {
+// Accumulation into the workgroup's LDS tables (LDS) or straight into the
+// global gradient. The tables are FP64: on gfx950 an LDS FP32 atomic add
+// takes about 195 cycles per wave instruction whatever the addresses, an
+// FP64 one about 29 (and the partial sums keep FP64 precision until the one
+// flush to the FP32 gradient). The mode is a template parameter: chosen at
+// run time inside one kernel, the two pointers would merge into one generic
+// address and the LDS adds would become flat atomics.
+template <bool LDS>
+__device__ __forceinline__ void acc_add(double* lds_base, float* glob, int64_t idx,
+                                        float v) {
   if (v == 0.f) return;
-  if (lds)
-    atomicAdd(lds_base + idx, v);
+  if constexpr (LDS)
+    atomicAdd(lds_base + idx, (double)v);
   else
     unsafeAtomicAdd(glob + idx, v);
 }
 
 // (three slots: the compiler's register choice lands two VGPRs above what
 // three waves per SIMD allow; asked for three it fits them without spilling)
-template <int NO>
+template <int NO, bool LDS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NO == 3 ? 3 : 1)))
 void grad_kernel(
     GradArgs A, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ bucket) {
-  extern __shared__ float sh[];  // [9K] object gradient, then [3Q] points
-  const bool lds = A.lds != 0;
+  extern __shared__ double sh[];  // [9K] object gradient, then [3Q] points
+  constexpr bool lds = LDS;
   const int64_t nsh = 9 * (int64_t)A.K + 3 * (int64_t)A.Q;
   if (lds) {
-    for (int64_t i = threadIdx.x; i < nsh; i += kBlock) sh[i] = 0.f;
+    for (int64_t i = threadIdx.x; i < nsh; i += kBlock) sh[i] = 0.0;
     __syncthreads();
   }
-  float* s_obj = sh;
-  float* s_pts = sh + 9 * (int64_t)A.K;
+  double* s_obj = sh;
+  double* s_pts = sh + 9 * (int64_t)A.K;
   int64_t begin = 0, count = A.N;
   if (bucket) {
     begin = bucket[NO - 1];
@@ -126,8 +134,8 @@ void grad_kernel(
         A.g_end[(int64_t)(3 + c) * A.N + p] = grx;
       }
       if (use) {
-        acc_add(s_pts, A.g_pts, (int64_t)c * A.Q + s, gtx, lds);
-        acc_add(s_pts, A.g_pts, (int64_t)c * A.Q + e, grx, lds);
+        acc_add<LDS>(s_pts, A.g_pts, (int64_t)c * A.Q + s, gtx);
+        acc_add<LDS>(s_pts, A.g_pts, (int64_t)c * A.Q + e, grx);
       }
     }
     // objects
@@ -151,7 +159,7 @@ void grad_kernel(
       for (int r = 0; r < 9; ++r) {
         float vv = use ? val[r] : z;
         if (A.g_slot) A.g_slot[(int64_t)(9 * j + r) * A.N + p] = vv;
-        if (use) acc_add(s_obj, A.g_obj, (int64_t)r * A.K + kid[j], vv, lds);
+        if (use) acc_add<LDS>(s_obj, A.g_obj, (int64_t)r * A.K + kid[j], vv);
       }
     }
     if (A.g_slot)
@@ -161,9 +169,9 @@ void grad_kernel(
   if (lds) {
     __syncthreads();
     for (int64_t i = threadIdx.x; i < 9 * (int64_t)A.K; i += kBlock)
-      if (s_obj[i] != 0.f) unsafeAtomicAdd(A.g_obj + i, s_obj[i]);
+      if (s_obj[i] != 0.0) unsafeAtomicAdd(A.g_obj + i, (float)s_obj[i]);
     for (int64_t i = threadIdx.x; i < 3 * (int64_t)A.Q; i += kBlock)
-      if (s_pts[i] != 0.f) unsafeAtomicAdd(A.g_pts + i, s_pts[i]);
+      if (s_pts[i] != 0.0) unsafeAtomicAdd(A.g_pts + i, (float)s_pts[i]);
   }
 }
 
@@ -187,8 +195,12 @@ template <int NO>
 static hipError_t launch_grad_order(const GradArgs& A, const int32_t* perm,
                                     const int64_t* bucket, int grid,
                                     size_t shmem, hipStream_t st) {
-  hipLaunchKernelGGL(grad_kernel<NO>, dim3(grid), dim3(kBlock), shmem, st, A,
-                     perm, bucket);
+  if (A.lds)
+    hipLaunchKernelGGL((grad_kernel<NO, true>), dim3(grid), dim3(kBlock), shmem, st, A,
+                       perm, bucket);
+  else
+    hipLaunchKernelGGL((grad_kernel<NO, false>), dim3(grid), dim3(kBlock), shmem, st, A,
+                       perm, bucket);
   return hipGetLastError();
 }
 
@@ -206,14 +218,15 @@ hipError_t launch_grad(int order, const GradArgs& A, const int32_t* perm,
   return hipErrorInvalidValue;
 }
 
+// The LDS-table kernel of an order (for the occupancy query).
 const void* grad_kernel_ptr(int order) {
   switch (order) {
-    case 1: return (const void*)grad_kernel<1>;
-    case 2: return (const void*)grad_kernel<2>;
-    case 3: return (const void*)grad_kernel<3>;
-    case 4: return (const void*)grad_kernel<4>;
-    case 5: return (const void*)grad_kernel<5>;
-    case 6: return (const void*)grad_kernel<6>;
+    case 1: return (const void*)grad_kernel<1, true>;
+    case 2: return (const void*)grad_kernel<2, true>;
+    case 3: return (const void*)grad_kernel<3, true>;
+    case 4: return (const void*)grad_kernel<4, true>;
+    case 5: return (const void*)grad_kernel<5, true>;
+    case 6: return (const void*)grad_kernel<6, true>;
   }
   return nullptr;
 }
