@@ -296,11 +296,17 @@ __global__ __launch_bounds__(kInferThreads) void mlp_infer_kernel(MlpInferArgs A
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the weight fragments come from L2: those of step k + 32 are loaded
+    // while step k's MFMAs run (the last step reloads its own, in bounds)
+    bf16x8 fb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) fb[b] = load8(W + (int64_t)(nc + 16 * b + li) * K + lk);
     for (int k = 0; k < K; k += 32) {
-      bf16x8 fa[4], fb[4];
+      const int kn = k + 32 < K ? k + 32 : k;
+      bf16x8 fa[4], fn[4];
 #pragma unroll
       for (int b = 0; b < 4; ++b)
-        fb[b] = load8(W + (int64_t)(nc + 16 * b + li) * K + k + lk);
+        fn[b] = load8(W + (int64_t)(nc + 16 * b + li) * K + kn + lk);
 #pragma unroll
       for (int a = 0; a < 4; ++a) fa[a] = load8s(sH + (mr + 16 * a + li) * kLdH + k + lk);
 #pragma unroll
@@ -308,6 +314,8 @@ __global__ __launch_bounds__(kInferThreads) void mlp_infer_kernel(MlpInferArgs A
 #pragma unroll
         for (int b = 0; b < 4; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) fb[b] = fn[b];
     }
     __syncthreads();  // every wave has read this layer's input
 #pragma unroll

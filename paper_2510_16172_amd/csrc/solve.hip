@@ -1322,6 +1322,9 @@ __device__ __forceinline__ void write_path64(const SolveArgs& A,
 
 // ------------------------------------------------------------- kernel -----
 
+// Highest order whose refinement passes keep the FP64 geometry in registers.
+constexpr int kRegGeoMax = 2;
+
 // Per-lane FP32 state of the BFGS iteration.
 template <int NO>
 struct State32 {
@@ -1867,7 +1870,12 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
     sub_range(A, begin, count);
   }
   constexpr bool quick = QUICK;
-  __shared__ float geo[geo_lds_rows(NO) * kBlock];
+  // At low orders the geometry stays in registers as FP64; from kRegGeoMax + 1
+  // on it sits in LDS as FP32 (GeoLds), widened on every use, which saves
+  // the registers the larger orders are short of.
+  constexpr bool reg_geo = NO <= kRegGeoMax;
+  using GeoT = typename std::conditional<reg_geo, Geo64<NO>, GeoLds<NO>>::type;
+  __shared__ float geo[reg_geo ? 1 : geo_lds_rows(NO) * kBlock];
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -1886,9 +1894,12 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
       p = perm ? (int64_t)perm[begin + idx] : begin + idx;
     }
     const bool valid = (A.status[p] & FPT_ST_INVALID) == 0;
-    GeoLds<NO> D;
+    GeoT D;
     float inv[NO][2];
-    load_geo_lds<NO>(A, p, geo + threadIdx.x, D, inv);
+    if constexpr (reg_geo)
+      load_geo64<NO>(A, p, D, inv);
+    else
+      load_geo_lds<NO>(A, p, geo + threadIdx.x, D, inv);
     double td[2 * NO];
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
