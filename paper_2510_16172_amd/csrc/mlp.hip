@@ -223,17 +223,23 @@ __global__ __launch_bounds__(kBlock) void mlp_prep_kernel(MlpPrepArgs A) {
 }
 
 // ------------------------------------------------------ fused inference ----
-// One workgroup of 8 wavefronts per tile of kTM = 128 paths computes the
+// One workgroup of 16 wavefronts per tile of kTM = 256 paths computes the
 // features, the three hidden layers and the output layer, with the
 // activations in LDS, and writes t_init: no activation goes through HBM. A
 // layer's products stay in the accumulators until every wave has read the
 // layer's input, so one LDS buffer holds the input features and then each
-// hidden activation in turn. Weights are read as MFMA fragments from global
-// memory (344 KB of bf16, L2-resident; the tile size sets how often they are
-// re-read). Wave w computes rows 64 (w / 4) .. + 63 and output columns
-// 64 (w % 4) .. + 63 of each hidden layer (4 x 4 tiles of 16 x 16).
-constexpr int kTM = 128, kLdH = kHid + 8;  // +8: fewer LDS bank conflicts
-constexpr int kInferThreads = 512;
+// hidden activation in turn. The hidden layers' weights (bf16, L2-resident)
+// pass through LDS in chunks of kKC input columns: the workgroup copies a
+// chunk with one coalesced 16-byte load per thread, the load of the next
+// chunk in flight while the MFMAs use this one, and every wave reads its
+// fragments from LDS. (Read from global memory as fragments, each weight
+// went through the L1 once for every wave that needed it, and that traffic
+// bounded the kernel.) Wave w computes rows 64 (w / 4) .. + 63 and output
+// columns 64 (w % 4) .. + 63 of each hidden layer (4 x 4 tiles of 16 x 16).
+constexpr int kTM = 256, kLdH = kHid + 8;  // +8: fewer LDS bank conflicts
+constexpr int kKC = 32, kLdW = kKC + 8;    // weight chunk [kHid][kKC], padded rows
+constexpr int kInferThreads = 1024;
+static_assert(kHid * kKC / 8 == kInferThreads, "one 16-byte copy per thread per chunk");
 
 struct MlpInferArgs {
   const float* obj;
@@ -255,9 +261,13 @@ __device__ __forceinline__ bf16x8 load8s(const bf16* p) {
 
 __global__ __launch_bounds__(kInferThreads) void mlp_infer_kernel(MlpInferArgs A) {
   __shared__ __align__(16) bf16 sH[kTM * kLdH];  // features, then H1, H2, H3
-  __shared__ float sY[kTM * kOut];
-  __shared__ float sN[kTM * kOut];  // |a| per output, 0 for an edge's padding
+  __shared__ __align__(16) bf16 sW[kHid * kLdW];  // a weight chunk
+  float* sY = reinterpret_cast<float*>(sW);       // after the hidden layers: outputs
+  static_assert(kTM * kOut * sizeof(float) <= kHid * kLdW * sizeof(bf16), "sY fits in sW");
   const int64_t row0 = (int64_t)blockIdx.x * kTM;
+  // threads < kTM: scale / |a| per output (unit-vector coordinates / S to the
+  // caller's parametrisation; 0 for an edge's padding)
+  float osc[kOut];
   if (threadIdx.x < kTM) {
     const int64_t i = row0 + threadIdx.x;
     float f[kInP], nrm[kMlpOrder][2];
@@ -278,14 +288,15 @@ __global__ __launch_bounds__(kInferThreads) void mlp_infer_kernel(MlpInferArgs A
     for (int k = 0; k < kInP; ++k) sH[threadIdx.x * kLdH + k] = (bf16)f[k];
 #pragma unroll
     for (int j = 0; j < kMlpOrder; ++j) {
-      sN[threadIdx.x * kOut + 2 * j] = nrm[j][0];
-      sN[threadIdx.x * kOut + 2 * j + 1] = edge[j] ? 0.f : nrm[j][1];
+      osc[2 * j] = nrm[j][0] > 0.f ? A.scale / nrm[j][0] : 0.f;
+      osc[2 * j + 1] = (edge[j] || !(nrm[j][1] > 0.f)) ? 0.f : A.scale / nrm[j][1];
     }
   }
-  __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = (lane >> 4) * 8;
   const int mr = 64 * (w >> 2), nc = 64 * (w & 3);
+  // this thread's share of a weight chunk: row cn, columns ck .. ck + 7
+  const int cn = threadIdx.x >> 2, ck = 8 * (threadIdx.x & 3);
 #pragma unroll 1
   for (int layer = 0; layer < 3; ++layer) {
     const int K = layer == 0 ? kInP : kHid;
@@ -296,17 +307,17 @@ __global__ __launch_bounds__(kInferThreads) void mlp_infer_kernel(MlpInferArgs A
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // the weight fragments come from L2: those of step k + 32 are loaded
-    // while step k's MFMAs run (the last step reloads its own, in bounds)
-    bf16x8 fb[4];
+    bf16x8 nxt = load8(W + (int64_t)cn * K + ck);
+    for (int k = 0; k < K; k += kKC) {
+      // every wave is done with the previous chunk (and, at k = 0, the
+      // layer's input is complete in sH)
+      __syncthreads();
+      *reinterpret_cast<bf16x8*>(sW + cn * kLdW + ck) = nxt;
+      if (k + kKC < K) nxt = load8(W + (int64_t)cn * K + k + kKC + ck);
+      __syncthreads();
+      bf16x8 fa[4], fb[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) fb[b] = load8(W + (int64_t)(nc + 16 * b + li) * K + lk);
-    for (int k = 0; k < K; k += 32) {
-      const int kn = k + 32 < K ? k + 32 : k;
-      bf16x8 fa[4], fn[4];
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        fn[b] = load8(W + (int64_t)(nc + 16 * b + li) * K + kn + lk);
+      for (int b = 0; b < 4; ++b) fb[b] = load8s(sW + (nc + 16 * b + li) * kLdW + lk);
 #pragma unroll
       for (int a = 0; a < 4; ++a) fa[a] = load8s(sH + (mr + 16 * a + li) * kLdH + k + lk);
 #pragma unroll
@@ -314,8 +325,6 @@ __global__ __launch_bounds__(kInferThreads) void mlp_infer_kernel(MlpInferArgs A
 #pragma unroll
         for (int b = 0; b < 4; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) fb[b] = fn[b];
     }
     __syncthreads();  // every wave has read this layer's input
 #pragma unroll
@@ -330,9 +339,10 @@ __global__ __launch_bounds__(kInferThreads) void mlp_infer_kernel(MlpInferArgs A
           sH[m * kLdH + n] = (bf16)fmaxf(acc[a][b][r] + bn, 0.f);
         }
     }
-    __syncthreads();
   }
+  __syncthreads();  // H3 complete; sW free for the outputs
   // output layer: wave w takes rows 16 w .. 16 w + 15, the first 16 outputs
+  // (their 8 KB of weights are read as fragments: L1-resident)
   {
     const bf16* W4 = A.wb + oW4;
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -353,12 +363,8 @@ __global__ __launch_bounds__(kInferThreads) void mlp_infer_kernel(MlpInferArgs A
     const int64_t i = row0 + threadIdx.x;
     if (i < A.N) {
 #pragma unroll
-      for (int q = 0; q < kOut; ++q) {
-        const float nq = sN[threadIdx.x * kOut + q];
-        // unit-vector coordinates / S -> the caller's parametrisation
-        A.t_init[(int64_t)q * A.N + i] =
-            nq > 0.f ? sY[threadIdx.x * kOut + q] * A.scale / nq : 0.f;
-      }
+      for (int q = 0; q < kOut; ++q)
+        A.t_init[(int64_t)q * A.N + i] = osc[q] > 0.f ? sY[threadIdx.x * kOut + q] * osc[q] : 0.f;
     }
   }
 }
