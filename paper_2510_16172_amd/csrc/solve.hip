@@ -1950,7 +1950,9 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
 // collapse has come much closer, with kMergeShortFull; it overwrites the
 // paths it certifies and leaves the others as written. Mode 0 takes one
 // round of merge_runs64 (most of its paths have one collapse, and the full
-// schedule follows for the others), mode 1 up to four.
+// schedule follows for the others), mode 1 up to three (a fourth certifies a
+// few hundredths of a per cent more of the highest orders and lengthens
+// their latency-bound tail).
 
 template <int NO>
 __global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St) {
@@ -1991,7 +1993,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St
       td[2 * j + 1] = D.edge(j) ? 0.0 : (double)t1 * (unit ? (double)inv[j][1] : 1.0);
     }
     const bool ok =
-        merge_runs64<NO>(D, td, A, unit ? kMergeShortQuick : kMergeShortFull, unit ? 1 : 4, work);
+        merge_runs64<NO>(D, td, A, unit ? kMergeShortQuick : kMergeShortFull, unit ? 1 : 3, work);
     const unsigned long long more = __ballot(!ok && St.out_list != nullptr);
     if (more) {
       const int region = (int)((idx >> 6) % kRegions);
