@@ -36,7 +36,10 @@ __device__ __forceinline__ void basis_inv32(const float* a1, const float* a2,
 }
 
 // Gradient of L at T (Sec. III-B Eq. 5): g_j = A_j^T (u_j - u_{j+1}).
-template <int NO>
+// D parameters per slot: 2 (the padded layout; an edge's second parameter
+// stays 0), or 1 for a path whose every interaction is an edge (Sec. III-B:
+// the padding only serves a uniform layout).
+template <int NO, int D = 2>
 __device__ __forceinline__ void grad32(const Geo32<NO>& G, const float* T,
                                        float* g, float (*r)[3], float* l2,
                                        float* il) {
@@ -45,8 +48,9 @@ __device__ __forceinline__ void grad32(const Geo32<NO>& G, const float* T,
   for (int j = 0; j < NO; ++j)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      x[j][c] = fmaf(T[2 * j + 1], G.a[j][1][c],
-                     fmaf(T[2 * j], G.a[j][0][c], G.b[j][c]));
+      x[j][c] = D == 2 ? fmaf(T[2 * j + 1], G.a[j][1][c],
+                              fmaf(T[2 * j], G.a[j][0][c], G.b[j][c]))
+                       : fmaf(T[j], G.a[j][0][c], G.b[j][c]);
   float u[NO + 1][3];
 #pragma unroll
   for (int i = 0; i <= NO; ++i) {
@@ -66,8 +70,8 @@ __device__ __forceinline__ void grad32(const Geo32<NO>& G, const float* T,
     float du[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) du[c] = u[j][c] - u[j + 1][c];
-    g[2 * j] = dot3(G.a[j][0], du);
-    g[2 * j + 1] = dot3(G.a[j][1], du);
+    g[D * j] = dot3(G.a[j][0], du);
+    if (D == 2) g[D * j + 1] = dot3(G.a[j][1], du);
   }
 }
 
@@ -1325,10 +1329,10 @@ __device__ __forceinline__ void write_path64(const SolveArgs& A,
 // Highest order whose refinement passes keep the FP64 geometry in registers.
 constexpr int kRegGeoMax = 2;
 
-// Per-lane FP32 state of the BFGS iteration.
-template <int NO>
+// Per-lane FP32 state of the BFGS iteration (D parameters per slot).
+template <int NO, int D = 2>
 struct State32 {
-  static constexpr int M = 2 * NO;
+  static constexpr int M = D * NO;
   static constexpr int HP = M * (M + 1) / 2;
   float T[M], g[M], P[M], H[HP];    // parameters, gradient, direction, H
   float r[NO + 1][3], l2[NO + 1], il[NO + 1];  // segments at T
@@ -1412,18 +1416,18 @@ __device__ __forceinline__ void set_identity(float* H) {
 }
 
 // T = t0, H = I, gradient and first direction P = -g.
-template <int NO>
+template <int NO, int D = 2>
 __device__ __forceinline__ void init_state(const Geo32<NO>& G,
                                            const float (*t0)[2],
-                                           State32<NO>& S) {
-  constexpr int M = State32<NO>::M, HP = State32<NO>::HP;
+                                           State32<NO, D>& S) {
+  constexpr int M = State32<NO, D>::M, HP = State32<NO, D>::HP;
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
-    S.T[2 * j] = t0[j][0];
-    S.T[2 * j + 1] = t0[j][1];
+    S.T[D * j] = t0[j][0];
+    if (D == 2) S.T[D * j + 1] = t0[j][1];
   }
   set_identity<M, HP>(S.H);
-  grad32<NO>(G, S.T, S.g, S.r, S.l2, S.il);
+  grad32<NO, D>(G, S.T, S.g, S.r, S.l2, S.il);
 #pragma unroll
   for (int k = 0; k < M; ++k) S.P[k] = -S.g[k];
 }
@@ -1435,17 +1439,18 @@ __device__ __forceinline__ void init_state(const Geo32<NO>& G,
 // choice of the initial inverse Hessian, Nocedal & Wright eq. 6.20): H = I
 // is off by the scale of the segment lengths. Returns the squared largest
 // point displacement of the step.
-template <int NO>
-__device__ __forceinline__ float bfgs_iter(const Geo32<NO>& G, State32<NO>& S,
+template <int NO, int D = 2>
+__device__ __forceinline__ float bfgs_iter(const Geo32<NO>& G, State32<NO, D>& S,
                                            int fp_iters, bool first) {
-  constexpr int M = State32<NO>::M, HP = State32<NO>::HP;
+  constexpr int M = State32<NO, D>::M, HP = State32<NO, D>::HP;
   // direction in point space: q_j = A_j p_j; segment change D_i
   float q[NO][3];
 #pragma unroll
   for (int j = 0; j < NO; ++j)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      q[j][c] = fmaf(S.P[2 * j + 1], G.a[j][1][c], S.P[2 * j] * G.a[j][0][c]);
+      q[j][c] = D == 2 ? fmaf(S.P[2 * j + 1], G.a[j][1][c], S.P[2 * j] * G.a[j][0][c])
+                       : S.P[j] * G.a[j][0][c];
   float dr[NO + 1], dd[NO + 1];
   float num0 = 0.f, den0 = 0.f, phi0 = 0.f;
 #pragma unroll
@@ -1491,7 +1496,7 @@ __device__ __forceinline__ float bfgs_iter(const Geo32<NO>& G, State32<NO>& S,
     s[k] = alpha * S.P[k];
     S.T[k] += s[k];
   }
-  grad32<NO>(G, S.T, gn, S.r, S.l2, S.il);
+  grad32<NO, D>(G, S.T, gn, S.r, S.l2, S.il);
   // BFGS inverse update (Nocedal & Wright eq. 6.17), with
   // H y = H g' - H g = H g' + P
   float Hg[M], Hy[M], y[M];
@@ -1581,7 +1586,7 @@ constexpr float kPolishEps = 1e-7f;
 
 template <int NO>
 __device__ __forceinline__ void polish32(const SolveArgs& A, const Geo32<NO>& G,
-                                         State32<NO>& S) {
+                                         float* ST) {
   if (A.polish_steps <= 0) return;
   Geo32View<NO> V{G, {}};
   float T[2 * NO];
@@ -1589,7 +1594,7 @@ __device__ __forceinline__ void polish32(const SolveArgs& A, const Geo32<NO>& G,
   for (int j = 0; j < NO; ++j)
     V.edge_[j] = G.a[j][1][0] == 0.f && G.a[j][1][1] == 0.f && G.a[j][1][2] == 0.f;
 #pragma unroll
-  for (int q = 0; q < 2 * NO; ++q) T[q] = S.T[q];
+  for (int q = 0; q < 2 * NO; ++q) T[q] = ST[q];
   NewtonTrack k;
   const float eps = kPolishEps * A.scale;
   newton_run64(V, T, eps * eps, A.polish_steps, 0.f, true, k);
@@ -1597,23 +1602,51 @@ __device__ __forceinline__ void polish32(const SolveArgs& A, const Geo32<NO>& G,
 #pragma unroll
   for (int q = 0; q < 2 * NO; ++q) fin = fin && isfinite(T[q]);
 #pragma unroll
-  for (int q = 0; q < 2 * NO; ++q) S.T[q] = fin ? T[q] : S.T[q];
+  for (int q = 0; q < 2 * NO; ++q) ST[q] = fin ? T[q] : ST[q];
 }
 
 // hands a path over to the refinement kernel: unit-vector parameters,
 // iteration count, validity
 template <int NO>
 __device__ __forceinline__ void store_phase1(const SolveArgs& A, int64_t p,
-                                             const State32<NO>& S, int it,
-                                             bool valid) {
+                                             const float* ST, int it, bool valid) {
 #pragma unroll
-  for (int k = 0; k < 2 * NO; ++k) A.t[(int64_t)k * A.N + p] = S.T[k];
+  for (int k = 0; k < 2 * NO; ++k) A.t[(int64_t)k * A.N + p] = ST[k];
   A.iters[p] = (uint16_t)(it > 65535 ? 65535 : it);
   A.status[p] = valid ? 0 : FPT_ST_INVALID;
 }
 
+// The BFGS iterations of one path with D parameters per slot, from t0; the
+// result in the padded layout (an edge's second parameter 0).
+template <int NO, int D>
+__device__ __forceinline__ void bfgs_run(const SolveArgs& A, const Geo32<NO>& G,
+                                         const float (*t0)[2], float* T) {
+  State32<NO, D> S;
+  init_state<NO, D>(G, t0, S);
+  for (int it = 0; it < A.n_iter; ++it) bfgs_iter<NO, D>(G, S, A.fp_iters, it == 0);
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    T[2 * j] = S.T[D * j];
+    T[2 * j + 1] = D == 2 ? S.T[D * j + 1] : 0.f;
+  }
+}
+
 // Phase 1, fixed iteration count (Sec. III-C runs every path for the same
-// number of iterations so that all lanes finish together).
+// number of iterations so that all lanes finish together). Up to order
+// kUnpaddedMax, a wave whose paths all have only edges runs the BFGS on n
+// parameters instead of the padded 2n (Sec. III-B): the padded rows of H
+// stay exactly 0 in the padded iteration, so both compute the same iterates
+// (they agree to FP32 rounding), and the unpadded one skips the padded
+// rows' arithmetic. The test is one ballot on the loaded geometry, so it
+// costs nothing where such waves are rare (paths in random order) and pays
+// where edge-only paths come in runs (candidates enumerated in order of
+// their objects, as the enumeration kernel writes them). Putting the
+// edge-only paths of each 256 first in a workgroup, by a partition through
+// LDS, made every wave pay for a second read of the object indices and
+// three barriers, and it was slower on paths in random order. From order 3
+// on the unpadded code path would cost the kernel a wave per SIMD.
+constexpr int kUnpaddedMax = 2;
+
 template <int NO>
 __global__ __launch_bounds__(kBlock) void bfgs_kernel(
     SolveArgs A, const int32_t* __restrict__ perm,
@@ -1630,13 +1663,22 @@ __global__ __launch_bounds__(kBlock) void bfgs_kernel(
        idx += stride) {
     const int64_t p = perm ? (int64_t)perm[begin + idx] : begin + idx;
     Geo32<NO> G;
-    float t0[NO][2];
+    float t0[NO][2], T[2 * NO];
     bool valid = load_path32<NO>(A, p, G, t0);
-    State32<NO> S;
-    init_state<NO>(G, t0, S);
-    for (int it = 0; it < A.n_iter; ++it) bfgs_iter<NO>(G, S, A.fp_iters, it == 0);
-    polish32<NO>(A, G, S);
-    store_phase1<NO>(A, p, S, A.n_iter, valid);
+    bool unpadded = false;
+    if constexpr (NO <= kUnpaddedMax) {
+      bool e = true;
+#pragma unroll
+      for (int j = 0; j < NO; ++j)
+        e = e && G.a[j][1][0] == 0.f && G.a[j][1][1] == 0.f && G.a[j][1][2] == 0.f;
+      unpadded = __ballot(e) == __ballot(true);
+    }
+    if (unpadded)
+      bfgs_run<NO, 1>(A, G, t0, T);
+    else
+      bfgs_run<NO, 2>(A, G, t0, T);
+    polish32<NO>(A, G, T);
+    store_phase1<NO>(A, p, T, A.n_iter, valid);
   }
 }
 
@@ -1785,8 +1827,8 @@ __global__ __launch_bounds__(kBlock) void bfgs_stage_kernel(
     }
     const bool fin = done || !St.out_list || !valid;
     if (fin) {
-      polish32<NO>(A, G, S);
-      store_phase1<NO>(A, p, S, it, valid);
+      polish32<NO>(A, G, S.T);
+      store_phase1<NO>(A, p, S.T, it, valid);
     }
     const unsigned long long more = __ballot(!fin);
     if (more) {

@@ -425,6 +425,37 @@ def test_warm_start_in_place(solver):
             assert np.all(np.isnan(want["x"][n:, :, b.order == n]))
 
 
+@pytest.mark.parametrize("n", [1, 2])
+def test_unpadded_edge_paths_match_padded(solver, oracle_mod, n):
+    """Paths whose every interaction is an edge run the BFGS on n parameters
+    when a whole wave of them comes together, else in the padded layout; the
+    padded rows stay exactly 0, so both compute the same iterates (to FP32
+    rounding), and after the FP64 refinement the same bits. Edge-only paths
+    alone (every wave unpadded) against the same paths spread one in six
+    among face paths (no wave of 64 edge-only paths), and the oracle."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 150000, seed=5100 + n, n=n)
+    edge = np.all(b.obj[6:9] == 0, axis=0)
+    eo = np.all(edge[b.ids[:n]], axis=0)
+    face = np.all(~edge[b.ids[:n]], axis=0)
+    E = np.nonzero(eo)[0][:3000]
+    F = np.nonzero(face)[0][:5 * len(E)]
+    assert len(E) == 3000 and len(F) == 5 * len(E)
+    mix = np.empty(6 * len(E), np.int64)
+    mix[0::6] = E
+    for r in range(5):
+        mix[r + 1::6] = F[r::5]
+    opts = _opts(b.S, iters=10)
+    ge = gpu_util.run_gpu(solver, b.subset(E), opts, with_order=False)
+    gm = gpu_util.run_gpu(solver, b.subset(mix), opts, with_order=False)
+    for k in ge:
+        np.testing.assert_array_equal(ge[k], gm[k][..., 0::6], err_msg=k)
+    sub = b.subset(E[:1000])
+    ref = oracle_mod.solve(sub)
+    g1 = {k: v[..., :1000] for k, v in ge.items()}
+    _check_common(sub, g1, ref)
+
+
 def test_bucketing_ragged_unaligned_and_invalid_orders(solver):
     """Order bucketing over a ragged size (three chunks of 8,192 paths and a
     tail) with an order array that starts off 16-byte alignment (the
@@ -554,7 +585,14 @@ def test_split_variants_equal_one_part(solver, variant):
     g = gpu_util.run_gpu(solver, b, _opts(b.S, split=2,
                                           concurrent_orders=(variant == "concurrent"), **kw))
     for key in ref:
-        np.testing.assert_array_equal(g[key], ref[key], err_msg=f"{variant} {key}")
+        if variant == "no_refinement" and key in ("x", "t", "len"):
+            # the raw FP32 phase: an edge-only path of order <= 2 may run
+            # unpadded in one split and padded in the other (a workgroup's
+            # paths differ), the same iterates up to FP32 rounding
+            np.testing.assert_allclose(g[key], ref[key], rtol=1e-6, atol=1e-6 * b.S,
+                                       err_msg=f"{variant} {key}")
+        else:
+            np.testing.assert_array_equal(g[key], ref[key], err_msg=f"{variant} {key}")
 
 
 def test_three_quick_steps_keep_parity(solver, oracle_mod):
