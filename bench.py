@@ -215,6 +215,7 @@ def run_fwd_grad(args, fpt, scenes, torch):
                      & ((out["status"] & fpt.ST_NOGRAD) == 0)).sum().item())
     nograd = float(((out["status"] & fpt.ST_NOGRAD) != 0).float().mean().item())
     tg_kernel = kt[fpt.T_GRAD]
+    cg = read_counters("grad_kernel_3", "canyon_c4", "grad")
     res = {
         "workload": "street canyon: 1,048,576 sampled order-3 paths, "
                     "upstream gradients N(0,1)",
@@ -229,8 +230,12 @@ def run_fwd_grad(args, fpt, scenes, torch):
             "kernel": "grad_kernel<3>", "bound": "hbm",
             "achieved": grad_bytes_per_path(3) * b.N / (tg_kernel * 1e-3) / 1e9,
             "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-            "frac": grad_bytes_per_path(3) * b.N / (tg_kernel * 1e-3) / PEAK_HBM},
+            "frac": grad_bytes_per_path(3) * b.N / (tg_kernel * 1e-3) / PEAK_HBM,
+            "traffic": cg["hbm_bytes_per_launch"] if cg else None},
     }
+    if args.no_autodiff:
+        solver.close()
+        return res
     # autodiff through unrolled iterations vs implicit, same subset
     M = 1 << 18
     sub = b.subset(np.arange(M))
@@ -285,19 +290,26 @@ def run_fwd_grad(args, fpt, scenes, torch):
 
 
 
-def source_digest() -> str:
-    """Digest of the kernels' sources (the host code that launches them,
-    api.hip, changes no kernel's bytes or arithmetic and is left out)."""
+# The sources each group of kernels is built from (the host code that
+# launches them, api.hip, changes no kernel's bytes or arithmetic).
+KERNEL_SOURCES = {"solve": ("solve.hip", "path64.h", "common.h"),
+                  "grad": ("grad.hip", "path64.h", "common.h"),
+                  "mlp": ("mlp.hip", "common.h")}
+
+
+def source_digest(group: str = "solve") -> str:
+    """Digest of the sources of one group of kernels."""
     h = hashlib.sha256()
-    for f in ("solve.hip", "path64.h", "common.h", "grad.hip", "mlp.hip"):
+    for f in KERNEL_SOURCES[group]:
         with open(os.path.join(ROOT, "paper_2510_16172_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_counters(kernel: str, workload: str):
+def read_counters(kernel: str, workload: str, group: str = "solve"):
     """The committed rocprofv3 counter summary of a kernel (group) on a
-    workload, or None if there is none for the current kernel sources."""
+    workload, or None if there is none for the current sources of its
+    kernels."""
     path = os.path.join(ROOT, "profiles", f"{kernel}__{workload}.counters.json")
     if not os.path.exists(path):
         return None
@@ -305,7 +317,7 @@ def read_counters(kernel: str, workload: str):
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("source_digest") != source_digest():
+    if d.get("source_digest") != source_digest(group):
         return None
     return d
 
@@ -773,6 +785,16 @@ def run_learned(args, fpt, torch):
                               epochs=args.mlp_epochs,
                               log=lambda m: print(m, file=sys.stderr, flush=True))
     solver.close()
+    ms = (res.get("equal_iterations") or {}).get("ms_inference")
+    if ms:
+        # 66 -> 256 -> 256 -> 256 -> 8 with FMA = 2: 300,032 FLOP per path
+        fl = 300032 * res["paths"]
+        cm = read_counters("mlp_infer_kernel", "canyon_c5", "mlp")
+        res["infer_roofline"] = {
+            "kernel": "mlp_infer_kernel", "bound": "mfma", "paths": res["paths"],
+            "achieved": fl / (ms * 1e-3) / 1e12, "peak": PEAK_BF16 / 1e12,
+            "unit": "TFLOP/s", "frac": fl / (ms * 1e-3) / PEAK_BF16, "ms": ms,
+            "traffic": cm["hbm_bytes_per_launch"] if cm else None}
     return res
 
 
@@ -804,6 +826,8 @@ def main():
                     help="skip the FP32 Newton variant on the c2 leg")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the solve + implicit gradient leg")
+    ap.add_argument("--no-autodiff", action="store_true",
+                    help="fwd_grad leg without the unrolled-autodiff comparison")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training and evaluating the learned initialiser")
     ap.add_argument("--mlp-epochs", type=int, default=40)
