@@ -650,7 +650,8 @@ def run_c3(args, fpt, scenes, torch):
 def run_c2(args, fpt, scenes, torch, post=True, variant=True, check_seconds=0.0):
     """All order <= 2 sequences; then (not in the metric) validity of the
     solved paths, candidate enumeration and the chain enumerate -> solve ->
-    validity, and the FP32 Newton variant of the first phase."""
+    validity, and the solver variants of the first phase (FP32 Newton,
+    Armijo line search)."""
     scene = scenes.canyon_scene()
     batch = scenes.canyon_all_paths(scene, n_max=2)
     N = batch.N
@@ -667,28 +668,38 @@ def run_c2(args, fpt, scenes, torch, post=True, variant=True, check_seconds=0.0)
     solver.solve(db, opts, out=out)
     torch.cuda.synchronize()
     if variant:
-        opts_n = fpt.Opts(scale=batch.S, method=fpt.METHOD_NEWTON32)
         from paper_2510_16172_amd import autotune
-        chosen_n, _ = tune_or_fix(args, solver, batch, opts_n, 1 << 20, 3, None,
-                                  candidates=autotune.NEWTON32_CANDIDATES)
-        outv = solver.alloc_out(db)
-        for _ in range(args.warmup):
-            solver.solve(db, opts_n, out=outv, stream=stream)
-        torch.cuda.synchronize()
-        v0, v1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        v0.record(stream)
-        for _ in range(args.steps):
-            solver.solve(db, opts_n, out=outv, stream=stream)
-        v1.record(stream)
-        torch.cuda.synchronize()
-        ms_n = v0.elapsed_time(v1) / args.steps
-        outs["newton32"] = {k: v.cpu().numpy() for k, v in outv.items()}
-        cert_n = int(((outs["newton32"]["status"] & fpt.ST_CONVERGED) != 0).sum())
+
+        def time_variant(opts_v, candidates):
+            chosen_v, _ = tune_or_fix(args, solver, batch, opts_v, 1 << 20, 3, None,
+                                      candidates=candidates)
+            outv = solver.alloc_out(db)
+            for _ in range(args.warmup):
+                solver.solve(db, opts_v, out=outv, stream=stream)
+            torch.cuda.synchronize()
+            v0, v1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            v0.record(stream)
+            for _ in range(args.steps):
+                solver.solve(db, opts_v, out=outv, stream=stream)
+            v1.record(stream)
+            torch.cuda.synchronize()
+            ms_v = v0.elapsed_time(v1) / args.steps
+            o = {k: v.cpu().numpy() for k, v in outv.items()}
+            cert_v = int(((o["status"] & fpt.ST_CONVERGED) != 0).sum())
+            return o, {"schedule": {str(k): v for k, v in chosen_v.items()},
+                       "ms_per_step": ms_v, "certified_fraction": cert_v / N,
+                       "certified_paths_per_s": cert_v / (ms_v * 1e-3)}
+
+        outs["newton32"], r = time_variant(fpt.Opts(scale=batch.S, method=fpt.METHOD_NEWTON32),
+                                           autotune.NEWTON32_CANDIDATES)
         res["variant_newton32"] = {
-            "method": "FP32 exact-Hessian Newton first phase (fpt_opts.method = 1)",
-            "schedule": {str(k): v for k, v in chosen_n.items()},
-            "ms_per_step": ms_n, "certified_fraction": cert_n / N,
-            "certified_paths_per_s": cert_n / (ms_n * 1e-3)}
+            "method": "FP32 exact-Hessian Newton first phase (fpt_opts.method = 1)", **r}
+        outs["armijo"], r = time_variant(
+            fpt.Opts(scale=batch.S, line_search=fpt.LS_ARMIJO),
+            [c for c in autotune.DEFAULT_CANDIDATES if not c.get("early_exit")])
+        res["variant_armijo"] = {
+            "method": "BFGS with Armijo backtracking in place of the Eq. 6 step "
+                      "(fpt_opts.line_search = 1)", **r}
         for n in (1, 2):
             solver.set_launch(n, chosen.get(n))
         solver.solve(db, opts, out=out)
@@ -900,7 +911,7 @@ def main():
         "phase_rooflines": head["phase_rooflines"],
         "kernel_ms_orders_one_after_another": head["kernel_ms_orders_one_after_another"],
     }
-    for k in ("validate", "enumerate", "chain", "variant_newton32"):
+    for k in ("validate", "enumerate", "chain", "variant_newton32", "variant_armijo"):
         if k in head:
             res[k] = head[k]
     if not args.no_cpu_baseline and batch is not None:

@@ -164,16 +164,25 @@ typedef struct {
                            part's latency-bound passes overlap another's;
                            the results are the same. 0: 2 parts from 2^21
                            paths on, else 1. Early exit uses 1 */
+  int32_t line_search;  /* step size of the BFGS (method FPT_METHOD_BFGS, fixed
+                           iteration count): FPT_LS_EQ6, the fixed-point
+                           iteration of Eq. 6 (Sec. III-C, the paper's); or
+                           FPT_LS_ARMIJO, a solver variant (Sec. V names
+                           better line searches): backtracking from the unit
+                           step, halved until L(T + a P) <= L(T) + 1e-4 a g.P,
+                           at most 8 times, else the majorant step of Eq. 6
+                           from 0. Early exit uses FPT_LS_EQ6 */
 } fpt_opts;
 
 enum { FPT_METHOD_BFGS = 0, FPT_METHOD_NEWTON32 = 1 };
+enum { FPT_LS_EQ6 = 0, FPT_LS_ARMIJO = 1 };
 
 /* Defaults: the BFGS method, 64 iterations, 1 fixed-point iteration, 1
  * polish step, no early exit (exit_rtol = 1e-6, stages of 16, 16 and 32
  * iterations), refinement levels eps/S = 1e-3, 1e-5, 1e-7 (2 steps each) and
  * 1e-9 (3 steps) after a quick pass of 2 steps at 1e-9 (twice: quick_passes
  * = 2), cert_rtol = 1e-5, scale = 1, orders one after another, split 0
- * (automatic). */
+ * (automatic), the Eq. 6 step (line_search = FPT_LS_EQ6). */
 void fpt_default_opts(fpt_opts* opts);
 
 typedef struct {

@@ -140,6 +140,7 @@ extern "C" void fpt_default_opts(fpt_opts* o) {
   o->method = FPT_METHOD_BFGS;
   o->polish_steps = 1;
   o->split = 0;
+  o->line_search = FPT_LS_EQ6;
 }
 
 // Keeps the caller's current device and switches to the handle's for the
@@ -297,6 +298,8 @@ static fpt_status check_opts(const fpt_opts* o) {
     return fail(FPT_EINVAL, "fpt_solve: unknown method");
   if (o->polish_steps < 0 || o->polish_steps > 8)
     return fail(FPT_EINVAL, "fpt_solve: polish_steps outside 0..8");
+  if (o->line_search != FPT_LS_EQ6 && o->line_search != FPT_LS_ARMIJO)
+    return fail(FPT_EINVAL, "fpt_solve: unknown line_search");
   if (o->split < 0 || o->split > kMaxSplit)
     return fail(FPT_EINVAL, "fpt_solve: split outside 0..4");
   if (o->early_exit) {
@@ -696,6 +699,7 @@ static fpt_status solve_run(fpt_handle* h, const fpt_scene* sc, const fpt_paths*
   A.early_exit = o->early_exit ? 1 : 0;
   A.method = o->method;
   A.polish_steps = o->polish_steps;
+  A.line_search = o->line_search;
   float ed = o->exit_rtol * o->scale;
   A.exit_d2 = ed * ed;
   A.scale = o->scale;

@@ -89,6 +89,7 @@ struct SolveArgs {
   // options
   int32_t n_iter, fp_iters, early_exit, method;
   int32_t polish_steps;  // FP32 Newton steps at the end of the BFGS phase
+  int32_t line_search;   // FPT_LS_EQ6 or FPT_LS_ARMIJO (fixed-count BFGS)
   int32_t sub, nsub;     // this launch is part sub of nsub of its range (sub_range)
   float exit_d2;  // (exit_rtol * scale)^2
   float scale;

@@ -1432,6 +1432,11 @@ __device__ __forceinline__ void init_state(const Geo32<NO>& G,
   for (int k = 0; k < M; ++k) S.P[k] = -S.g[k];
 }
 
+// The line-search variant (fpt_opts.line_search): Armijo's sufficient
+// decrease constant and the number of halvings before the majorant step.
+constexpr float kArmijoC1 = 1e-4f;
+constexpr int kArmijoHalvings = 8;
+
 // One BFGS iteration (Sec. III-C): step size by the fixed-point iteration of
 // Eq. 6 (from the unit step, with the majorant step from 0 as fallback),
 // step, new gradient, inverse-Hessian update. On the first iteration the
@@ -1439,7 +1444,7 @@ __device__ __forceinline__ void init_state(const Geo32<NO>& G,
 // choice of the initial inverse Hessian, Nocedal & Wright eq. 6.20): H = I
 // is off by the scale of the segment lengths. Returns the squared largest
 // point displacement of the step.
-template <int NO, int D = 2>
+template <int NO, int D = 2, int LS = FPT_LS_EQ6>
 __device__ __forceinline__ float bfgs_iter(const Geo32<NO>& G, State32<NO, D>& S,
                                            int fp_iters, bool first) {
   constexpr int M = State32<NO, D>::M, HP = State32<NO, D>::HP;
@@ -1468,8 +1473,26 @@ __device__ __forceinline__ float bfgs_iter(const Geo32<NO>& G, State32<NO, D>& S
   // Eq. 6 started at alpha = 0: one step is the majorant minimiser
   float a_mm = (den0 > 1e-30f) ? -num0 * rcp32(den0) : 0.f;
   if (!isfinite(a_mm)) a_mm = 0.f;
-  // Eq. 6 iterated from the unit step
   float alpha = 1.f;
+  if constexpr (LS == FPT_LS_ARMIJO) {
+    // backtracking from the unit step: the length along the direction,
+    // sum_i |r_i + a D_i|, needs one rsq per segment and trial; its slope at
+    // 0 is num0 (= g.P)
+    bool ok = false;
+#pragma unroll 1
+    for (int h = 0; h <= kArmijoHalvings && !ok; ++h) {
+      if (h > 0) alpha *= 0.5f;
+      float phi = 0.f;
+#pragma unroll
+      for (int i = 0; i <= NO; ++i) {
+        const float rho2 = fmaxf(fmaf(alpha, fmaf(alpha, dd[i], 2.f * dr[i]), S.l2[i]), 1e-30f);
+        phi = fmaf(rho2, rsq32(rho2), phi);
+      }
+      ok = phi <= fmaf(kArmijoC1 * alpha, num0, phi0);
+    }
+    if (!ok || !isfinite(alpha)) alpha = a_mm;
+  } else {
+  // Eq. 6 iterated from the unit step
   for (int f = 0; f < fp_iters; ++f) {
     float num = 0.f, den = 0.f;
 #pragma unroll
@@ -1489,6 +1512,7 @@ __device__ __forceinline__ float bfgs_iter(const Geo32<NO>& G, State32<NO, D>& S
     phi = fmaf(rho2, rsq32(rho2), phi);
   }
   if (!(phi < phi0) || !(alpha > 0.f) || !isfinite(alpha)) alpha = a_mm;
+  }
   // step, new gradient
   float s[M], gn[M];
 #pragma unroll
@@ -1616,14 +1640,14 @@ __device__ __forceinline__ void store_phase1(const SolveArgs& A, int64_t p,
   A.status[p] = valid ? 0 : FPT_ST_INVALID;
 }
 
-// The BFGS iterations of one path with D parameters per slot, from t0; the
-// result in the padded layout (an edge's second parameter 0).
-template <int NO, int D>
+// The BFGS iterations of one path with D parameters per slot and step rule
+// LS, from t0; the result in the padded layout (an edge's second parameter 0).
+template <int NO, int D, int LS = FPT_LS_EQ6>
 __device__ __forceinline__ void bfgs_run(const SolveArgs& A, const Geo32<NO>& G,
                                          const float (*t0)[2], float* T) {
   State32<NO, D> S;
   init_state<NO, D>(G, t0, S);
-  for (int it = 0; it < A.n_iter; ++it) bfgs_iter<NO, D>(G, S, A.fp_iters, it == 0);
+  for (int it = 0; it < A.n_iter; ++it) bfgs_iter<NO, D, LS>(G, S, A.fp_iters, it == 0);
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
     T[2 * j] = S.T[D * j];
@@ -1647,7 +1671,9 @@ __device__ __forceinline__ void bfgs_run(const SolveArgs& A, const Geo32<NO>& G,
 // on the unpadded code path would cost the kernel a wave per SIMD.
 constexpr int kUnpaddedMax = 2;
 
-template <int NO>
+// (LS: the step rule. The line-search variant is an instantiation of its
+// own, so that its code costs the default kernel no registers.)
+template <int NO, int LS = FPT_LS_EQ6>
 __global__ __launch_bounds__(kBlock) void bfgs_kernel(
     SolveArgs A, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ bucket) {
@@ -1666,7 +1692,7 @@ __global__ __launch_bounds__(kBlock) void bfgs_kernel(
     float t0[NO][2], T[2 * NO];
     bool valid = load_path32<NO>(A, p, G, t0);
     bool unpadded = false;
-    if constexpr (NO <= kUnpaddedMax) {
+    if constexpr (NO <= kUnpaddedMax && LS == FPT_LS_EQ6) {
       bool e = true;
 #pragma unroll
       for (int j = 0; j < NO; ++j)
@@ -1674,9 +1700,9 @@ __global__ __launch_bounds__(kBlock) void bfgs_kernel(
       unpadded = __ballot(e) == __ballot(true);
     }
     if (unpadded)
-      bfgs_run<NO, 1>(A, G, t0, T);
+      bfgs_run<NO, 1, LS>(A, G, t0, T);
     else
-      bfgs_run<NO, 2>(A, G, t0, T);
+      bfgs_run<NO, 2, LS>(A, G, t0, T);
     polish32<NO>(A, G, T);
     store_phase1<NO>(A, p, T, A.n_iter, valid);
   }
@@ -2444,10 +2470,13 @@ static hipError_t launch_phase(int phase, const SolveArgs& A,
                                const int32_t* perm, const int64_t* bucket,
                                const StageArgs* stage, int grid,
                                hipStream_t st) {
-  if (phase == 0)
-    hipLaunchKernelGGL(bfgs_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A,
-                       perm, bucket);
-  else if (phase == 4)
+  if (phase == 0) {
+    if (A.line_search == FPT_LS_ARMIJO)
+      hipLaunchKernelGGL((bfgs_kernel<NO, FPT_LS_ARMIJO>), dim3(grid), dim3(kBlock), 0, st, A,
+                         perm, bucket);
+    else
+      hipLaunchKernelGGL(bfgs_kernel<NO>, dim3(grid), dim3(kBlock), 0, st, A, perm, bucket);
+  } else if (phase == 4)
     hipLaunchKernelGGL((refine_kernel<NO, true>), dim3(grid), dim3(kBlock), 0, st, A,
                        perm, bucket, *stage);
   else if (phase == 1)

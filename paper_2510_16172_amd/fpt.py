@@ -46,7 +46,8 @@ class _Opts(ctypes.Structure):
                 ("stage_iters", ctypes.c_int32 * 4),
                 ("quick_steps", ctypes.c_int32), ("quick_passes", ctypes.c_int32),
                 ("concurrent_orders", ctypes.c_int32), ("method", ctypes.c_int32),
-                ("polish_steps", ctypes.c_int32), ("split", ctypes.c_int32)]
+                ("polish_steps", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("line_search", ctypes.c_int32)]
 
 
 class _LaunchCfg(ctypes.Structure):
@@ -81,6 +82,7 @@ T_BUCKET, T_BFGS, T_REFINE, T_GRAD, T_REDUCE, T_MLP, T_VALIDATE, T_UNSORT, TIMER
 VALID_EXTENT, VALID_SPECULAR, VALID_VISIBLE = 1, 2, 4
 VALIDATE_ALL, VALIDATE_LAZY = 0, 1
 METHOD_BFGS, METHOD_NEWTON32 = 0, 1
+LS_EQ6, LS_ARMIJO = 0, 1
 MLP_PARAMS = 172864  # padded parameter count: state[0:MLP_PARAMS] = weights
 
 _lib = None
@@ -184,6 +186,7 @@ class Opts:
     method: int = 0  # METHOD_BFGS (the paper's) or METHOD_NEWTON32 (variant)
     polish_steps: int = 1
     split: int = 0  # parts per order on their own streams (0: automatic)
+    line_search: int = 0  # LS_EQ6 (the paper's Eq. 6 step) or LS_ARMIJO (variant)
 
     def to_c(self) -> _Opts:
         o = _Opts()
@@ -212,6 +215,7 @@ class Opts:
         o.method = int(self.method)
         o.polish_steps = int(self.polish_steps)
         o.split = int(self.split)
+        o.line_search = int(self.line_search)
         return o
 
 

@@ -42,7 +42,7 @@ def test_default_opts_and_struct_layout():
     assert ctypes.sizeof(fpt._Paths) == 56
     assert ctypes.sizeof(fpt._Out) == 40
     assert ctypes.sizeof(fpt._LaunchCfg) == 4 * 3 + 16 + 4 + 4 + 4 + 4
-    assert ctypes.sizeof(fpt._Opts) == 4 * 6 + 4 * 8 * 2 + 4 + 16 + 4 + 4 + 4 + 4 + 4 + 4
+    assert ctypes.sizeof(fpt._Opts) == 4 * 6 + 4 * 8 * 2 + 4 + 16 + 4 + 4 + 4 + 4 + 4 + 4 + 4
     assert o.method == fpt.METHOD_BFGS and o.polish_steps == 1 and o.split == 0
     assert o.quick_steps == 2
     assert o.quick_passes == 2
