@@ -86,9 +86,11 @@ enum {
   FPT_ST_NONFINITE = 8, /* the solve produced a non-finite value */
   FPT_ST_INVALID = 16,  /* bad order / id / point index, or non-finite input */
   FPT_ST_NOGRAD = 32    /* fpt_grad gives this path no gradient (zero): set
-                           with FPT_ST_COLLAPSED, FPT_ST_NONFINITE or
-                           FPT_ST_INVALID, where the Hessian of Sec. III-D is
-                           singular or undefined */
+                           with FPT_ST_NONFINITE or FPT_ST_INVALID, and with
+                           FPT_ST_COLLAPSED unless the collapse is one
+                           interior zero-length segment whose two objects'
+                           unit directions span space (the determinant of
+                           the sum of their outer products above 1e-3) */
 };
 
 typedef struct fpt_handle fpt_handle;
@@ -240,9 +242,12 @@ int64_t fpt_noalloc_max_paths(void);
  * d loss / d obj into g_obj [9][K] (rows b, a1, a2; the padded a2 of an
  * edge receives nothing). g_slot [n_max][9][N] (optional, may be NULL)
  * receives the unreduced per-path, per-interaction object gradient; g_end
- * [6][N] (optional) the per-path TX and RX gradients. Paths whose status
- * has FPT_ST_COLLAPSED, FPT_ST_INVALID or FPT_ST_NONFINITE contribute zero
- * (the Hessian of Eq. 12 is singular or undefined there). */
+ * [6][N] (optional) the per-path TX and RX gradients. A collapsed minimiser
+ * without FPT_ST_NOGRAD (one interior zero-length segment) is differentiated
+ * as the minimiser of the length without that segment under the constraint
+ * that its two points coincide (the implicit function theorem of Sec. III-D
+ * applied to that problem's KKT conditions; the Hessian of Eq. 12 itself is
+ * unbounded there). Paths with FPT_ST_NOGRAD contribute zero. */
 fpt_status fpt_grad(fpt_handle* h, const fpt_scene* scene,
                     const fpt_paths* paths, const fpt_out* fwd,
                     const float* g_len, const float* g_x, float* g_pts,

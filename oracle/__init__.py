@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfermat_oracle.so")
 SOURCES = [os.path.join(HERE, "fermat_oracle.c")]
 
-COLLAPSED, ILL, NOCONV, INVALID = 1, 2, 4, 8
+COLLAPSED, ILL, NOCONV, INVALID, KKT = 1, 2, 4, 8, 16
 EXTENT, SPECULAR, VISIBLE = 1, 2, 4
 
 
@@ -107,8 +107,10 @@ def grad(b, t_sol, g_len, g_x, threads: int = 0):
 
     ``g_len [N]`` and ``g_x [N][n_max][3]`` are the upstream cotangents.
     Returns per-path ``g_tx, g_rx [N][3]``, ``g_b [N][n_max][3]``,
-    ``g_a [N][n_max][2][3]`` and ``status [N]`` (COLLAPSED where the IFT
-    does not apply)."""
+    ``g_a [N][n_max][2][3]`` and ``status [N]``: 0 at a smooth minimiser,
+    KKT at a minimiser with one interior zero-length segment (the IFT on the
+    collapse constraint's KKT conditions), COLLAPSED where neither applies
+    (outputs NaN)."""
     lib = _load()
     N, n_max = b.N, b.n_max
     t_sol = np.ascontiguousarray(t_sol, np.float64)

@@ -135,9 +135,10 @@ static double length_eps(const path_t *p, const double *t, double eps) {
  *   dl_i/dr_i = v_i,  d^2 l_i/dr_i^2 = M_i = (I - r_i r_i^T / l_i^2) / l_i.
  * Point x_j enters r_{j-1} with sign +1 and r_j with sign -1, so
  *   g_c   = a_c . (v_{j-1} - v_j)                       (c on slot j),
- *   H_cd  = sum_i s_ic s_id a_c^T M_i a_d               (c, d touching i). */
-static void grad_hess(const path_t *p, const double *t, double eps, double *g,
-                      double H[MMAX][MMAX]) {
+ *   H_cd  = sum_i s_ic s_id a_c^T M_i a_d               (c, d touching i).
+ * Segment `skip` (if 0..n) is left out of both: the length without it. */
+static void grad_hess_skip(const path_t *p, const double *t, double eps,
+                           int skip, double *g, double H[MMAX][MMAX]) {
   double x[NMAX + 2][3];
   points(p, t, x);
   int m = p->m, n = p->n;
@@ -151,6 +152,12 @@ static void grad_hess(const path_t *p, const double *t, double eps, double *g,
     for (int q = 0; q < 3; ++q)
       for (int w = 0; w < 3; ++w)
         M[i][q][w] = ((q == w ? 1.0 : 0.0) - r[q] * r[w] / (l * l)) / l;
+    if (i == skip) {
+      for (int q = 0; q < 3; ++q) {
+        v[i][q] = 0.0;
+        for (int w = 0; w < 3; ++w) M[i][q][w] = 0.0;
+      }
+    }
   }
   for (int c = 0; c < m; ++c) {
     int j = p->cs[c];
@@ -186,39 +193,53 @@ static void grad_hess(const path_t *p, const double *t, double eps, double *g,
   }
 }
 
-/* Dense Gaussian elimination with partial pivoting: solves A y = rhs.
- * A is overwritten. Returns -1 if a pivot is exactly zero. */
-static int gauss_solve(int m, double A[MMAX][MMAX], const double *rhs,
-                       double *y) {
-  double b[MMAX];
+static void grad_hess(const path_t *p, const double *t, double eps, double *g,
+                      double H[MMAX][MMAX]) {
+  grad_hess_skip(p, t, eps, -1, g, H);
+}
+
+/* Dense Gaussian elimination with partial pivoting: solves A y = rhs for an
+ * m x m matrix stored with row stride ld (m <= KMAX). A is overwritten.
+ * Returns -1 if a pivot is exactly zero. */
+#define KMAX (MMAX + 3)
+static int gauss_solve_ld(int m, int ld, double *A, const double *rhs,
+                          double *y) {
+  double b[KMAX];
   memcpy(b, rhs, sizeof(double) * m);
+#define AE(r, c) A[(r) * ld + (c)]
   for (int k = 0; k < m; ++k) {
     int piv = k;
     for (int r = k + 1; r < m; ++r)
-      if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
-    if (A[piv][k] == 0.0) return -1;
+      if (fabs(AE(r, k)) > fabs(AE(piv, k))) piv = r;
+    if (AE(piv, k) == 0.0) return -1;
     if (piv != k) {
       for (int c = 0; c < m; ++c) {
-        double tmp = A[k][c];
-        A[k][c] = A[piv][c];
-        A[piv][c] = tmp;
+        double tmp = AE(k, c);
+        AE(k, c) = AE(piv, c);
+        AE(piv, c) = tmp;
       }
       double tmp = b[k];
       b[k] = b[piv];
       b[piv] = tmp;
     }
     for (int r = k + 1; r < m; ++r) {
-      double f = A[r][k] / A[k][k];
-      for (int c = k; c < m; ++c) A[r][c] -= f * A[k][c];
+      double f = AE(r, k) / AE(k, k);
+      for (int c = k; c < m; ++c) AE(r, c) -= f * AE(k, c);
       b[r] -= f * b[k];
     }
   }
   for (int k = m - 1; k >= 0; --k) {
     double s = b[k];
-    for (int c = k + 1; c < m; ++c) s -= A[k][c] * y[c];
-    y[k] = s / A[k][k];
+    for (int c = k + 1; c < m; ++c) s -= AE(k, c) * y[c];
+    y[k] = s / AE(k, k);
   }
+#undef AE
   return 0;
+}
+
+static int gauss_solve(int m, double A[MMAX][MMAX], const double *rhs,
+                       double *y) {
+  return gauss_solve_ld(m, MMAX, &A[0][0], rhs, y);
 }
 
 /* Cyclic Jacobi eigenvalues of a symmetric matrix (for the ILL flag). */
@@ -457,6 +478,129 @@ static int grad_one(const path_t *p, const double *t, double gl,
   return 0;
 }
 
+/* One path at a collapsed minimiser: exactly one segment z shorter than
+ * 1e-6 S, an interior one (1 <= z <= n-1, joining slot z-1 = point z and
+ * slot z = point z+1). Sec. III-D differentiates smooth minimisers only;
+ * this extends it. Near such a minimiser the solution stays collapsed, so it
+ * is the minimiser of
+ *     L_s(T) = sum_{i != z} l_i   subject to   c(T) = x_z - x_{z+1} = 0,
+ * with a multiplier mu: grad L_s + C^T mu = 0 (C = dc/dT, 3 x m). The
+ * implicit function theorem applied to these KKT conditions gives:
+ *   L* part:  dL* / dtheta = d(L_s + mu . c) / dtheta at fixed (T, mu);
+ *   X* part:  [H_s C^T; C 0] [lam; nu] = [w; 0] (H_s the Hessian of L_s)
+ *             and the contribution -lam . d(grad L_s + C^T mu)/d theta
+ *             - nu . dc/d theta.
+ * With w_z = -mu (a subgradient of the zero length: A_{z-1}^T (u_{z-1} -
+ * w_z) = 0 and A_z^T (w_z - u_{z+1}) = 0) the closed forms of grad_one
+ * hold with u_z replaced by w_z and c_z = 0, plus -nu on g_b of slot z-1
+ * and +nu on g_b of slot z (dc/db), which g_A picks up through t g_b.
+ * mu is the least-squares solution of C^T mu = -grad L_s (exact at the
+ * minimiser); it is unique when the unit directions of the two objects
+ * span space: det(sum of their outer products) > 1e-3 is required.
+ * Returns -1 where this does not apply. */
+static int grad_one_kkt(const path_t *p, const double *t, double gl,
+                        const double *gx, double *g_tx, double *g_rx,
+                        double *g_b, double *g_a, double S) {
+  const int n = p->n, m = p->m;
+  double x[NMAX + 2][3];
+  points(p, t, x);
+  double u[NMAX + 1][3], l[NMAX + 1];
+  int z = -1, nz = 0;
+  for (int i = 0; i <= n; ++i) {
+    double r[3] = {x[i + 1][0] - x[i][0], x[i + 1][1] - x[i][1],
+                   x[i + 1][2] - x[i][2]};
+    l[i] = sqrt(dot3(r, r));
+    if (!(l[i] > 1e-6 * S)) {
+      z = i;
+      ++nz;
+    }
+    for (int q = 0; q < 3; ++q) u[i][q] = r[q] / l[i];
+  }
+  if (nz != 1 || z < 1 || z > n - 1) return -1;
+  double N3[3][3] = {{0}};
+  for (int j = z - 1; j <= z; ++j)
+    for (int k = 0; k < p->d[j]; ++k) {
+      const double *a = p->a[j][k];
+      double aa = dot3(a, a);
+      for (int q = 0; q < 3; ++q)
+        for (int r = 0; r < 3; ++r) N3[q][r] += a[q] * a[r] / aa;
+    }
+  double det = N3[0][0] * (N3[1][1] * N3[2][2] - N3[1][2] * N3[2][1]) -
+               N3[0][1] * (N3[1][0] * N3[2][2] - N3[1][2] * N3[2][0]) +
+               N3[0][2] * (N3[1][0] * N3[2][1] - N3[1][1] * N3[2][0]);
+  if (!(det > 1e-3)) return -1;
+  /* grad L_s, H_s and C */
+  double gs[MMAX], Hs[MMAX][MMAX], C[3][MMAX];
+  grad_hess_skip(p, t, 0.0, z, gs, Hs);
+  for (int c = 0; c < m; ++c) {
+    int j = p->cs[c];
+    double sg = (j == z - 1) ? 1.0 : (j == z ? -1.0 : 0.0);
+    for (int q = 0; q < 3; ++q) C[q][c] = sg * p->a[j][p->ck[c]][q];
+  }
+  /* mu from the normal equations C C^T mu = -C gs */
+  double CC[3][3], rc[3], mu[3];
+  for (int q = 0; q < 3; ++q) {
+    rc[q] = 0.0;
+    for (int c = 0; c < m; ++c) rc[q] -= C[q][c] * gs[c];
+    for (int r = 0; r < 3; ++r) {
+      CC[q][r] = 0.0;
+      for (int c = 0; c < m; ++c) CC[q][r] += C[q][c] * C[r][c];
+    }
+  }
+  if (gauss_solve_ld(3, 3, &CC[0][0], rc, mu) != 0) return -1;
+  /* the KKT system */
+  const int mk = m + 3;
+  double Kk[KMAX][KMAX], rk[KMAX], sol[KMAX];
+  for (int r = 0; r < mk; ++r)
+    for (int c = 0; c < mk; ++c) Kk[r][c] = 0.0;
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < m; ++c) Kk[r][c] = Hs[r][c];
+  for (int q = 0; q < 3; ++q)
+    for (int c = 0; c < m; ++c) Kk[c][m + q] = Kk[m + q][c] = C[q][c];
+  for (int c = 0; c < m; ++c)
+    rk[c] = dot3(p->a[p->cs[c]][p->ck[c]], gx + 3 * p->cs[c]);
+  for (int q = 0; q < 3; ++q) rk[m + q] = 0.0;
+  if (gauss_solve_ld(mk, KMAX, &Kk[0][0], rk, sol) != 0) return -1;
+  const double *lam = sol, *nu = sol + m;
+  /* the closed forms of grad_one with u_z = -mu and c_z = 0 */
+  for (int q = 0; q < 3; ++q) u[z][q] = -mu[q];
+  double lamj[NMAX][2] = {{0}}, tj[NMAX][2] = {{0}};
+  for (int c = 0; c < m; ++c) {
+    lamj[p->cs[c]][p->ck[c]] = lam[c];
+    tj[p->cs[c]][p->ck[c]] = t[c];
+  }
+  double qp[NMAX + 2][3] = {{0}}, cseg[NMAX + 1][3];
+  for (int j = 0; j < n; ++j)
+    for (int q = 0; q < 3; ++q)
+      qp[j + 1][q] = lamj[j][0] * p->a[j][0][q] + lamj[j][1] * p->a[j][1][q];
+  for (int i = 0; i <= n; ++i) {
+    double dl[3] = {qp[i + 1][0] - qp[i][0], qp[i + 1][1] - qp[i][1],
+                    qp[i + 1][2] - qp[i][2]};
+    double ud = dot3(u[i], dl);
+    for (int q = 0; q < 3; ++q)
+      cseg[i][q] = (i == z) ? 0.0 : (dl[q] - u[i][q] * ud) / l[i];
+  }
+  for (int q = 0; q < 3; ++q) {
+    g_tx[q] = -gl * u[0][q] + cseg[0][q];
+    g_rx[q] = gl * u[n][q] - cseg[n][q];
+  }
+  for (int j = 0; j < n; ++j) {
+    double du[3], gb[3];
+    for (int q = 0; q < 3; ++q) {
+      du[q] = u[j][q] - u[j + 1][q];
+      gb[q] = gl * du[q] + gx[3 * j + q] - (cseg[j][q] - cseg[j + 1][q]);
+      if (j == z - 1) gb[q] -= nu[q];
+      if (j == z) gb[q] += nu[q];
+      g_b[3 * j + q] = gb[q];
+    }
+    for (int k = 0; k < 2; ++k)
+      for (int q = 0; q < 3; ++q)
+        g_a[(j * 2 + k) * 3 + q] =
+            (k < p->d[j]) ? tj[j][k] * gb[q] - lamj[j][k] * du[q] : 0.0;
+  }
+  return 0;
+}
+
 int oracle_grad(int64_t N, int n_max, const float *obj, int64_t K,
                 const float *pts, int64_t Q, const int32_t *src,
                 const int32_t *dst, const uint8_t *order, const int32_t *ids,
@@ -482,10 +626,18 @@ int oracle_grad(int64_t N, int n_max, const float *obj, int64_t K,
     double t[MMAX];
     for (int c = 0; c < p.m; ++c)
       t[c] = t_sol[i * n_max * 2 + p.cs[c] * 2 + p.ck[c]];
-    status[i] = grad_one(&p, t, g_len[i], g_x + i * n_max * 3, gtx, grx, gb,
-                         ga, S)
-                    ? ORACLE_COLLAPSED
-                    : 0;
+    status[i] = 0;
+    if (grad_one(&p, t, g_len[i], g_x + i * n_max * 3, gtx, grx, gb, ga, S)) {
+      /* a collapsed minimiser: the constrained form, where it applies */
+      status[i] = ORACLE_KKT;
+      if (grad_one_kkt(&p, t, g_len[i], g_x + i * n_max * 3, gtx, grx, gb, ga,
+                       S)) {
+        status[i] = ORACLE_COLLAPSED;
+        for (int q = 0; q < 3; ++q) gtx[q] = grx[q] = NAN;
+        for (int k = 0; k < n_max * 3; ++k) gb[k] = NAN;
+        for (int k = 0; k < n_max * 6; ++k) ga[k] = NAN;
+      }
+    }
   }
   return 0;
 }

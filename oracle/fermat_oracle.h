@@ -30,7 +30,8 @@ enum {
   ORACLE_COLLAPSED = 1, /* two consecutive points closer than 1e-6 S */
   ORACLE_ILL = 2,       /* Hessian condition number above 1e12 */
   ORACLE_NOCONV = 4,    /* last smoothing level hit its iteration cap */
-  ORACLE_INVALID = 8    /* bad id / order / point index or non-finite input */
+  ORACLE_INVALID = 8,   /* bad id / order / point index or non-finite input */
+  ORACLE_KKT = 16       /* gradient of a collapsed minimiser (constrained form) */
 };
 
 /* validity bits of oracle_validate */
@@ -45,8 +46,12 @@ int oracle_solve(int64_t N, int n_max, const float *obj, int64_t K,
 /* Gradient of  sum_i g_len[i] L*_i + sum_{i,j} g_x[i][j] . x*_ij  with respect
  * to TX (g_tx[N][3]), RX (g_rx[N][3]) and each slot's object b (g_b[N][n][3])
  * and basis vectors (g_a[N][n][2][3]), per path (not summed over objects).
- * t_sol is a solution in the t_out layout. status[i] is ORACLE_COLLAPSED where
- * a segment is shorter than 1e-6 S (the IFT does not apply; outputs NaN). */
+ * t_sol is a solution in the t_out layout. status[i] is 0 for a smooth
+ * minimiser (the IFT of Sec. III-D), ORACLE_KKT for a minimiser with one
+ * interior segment shorter than 1e-6 S whose two objects' directions span
+ * space (the IFT on the KKT conditions of the collapse constraint), and
+ * ORACLE_COLLAPSED for any other collapse or a singular system (outputs
+ * NaN). */
 int oracle_grad(int64_t N, int n_max, const float *obj, int64_t K,
                 const float *pts, int64_t Q, const int32_t *src,
                 const int32_t *dst, const uint8_t *order, const int32_t *ids,

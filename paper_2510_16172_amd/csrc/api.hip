@@ -24,9 +24,9 @@ hipError_t launch_unsort(const SolveArgs& S, const SolveArgs& A, const int32_t* 
                          const int64_t* bucket, int grid, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 hipError_t launch_grad(int order, const GradArgs& A, const int32_t* perm,
-                       const int64_t* bucket, int grid, size_t shmem,
+                       const int64_t* bucket, int grid, int kkt_grid, size_t shmem,
                        hipStream_t st);
-const void* grad_kernel_ptr(int order);
+const void* grad_kernel_ptr(int order, bool kkt);
 hipError_t launch_face_table(const float* obj, int32_t K, float* tab, float* nrm,
                              int32_t* nfaces, hipStream_t st);
 hipError_t launch_validate(int order, const ValidateArgs& A, bool lazy, const int32_t* perm,
@@ -1068,21 +1068,26 @@ extern "C" fpt_status fpt_grad(fpt_handle* h, const fpt_scene* sc,
   A.lds = shmem <= kGradLdsMax ? 1 : 0;
   if (!A.lds) shmem = 0;
   int64_t cap = (pa->N + fpt::kBlock - 1) / fpt::kBlock;
-  auto grid_for = [&](int n) -> int {
-    if (!A.lds) return (int)cap;  // one path per thread
+  // the collapsed-path kernel takes 1024 entries per workgroup and pass
+  const int64_t kkt_cap = (pa->N + 1023) / 1024;
+  auto grid_for = [&](int n, bool kkt) -> int {
+    const int64_t c = kkt ? kkt_cap : cap;
+    if (!A.lds) return (int)c;  // one pass over the paths
+    const void* fn = fpt::grad_kernel_ptr(n, kkt);
+    if (!fn) return 1;
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, fpt::grad_kernel_ptr(n), fpt::kBlock, shmem) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, fpt::kBlock, shmem) !=
+            hipSuccess ||
         occ < 1)
       occ = 1;
     int64_t gsz = (int64_t)h->num_cu * occ;
-    return (int)(gsz < cap ? gsz : cap);
+    return (int)(gsz < c ? gsz : c);
   };
   hipError_t e;
   if (!pa->order) {
     SlotTimer tm(h, FPT_T_GRAD, st);
-    e = fpt::launch_grad(pa->n_max, A, nullptr, nullptr, grid_for(pa->n_max),
-                         shmem, st);
+    e = fpt::launch_grad(pa->n_max, A, nullptr, nullptr, grid_for(pa->n_max, false),
+                         grid_for(pa->n_max, true), shmem, st);
     if (e != hipSuccess) return hip_fail(e, "fpt_grad: launch");
     return FPT_OK;
   }
@@ -1099,8 +1104,9 @@ extern "C" fpt_status fpt_grad(fpt_handle* h, const fpt_scene* sc,
     SlotTimer tm(h, FPT_T_GRAD, st);
     for (int n = 1; n <= pa->n_max; ++n) {
       // persistent grid: the bucket size is only known on the device
-      int grid = A.lds ? grid_for(n) : (int)(cap < (int64_t)h->num_cu * 8 ? cap : (int64_t)h->num_cu * 8);
-      e = fpt::launch_grad(n, A, h->perm, h->bucket, grid, shmem, st);
+      int grid = A.lds ? grid_for(n, false) : (int)(cap < (int64_t)h->num_cu * 8 ? cap : (int64_t)h->num_cu * 8);
+      int kgrid = A.lds ? grid_for(n, true) : (int)(kkt_cap < (int64_t)h->num_cu * 8 ? kkt_cap : (int64_t)h->num_cu * 8);
+      e = fpt::launch_grad(n, A, h->perm, h->bucket, grid, kgrid, shmem, st);
       if (e != hipSuccess) return hip_fail(e, "fpt_grad: launch");
     }
     e = fpt::launch_grad_invalid(A, h->perm, h->bucket, sgrid, st);

@@ -274,4 +274,187 @@ __device__ __forceinline__ bool hess_solve64(const GEO& G, const R (*v)[3], cons
   return ok;
 }
 
+// For the constraint x_{z-1} = x_z at a collapsed minimiser, with segment z
+// left out of H (il[z] = 0, so H splits into two chains at z): the 3x3
+// matrix S = C H^{-1} C^T and the vector r = C H^{-1} w, C v = A_{z-1}
+// v_{z-1} - A_z v_z. One block-Thomas elimination as in hess_solve64, with
+// the three right-hand sides C^T e_k (nonzero at slots z-1 and z only); the
+// back substitution accumulates S and r (r_k = (H^{-1} C^T e_k) . w, H
+// being symmetric) instead of keeping the three solutions.
+// Returns false if a pivot block is not positive definite or a value is not
+// finite.
+template <class GEO, class R = typename GEO::real>
+__device__ __forceinline__ bool hess_schur64(const GEO& G, const R (*v)[3], const R* il,
+                                             const R* w, int z, R (&S)[3][3], R (&r)[3]) {
+  constexpr int NO = GEO::kOrder;
+  R W[NO][4], y[NO][3][2];
+  R pW[4] = {0, 0, 0, 0}, pE[4] = {0, 0, 0, 0}, py[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    R a0[3], a1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a0[c] = G.a(j, 0, c);
+      a1[c] = G.a(j, 1, c);
+    }
+    R pin0 = dot3r(a0, v[j]), pin1 = dot3r(a1, v[j]);
+    R pout0 = dot3r(a0, v[j + 1]), pout1 = dot3r(a1, v[j + 1]);
+    R G00 = dot3r(a0, a0), G01 = dot3r(a0, a1), G11 = dot3r(a1, a1);
+    R D00 = (G00 - pin0 * pin0) * il[j] + (G00 - pout0 * pout0) * il[j + 1];
+    R D01 = (G01 - pin0 * pin1) * il[j] + (G01 - pout0 * pout1) * il[j + 1];
+    R D11 = (G11 - pin1 * pin1) * il[j] + (G11 - pout1 * pout1) * il[j + 1];
+    const R sg = j == z - 1 ? R(1) : (j == z ? R(-1) : R(0));
+    R rh[3][2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      rh[k][0] = sg * a0[k];
+      rh[k][1] = sg * a1[k];
+    }
+    if (G.edge(j)) {
+      D01 = R(0);
+      D11 = R(1);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) rh[k][1] = R(0);
+    }
+    if (G.fixed(j)) {
+      D00 = R(1);
+      D01 = R(0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) rh[k][0] = R(0);
+    }
+    if (j > 0) {
+      D00 -= pE[0] * pW[0] + pE[2] * pW[2];
+      D01 -= pE[0] * pW[1] + pE[2] * pW[3];
+      D11 -= pE[1] * pW[1] + pE[3] * pW[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        rh[k][0] -= pE[0] * py[k][0] + pE[2] * py[k][1];
+        rh[k][1] -= pE[1] * py[k][0] + pE[3] * py[k][1];
+      }
+    }
+    R det = D00 * D11 - D01 * D01;
+    ok = ok && (det > R(0)) && (D00 > R(0)) && isfinite(det);
+    R idet = rcpr(det);
+    const R S0 = D11 * idet, S1 = -D01 * idet, S2 = D00 * idet;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      y[j][k][0] = S0 * rh[k][0] + S1 * rh[k][1];
+      y[j][k][1] = S1 * rh[k][0] + S2 * rh[k][1];
+    }
+    R E[4] = {R(0), R(0), R(0), R(0)};
+    if (j + 1 < NO) {
+      R b0[3], b1[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        b0[c] = G.a(j + 1, 0, c);
+        b1[c] = G.a(j + 1, 1, c);
+      }
+      R qn0 = dot3r(b0, v[j + 1]), qn1 = dot3r(b1, v[j + 1]);
+      R il1 = il[j + 1];
+      E[0] = -(dot3r(a0, b0) - pout0 * qn0) * il1;
+      E[1] = -(dot3r(a0, b1) - pout0 * qn1) * il1;
+      E[2] = -(dot3r(a1, b0) - pout1 * qn0) * il1;
+      E[3] = -(dot3r(a1, b1) - pout1 * qn1) * il1;
+      if (G.edge(j)) E[2] = E[3] = R(0);
+      if (G.edge(j + 1)) E[1] = E[3] = R(0);
+      if (G.fixed(j)) E[0] = E[1] = R(0);
+      if (G.fixed(j + 1)) E[0] = E[2] = R(0);
+    }
+    W[j][0] = S0 * E[0] + S1 * E[2];
+    W[j][1] = S0 * E[1] + S1 * E[3];
+    W[j][2] = S1 * E[0] + S2 * E[2];
+    W[j][3] = S1 * E[1] + S2 * E[3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      pW[k] = W[j][k];
+      pE[k] = E[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      py[k][0] = y[j][k][0];
+      py[k][1] = y[j][k][1];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r[k] = R(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S[c][k] = R(0);
+  }
+  R n[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+  for (int j = NO - 1; j >= 0; --j) {
+    const R sg = j == z - 1 ? R(1) : (j == z ? R(-1) : R(0));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      R d0 = y[j][k][0] - (W[j][0] * n[k][0] + W[j][1] * n[k][1]);
+      R d1 = y[j][k][1] - (W[j][2] * n[k][0] + W[j][3] * n[k][1]);
+      if (G.edge(j)) d1 = R(0);
+      if (G.fixed(j)) d0 = R(0);
+      n[k][0] = d0;
+      n[k][1] = d1;
+      r[k] = fma(d0, w[2 * j], fma(d1, w[2 * j + 1], r[k]));
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        S[c][k] = fma(sg, fma(d1, G.a(j, 1, c), d0 * G.a(j, 0, c)), S[c][k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    ok = ok && isfinite(r[k]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ok = ok && isfinite(S[c][k]);
+  }
+  return ok;
+}
+
+// The collapsed minimisers the implicit gradient covers (Sec. III-D extended
+// to a minimiser with one zero-length segment): at the points x, exactly one
+// segment shorter than sqrt(cs2), an interior one (between slots z - 1 and
+// z), and the two objects' directions span space, so that the subgradient
+// of the zero-length segment, and with it the multiplier of the constraint
+// x_{z-1} = x_z, is unique. Returns z, or -1 (no gradient: several
+// collapses, a point at TX or RX, two edges, or objects whose directions
+// lie in one plane).
+template <class GEO, class R = typename GEO::real>
+__device__ __forceinline__ int single_collapse(const GEO& G, const R (*x)[3], R cs2) {
+  constexpr int NO = GEO::kOrder;
+  int nz = 0, z = -1;
+#pragma unroll
+  for (int i = 0; i <= NO; ++i) {
+    R r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      r[c] = ((i == NO) ? G.rx(c) : x[i][c]) - ((i == 0) ? G.tx(c) : x[i - 1][c]);
+    const bool zi = dot3r(r, r) < cs2;
+    nz += zi ? 1 : 0;
+    z = zi ? i : z;
+  }
+  if (nz != 1 || z <= 0 || z >= NO) return -1;
+  // N = sum of v v^T / |v|^2 over both objects' directions: rank 3 iff they
+  // span space (det 2 sin^2 of the angle between two planes)
+  R N[3][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    const bool in = j == z - 1 || j == z;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      R v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c] = G.a(j, k, c);
+      const R n2 = dot3r(v, v);
+      const R w = (in && n2 > R(0)) ? rcpr(n2) : R(0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) N[c][e] = fma(w * v[c], v[e], N[c][e]);
+    }
+  }
+  const R det = N[0][0] * (N[1][1] * N[2][2] - N[1][2] * N[2][1]) -
+                N[0][1] * (N[1][0] * N[2][2] - N[1][2] * N[2][0]) +
+                N[0][2] * (N[1][0] * N[2][1] - N[1][1] * N[2][0]);
+  return det > R(1e-3) ? z : -1;
+}
+
 }  // namespace fpt

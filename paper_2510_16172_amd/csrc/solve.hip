@@ -1305,7 +1305,11 @@ __device__ __forceinline__ void write_path64(const SolveArgs& A,
     if (minl2 < cs * cs || collapsed) st |= FPT_ST_COLLAPSED;
     if (!finite) st |= FPT_ST_NONFINITE;
   }
-  if (st & (FPT_ST_COLLAPSED | FPT_ST_NONFINITE | FPT_ST_INVALID)) st |= FPT_ST_NOGRAD;
+  // no implicit gradient: invalid, non-finite, or a collapse it does not
+  // cover (single_collapse)
+  if ((st & (FPT_ST_NONFINITE | FPT_ST_INVALID)) ||
+      ((st & FPT_ST_COLLAPSED) && single_collapse(D, xs, 1e-12 * (double)A.scale * (double)A.scale) < 0))
+    st |= FPT_ST_NOGRAD;
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
 #pragma unroll

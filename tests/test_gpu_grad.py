@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import gpu_util
+import pins
 from paper_2510_16172_amd import scenes
 
 pytestmark = pytest.mark.gpu
@@ -75,10 +76,23 @@ def test_grad_vs_oracle_canyon(solver, oracle_mod, n):
     bad = _compare_per_path(b, o, g_slot, g_end, ref, gref, mask, rtol=2e-3)
     print(f"n={n} compared={mask.sum()} bad={bad}", flush=True)
     assert bad <= max(1, int(0.002 * mask.sum()))
-    # skipped paths carry the no-gradient status and contribute exactly zero
-    skip = (o["status"] & (fpt.ST_COLLAPSED | fpt.ST_INVALID | fpt.ST_NONFINITE)) != 0
-    np.testing.assert_array_equal((o["status"] & fpt.ST_NOGRAD) != 0, skip)
-    assert np.all(g_slot[:, :, skip] == 0) and np.all(g_end[:, skip] == 0)
+    # collapsed minimisers with one interior zero-length segment: the
+    # constrained (KKT) gradient, against the oracle's at its solution
+    nograd = (o["status"] & fpt.ST_NOGRAD) != 0
+    kkt = (s["cert"] & col_gpu & ~nograd & s["col"] & (gref["status"] == oracle_mod.KKT))
+    if n >= 2:
+        assert kkt.sum() > 0.5 * (col_gpu & s["cert"]).sum()
+        bad_k = _compare_per_path(b, o, g_slot, g_end, ref, gref, kkt, rtol=2e-3)
+        print(f"n={n} collapsed compared={kkt.sum()} bad={bad_k}", flush=True)
+        assert bad_k <= max(1, int(0.002 * kkt.sum()))
+    # no gradient: invalid and non-finite paths, and collapses the
+    # constrained form does not cover; they contribute exactly zero
+    bad_in = (o["status"] & (fpt.ST_INVALID | fpt.ST_NONFINITE)) != 0
+    assert np.all(nograd[bad_in])
+    assert not np.any(nograd & ~bad_in & ~col_gpu)
+    if n == 1:
+        np.testing.assert_array_equal(nograd, bad_in | col_gpu)
+    assert np.all(g_slot[:, :, nograd] == 0) and np.all(g_end[:, nograd] == 0)
 
 
 def test_grad_reduction_matches_per_path_sum(solver):
@@ -162,6 +176,39 @@ def test_grad_vs_finite_differences(solver, oracle_mod):
         np.testing.assert_allclose(got, want, atol=2e-3 * scale)
         checked += 1
     assert checked >= 50
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_collapsed_grad_vs_finite_differences(solver, oracle_mod, n):
+    """Collapsed minimisers (one interior zero-length segment, stable under
+    perturbation): the GPU gradient against central differences of the FP64
+    oracle's solve, over all inputs of each path."""
+    import test_oracle_pins as T
+    paths, S = T.stable_single_collapses(oracle_mod, n, 48, seed=5500 + n)
+    assert len(paths) >= 24
+    b = pins.batch_from_paths(paths, S=S)
+    g_len, g_x = scenes.upstream_grads(b.N, b.n_max, seed=5501)
+    o, g_slot, g_end, g_pts, g_obj = _fwd_grad(solver, b, g_len, g_x)
+    gl = g_len.astype(np.float64)
+    gx = np.transpose(g_x, (2, 0, 1)).astype(np.float64)
+    h = 2.0 ** -10
+    d1 = T._fd_grad(oracle_mod, b, gl, gx, h)
+    d2 = T._fd_grad(oracle_mod, b, gl, gx, h / 2)
+    fd_tx, fd_rx, fd_obj = [(4.0 * y - x) / 3.0 for x, y in zip(d1, d2)]
+    from paper_2510_16172_amd import fpt
+    st = o["status"]
+    cert = (st & fpt.ST_CONVERGED) != 0
+    has = cert & ((st & fpt.ST_COLLAPSED) != 0) & ((st & fpt.ST_NOGRAD) == 0)
+    assert has.mean() > 0.8
+    for i in np.nonzero(has)[0]:
+        want = np.concatenate([fd_tx[i], fd_rx[i], fd_obj[i].ravel()])
+        got = np.concatenate([g_pts[:, b.src[i]], g_pts[:, b.dst[i]],
+                              np.stack([g_obj[:, b.ids[j, i]] for j in range(n)]).ravel()])
+        for j in range(n):
+            if np.all(b.obj[6:9, b.ids[j, i]] == 0):
+                want[6 + 9 * j + 6: 6 + 9 * j + 9] = 0.0
+        scale = 1.0 + np.abs(want).max()
+        np.testing.assert_allclose(got, want, atol=2e-3 * scale)
 
 
 def test_autograd_function(solver, oracle_mod):

@@ -332,6 +332,77 @@ def test_gradient_vs_finite_differences(oracle_mod, n):
             np.testing.assert_allclose(ga[i, j], want, atol=2e-5 * scale)
 
 
+def stable_single_collapses(oracle_mod, n, count, seed, wmax=0.9):
+    """Canyon paths of order n whose oracle minimiser has exactly one
+    zero-length segment, an interior one, with a subgradient of norm below
+    wmax (so that the minimiser stays collapsed under small perturbations),
+    each returned as its own geometry (tx, rx, objs)."""
+    sc = scenes.canyon_scene()
+    b0 = scenes.canyon_sample_paths(sc, 4000, seed=seed, n=n)
+    r0 = oracle_mod.solve(b0, threads=4)  # (unconverged paths skipped below)
+    out = []
+    for i in np.nonzero((r0["flags"] & oracle_mod.COLLAPSED) != 0)[0]:
+        if r0["flags"][i] & (oracle_mod.NOCONV | oracle_mod.INVALID):
+            continue
+        tx, rx, objs = pins.path_geometry(b0, int(i))
+        xs = np.vstack([tx, r0["x"][i, :n], rx])
+        runs, ell = pins.collapse_runs(xs, b0.S)
+        if ell[0] < 1e-6 * b0.S or ell[n] < 1e-6 * b0.S:
+            continue
+        long_runs = [rn for rn in runs if len(rn) > 1]
+        if len(long_runs) != 1 or len(long_runs[0]) != 2:
+            continue
+        a, bb = long_runs[0]
+        u = np.diff(xs, axis=0) / ell[:, None]
+        _, res, wm = pins.run_subgradient([objs[a], objs[bb]], u[a], u[bb + 1])
+        # directions that do not span space (two edges, an edge in a face's
+        # plane) leave the multiplier undetermined: not covered
+        dirs = [v / np.linalg.norm(v) for k in (a, bb) for v in objs[k][1:]
+                if np.any(v != 0)]
+        if np.linalg.det(sum(np.outer(v, v) for v in dirs)) <= 1e-3:
+            continue
+        if wm < wmax and res < 1e-6:
+            out.append((tx, rx, objs))
+        if len(out) == count:
+            break
+    return out, b0.S
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_collapsed_gradient_vs_finite_differences(oracle_mod, n):
+    """The constrained (KKT) gradient at a minimiser with one interior
+    zero-length segment against central differences of the oracle's own
+    solve (Richardson-extrapolated), over all inputs of each path."""
+    paths, S = stable_single_collapses(oracle_mod, n, 24, seed=95 + n)
+    assert len(paths) >= 12
+    b = pins.batch_from_paths(paths, S=S)
+    r = _solve(oracle_mod, b)
+    rng = np.random.default_rng(96)
+    gl = rng.standard_normal(b.N)
+    gx = rng.standard_normal((b.N, n, 3))
+    g = oracle_mod.grad(b, r["t"], gl, gx, threads=4)
+    kkt = g["status"] == oracle_mod.KKT
+    assert kkt.sum() >= len(paths) - 1
+    h = 2.0 ** -10
+    d1 = _fd_grad(oracle_mod, b, gl, gx, h)
+    d2 = _fd_grad(oracle_mod, b, gl, gx, h / 2)
+    fd_tx, fd_rx, fd_obj = [(4.0 * b2 - b1) / 3.0 for b1, b2 in zip(d1, d2)]
+    edge = np.stack([np.all(b.obj[6:9, b.ids[j]] == 0, axis=0)
+                     for j in range(n)], 1)
+    ga = g["g_a"].reshape(b.N, n, 6)
+    for i in np.nonzero(kkt)[0]:
+        scale = 1.0 + np.abs(fd_obj[i]).max()
+        np.testing.assert_allclose(g["g_tx"][i], fd_tx[i], atol=1e-7 * scale)
+        np.testing.assert_allclose(g["g_rx"][i], fd_rx[i], atol=1e-7 * scale)
+        np.testing.assert_allclose(g["g_b"][i], fd_obj[i, :, 0:3],
+                                   atol=1e-7 * scale)
+        for j in range(n):
+            want = fd_obj[i, j, 3:9].copy()
+            if edge[i, j]:
+                want[3:] = 0.0
+            np.testing.assert_allclose(ga[i, j], want, atol=1e-7 * scale)
+
+
 def test_gradient_structure(oracle_mod):
     """A_j^T g_b_j = 0: moving an object within its own span leaves the
     solution unchanged; with g_x = 0 the gradient is the envelope term."""
