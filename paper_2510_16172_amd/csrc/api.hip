@@ -15,9 +15,13 @@ hipError_t launch_solve(int phase, int order, const SolveArgs& A,
                         const StageArgs* stage, int grid, hipStream_t st);
 int stage_fields_for(int order);
 const void* solve_kernel_ptr(int phase, int order);
+// bucket[n-1] .. bucket[n]: order n; bucket[n_max] .. bucket[n_max+1]:
+// invalid orders; with status, bucket[n_max+1] .. bucket[n_max+2]: the
+// collapsed minimisers with a gradient (orders >= 2, any order)
 hipError_t launch_bucketing(const uint8_t* order, int64_t N, int n_max,
                             uint32_t* ccount, int64_t* bucket, int32_t* perm,
-                            hipStream_t st, int32_t* inv = nullptr);
+                            hipStream_t st, int32_t* inv = nullptr,
+                            const uint8_t* status = nullptr);
 hipError_t launch_invalid(const SolveArgs& A, const int32_t* perm,
                           const int64_t* bucket, int grid, hipStream_t st);
 hipError_t launch_unsort(const SolveArgs& S, const SolveArgs& A, const int32_t* inv,
@@ -1097,7 +1101,7 @@ extern "C" fpt_status fpt_grad(fpt_handle* h, const fpt_scene* sc,
   {
     SlotTimer tm(h, FPT_T_BUCKET, st);
     e = fpt::launch_bucketing(pa->order, pa->N, pa->n_max, h->ccount,
-                              h->bucket, h->perm, st);
+                              h->bucket, h->perm, st, nullptr, fwd->status);
     if (e != hipSuccess) return hip_fail(e, "fpt_grad: bucketing launch");
   }
   {

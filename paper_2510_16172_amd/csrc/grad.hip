@@ -184,22 +184,13 @@ __device__ __forceinline__ void grad_path(const GradArgs& A, int64_t p, uint8_t 
     w[2 * j] = G.a(j, 0, 0) * gx[j][0] + G.a(j, 0, 1) * gx[j][1] + G.a(j, 0, 2) * gx[j][2];
     w[2 * j + 1] = G.a(j, 1, 0) * gx[j][0] + G.a(j, 1, 1) * gx[j][1] + G.a(j, 1, 2) * gx[j][2];
   }
-  double nu[3] = {0.0, 0.0, 0.0};
-  if (col) {
-    // the constraint's Schur complement S = C H_s^{-1} C^T and C lam0 =
-    // C H_s^{-1} w_T; then lam = H_s^{-1} (w_T - C^T nu) below.
-    double S[3][3], rn[3];
-    use = use && hess_schur64(G, u, il, w, z, S, rn);
-    use = use && solve3(S, rn, nu);
-#pragma unroll
-    for (int j = 0; j < NO; ++j) {
-      const double sg = j == z - 1 ? 1.0 : (j == z ? -1.0 : 0.0);
-      w[2 * j] -= sg * (G.a(j, 0, 0) * nu[0] + G.a(j, 0, 1) * nu[1] + G.a(j, 0, 2) * nu[2]);
-      w[2 * j + 1] -= sg * (G.a(j, 1, 0) * nu[0] + G.a(j, 1, 1) * nu[1] + G.a(j, 1, 2) * nu[2]);
-    }
-  }
-  double lam[2 * NO];
-  bool ok = hess_solve64(G, u, il, w, lam);
+  // (the solve runs on every lane: no branch around it)
+  double lam[2 * NO], nu[3] = {0.0, 0.0, 0.0};
+  bool ok;
+  if constexpr (KKT)
+    ok = kkt_solve64(G, u, il, w, z, lam, nu);
+  else
+    ok = hess_solve64(G, u, il, w, lam);
   use = use && ok;
   // c_i = P_i delta_i for every segment
   double cseg[NO + 1][3];
@@ -288,10 +279,11 @@ __device__ __forceinline__ void run_kkt_list(const GradArgs& A, const int32_t* _
     for (int64_t i = threadIdx.x; i < nsh; i += kBlock) sh[i] = 0.0;
   double* s_obj = sh;
   double* s_pts = sh + 9 * (int64_t)A.K;
+  // (bucketed: the bin of the collapsed minimisers of every order)
   int64_t begin = 0, count = A.N;
   if (bucket) {
-    begin = bucket[NO - 1];
-    count = bucket[NO] - begin;
+    begin = bucket[A.n_max + 1];
+    count = bucket[A.n_max + 2] - begin;
   }
   const int lane = threadIdx.x & 63;
   if (threadIdx.x == 0) n_list = 0;
@@ -305,7 +297,7 @@ __device__ __forceinline__ void run_kkt_list(const GradArgs& A, const int32_t* _
       bool take = false;
       if (idx < count) {
         p = perm ? (int64_t)perm[begin + idx] : idx;
-        take = kkt_path(A.status[p]);
+        take = kkt_path(A.status[p]) && (!A.order || (int)A.order[p] == NO);
       }
       const uint64_t m = __ballot(take);
       int at = 0;

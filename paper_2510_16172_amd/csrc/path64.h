@@ -274,21 +274,26 @@ __device__ __forceinline__ bool hess_solve64(const GEO& G, const R (*v)[3], cons
   return ok;
 }
 
-// For the constraint x_{z-1} = x_z at a collapsed minimiser, with segment z
-// left out of H (il[z] = 0, so H splits into two chains at z): the 3x3
-// matrix S = C H^{-1} C^T and the vector r = C H^{-1} w, C v = A_{z-1}
-// v_{z-1} - A_z v_z. One block-Thomas elimination as in hess_solve64, with
-// the three right-hand sides C^T e_k (nonzero at slots z-1 and z only); the
-// back substitution accumulates S and r (r_k = (H^{-1} C^T e_k) . w, H
-// being symmetric) instead of keeping the three solutions.
-// Returns false if a pivot block is not positive definite or a value is not
-// finite.
+// The KKT system of a collapsed minimiser, [H C^T; C 0] [lam; nu] = [w; 0],
+// for the constraint x_{z-1} = x_z (C v = A_{z-1} v_{z-1} - A_z v_z), with
+// segment z left out of H (il[z] = 0, so H splits into two chains at z).
+// One block-Thomas forward elimination as in hess_solve64 carries four
+// right-hand sides: w and the three columns C^T e_k (nonzero at slots z-1
+// and z only). A first back substitution of the three columns accumulates
+// the Schur complement S = C H^{-1} C^T and r = C H^{-1} w (r_k =
+// (H^{-1} C^T e_k) . w, H being symmetric) without keeping the solutions;
+// nu = S^{-1} r. The forward results are linear in the right-hand side, so
+// the second back substitution starts from y_w - sum_k nu_k y_k and gives
+// lam = H^{-1} (w - C^T nu) directly.
+// Returns false if a pivot block is not positive definite, S is singular or
+// a value is not finite.
 template <class GEO, class R = typename GEO::real>
-__device__ __forceinline__ bool hess_schur64(const GEO& G, const R (*v)[3], const R* il,
-                                             const R* w, int z, R (&S)[3][3], R (&r)[3]) {
+__device__ __forceinline__ bool kkt_solve64(const GEO& G, const R (*v)[3], const R* il,
+                                            const R* w, int z, R* lam, R (&nu)[3]) {
   constexpr int NO = GEO::kOrder;
-  R W[NO][4], y[NO][3][2];
-  R pW[4] = {0, 0, 0, 0}, pE[4] = {0, 0, 0, 0}, py[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  R W[NO][4], y[NO][4][2];  // right-hand sides: 0..2 the columns, 3 w
+  R pW[4] = {0, 0, 0, 0}, pE[4] = {0, 0, 0, 0};
+  R py[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
@@ -305,30 +310,32 @@ __device__ __forceinline__ bool hess_schur64(const GEO& G, const R (*v)[3], cons
     R D01 = (G01 - pin0 * pin1) * il[j] + (G01 - pout0 * pout1) * il[j + 1];
     R D11 = (G11 - pin1 * pin1) * il[j] + (G11 - pout1 * pout1) * il[j + 1];
     const R sg = j == z - 1 ? R(1) : (j == z ? R(-1) : R(0));
-    R rh[3][2];
+    R rh[4][2];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       rh[k][0] = sg * a0[k];
       rh[k][1] = sg * a1[k];
     }
+    rh[3][0] = w[2 * j];
+    rh[3][1] = w[2 * j + 1];
     if (G.edge(j)) {
       D01 = R(0);
       D11 = R(1);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) rh[k][1] = R(0);
+      for (int k = 0; k < 4; ++k) rh[k][1] = R(0);
     }
     if (G.fixed(j)) {
       D00 = R(1);
       D01 = R(0);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) rh[k][0] = R(0);
+      for (int k = 0; k < 4; ++k) rh[k][0] = R(0);
     }
     if (j > 0) {
       D00 -= pE[0] * pW[0] + pE[2] * pW[2];
       D01 -= pE[0] * pW[1] + pE[2] * pW[3];
       D11 -= pE[1] * pW[1] + pE[3] * pW[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < 4; ++k) {
         rh[k][0] -= pE[0] * py[k][0] + pE[2] * py[k][1];
         rh[k][1] -= pE[1] * py[k][0] + pE[3] * py[k][1];
       }
@@ -338,7 +345,7 @@ __device__ __forceinline__ bool hess_schur64(const GEO& G, const R (*v)[3], cons
     R idet = rcpr(det);
     const R S0 = D11 * idet, S1 = -D01 * idet, S2 = D00 * idet;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
       y[j][k][0] = S0 * rh[k][0] + S1 * rh[k][1];
       y[j][k][1] = S1 * rh[k][0] + S2 * rh[k][1];
     }
@@ -369,13 +376,12 @@ __device__ __forceinline__ bool hess_schur64(const GEO& G, const R (*v)[3], cons
     for (int k = 0; k < 4; ++k) {
       pW[k] = W[j][k];
       pE[k] = E[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
       py[k][0] = y[j][k][0];
       py[k][1] = y[j][k][1];
     }
   }
+  // the three columns: S and r
+  R S[3][3], r[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     r[k] = R(0);
@@ -400,13 +406,42 @@ __device__ __forceinline__ bool hess_schur64(const GEO& G, const R (*v)[3], cons
         S[c][k] = fma(sg, fma(d1, G.a(j, 1, c), d0 * G.a(j, 0, c)), S[c][k]);
     }
   }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    ok = ok && isfinite(r[k]);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ok = ok && isfinite(S[c][k]);
+  // nu = S^{-1} r (adjugate; S is symmetric positive definite)
+  {
+    const R c00 = S[1][1] * S[2][2] - S[1][2] * S[2][1];
+    const R c01 = S[1][2] * S[2][0] - S[1][0] * S[2][2];
+    const R c02 = S[1][0] * S[2][1] - S[1][1] * S[2][0];
+    const R det = S[0][0] * c00 + S[0][1] * c01 + S[0][2] * c02;
+    ok = ok && fabs(det) > R(0) && isfinite(det);
+    const R id = rcpr(det);
+    const R i01 = (S[0][2] * S[2][1] - S[0][1] * S[2][2]);
+    const R i02 = (S[0][1] * S[1][2] - S[0][2] * S[1][1]);
+    const R i11 = (S[0][0] * S[2][2] - S[0][2] * S[2][0]);
+    const R i12 = (S[0][2] * S[1][0] - S[0][0] * S[1][2]);
+    const R i21 = (S[0][1] * S[2][0] - S[0][0] * S[2][1]);
+    const R i22 = (S[0][0] * S[1][1] - S[0][1] * S[1][0]);
+    nu[0] = (c00 * r[0] + i01 * r[1] + i02 * r[2]) * id;
+    nu[1] = (c01 * r[0] + i11 * r[1] + i12 * r[2]) * id;
+    nu[2] = (c02 * r[0] + i21 * r[1] + i22 * r[2]) * id;
   }
-  return ok;
+  // lam = H^{-1} (w - C^T nu): the same back substitution from the
+  // combined forward results
+  R m0 = R(0), m1 = R(0);
+#pragma unroll
+  for (int j = NO - 1; j >= 0; --j) {
+    const R y0 = y[j][3][0] - (nu[0] * y[j][0][0] + nu[1] * y[j][1][0] + nu[2] * y[j][2][0]);
+    const R y1 = y[j][3][1] - (nu[0] * y[j][0][1] + nu[1] * y[j][1][1] + nu[2] * y[j][2][1]);
+    R d0 = y0 - (W[j][0] * m0 + W[j][1] * m1);
+    R d1 = y1 - (W[j][2] * m0 + W[j][3] * m1);
+    if (G.edge(j)) d1 = R(0);
+    if (G.fixed(j)) d0 = R(0);
+    lam[2 * j] = d0;
+    lam[2 * j + 1] = d1;
+    m0 = d0;
+    m1 = d1;
+    ok = ok && isfinite(d0) && isfinite(d1);
+  }
+  return ok && isfinite(nu[0]) && isfinite(nu[1]) && isfinite(nu[2]);
 }
 
 // The collapsed minimisers the implicit gradient covers (Sec. III-D extended

@@ -2096,25 +2096,45 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St
 constexpr int kSortPer = kSortChunk / kBlock;  // paths per thread
 static_assert(kSortPer == 32, "two 16-byte loads per thread");
 
-// Bins of this thread's paths: 1..n_max, 0 for an invalid order, -1 past
-// the end of the chunk.
-__device__ __forceinline__ void sort_bins(const uint8_t* __restrict__ order, int64_t base,
-                                          int64_t c1, int n_max, int (&bins)[kSortPer]) {
-  uint8_t o[kSortPer];
-  if (base + kSortPer <= c1 && (((uintptr_t)(order + base)) & 15) == 0) {
-    const uint4 v0 = *reinterpret_cast<const uint4*>(order + base);
-    const uint4 v1 = *reinterpret_cast<const uint4*>(order + base + 16);
+// A thread's 32 consecutive bytes of a per-path byte array (two 16-byte
+// loads where aligned; zero past the end).
+__device__ __forceinline__ void load32_bytes(const uint8_t* __restrict__ a, int64_t base,
+                                             int64_t c1, uint8_t (&o)[kSortPer]) {
+  if (base + kSortPer <= c1 && (((uintptr_t)(a + base)) & 15) == 0) {
+    const uint4 v0 = *reinterpret_cast<const uint4*>(a + base);
+    const uint4 v1 = *reinterpret_cast<const uint4*>(a + base + 16);
     const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
     for (int q = 0; q < kSortPer; ++q) o[q] = (uint8_t)(w[q >> 2] >> (8 * (q & 3)));
   } else {
 #pragma unroll
-    for (int q = 0; q < kSortPer; ++q) o[q] = (base + q < c1) ? order[base + q] : 0;
+    for (int q = 0; q < kSortPer; ++q) o[q] = (base + q < c1) ? a[base + q] : 0;
   }
+}
+
+// Bins of this thread's paths: 1..n_max, 0 for an invalid order, -1 past
+// the end of the chunk. With a status array (the backward pass), bin 7
+// takes the collapsed minimisers of orders >= 2 that carry a gradient
+// (FPT_ST_COLLAPSED without FPT_ST_NOGRAD), which the backward pass
+// differentiates in a kernel of their own.
+__device__ __forceinline__ void sort_bins(const uint8_t* __restrict__ order,
+                                          const uint8_t* __restrict__ status, int64_t base,
+                                          int64_t c1, int n_max, int (&bins)[kSortPer]) {
+  uint8_t o[kSortPer];
+  load32_bytes(order, base, c1, o);
 #pragma unroll
   for (int q = 0; q < kSortPer; ++q) {
     const int b = (o[q] >= 1 && o[q] <= n_max) ? (int)o[q] : 0;
     bins[q] = (base + q < c1) ? b : -1;
+  }
+  if (status) {
+    uint8_t st[kSortPer];
+    load32_bytes(status, base, c1, st);
+#pragma unroll
+    for (int q = 0; q < kSortPer; ++q) {
+      const bool kkt = (st[q] & FPT_ST_COLLAPSED) && !(st[q] & FPT_ST_NOGRAD);
+      bins[q] = (kkt && bins[q] >= 2) ? 7 : bins[q];
+    }
   }
 }
 
@@ -2137,14 +2157,14 @@ __device__ __forceinline__ void bin_counts(const int (&bins)[kSortPer],
 }
 
 __global__ __launch_bounds__(kBlock) void bucket_count_kernel(
-    const uint8_t* __restrict__ order, int64_t N, int n_max,
-    uint32_t* __restrict__ ccount) {
+    const uint8_t* __restrict__ order, const uint8_t* __restrict__ status, int64_t N,
+    int n_max, uint32_t* __restrict__ ccount) {
   __shared__ uint32_t wsum[kBlock / 64][8];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
   const int64_t c1 = min(N, c0 + (int64_t)kSortChunk);
   int bins[kSortPer];
-  sort_bins(order, c0 + (int64_t)threadIdx.x * kSortPer, c1, n_max, bins);
+  sort_bins(order, status, c0 + (int64_t)threadIdx.x * kSortPer, c1, n_max, bins);
   uint32_t cnt[8];
   bin_counts(bins, cnt);
 #pragma unroll
@@ -2217,6 +2237,9 @@ __global__ __launch_bounds__(kBlock) void bucket_scan_kernel(
     start[0] = acc;
     acc += part[cur][kBlock - 1][0];
     bucket[n_max + 1] = (int64_t)acc;
+    start[7] = acc;  // (bin 7: backward pass only, empty otherwise)
+    acc += part[cur][kBlock - 1][7];
+    bucket[n_max + 2] = (int64_t)acc;
   }
   __syncthreads();
   unsigned long long run[8];
@@ -2250,7 +2273,7 @@ __global__ __launch_bounds__(kBlock) void bucket_scan_kernel(
 __device__ __forceinline__ int sort_skew(int i) { return i + (i >> 5); }
 
 __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
-    const uint8_t* __restrict__ order, int64_t N, int n_max,
+    const uint8_t* __restrict__ order, const uint8_t* __restrict__ status, int64_t N, int n_max,
     const uint32_t* __restrict__ coff, int32_t* __restrict__ perm,
     int32_t* __restrict__ inv) {
   __shared__ uint32_t wtot[kBlock / 64][8];
@@ -2263,7 +2286,7 @@ __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
   const int64_t c1 = min(N, c0 + (int64_t)kSortChunk);
   const int64_t base = c0 + (int64_t)threadIdx.x * kSortPer;
   int bins[kSortPer];
-  sort_bins(order, base, c1, n_max, bins);
+  sort_bins(order, status, base, c1, n_max, bins);
   uint32_t cnt[8], incl[8];
   bin_counts(bins, cnt);
 #pragma unroll
@@ -2553,14 +2576,14 @@ const void* solve_kernel_ptr(int phase, int order) {
 
 hipError_t launch_bucketing(const uint8_t* order, int64_t N, int n_max,
                             uint32_t* ccount, int64_t* bucket, int32_t* perm,
-                            hipStream_t st, int32_t* inv) {
+                            hipStream_t st, int32_t* inv, const uint8_t* status) {
   const int64_t nchunks = (N + kSortChunk - 1) / kSortChunk;
   hipLaunchKernelGGL(bucket_count_kernel, dim3((unsigned)nchunks), dim3(kBlock), 0, st,
-                     order, N, n_max, ccount);
+                     order, status, N, n_max, ccount);
   hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(kBlock), 0, st, ccount,
                      nchunks, n_max, bucket);
   hipLaunchKernelGGL(bucket_scatter_kernel, dim3((unsigned)nchunks), dim3(kBlock), 0, st,
-                     order, N, n_max, ccount, perm, inv);
+                     order, status, N, n_max, ccount, perm, inv);
   return hipGetLastError();
 }
 
