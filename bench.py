@@ -158,9 +158,11 @@ def refine_final_flops(n: int) -> int:
 
 
 def grad_bytes_per_path(n: int) -> int:
-    """Algorithmic HBM bytes of grad_kernel<n> per path: reads T* (8n),
-    status (1), g_len (4), g_x (12n), src/dst (8), ids (4n); the scene
-    tables and the reduced gradient stay in cache / LDS."""
+    """Algorithmic HBM bytes of the gradient pass of order n per path
+    (grad_kernel<n> for smooth minimisers, grad_kkt_kernel<n> for collapsed
+    ones): reads T* (8n), status (1), g_len (4), g_x (12n), src/dst (8),
+    ids (4n); the scene tables and the reduced gradient stay in cache /
+    LDS."""
     return 8 * n + 1 + 4 + 12 * n + 8 + 4 * n
 
 
@@ -215,7 +217,7 @@ def run_fwd_grad(args, fpt, scenes, torch):
                      & ((out["status"] & fpt.ST_NOGRAD) == 0)).sum().item())
     nograd = float(((out["status"] & fpt.ST_NOGRAD) != 0).float().mean().item())
     tg_kernel = kt[fpt.T_GRAD]
-    cg = read_counters("grad_kernel_3", "canyon_c4", "grad")
+    cg = read_counters("grad_kernels_3", "canyon_c4", "grad")
     res = {
         "workload": "street canyon: 1,048,576 sampled order-3 paths, "
                     "upstream gradients N(0,1)",
@@ -227,7 +229,7 @@ def run_fwd_grad(args, fpt, scenes, torch):
         "converged_paths_per_s_fwd_grad": cert_grad / ((t_f + t_g) * 1e-3),
         "certified_paths_per_s_fwd_grad_incl_no_gradient": cert / ((t_f + t_g) * 1e-3),
         "grad_roofline": {
-            "kernel": "grad_kernel<3>", "bound": "hbm",
+            "kernel": "grad_kernel<3> + grad_kkt_kernel<3>", "bound": "hbm",
             "achieved": grad_bytes_per_path(3) * b.N / (tg_kernel * 1e-3) / 1e9,
             "peak": PEAK_HBM / 1e9, "unit": "GB/s",
             "frac": grad_bytes_per_path(3) * b.N / (tg_kernel * 1e-3) / PEAK_HBM,
