@@ -75,6 +75,59 @@ __device__ __forceinline__ void acc_add(double* lds_base, float* glob, int64_t i
     unsafeAtomicAdd(glob + idx, v);
 }
 
+// Geometry of one lane in FP32 registers (the scene's values, exact in
+// FP64), widened at each use: the empty asm hides the value from the
+// compiler, so that every use converts again instead of FP64 copies staying
+// live through the kernel. The same holds the path's T* and g_X in FP32.
+// At three slots the kernel needs 145 VGPRs instead of 168; at six, 247
+// instead of 256 plus spills, two waves per SIMD instead of one.
+__device__ __forceinline__ double widen(float v) {
+  asm volatile("" : "+v"(v));
+  return (double)v;
+}
+
+template <int NO>
+struct GeoF32 {
+  static constexpr int kOrder = NO;
+  using real = double;
+  float tx_[3], rx_[3], b_[NO][3], a_[NO][2][3];
+  bool edge_[NO];
+  __device__ __forceinline__ double tx(int c) const { return widen(tx_[c]); }
+  __device__ __forceinline__ double rx(int c) const { return widen(rx_[c]); }
+  __device__ __forceinline__ double b(int j, int c) const { return widen(b_[j][c]); }
+  __device__ __forceinline__ double a(int j, int k, int c) const { return widen(a_[j][k][c]); }
+  __device__ __forceinline__ bool edge(int j) const { return edge_[j]; }
+  __device__ __forceinline__ bool fixed(int) const { return false; }
+};
+
+template <int NO>
+__device__ __forceinline__ void load_geo_f32(const GradArgs& A, int32_t s, int32_t e,
+                                             int64_t p, GeoF32<NO>& D) {
+  s = (s >= 0 && s < A.Q) ? s : 0;
+  e = (e >= 0 && e < A.Q) ? e : 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    D.tx_[c] = A.pts[(int64_t)c * A.Q + s];
+    D.rx_[c] = A.pts[(int64_t)c * A.Q + e];
+  }
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    int32_t k = A.ids[(int64_t)j * A.N + p];
+    k = (k >= 0 && k < A.K) ? k : 0;
+    float a2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      D.b_[j][c] = A.obj[(int64_t)c * A.K + k];
+      D.a_[j][0][c] = A.obj[(int64_t)(3 + c) * A.K + k];
+      a2[c] = A.obj[(int64_t)(6 + c) * A.K + k];
+    }
+    const bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
+    D.edge_[j] = edge;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) D.a_[j][1][c] = edge ? 0.f : a2[c];
+  }
+}
+
 // A collapsed minimiser that carries a gradient (the forward pass leaves
 // FPT_ST_NOGRAD off only for the collapses single_collapse covers).
 __device__ __forceinline__ bool kkt_path(uint8_t st) {
@@ -109,17 +162,20 @@ __device__ __forceinline__ void grad_path(const GradArgs& A, int64_t p, uint8_t 
     kid[j] = A.ids[(int64_t)j * A.N + p];
     use = use && kid[j] >= 0 && kid[j] < A.K;
   }
-  Geo64<NO> G;
-  load_geo64<NO>(A.obj, A.pts, A.ids, s, e, A.K, A.Q, A.N, p, G);
-  double t[2 * NO];
+  GeoF32<NO> G;
+  load_geo_f32<NO>(A, s, e, p, G);
+  float tf[2 * NO];
 #pragma unroll
   for (int k = 0; k < 2 * NO; ++k) {
-    t[k] = (double)A.t[(int64_t)k * A.N + p];
-    use = use && isfinite(t[k]);
+    tf[k] = A.t[(int64_t)k * A.N + p];
+    use = use && isfinite(tf[k]);
   }
 #pragma unroll
   for (int j = 0; j < NO; ++j)
-    if (G.edge(j)) t[2 * j + 1] = 0.0;
+    if (G.edge(j)) tf[2 * j + 1] = 0.f;
+  double t[2 * NO];
+#pragma unroll
+  for (int k = 0; k < 2 * NO; ++k) t[k] = (double)tf[k];
   double u[NO + 1][3], il[NO + 1];
   segments64(G, t, 0.0, u, il);
   // a collapsed minimiser (one zero-length interior segment z): w in place
@@ -175,14 +231,15 @@ __device__ __forceinline__ void grad_path(const GradArgs& A, int64_t p, uint8_t 
     }
   }
   const double gl = A.g_len ? (double)A.g_len[p] : 0.0;
-  double gx[NO][3], w[2 * NO];
+  float gx[NO][3];
+  double w[2 * NO];
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      gx[j][c] = A.g_x ? (double)A.g_x[(int64_t)(3 * j + c) * A.N + p] : 0.0;
-    w[2 * j] = G.a(j, 0, 0) * gx[j][0] + G.a(j, 0, 1) * gx[j][1] + G.a(j, 0, 2) * gx[j][2];
-    w[2 * j + 1] = G.a(j, 1, 0) * gx[j][0] + G.a(j, 1, 1) * gx[j][1] + G.a(j, 1, 2) * gx[j][2];
+      gx[j][c] = A.g_x ? A.g_x[(int64_t)(3 * j + c) * A.N + p] : 0.f;
+    w[2 * j] = G.a(j, 0, 0) * widen(gx[j][0]) + G.a(j, 0, 1) * widen(gx[j][1]) + G.a(j, 0, 2) * widen(gx[j][2]);
+    w[2 * j + 1] = G.a(j, 1, 0) * widen(gx[j][0]) + G.a(j, 1, 1) * widen(gx[j][1]) + G.a(j, 1, 2) * widen(gx[j][2]);
   }
   // (the solve runs on every lane: no branch around it)
   double lam[2 * NO], nu[3] = {0.0, 0.0, 0.0};
@@ -232,7 +289,7 @@ __device__ __forceinline__ void grad_path(const GradArgs& A, int64_t p, uint8_t 
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       du[c] = u[j][c] - u[j + 1][c];
-      gb[c] = gl * du[c] + gx[j][c] - (cseg[j][c] - cseg[j + 1][c]);
+      gb[c] = gl * du[c] + widen(gx[j][c]) - (cseg[j][c] - cseg[j + 1][c]);
       // -nu . dc/db: c = x_{z-1} - x_z
       gb[c] += (j == z - 1) ? -nu[c] : ((j == z) ? nu[c] : 0.0);
     }
@@ -240,9 +297,9 @@ __device__ __forceinline__ void grad_path(const GradArgs& A, int64_t p, uint8_t 
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       val[c] = (float)gb[c];
-      val[3 + c] = (float)(t[2 * j] * gb[c] - lam[2 * j] * du[c]);
+      val[3 + c] = (float)(widen(tf[2 * j]) * gb[c] - lam[2 * j] * du[c]);
       val[6 + c] = G.edge(j) ? 0.f
-                             : (float)(t[2 * j + 1] * gb[c] - lam[2 * j + 1] * du[c]);
+                             : (float)(widen(tf[2 * j + 1]) * gb[c] - lam[2 * j + 1] * du[c]);
     }
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
@@ -328,8 +385,8 @@ __device__ __forceinline__ void run_kkt_list(const GradArgs& A, const int32_t* _
   if (LDS) flush_tables(A, sh);
 }
 
-// (three slots: the compiler's register choice lands two VGPRs above what
-// three waves per SIMD allow; asked for three it fits them without spilling)
+// (three slots: asked for three waves per SIMD, the compiler stays within
+// their 168 VGPRs)
 template <int NO, bool LDS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NO == 3 ? 3 : 1)))
 void grad_kernel(GradArgs A, const int32_t* __restrict__ perm,
