@@ -5,8 +5,11 @@ Backward: the implicit-differentiation kernel (Sec. III-D, Eqs. 8-13): one
 block-tridiagonal Hessian solve per path, no unrolled iterations. Gradients
 flow to the endpoint table ``pts [3][Q]`` and the object table
 ``obj [9][K]`` (rows b, a1, a2); ids, order, src and dst are not
-differentiable. Paths flagged COLLAPSED / INVALID / NONFINITE contribute no
-gradient (the Hessian is singular or undefined there).
+differentiable. A collapsed minimiser with one interior zero-length
+segment is differentiated as the minimiser of the length without that
+segment under the constraint that its two points coincide (the implicit
+function theorem on that problem's KKT conditions). Paths flagged NOGRAD
+(invalid, non-finite, or any other collapse) contribute no gradient.
 """
 from __future__ import annotations
 

@@ -95,6 +95,33 @@ def test_grad_vs_oracle_canyon(solver, oracle_mod, n):
     assert np.all(g_slot[:, :, nograd] == 0) and np.all(g_end[:, nograd] == 0)
 
 
+def test_grad_vs_oracle_mixed_orders(solver, oracle_mod):
+    """Orders 1-6 in one bucketed batch: the smooth kernels take their
+    order's bucket, the collapsed-minimiser kernels the shared bin of
+    collapsed paths filtered by order; per path against the oracle."""
+    sc = scenes.canyon_scene()
+    b = scenes.canyon_sample_paths(sc, 24000, seed=5050, n=None, n_max=6)
+    g_len, g_x = scenes.upstream_grads(b.N, b.n_max, seed=5051)
+    o, g_slot, g_end, g_pts, g_obj = _fwd_grad(solver, b, g_len, g_x)
+    ref = oracle_mod.solve(b, threads=8)
+    gref = oracle_mod.grad(b, ref["t"], g_len.astype(np.float64),
+                           np.transpose(g_x, (2, 0, 1)).astype(np.float64), threads=8)
+    s = gpu_util.summary(b, o, ref)
+    from paper_2510_16172_amd import fpt
+    col_gpu = (o["status"] & fpt.ST_COLLAPSED) != 0
+    nograd = (o["status"] & fpt.ST_NOGRAD) != 0
+    smooth = s["cert"] & ~s["col"] & ~s["ill"] & (gref["status"] == 0) & ~col_gpu
+    kkt = s["cert"] & col_gpu & ~nograd & s["col"] & (gref["status"] == oracle_mod.KKT)
+    for name, m in (("smooth", smooth), ("collapsed", kkt)):
+        for n in range(1 if name == "smooth" else 2, 7):
+            mo = m & (b.order == n)
+            assert mo.sum() > 20, (name, n, mo.sum())
+            bad = _compare_per_path(b, o, g_slot, g_end, ref, gref, mo, rtol=2e-3)
+            print(f"{name} n={n} compared={mo.sum()} bad={bad}", flush=True)
+            assert bad <= max(1, int(0.002 * mo.sum()))
+    assert np.all(g_slot[:, :, nograd] == 0) and np.all(g_end[:, nograd] == 0)
+
+
 def test_grad_reduction_matches_per_path_sum(solver):
     """g_obj / g_pts equal the sums of the per-path outputs (float atomics:
     to rounding), for the LDS-accumulated canyon tables."""
