@@ -75,58 +75,10 @@ __device__ __forceinline__ void acc_add(double* lds_base, float* glob, int64_t i
     unsafeAtomicAdd(glob + idx, v);
 }
 
-// Geometry of one lane in FP32 registers (the scene's values, exact in
-// FP64), widened at each use: the empty asm hides the value from the
-// compiler, so that every use converts again instead of FP64 copies staying
-// live through the kernel. The same holds the path's T* and g_X in FP32.
-// At three slots the kernel needs 145 VGPRs instead of 168; at six, 247
-// instead of 256 plus spills, two waves per SIMD instead of one.
-__device__ __forceinline__ double widen(float v) {
-  asm volatile("" : "+v"(v));
-  return (double)v;
-}
-
-template <int NO>
-struct GeoF32 {
-  static constexpr int kOrder = NO;
-  using real = double;
-  float tx_[3], rx_[3], b_[NO][3], a_[NO][2][3];
-  bool edge_[NO];
-  __device__ __forceinline__ double tx(int c) const { return widen(tx_[c]); }
-  __device__ __forceinline__ double rx(int c) const { return widen(rx_[c]); }
-  __device__ __forceinline__ double b(int j, int c) const { return widen(b_[j][c]); }
-  __device__ __forceinline__ double a(int j, int k, int c) const { return widen(a_[j][k][c]); }
-  __device__ __forceinline__ bool edge(int j) const { return edge_[j]; }
-  __device__ __forceinline__ bool fixed(int) const { return false; }
-};
-
-template <int NO>
-__device__ __forceinline__ void load_geo_f32(const GradArgs& A, int32_t s, int32_t e,
-                                             int64_t p, GeoF32<NO>& D) {
-  s = (s >= 0 && s < A.Q) ? s : 0;
-  e = (e >= 0 && e < A.Q) ? e : 0;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    D.tx_[c] = A.pts[(int64_t)c * A.Q + s];
-    D.rx_[c] = A.pts[(int64_t)c * A.Q + e];
-  }
-#pragma unroll
-  for (int j = 0; j < NO; ++j) {
-    int32_t k = A.ids[(int64_t)j * A.N + p];
-    k = (k >= 0 && k < A.K) ? k : 0;
-    float a2[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      D.b_[j][c] = A.obj[(int64_t)c * A.K + k];
-      D.a_[j][0][c] = A.obj[(int64_t)(3 + c) * A.K + k];
-      a2[c] = A.obj[(int64_t)(6 + c) * A.K + k];
-    }
-    const bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
-    D.edge_[j] = edge;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) D.a_[j][1][c] = edge ? 0.f : a2[c];
-  }
-}
+// The geometry, T* and g_X are held in FP32 registers and widened at each
+// use (GeoF32, widen): at three slots the kernel needs 145 VGPRs instead of
+// 168; at six, 247 instead of 256 plus spills, two waves per SIMD instead of
+// one.
 
 // A collapsed minimiser that carries a gradient (the forward pass leaves
 // FPT_ST_NOGRAD off only for the collapses single_collapse covers).
@@ -163,7 +115,7 @@ __device__ __forceinline__ void grad_path(const GradArgs& A, int64_t p, uint8_t 
     use = use && kid[j] >= 0 && kid[j] < A.K;
   }
   GeoF32<NO> G;
-  load_geo_f32<NO>(A, s, e, p, G);
+  load_geo_f32<NO>(A.obj, A.pts, A.ids, s, e, A.K, A.Q, A.N, p, G);
   float tf[2 * NO];
 #pragma unroll
   for (int k = 0; k < 2 * NO; ++k) {

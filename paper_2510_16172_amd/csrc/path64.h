@@ -15,7 +15,8 @@
 namespace fpt {
 
 // The FP64 helpers below take the geometry of one path through accessors,
-// so that it can live in registers (Geo64) or in LDS (GeoLds).
+// so that it can live in registers (Geo64 in FP64, GeoF32 in FP32) or in LDS
+// (GeoLds).
 template <int NO>
 struct Geo64 {
   static constexpr int kOrder = NO;
@@ -32,6 +33,66 @@ struct Geo64 {
   __device__ __forceinline__ bool edge(int j) const { return edge_[j]; }
   __device__ __forceinline__ bool fixed(int j) const { return fixed_[j]; }
 };
+
+// An FP32 value widened to FP64 behind an empty asm, which hides the value
+// from the compiler: each use converts again instead of an FP64 copy staying
+// live through the kernel (with the conversions merged, FP32 storage saves
+// no registers). The gradient kernels gain from it; the refinement kernels,
+// which use the geometry in every Newton step, lost 10-30 % to the extra
+// conversions, also where it raised their occupancy, and keep FP64 copies.
+__device__ __forceinline__ double widen(float v) {
+  asm volatile("" : "+v"(v));
+  return (double)v;
+}
+
+// Geometry of one lane in FP32 registers (the scene's values, exact in
+// FP64), widened at each use.
+template <int NO>
+struct GeoF32 {
+  static constexpr int kOrder = NO;
+  using real = double;
+  float tx_[3], rx_[3], b_[NO][3], a_[NO][2][3];
+  bool edge_[NO];
+  __device__ __forceinline__ double tx(int c) const { return widen(tx_[c]); }
+  __device__ __forceinline__ double rx(int c) const { return widen(rx_[c]); }
+  __device__ __forceinline__ double b(int j, int c) const { return widen(b_[j][c]); }
+  __device__ __forceinline__ double a(int j, int k, int c) const { return widen(a_[j][k][c]); }
+  __device__ __forceinline__ bool edge(int j) const { return edge_[j]; }
+  __device__ __forceinline__ bool fixed(int) const { return false; }
+};
+
+// Path p's geometry from the tables, indices out of range clamped to 0 (the
+// caller has flagged such a path invalid).
+template <int NO>
+__device__ __forceinline__ void load_geo_f32(const float* __restrict__ obj,
+                                             const float* __restrict__ pts,
+                                             const int32_t* __restrict__ ids, int32_t s,
+                                             int32_t e, int32_t K, int32_t Q, int64_t N,
+                                             int64_t p, GeoF32<NO>& D) {
+  s = (s >= 0 && s < Q) ? s : 0;
+  e = (e >= 0 && e < Q) ? e : 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    D.tx_[c] = pts[(int64_t)c * Q + s];
+    D.rx_[c] = pts[(int64_t)c * Q + e];
+  }
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    int32_t k = ids[(int64_t)j * N + p];
+    k = (k >= 0 && k < K) ? k : 0;
+    float a2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      D.b_[j][c] = obj[(int64_t)c * K + k];
+      D.a_[j][0][c] = obj[(int64_t)(3 + c) * K + k];
+      a2[c] = obj[(int64_t)(6 + c) * K + k];
+    }
+    const bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
+    D.edge_[j] = edge;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) D.a_[j][1][c] = edge ? 0.f : a2[c];
+  }
+}
 
 // Geometry of one lane in LDS: the FP32 scene values (exact in FP64, widened
 // on use) in one column of a [geo_lds_rows(NO)][kBlock] float array, so that
