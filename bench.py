@@ -234,6 +234,13 @@ def run_fwd_grad(args, fpt, scenes, torch):
             "peak": PEAK_HBM / 1e9, "unit": "GB/s",
             "frac": grad_bytes_per_path(3) * b.N / (tg_kernel * 1e-3) / PEAK_HBM,
             "traffic": cg["hbm_bytes_per_launch"] if cg else None},
+        # the same pass against the FP64 vector peak, by the committed
+        # counter FLOPs (latency-bound FP64: neither peak is reached)
+        "grad_roofline_fp64": None if not (cg and cg.get("counter_fp64_flop_per_launch")) else {
+            "kernel": "grad_kernel<3> + grad_kkt_kernel<3>", "bound": "alu",
+            "achieved": cg["counter_fp64_flop_per_launch"] / (tg_kernel * 1e-3) / 1e12,
+            "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+            "frac": cg["counter_fp64_flop_per_launch"] / (tg_kernel * 1e-3) / PEAK_FP64},
     }
     if args.no_autodiff:
         solver.close()
