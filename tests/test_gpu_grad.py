@@ -167,6 +167,36 @@ def test_grad_global_atomics_path(solver, oracle_mod):
                                    rtol=1e-6)
 
 
+def test_grad_global_atomics_collapsed(solver, oracle_mod):
+    """Canyon order-3 paths, each with its own objects (K = 3N: too large
+    for the LDS tables), so both gradient kernels add straight into the
+    global gradient; smooth and collapsed paths against the oracle, and the
+    reduced table equal to the per-path one."""
+    sc = scenes.canyon_scene()
+    b0 = scenes.canyon_sample_paths(sc, 3000, seed=5310, n=3)
+    b = pins.batch_from_paths([pins.path_geometry(b0, i) for i in range(b0.N)], S=b0.S)
+    assert 9 * b.K * 8 > 48 * 1024
+    g_len, g_x = scenes.upstream_grads(b.N, b.n_max, seed=5311)
+    o, g_slot, g_end, g_pts, g_obj = _fwd_grad(solver, b, g_len, g_x)
+    ref = oracle_mod.solve(b, threads=8)
+    gref = oracle_mod.grad(b, ref["t"], g_len.astype(np.float64),
+                           np.transpose(g_x, (2, 0, 1)).astype(np.float64), threads=8)
+    s = gpu_util.summary(b, o, ref)
+    from paper_2510_16172_amd import fpt
+    col_gpu = (o["status"] & fpt.ST_COLLAPSED) != 0
+    nograd = (o["status"] & fpt.ST_NOGRAD) != 0
+    smooth = s["cert"] & ~s["col"] & ~s["ill"] & (gref["status"] == 0) & ~col_gpu
+    kkt = s["cert"] & col_gpu & ~nograd & s["col"] & (gref["status"] == oracle_mod.KKT)
+    assert smooth.sum() > 1000 and kkt.sum() > 300
+    for m in (smooth, kkt):
+        bad = _compare_per_path(b, o, g_slot, g_end, ref, gref, m, rtol=2e-3)
+        assert bad <= max(1, int(0.002 * m.sum()))
+    for j in range(3):
+        np.testing.assert_allclose(g_obj[:, b.ids[j]], g_slot[j], atol=1e-6, rtol=1e-6)
+    np.testing.assert_allclose(g_pts[:, b.src], g_end[0:3], atol=1e-6, rtol=1e-6)
+    np.testing.assert_allclose(g_pts[:, b.dst], g_end[3:6], atol=1e-6, rtol=1e-6)
+
+
 def test_grad_vs_finite_differences(solver, oracle_mod):
     """GPU gradient of sum(gl L + gx . x) vs central differences of the FP64
     oracle's solve (h = 2^-10 m ~ 1e-3 m, Richardson-extrapolated), over all
