@@ -1084,6 +1084,10 @@ extern "C" fpt_status fpt_grad(fpt_handle* h, const fpt_scene* sc,
             hipSuccess ||
         occ < 1)
       occ = 1;
+    // (the collapsed-path kernel: at most two workgroups per CU. It sees a
+    // fraction of the paths, and every workgroup clears and flushes its own
+    // tables; at order 2, three per CU took 37 us against 31 with two)
+    if (kkt && occ > 2) occ = 2;
     int64_t gsz = (int64_t)h->num_cu * occ;
     return (int)(gsz < c ? gsz : c);
   };

@@ -100,26 +100,83 @@ __device__ __forceinline__ void flush_tables(const GradArgs& A, const double* sh
 // One path's gradient: its per-path outputs and its adds to the object and
 // point gradients. KKT: the path is a collapsed minimiser (the constrained
 // form above); otherwise a smooth one.
+// One path's per-path inputs (everything but the scene tables), loaded
+// ahead of its computation.
+template <int NO>
+struct PathIn {
+  int64_t p;
+  int32_t s, e, kid[NO];
+  float t[2 * NO], gx[NO][3], gl;
+  uint8_t st, ord;
+};
+
+template <int NO>
+__device__ __forceinline__ void load_in(const GradArgs& A, int64_t p, PathIn<NO>& I) {
+  I.p = p;
+  I.st = A.status[p];
+  I.ord = A.order ? A.order[p] : (uint8_t)NO;
+  I.s = A.src[p];
+  I.e = A.dst[p];
+#pragma unroll
+  for (int j = 0; j < NO; ++j) I.kid[j] = A.ids[(int64_t)j * A.N + p];
+#pragma unroll
+  for (int k = 0; k < 2 * NO; ++k) I.t[k] = A.t[(int64_t)k * A.N + p];
+#pragma unroll
+  for (int j = 0; j < NO; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      I.gx[j][c] = A.g_x ? A.g_x[(int64_t)(3 * j + c) * A.N + p] : 0.f;
+  I.gl = A.g_len ? A.g_len[p] : 0.f;
+}
+
+// The geometry of a path whose inputs are loaded.
+template <int NO>
+__device__ __forceinline__ void load_geo_in(const GradArgs& A, const PathIn<NO>& I,
+                                            GeoF32<NO>& D) {
+  const int32_t s = (I.s >= 0 && I.s < A.Q) ? I.s : 0;
+  const int32_t e = (I.e >= 0 && I.e < A.Q) ? I.e : 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    D.tx_[c] = A.pts[(int64_t)c * A.Q + s];
+    D.rx_[c] = A.pts[(int64_t)c * A.Q + e];
+  }
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    const int32_t k = (I.kid[j] >= 0 && I.kid[j] < A.K) ? I.kid[j] : 0;
+    float a2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      D.b_[j][c] = A.obj[(int64_t)c * A.K + k];
+      D.a_[j][0][c] = A.obj[(int64_t)(3 + c) * A.K + k];
+      a2[c] = A.obj[(int64_t)(6 + c) * A.K + k];
+    }
+    const bool edge = (a2[0] == 0.f) && (a2[1] == 0.f) && (a2[2] == 0.f);
+    D.edge_[j] = edge;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) D.a_[j][1][c] = edge ? 0.f : a2[c];
+  }
+}
+
 template <int NO, bool LDS, bool KKT>
-__device__ __forceinline__ void grad_path(const GradArgs& A, int64_t p, uint8_t stp,
-                                          double* s_obj, double* s_pts) {
-  const int32_t s = A.src[p], e = A.dst[p];
+__device__ __forceinline__ void grad_path(const GradArgs& A, const PathIn<NO>& I,
+                                          const GeoF32<NO>& G, double* s_obj, double* s_pts) {
+  const int64_t p = I.p;
+  const uint8_t stp = I.st;
+  const int32_t s = I.s, e = I.e;
   // (no gradient: FPT_ST_NOGRAD, or a collapse where the smooth form runs)
   constexpr uint8_t kOff = KKT ? FPT_ST_NOGRAD : (FPT_ST_NOGRAD | FPT_ST_COLLAPSED);
   bool use = (stp & kOff) == 0 && s >= 0 && s < A.Q && e >= 0 && e < A.Q;
-  if (A.order) use = use && (int)A.order[p] == NO;
+  use = use && (int)I.ord == NO;
   int32_t kid[NO];
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
-    kid[j] = A.ids[(int64_t)j * A.N + p];
+    kid[j] = I.kid[j];
     use = use && kid[j] >= 0 && kid[j] < A.K;
   }
-  GeoF32<NO> G;
-  load_geo_f32<NO>(A.obj, A.pts, A.ids, s, e, A.K, A.Q, A.N, p, G);
   float tf[2 * NO];
 #pragma unroll
   for (int k = 0; k < 2 * NO; ++k) {
-    tf[k] = A.t[(int64_t)k * A.N + p];
+    tf[k] = I.t[k];
     use = use && isfinite(tf[k]);
   }
 #pragma unroll
@@ -182,14 +239,13 @@ __device__ __forceinline__ void grad_path(const GradArgs& A, int64_t p, uint8_t 
       il[i] = zi ? 0.0 : il[i];
     }
   }
-  const double gl = A.g_len ? (double)A.g_len[p] : 0.0;
+  const double gl = (double)I.gl;
   float gx[NO][3];
   double w[2 * NO];
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      gx[j][c] = A.g_x ? A.g_x[(int64_t)(3 * j + c) * A.N + p] : 0.f;
+    for (int c = 0; c < 3; ++c) gx[j][c] = I.gx[j][c];
     w[2 * j] = G.a(j, 0, 0) * widen(gx[j][0]) + G.a(j, 0, 1) * widen(gx[j][1]) + G.a(j, 0, 2) * widen(gx[j][2]);
     w[2 * j + 1] = G.a(j, 1, 0) * widen(gx[j][0]) + G.a(j, 1, 1) * widen(gx[j][1]) + G.a(j, 1, 2) * widen(gx[j][2]);
   }
@@ -323,8 +379,11 @@ __device__ __forceinline__ void run_kkt_list(const GradArgs& A, const int32_t* _
     const bool last = base + step >= count;
     const int full = last ? n : n / kBlock * kBlock;
     for (int i = threadIdx.x; i < full; i += kBlock) {
-      const int64_t p = list[i];
-      grad_path<NO, LDS, true>(A, p, A.status[p], s_obj, s_pts);
+      PathIn<NO> I;
+      load_in<NO>(A, list[i], I);
+      GeoF32<NO> G;
+      load_geo_in<NO>(A, I, G);
+      grad_path<NO, LDS, true>(A, I, G, s_obj, s_pts);
     }
     // carry the rest (fewer than 256, at indices >= 256: no overlap)
     const int rest = n - full;
@@ -357,12 +416,34 @@ void grad_kernel(GradArgs A, const int32_t* __restrict__ perm,
     count = bucket[NO] - begin;
   }
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < count;
-       idx += stride) {
-    const int64_t p = perm ? (int64_t)perm[begin + idx] : idx;
-    const uint8_t stp = A.status[p];
-    if (NO >= 2 && kkt_path(stp)) continue;  // grad_kkt_kernel's
-    grad_path<NO, LDS, false>(A, p, stp, s_obj, s_pts);
+  int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if constexpr (NO >= 3 && NO <= 5) {
+    // the next path's inputs are loaded while this one is computed (issued
+    // after this one's geometry loads: the load counter drains in order).
+    // At orders 3-5 the registers they take leave the waves per SIMD as
+    // they are; at orders 1, 2 and 6 they would cost a wave and more time
+    // than the overlap gains.
+    PathIn<NO> nx;
+    if (idx < count) load_in<NO>(A, perm ? (int64_t)perm[begin + idx] : idx, nx);
+    for (; idx < count; idx += stride) {
+      const PathIn<NO> cu = nx;
+      GeoF32<NO> G;
+      load_geo_in<NO>(A, cu, G);
+      const int64_t i2 = idx + stride;
+      if (i2 < count) load_in<NO>(A, perm ? (int64_t)perm[begin + i2] : i2, nx);
+      if (kkt_path(cu.st)) continue;  // grad_kkt_kernel's
+      grad_path<NO, LDS, false>(A, cu, G, s_obj, s_pts);
+    }
+  } else {
+    for (; idx < count; idx += stride) {
+      const int64_t p = perm ? (int64_t)perm[begin + idx] : idx;
+      if (NO >= 2 && kkt_path(A.status[p])) continue;  // grad_kkt_kernel's
+      PathIn<NO> cu;
+      load_in<NO>(A, p, cu);
+      GeoF32<NO> G;
+      load_geo_in<NO>(A, cu, G);
+      grad_path<NO, LDS, false>(A, cu, G, s_obj, s_pts);
+    }
   }
   if (LDS) flush_tables(A, sh);
 }
