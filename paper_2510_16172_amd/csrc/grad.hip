@@ -75,11 +75,6 @@ __device__ __forceinline__ void acc_add(double* lds_base, float* glob, int64_t i
     unsafeAtomicAdd(glob + idx, v);
 }
 
-// The geometry, T* and g_X are held in FP32 registers and widened at each
-// use (GeoF32, widen): at three slots the kernel needs 145 VGPRs instead of
-// 168; at six, 247 instead of 256 plus spills, two waves per SIMD instead of
-// one.
-
 // A collapsed minimiser that carries a gradient (the forward pass leaves
 // FPT_ST_NOGRAD off only for the collapses single_collapse covers).
 __device__ __forceinline__ bool kkt_path(uint8_t st) {
@@ -97,11 +92,11 @@ __device__ __forceinline__ void flush_tables(const GradArgs& A, const double* sh
     if (s_pts[i] != 0.0) unsafeAtomicAdd(A.g_pts + i, (float)s_pts[i]);
 }
 
-// One path's gradient: its per-path outputs and its adds to the object and
-// point gradients. KKT: the path is a collapsed minimiser (the constrained
-// form above); otherwise a smooth one.
 // One path's per-path inputs (everything but the scene tables), loaded
-// ahead of its computation.
+// ahead of its computation. They and the geometry are held in FP32 registers
+// and widened at each use (GeoF32, widen): at three slots the smooth kernel
+// needs 145 VGPRs instead of 168 with FP64 copies; at six, 247 instead of
+// 256 plus spills, two waves per SIMD instead of one.
 template <int NO>
 struct PathIn {
   int64_t p;
@@ -157,6 +152,9 @@ __device__ __forceinline__ void load_geo_in(const GradArgs& A, const PathIn<NO>&
   }
 }
 
+// One path's gradient: its per-path outputs and its adds to the object and
+// point gradients. KKT: the path is a collapsed minimiser (the constrained
+// form above); otherwise a smooth one.
 template <int NO, bool LDS, bool KKT>
 __device__ __forceinline__ void grad_path(const GradArgs& A, const PathIn<NO>& I,
                                           const GeoF32<NO>& G, double* s_obj, double* s_pts) {
@@ -327,7 +325,8 @@ __device__ __forceinline__ void grad_path(const GradArgs& A, const PathIn<NO>& I
 // quarter of the paths of a dense scene, spread over all waves). The
 // constrained solve would raise the registers of every path, so it has a
 // kernel of its own. That kernel gathers its paths first: each workgroup
-// scans 4 x 256 bucket entries at a time, appends the collapsed ones to a
+// scans 4 x 256 entries at a time (of the batch, or of the bucket of
+// collapsed paths of a bucketed batch), appends its order's ones to a
 // list in LDS (one atomic per wave: ballot and lane count) and runs the list
 // in batches of 256, every lane busy; what is left over waits for the next
 // scan, and the workgroup's last scan runs the rest. (The smooth kernel
@@ -336,9 +335,10 @@ __device__ __forceinline__ void grad_path(const GradArgs& A, const PathIn<NO>& I
 constexpr int kScan = 4 * kBlock;
 
 template <int NO, bool LDS>
-__device__ __forceinline__ void run_kkt_list(const GradArgs& A, const int32_t* __restrict__ perm,
-                                         const int64_t* __restrict__ bucket, int32_t* list,
-                                         int32_t& n_list, double* sh) {
+__device__ __forceinline__ void run_kkt_list(const GradArgs& A,
+                                             const int32_t* __restrict__ perm,
+                                             const int64_t* __restrict__ bucket,
+                                             int32_t* list, int32_t& n_list, double* sh) {
   const int64_t nsh = 9 * (int64_t)A.K + 3 * (int64_t)A.Q;
   if (LDS)
     for (int64_t i = threadIdx.x; i < nsh; i += kBlock) sh[i] = 0.0;
