@@ -32,7 +32,12 @@
  * The gradient oracle (oracle_grad) applies the implicit function theorem of
  * Sec. III-D (Eqs. 8-13) with the Hessian and the mixed derivatives of the
  * optimality condition written out in closed form (derivation in the
- * comments of grad_one), in FP64, at a given solution.
+ * comments of grad_one), in FP64, at a given solution. At a minimiser with
+ * one interior zero-length segment it applies the same theorem to the KKT
+ * conditions of the length without that segment under the constraint that
+ * its two points coincide (grad_one_kkt, a dense solve of the bordered
+ * system): an extension of Sec. III-D, which covers smooth minimisers only,
+ * pinned by finite differences of the solve above.
  *
  * Inputs are the FP32 tables of the C ABI, widened exactly to FP64.
  * Outputs are path-major FP64 arrays (see fermat_oracle.h).
