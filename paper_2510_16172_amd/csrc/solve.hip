@@ -2340,13 +2340,21 @@ __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(
     perm[(int64_t)gstart[k] + (i - lstart[k])] = stage[sort_skew(i)];
   }
   if (!inv) return;
-  // the inverse permutation (inv[p] = slot of path p), if asked for: each
-  // thread writes its 32 consecutive paths
+  // the inverse permutation (inv[p] = slot of path p), if asked for: staged
+  // in LDS (the sorted chunk is out), then written with consecutive threads
+  // on consecutive addresses (a thread's own 32 paths would be 32 stores
+  // 128 bytes apart across the wave)
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < kSortPer; ++q) {
     const int b = bins[q];
-    if (b >= 0) inv[base + q] = (int32_t)(gstart[b] + (uint32_t)(lp[q] - lstart[b]));
+    if (b >= 0)
+      stage[sort_skew(threadIdx.x * kSortPer + q)] =
+          (int32_t)(gstart[b] + (uint32_t)(lp[q] - lstart[b]));
   }
+  __syncthreads();
+  const int len = (int)(c1 - c0);
+  for (int i = threadIdx.x; i < len; i += kBlock) inv[c0 + i] = stage[sort_skew(i)];
 }
 
 // Paths with an order outside 1..n_max: NaN outputs, INVALID status (perm
