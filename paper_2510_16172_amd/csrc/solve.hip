@@ -2185,17 +2185,19 @@ __global__ __launch_bounds__(kBlock) void bucket_count_kernel(
 
 // One workgroup: per-chunk offsets (in place over ccount) and bucket bounds.
 // Thread t sums a contiguous run of chunks; an exclusive scan over the
-// threads (per bin, in LDS, log2(kBlock) steps) gives each run's start.
+// threads gives each run's start: per bin, over the wave by shuffles, then
+// over the four waves' totals in LDS (two barriers; counts fit 32 bits, as
+// N < 2^31).
 __global__ __launch_bounds__(kBlock) void bucket_scan_kernel(
     uint32_t* __restrict__ ccount, int64_t nchunks, int n_max,
     int64_t* __restrict__ bucket) {
-  __shared__ unsigned long long part[2][kBlock][8];
-  __shared__ unsigned long long start[8];
-  if (threadIdx.x < 8) start[threadIdx.x] = 0;
+  __shared__ uint32_t wtot[kBlock / 64][8];
+  __shared__ uint32_t woff[kBlock / 64][8];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t per = (nchunks + kBlock - 1) / kBlock;
   const int64_t c0 = (int64_t)threadIdx.x * per;
   const int64_t c1 = min(nchunks, c0 + per);
-  unsigned long long sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   // (a chunk's 8 counts are 32 aligned bytes: two 16-byte loads, several
   // chunks in flight)
 #pragma unroll 4
@@ -2211,40 +2213,58 @@ __global__ __launch_bounds__(kBlock) void bucket_scan_kernel(
     sum[6] += hi.z;
     sum[7] += hi.w;
   }
+  uint32_t inc[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) part[0][threadIdx.x][k] = sum[k];
-  __syncthreads();
-  // inclusive Hillis-Steele scan over threads, ping-pong buffers
-  int cur = 0;
-  for (int d = 1; d < kBlock; d <<= 1) {
+  for (int k = 0; k < 8; ++k) {
+    inc[k] = sum[k];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      unsigned long long v = part[cur][threadIdx.x][k];
-      if ((int)threadIdx.x >= d) v += part[cur][threadIdx.x - d][k];
-      part[cur ^ 1][threadIdx.x][k] = v;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(inc[k], d);
+      if (lane >= d) inc[k] += v;
     }
-    cur ^= 1;
-    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    unsigned long long acc = 0;
-    bucket[0] = 0;
+  if (lane == 63)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) wtot[w][k] = inc[k];
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    // bin k: its waves' offsets, and its start among the bins (orders
+    // 1..n_max, then invalid orders, then bin 7, which only the backward
+    // pass fills)
+    const int k = threadIdx.x;
+    uint32_t tot[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      tot[b] = 0;
+#pragma unroll
+      for (int v = 0; v < kBlock / 64; ++v) tot[b] += wtot[v][b];
+    }
+    uint32_t acc = 0, st = 0;
     for (int n = 1; n <= n_max; ++n) {
-      start[n] = acc;
-      acc += part[cur][kBlock - 1][n];
-      bucket[n] = (int64_t)acc;
+      if (n == k) st = acc;
+      acc += tot[n];
+      if (k == 0) bucket[n] = (int64_t)acc;
     }
-    start[0] = acc;
-    acc += part[cur][kBlock - 1][0];
-    bucket[n_max + 1] = (int64_t)acc;
-    start[7] = acc;  // (bin 7: backward pass only, empty otherwise)
-    acc += part[cur][kBlock - 1][7];
-    bucket[n_max + 2] = (int64_t)acc;
+    if (k == 0) st = acc;
+    acc += tot[0];
+    if (k == 0) bucket[n_max + 1] = (int64_t)acc;
+    if (k == 7) st = acc;
+    acc += tot[7];
+    if (k == 0) {
+      bucket[0] = 0;
+      bucket[n_max + 2] = (int64_t)acc;
+    }
+    uint32_t o = st;
+#pragma unroll
+    for (int v = 0; v < kBlock / 64; ++v) {
+      woff[v][k] = o;
+      o += wtot[v][k];
+    }
   }
   __syncthreads();
-  unsigned long long run[8];
+  uint32_t run[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) run[k] = start[k] + part[cur][threadIdx.x][k] - sum[k];
+  for (int k = 0; k < 8; ++k) run[k] = woff[w][k] + inc[k] - sum[k];
 #pragma unroll 4
   for (int64_t c = c0; c < c1; ++c) {
     const uint4 lo = *reinterpret_cast<const uint4*>(ccount + c * 8);
@@ -2253,7 +2273,7 @@ __global__ __launch_bounds__(kBlock) void bucket_scan_kernel(
     uint32_t o[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      o[k] = (uint32_t)run[k];
+      o[k] = run[k];
       run[k] += v[k];
     }
     *reinterpret_cast<uint4*>(ccount + c * 8) = make_uint4(o[0], o[1], o[2], o[3]);
