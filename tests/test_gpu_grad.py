@@ -197,6 +197,28 @@ def test_grad_global_atomics_collapsed(solver, oracle_mod):
     np.testing.assert_allclose(g_pts[:, b.dst], g_end[3:6], atol=1e-6, rtol=1e-6)
 
 
+def test_grad_corner(solver, oracle_mod):
+    """Hand-built collapses: two planes meeting at a line (the constrained
+    gradient, against the oracle's) and two crossing edges (no gradient)."""
+    import test_oracle_pins as T
+    b = pins.batch_from_paths(T.corner_paths(200, seed=98), S=10.0)
+    g_len, g_x = scenes.upstream_grads(b.N, b.n_max, seed=5320)
+    o, g_slot, g_end, g_pts, g_obj = _fwd_grad(solver, b, g_len, g_x)
+    ref = oracle_mod.solve(b, threads=8)
+    gref = oracle_mod.grad(b, ref["t"], g_len.astype(np.float64),
+                           np.transpose(g_x, (2, 0, 1)).astype(np.float64), threads=8)
+    from paper_2510_16172_amd import fpt
+    st = o["status"]
+    assert st[0] & fpt.ST_COLLAPSED and st[0] & fpt.ST_NOGRAD and st[0] & fpt.ST_CONVERGED
+    assert np.all(g_slot[:, :, 0] == 0) and np.all(g_end[:, 0] == 0)
+    s = gpu_util.summary(b, o, ref)
+    kkt = (s["cert"] & ((st & fpt.ST_COLLAPSED) != 0) & ((st & fpt.ST_NOGRAD) == 0)
+           & (gref["status"] == oracle_mod.KKT))
+    assert kkt.sum() >= 60
+    bad = _compare_per_path(b, o, g_slot, g_end, ref, gref, kkt, rtol=2e-3)
+    assert bad == 0
+
+
 def test_grad_vs_finite_differences(solver, oracle_mod):
     """GPU gradient of sum(gl L + gx . x) vs central differences of the FP64
     oracle's solve (h = 2^-10 m ~ 1e-3 m, Richardson-extrapolated), over all

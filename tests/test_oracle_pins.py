@@ -403,6 +403,56 @@ def test_collapsed_gradient_vs_finite_differences(oracle_mod, n):
             np.testing.assert_allclose(ga[i, j], want, atol=1e-7 * scale)
 
 
+def corner_paths(n_face, seed):
+    """Hand-built collapses: the first path reflects off two edges that cross
+    at the origin (x- and y-axis) with TX and RX placed so that both points
+    sit at the crossing (subgradient sqrt(2/3) < 1: a collapsed minimiser
+    whose objects' directions span only a plane); then n_face paths off the
+    planes z = 0 and x = 0 from random TX, RX in the quadrant x, z > 0, of
+    which about half collapse onto the planes' meeting line."""
+    rng = np.random.default_rng(seed)
+    z3 = (0.0, 0.0, 0.0)
+    paths = [(np.array([-1.0, -1.0, 1.0]), np.array([1.0, 1.0, 1.0]),
+              [(np.array([-5.0, 0, 0]), np.array([10.0, 0, 0]), np.array(z3)),
+               (np.array([0, -5.0, 0]), np.array([0, 10.0, 0]), np.array(z3))])]
+    for _ in range(n_face):
+        tx = rng.uniform([0.2, -3, 0.2], [3, 3, 3])
+        rx = rng.uniform([0.2, -3, 0.2], [3, 3, 3])
+        paths.append((tx, rx, [
+            (np.array([-5.0, -5.0, 0.0]), np.array([10.0, 0, 0]), np.array([0, 10.0, 0])),
+            (np.array([0.0, -5.0, -5.0]), np.array([0, 10.0, 0]), np.array([0, 0, 10.0]))]))
+    return paths
+
+
+def test_collapsed_gradient_corner(oracle_mod):
+    """Two planes meeting at a line: paths that collapse onto the line get
+    the constrained gradient (checked by central differences); two crossing
+    edges (directions spanning only a plane) get none."""
+    b = pins.batch_from_paths(corner_paths(60, seed=99), S=10.0)
+    r = _solve(oracle_mod, b)
+    rng = np.random.default_rng(100)
+    gl = rng.standard_normal(b.N)
+    gx = rng.standard_normal((b.N, 2, 3))
+    g = oracle_mod.grad(b, r["t"], gl, gx, threads=4)
+    assert r["flags"][0] & oracle_mod.COLLAPSED
+    np.testing.assert_allclose(r["x"][0], 0.0, atol=1e-9)
+    assert g["status"][0] == oracle_mod.COLLAPSED and np.all(np.isnan(g["g_b"][0]))
+    col = np.nonzero((r["flags"][1:] & oracle_mod.COLLAPSED) != 0)[0] + 1
+    assert len(col) >= 15
+    assert np.all(g["status"][col] == oracle_mod.KKT)
+    h = 2.0 ** -10
+    d1 = _fd_grad(oracle_mod, b, gl, gx, h)
+    d2 = _fd_grad(oracle_mod, b, gl, gx, h / 2)
+    fd_tx, fd_rx, fd_obj = [(4.0 * b2 - b1) / 3.0 for b1, b2 in zip(d1, d2)]
+    ga = g["g_a"].reshape(b.N, 2, 6)
+    for i in col:
+        scale = 1.0 + np.abs(fd_obj[i]).max()
+        np.testing.assert_allclose(g["g_tx"][i], fd_tx[i], atol=1e-7 * scale)
+        np.testing.assert_allclose(g["g_rx"][i], fd_rx[i], atol=1e-7 * scale)
+        np.testing.assert_allclose(g["g_b"][i], fd_obj[i, :, 0:3], atol=1e-7 * scale)
+        np.testing.assert_allclose(ga[i], fd_obj[i, :, 3:9], atol=1e-7 * scale)
+
+
 def test_gradient_structure(oracle_mod):
     """A_j^T g_b_j = 0: moving an object within its own span leaves the
     solution unchanged; with g_x = 0 the gradient is the envelope term."""
