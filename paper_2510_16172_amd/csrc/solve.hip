@@ -2026,8 +2026,14 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(
 // few hundredths of a per cent more of the highest orders and lengthens
 // their latency-bound tail).
 
+// (three slots: asked for two waves per SIMD, the compiler spills 244 bytes
+// where it otherwise takes 48 AGPRs beyond 256 registers and runs one wave;
+// the order-3 refinement group took 3-6 % less time. At four to six slots
+// the spills that two waves take cost more than the wave gains, up to half
+// again at six; at two slots, three waves instead of two also lost.)
 template <int NO>
-__global__ __launch_bounds__(kBlock) void merge_kernel(SolveArgs A, StageArgs St) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NO == 3 ? 2 : 1)))
+void merge_kernel(SolveArgs A, StageArgs St) {
   __shared__ int64_t pre[kRegions + 1];
   if (threadIdx.x == 0) {
     int64_t acc = 0;
