@@ -1917,8 +1917,14 @@ __device__ __forceinline__ void add_work(unsigned long long* w, uint32_t (&work)
 // St.in_list == St.out_list == null: one pass with the full schedule.
 // QUICK (St.out_list != null) and the full schedule are separate
 // instantiations, so that each gets its own register budget.
+// (four and five slots: asked for two waves per SIMD, the full schedule at
+// four fits 251 VGPRs without spilling where it took 260 registers and one
+// wave, and five spills 68 / 132 bytes; each group ran about 2 % faster. At
+// six slots the spills of a second wave (228 / 316 bytes) made it 6 %
+// slower.)
 template <int NO, bool QUICK>
-__global__ __launch_bounds__(kBlock) void refine_kernel(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu((NO == 4 || NO == 5) ? 2 : 1))) void refine_kernel(
     SolveArgs A, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ bucket, StageArgs St) {
   __shared__ int64_t pre[kRegions + 1];
