@@ -1676,9 +1676,13 @@ __device__ __forceinline__ void bfgs_run(const SolveArgs& A, const Geo32<NO>& G,
 constexpr int kUnpaddedMax = 2;
 
 // (LS: the step rule. The line-search variant is an instantiation of its
-// own, so that its code costs the default kernel no registers.)
+// own, so that its code costs the default kernel no registers. Six slots:
+// asked for two waves per SIMD, the kernel spills 28 bytes where it took
+// six AGPRs beyond 256 registers and one wave, and runs 24 % faster; five
+// slots at three waves would spill 200 bytes and took twice as long.)
 template <int NO, int LS = FPT_LS_EQ6>
-__global__ __launch_bounds__(kBlock) void bfgs_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NO == 6 ? 2 : 1)))
+void bfgs_kernel(
     SolveArgs A, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ bucket) {
   clear_counters(A);
