@@ -448,8 +448,12 @@ void grad_kernel(GradArgs A, const int32_t* __restrict__ perm,
   if (LDS) flush_tables(A, sh);
 }
 
+// (four and five slots: asked for two waves per SIMD, the kernel spills 36
+// / 208 bytes where it took AGPRs beyond 256 registers and one wave; the
+// pass ran 7 / 4 % faster)
 template <int NO, bool LDS>
-__global__ __launch_bounds__(kBlock) void grad_kkt_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NO == 4 || NO == 5) ? 2 : 1)))
+void grad_kkt_kernel(
     GradArgs A, const int32_t* __restrict__ perm, const int64_t* __restrict__ bucket) {
   extern __shared__ double sh[];
   __shared__ int32_t list[kScan + kBlock];
